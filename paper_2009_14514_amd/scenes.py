@@ -1,0 +1,180 @@
+"""Seeded synthetic scene generators (dam-break columns, box walls, batches).
+
+This module only places particles and names run parameters.  It holds none
+of the method's arithmetic: no kernel, no mass calibration, no time-step
+criterion.  Both the HIP library (through the Python binding) and the CPU
+oracle consume the arrays it returns, so the two sides start from identical
+inputs.
+
+Random draws use SplitMix64 (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014): output k of the stream with
+seed S is mix(S + (k + 1) * 0x9E3779B97F4A7C15).  The jitter of particle i
+along axis c uses output k = 3 i + c, u = (out >> 40) * 2^-24, and the offset
+is j * (2u - 1).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, idx: np.ndarray) -> np.ndarray:
+    """Outputs number ``idx`` (0-based, uint64 array) of the SplitMix64 stream."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (idx.astype(np.uint64) + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform01(seed: int, idx: np.ndarray) -> np.ndarray:
+    """24-bit uniform in [0, 1) from stream outputs ``idx``."""
+    return (splitmix64(seed, idx) >> np.uint64(40)).astype(np.float64) * (2.0 ** -24)
+
+
+def lattice_column(counts, spacing, corner, jitter=0.0, seed=0, first_index=0):
+    """Particles at corner + (i + 1/2) * spacing, i over ``counts`` (x fastest).
+
+    Returns float64 (N, 3).  ``jitter`` is the half-width of the uniform
+    per-axis offset; ``first_index`` offsets the SplitMix64 stream so that
+    several columns of one scene draw disjoint numbers.
+    """
+    nx, ny, nz = (int(c) for c in counts)
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    idx = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    pos = np.asarray(corner, np.float64)[None, :] + (idx + 0.5) * spacing
+    if jitter != 0.0 and pos.shape[0] > 0:
+        k = np.arange(pos.shape[0] * 3, dtype=np.uint64) + np.uint64(3 * first_index)
+        u = uniform01(seed, k).reshape(-1, 3)
+        pos = pos + jitter * (2.0 * u - 1.0)
+    return pos
+
+
+def box_walls(box_min, box_max, spacing, layers):
+    """Static wall particles: a shell ``layers`` deep around the box.
+
+    Lattice points at box_min + (i + 1/2) * spacing for i in [-layers, n + layers)
+    per axis, minus the points inside the box.  Returns float64 (Nw, 3).
+    """
+    bmin = np.asarray(box_min, np.float64)
+    bmax = np.asarray(box_max, np.float64)
+    n = np.rint((bmax - bmin) / spacing).astype(np.int64)
+    axes = [np.arange(-layers, n[c] + layers) for c in range(3)]
+    iz, iy, ix = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    inside = (ix >= 0) & (ix < n[0]) & (iy >= 0) & (iy < n[1]) & (iz >= 0) & (iz < n[2])
+    keep = ~inside
+    idx = np.stack([ix[keep], iy[keep], iz[keep]], axis=1).astype(np.float64)
+    return bmin[None, :] + (idx + 0.5) * spacing
+
+
+@dataclass
+class Scene:
+    """One scene: fluid and wall particles plus the run parameters."""
+    name: str
+    pos: np.ndarray                      # (N, 3) float64, fluid
+    vel: np.ndarray                      # (N, 3) float64
+    walls: np.ndarray                    # (Nw, 3) float64
+    params: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def nw(self) -> int:
+        return int(self.walls.shape[0])
+
+
+def base_params(spacing, box_min, box_max, *, c0, layers=4, h_ratio=2.0,
+                support_ratio=2.0, edge_ratio=1.0, dt_base=0.0, level_cap=3,
+                n_levels=4, mode="rts", solver="wcsph"):
+    """Parameter dictionary shared by both sides.
+
+    ``dt_base = 0`` asks each side to take the base step from the sound-speed
+    criterion.  The domain is the box grown by the wall shell.
+    """
+    h = h_ratio * spacing
+    support = support_ratio * h
+    margin = layers * spacing
+    return dict(
+        solver=solver, mode=mode,
+        spacing=spacing, h=h, support=support, block_edge=edge_ratio * support,
+        rho0=1000.0, c0=float(c0), gamma=7.0, visc_alpha=0.05, visc_eps=0.01,
+        gravity=(0.0, -9.81, 0.0),
+        box_min=tuple(float(b) for b in box_min), box_max=tuple(float(b) for b in box_max),
+        domain_min=tuple(float(b) - margin for b in box_min),
+        domain_max=tuple(float(b) + margin for b in box_max),
+        dt_base=float(dt_base), r_crit=h, lambda_v=0.4, lambda_f=0.25,
+        alpha_rts=0.4 if solver == "wcsph" else 1.0, beta2=0.4, beta_ratio=0.2,
+        n_levels=n_levels, level_cap=level_cap, clamp_p=1, serna_correct=1,
+        wall_layers=layers,
+        # PCISPH settings (unused by WCSPH)
+        eta=0.01, eta_T=0.0025, it_min=3, it_max=50, n_minor=4, expand_layers=4,
+        local_fail_limit=3, global_reset_limit=6, clean_major_revert=10,
+    )
+
+
+def sound_speed_for_column(height, g=9.81):
+    """c0 = 10 * sqrt(2 g H): the usual weakly-compressible choice for a column of height H."""
+    return 10.0 * math.sqrt(2.0 * g * height)
+
+
+def dam_break_small(seed=0):
+    """4,096 particles (16^3, spacing 0.02 m) in a 0.6 x 0.4 x 0.4 m box, c0 = 20 m/s,
+    global fixed dt = 2e-4 s, jitter +-1e-4 m."""
+    s = 0.02
+    bmin, bmax = (0.0, 0.0, 0.0), (0.6, 0.4, 0.4)
+    pos = lattice_column((16, 16, 16), s, bmin, jitter=1e-4, seed=seed)
+    p = base_params(s, bmin, bmax, c0=20.0, dt_base=2e-4, level_cap=0, mode="global_fixed")
+    return Scene("dam_break_4k", pos, np.zeros_like(pos), box_walls(bmin, bmax, s, p["wall_layers"]), p)
+
+
+def dam_break_column(counts=(50, 100, 50), spacing=0.01, box=(2.0, 1.0, 1.0), seed=0,
+                     jitter_frac=0.005, c0=None, mode="rts", level_cap=3, name=None):
+    """Dam break: a column of ``counts`` lattice particles at the x = 0 corner of a box.
+
+    The default is the 250,000-particle column (0.5 x 1.0 x 0.5 m, spacing 0.01 m)
+    in a 2 x 1 x 1 m box with block levels 0..3.
+    """
+    bmin, bmax = (0.0, 0.0, 0.0), tuple(float(b) for b in box)
+    height = counts[1] * spacing
+    if c0 is None:
+        c0 = sound_speed_for_column(height)
+    pos = lattice_column(counts, spacing, bmin, jitter=jitter_frac * spacing, seed=seed)
+    p = base_params(spacing, bmin, bmax, c0=c0, dt_base=0.0, level_cap=level_cap, mode=mode)
+    p["column_height"] = height
+    return Scene(name or f"dam_break_{pos.shape[0]}", pos, np.zeros_like(pos),
+                 box_walls(bmin, bmax, spacing, p["wall_layers"]), p)
+
+
+def double_dam_break(spacing=0.4 / 63, col=(0.4, 0.8, 0.4), box=(2.0, 1.0, 1.0), seed=0,
+                     jitter_frac=0.005, dt_base=1e-3):
+    """PCISPH double dam break: two columns at both x-ends of a 2 x 1 x 1 m box.
+
+    At spacing 0.4/63 m each column is 63 x 126 x 63 (1,000,188 particles total).
+    """
+    n = tuple(int(round(c / spacing)) for c in col)
+    bmin, bmax = (0.0, 0.0, 0.0), tuple(float(b) for b in box)
+    a = lattice_column(n, spacing, (0.0, 0.0, 0.0), jitter=jitter_frac * spacing, seed=seed)
+    b = lattice_column(n, spacing, (box[0] - n[0] * spacing, 0.0, 0.0),
+                       jitter=jitter_frac * spacing, seed=seed, first_index=a.shape[0])
+    pos = np.concatenate([a, b], axis=0)
+    p = base_params(spacing, bmin, bmax, c0=sound_speed_for_column(col[1]), dt_base=dt_base,
+                    solver="pcisph", edge_ratio=1.1, level_cap=3)
+    return Scene(f"double_dam_break_{pos.shape[0]}", pos, np.zeros_like(pos),
+                 box_walls(bmin, bmax, spacing, p["wall_layers"]), p)
+
+
+def batch_sizes(n_scenes=64, lo=2000, hi=200000, seed=0):
+    """Particle counts log-uniform in [lo, hi] and column aspect ratios U(0.3, 1.5)."""
+    k = np.arange(2 * n_scenes, dtype=np.uint64)
+    u = uniform01(seed, k).reshape(n_scenes, 2)
+    counts = np.rint(np.exp(math.log(lo) + u[:, 0] * (math.log(hi) - math.log(lo)))).astype(np.int64)
+    aspect = 0.3 + 1.2 * u[:, 1]
+    return counts, aspect
