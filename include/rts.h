@@ -1,0 +1,204 @@
+/*
+ * rts.h -- C ABI of the MI355X regional time stepping (RTS) SPH library.
+ *
+ * Method: Goswami & Batty, "Asynchronous Liquids: Regional Time Stepping for
+ * Faster SPH and PCISPH".  The fluid domain is cut into blocks whose edge is
+ * at least the kernel support (Section 3); each block gets a time step from
+ * the speed and acceleration of its particles (Section 3.1, Eq. 1-3), and
+ * only particles whose step ends re-evaluate density and forces, with the
+ * predictor-corrector of Serna et al. keeping everyone in step (Section 4,
+ * Algorithm 1).
+ *
+ * Conventions for every entry point
+ *   - Pointers named d_* are device memory owned by the caller and borrowed
+ *     only for the duration of the call (or, for the workspace, until
+ *     rts_destroy).  Pointers named h_* are host memory.
+ *   - Vector arrays passed in or out are structure-of-arrays planes of
+ *     float32: x[0..n), then y[0..n), then z[0..n).
+ *   - Per-particle outputs are in the caller's original particle order
+ *     (the order given to rts_set_state).
+ *   - Work is enqueued on the HIP stream given to rts_create and calls
+ *     return before it finishes, except rts_sync, rts_assign_levels and the
+ *     getters that return host values, which wait for the stream.
+ *   - Every call returns an rts_status.  rts_last_error() gives a message.
+ *     Invalid arguments are rejected before any device work is enqueued.
+ *     After RTS_E_NUMERICAL or RTS_E_CAPACITY is reported by rts_sync the
+ *     context stays valid, but rts_advance returns RTS_E_STATE until the
+ *     state is replaced by rts_set_state or rts_load_state.
+ *   - One context per host thread; contexts are independent.
+ */
+#ifndef RTS_H
+#define RTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RTS_OK = 0,
+  RTS_E_INVALID = 1,     /* bad argument or configuration */
+  RTS_E_CAPACITY = 2,    /* neighbour list, block population or workspace too small */
+  RTS_E_DEVICE = 3,      /* a HIP runtime call failed */
+  RTS_E_NUMERICAL = 4,   /* a particle became non-finite or left the domain */
+  RTS_E_STATE = 5,       /* call not allowed in the current state */
+  RTS_E_UNSUPPORTED = 6  /* configuration value this build does not implement */
+} rts_status;
+
+typedef enum { RTS_WCSPH = 0, RTS_PCISPH = 1 } rts_solver;
+
+/* RTS: Algorithm 1 with block levels.  GLOBAL_FIXED: the same loop with
+ * every block at level 0.  GLOBAL_ADAPTIVE: every particle active each step,
+ * step length min(lambda_v r / c0, lambda_f sqrt(r / max|a|)). */
+typedef enum { RTS_MODE_RTS = 0, RTS_MODE_GLOBAL_FIXED = 1, RTS_MODE_GLOBAL_ADAPTIVE = 2 } rts_mode;
+
+#define RTS_MAX_LEVELS 8
+
+/* Run configuration.  SI units, double precision so that derived float
+ * thresholds are rounded once from the exact configured values.
+ * rts_default_config fills every field. */
+typedef struct rts_config {
+  int32_t solver;        /* rts_solver */
+  int32_t mode;          /* rts_mode */
+  int32_t n_levels;      /* number of block levels; level l steps 2^l base steps (<= 8) */
+  int32_t level_cap;     /* highest level a block may take */
+  int32_t clamp_p;       /* clamp pressure at zero */
+  int32_t serna_correct; /* 1: apply the predictor-corrector correction (Section 4.1) */
+  int32_t nbr_cap;       /* neighbour list capacity per particle */
+  int32_t use_graph;     /* 1: replay each base step as a captured HIP graph */
+  double spacing;         /* initial particle spacing s */
+  double h;               /* smoothing length of the cubic spline (support 2h) */
+  double support;         /* kernel support radius, 2h */
+  double block_edge;      /* block edge, >= support */
+  double r_crit;          /* length r of Eq. 1-3 (<= 0: support) */
+  double rho0;            /* rest density */
+  double mass;            /* particle mass (<= 0: rho0 / lattice sum of W) */
+  double c0;              /* speed of sound */
+  double gamma;           /* Tait exponent (this build: 7) */
+  double B;               /* Tait stiffness (<= 0: rho0 c0^2 / gamma) */
+  double visc_alpha;      /* artificial viscosity alpha */
+  double visc_eps;        /* viscosity regulariser, times h^2 */
+  double gravity[3];
+  double domain_min[3];   /* block grid covers [domain_min, domain_max] */
+  double domain_max[3];
+  double dt_base;         /* base step (<= 0: lambda_v r_crit / c0, Eq. 1) */
+  double lambda_v;        /* Eq. 1 coefficient (paper: <= 0.4) */
+  double lambda_f;        /* Eq. 2 coefficient (paper: <= 0.25) */
+  double alpha_rts;       /* Eq. 3 alpha (paper: 0.4 WCSPH, 1 PCISPH) */
+  double beta2;           /* beta_2 of Eq. 3 (paper: 0.4) */
+  double beta_ratio;      /* beta_{n+1} / beta_n (paper: 0.2) */
+} rts_config;
+
+/* Per-run counters, filled by rts_sync. */
+typedef struct rts_stats {
+  int64_t step;                      /* base steps taken */
+  double time;                       /* simulated time */
+  double dt_last;                    /* length of the last step */
+  int64_t active_last;               /* particles active in the last step */
+  int64_t inter_last;                /* neighbour pairs of active particles in the last step */
+  int64_t active_total;              /* sum over steps of active particles */
+  int64_t inter_total;               /* sum over steps of neighbour pairs evaluated */
+  float err_max_last;                /* max over particles of max(rho - rho0, 0) / rho0, last step */
+  float err_max_run;                 /* the same, max over all steps */
+  int32_t level_hist[RTS_MAX_LEVELS];/* particles per level after the last step's flags */
+  int32_t nbr_max;                   /* largest neighbour count seen */
+  int32_t status;                    /* device status (rts_status) */
+  int32_t bad_index;                 /* particle (caller order) that raised the status, or -1 */
+} rts_stats;
+
+typedef struct rts_ctx rts_ctx;
+
+/* Fills *cfg with the defaults (Section 3.1 constants, cubic spline h = 2s). */
+void rts_default_config(rts_config *cfg);
+
+/* Device workspace bytes for up to n_fluid_max fluid and n_wall_max wall
+ * particles under cfg.  Returns RTS_E_INVALID for a bad configuration. */
+rts_status rts_workspace_size(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
+                              size_t *bytes);
+
+/* Creates a context on the current HIP device.  d_workspace: caller device
+ * memory of at least rts_workspace_size bytes, 256-byte aligned, kept alive
+ * until rts_destroy.  hip_stream: the hipStream_t to enqueue on (NULL: the
+ * null stream).  The context is empty until rts_set_state. */
+rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
+                      void *d_workspace, size_t bytes, void *hip_stream, rts_ctx **out);
+
+/* Releases the host context and its graphs.  The workspace stays the caller's. */
+void rts_destroy(rts_ctx *ctx);
+
+/* Static wall particles (boundary; Section 6 uses static boundary particles).
+ * d_pos: 3*nw floats (planes).  Sorted into the block grid once. */
+rts_status rts_set_walls(rts_ctx *ctx, const float *d_pos, int64_t nw);
+
+/* Replaces the fluid state: n particles, d_pos and d_vel 3*n floats each.
+ * Accelerations start at zero and every particle starts with validity 0,
+ * so the first step evaluates all of them (Algorithm 1 initialisation). */
+rts_status rts_set_state(rts_ctx *ctx, const float *d_pos, const float *d_vel, int64_t n);
+
+/* Region determination only (Section 3.1 and R_min of Section 4.2): rebuilds
+ * the block grid, takes block maxima and levels and smooths them, without
+ * touching particle flags or physics.  h_level_hist[n_levels]: number of
+ * occupied blocks per level.  Waits for the stream. */
+rts_status rts_assign_levels(rts_ctx *ctx, int32_t *h_level_hist);
+
+/* Advances n_steps base steps of Algorithm 1 (or of the global comparator
+ * chosen by cfg.mode).  Asynchronous. */
+rts_status rts_advance(rts_ctx *ctx, int32_t n_steps);
+
+/* Waits for the stream and copies the counters to *h_out (may be NULL).
+ * Returns the device status. */
+rts_status rts_sync(rts_ctx *ctx, rts_stats *h_out);
+
+/* Copies the state out in caller order.  Any pointer may be NULL.
+ * d_pos, d_vel, d_acc: 3*n floats; d_rho, d_p: n floats; d_level: n bytes. */
+rts_status rts_get_state(rts_ctx *ctx, float *d_pos, float *d_vel, float *d_acc, float *d_rho,
+                         float *d_p, uint8_t *d_level);
+
+/* Saves / restores the complete particle state and counters, so that a
+ * restored run continues bit for bit.  d_buf: device memory. */
+rts_status rts_state_bytes(rts_ctx *ctx, size_t *bytes);
+rts_status rts_save_state(rts_ctx *ctx, void *d_buf, size_t cap);
+rts_status rts_load_state(rts_ctx *ctx, const void *d_buf, size_t len);
+
+/* Debug views of internal buffers, copied raw to d_out (device).  *n_out
+ * receives the element count.  Layouts:
+ *   RTS_DBG_POS/VEL/ACC/ACC_NEW: float4 per particle, sorted order
+ *   RTS_DBG_META: uint32 per particle (bits 0-3 level, 4 compute, 5-15 age,
+ *                 16-31 validity as int16), sorted order
+ *   RTS_DBG_ID: caller index of each sorted particle
+ *   RTS_DBG_KEY: block key of each sorted particle
+ *   RTS_DBG_PERM: previous sorted position of each sorted particle
+ *   RTS_DBG_CELL_START: nblocks + 1 uint32
+ *   RTS_DBG_BLK_LEVEL_RAW / BLK_LEVEL: uint8 per block, before / after R_min
+ *   RTS_DBG_NNB: uint32 per particle;  RTS_DBG_NBR: nbr_cap x ncap uint32,
+ *                 slot k of particle i at k * ncap + i
+ *   RTS_DBG_PRESSURE: float per sorted slot, valid for the last step's active
+ *                 particles only
+ *   RTS_DBG_PRE_POS/VEL/ACC/META/ID: the arrays as they were before the last
+ *                 step's sort (the step's input), in their previous order
+ *   RTS_DBG_WALL_POS: float4 per wall particle, sorted; RTS_DBG_WALL_ID:
+ *                 caller index of each sorted wall; RTS_DBG_WALL_CELL_START
+ *   RTS_DBG_ACTIVE: sorted indices of the last step's active particles
+ *                 (any order). */
+typedef enum {
+  RTS_DBG_POS = 0, RTS_DBG_VEL, RTS_DBG_ACC, RTS_DBG_ACC_NEW, RTS_DBG_META, RTS_DBG_ID,
+  RTS_DBG_KEY, RTS_DBG_PERM, RTS_DBG_CELL_START, RTS_DBG_BLK_LEVEL_RAW, RTS_DBG_BLK_LEVEL,
+  RTS_DBG_NNB, RTS_DBG_NBR, RTS_DBG_PRESSURE, RTS_DBG_PRE_POS, RTS_DBG_PRE_VEL,
+  RTS_DBG_PRE_ACC, RTS_DBG_PRE_META, RTS_DBG_PRE_ID, RTS_DBG_WALL_POS, RTS_DBG_WALL_ID,
+  RTS_DBG_WALL_CELL_START, RTS_DBG_ACTIVE, RTS_DBG_COUNT_
+} rts_debug_what;
+rts_status rts_debug_get(rts_ctx *ctx, int32_t what, void *d_out, size_t cap_bytes, size_t *n_out);
+
+/* Grid and derived numbers: nc[3], nblocks, particle mass, Tait B, base step. */
+rts_status rts_grid_info(rts_ctx *ctx, int32_t *h_nc3, int64_t *h_nblocks, double *h_mass,
+                         double *h_B, double *h_dt_base);
+
+const char *rts_last_error(const rts_ctx *ctx);
+const char *rts_status_string(rts_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTS_H */

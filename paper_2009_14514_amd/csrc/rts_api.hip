@@ -1,0 +1,625 @@
+// C ABI of the RTS library: configuration, workspace carving, state
+// transfer, the base-step driver (replayed as HIP graphs) and counters.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "rts_internal.h"
+
+using namespace rts;
+
+struct rts_ctx {
+  rts_config cfg;
+  DevParams prm;
+  DevPtrs d;
+  int cur;
+  hipStream_t stream;
+  hipStream_t cap_stream;
+  hipGraphExec_t gexec[2];
+  hipGraph_t graph[2];
+  bool graph_ok;
+  int64_t ncap, nwcap;
+  int grid_persist;
+  bool has_state;
+  bool poisoned;
+  double mass, B, dt_base;
+  char err[512];
+};
+
+namespace {
+
+rts_status fail(rts_ctx *c, rts_status s, const char *fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+#define HIP_OK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((ctx), RTS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// Cubic spline shape, used on the host for the mass calibration.
+double w_shape_d(double q) {
+  if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+  if (q < 2.0) {
+    double t = 2.0 - q;
+    return 0.25 * t * t * t;
+  }
+  return 0.0;
+}
+
+// Sum of W over the cubic lattice around one site, self included: a
+// particle in the interior of the rest lattice then has density rho0.
+double lattice_w_sum(const rts_config &c) {
+  double s = c.spacing, r = c.support;
+  double sigma = 1.0 / (M_PI * c.h * c.h * c.h);
+  int m = (int)ceil(r / s) + 1;
+  double sum = 0.0;
+  for (int k = -m; k <= m; ++k)
+    for (int j = -m; j <= m; ++j)
+      for (int i = -m; i <= m; ++i) {
+        double d = s * sqrt((double)(i * i + j * j + k * k));
+        if (d < r) sum += sigma * w_shape_d(d / c.h);
+      }
+  return sum;
+}
+
+double r_crit_of(const rts_config &c) { return c.r_crit > 0.0 ? c.r_crit : c.support; }
+
+rts_status validate(const rts_config *c, char *msg, size_t cap) {
+  if (!c) { snprintf(msg, cap, "config is NULL"); return RTS_E_INVALID; }
+  if (c->solver != RTS_WCSPH) { snprintf(msg, cap, "solver %d not built", c->solver); return RTS_E_UNSUPPORTED; }
+  if (c->mode < 0 || c->mode > 2) { snprintf(msg, cap, "bad mode %d", c->mode); return RTS_E_INVALID; }
+  if (!(c->spacing > 0 && c->h > 0 && c->support > 0 && c->rho0 > 0 && c->c0 > 0)) {
+    snprintf(msg, cap, "spacing, h, support, rho0 and c0 must be positive");
+    return RTS_E_INVALID;
+  }
+  if (!(c->support <= 2.0 * c->h * (1.0 + 1e-12))) {
+    snprintf(msg, cap, "support %g exceeds the cubic spline's 2h", c->support);
+    return RTS_E_INVALID;
+  }
+  if (!(c->block_edge >= c->support)) {
+    snprintf(msg, cap, "block_edge %g must be >= support %g", c->block_edge, c->support);
+    return RTS_E_INVALID;
+  }
+  if (c->gamma != 7.0) { snprintf(msg, cap, "only gamma = 7 is built"); return RTS_E_UNSUPPORTED; }
+  if (c->n_levels < 1 || c->n_levels > RTS_MAX_LEVELS) {
+    snprintf(msg, cap, "n_levels must be in [1, %d]", RTS_MAX_LEVELS);
+    return RTS_E_INVALID;
+  }
+  if (c->nbr_cap < 1 || c->nbr_cap > 4096) { snprintf(msg, cap, "nbr_cap must be in [1, 4096]"); return RTS_E_INVALID; }
+  if (!(c->lambda_v > 0 && c->lambda_f > 0 && c->alpha_rts > 0 && c->beta2 > 0 && c->beta_ratio > 0)) {
+    snprintf(msg, cap, "time-step coefficients must be positive");
+    return RTS_E_INVALID;
+  }
+  double nb = 1;
+  for (int d = 0; d < 3; ++d) {
+    double ext = c->domain_max[d] - c->domain_min[d];
+    if (!(ext > 0)) { snprintf(msg, cap, "empty domain on axis %d", d); return RTS_E_INVALID; }
+    nb *= ceil(ext / c->block_edge);
+  }
+  if (nb > 2.0e9) { snprintf(msg, cap, "too many blocks (%g)", nb); return RTS_E_INVALID; }
+  return RTS_OK;
+}
+
+void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, double &mass,
+            double &B, double &dtb) {
+  memset(&p, 0, sizeof(p));
+  p.ncap = (int32_t)ncap;
+  p.kcap = c.nbr_cap;
+  int64_t nb = 1;
+  for (int d = 0; d < 3; ++d) {
+    int32_t n = (int32_t)ceil((c.domain_max[d] - c.domain_min[d]) / c.block_edge);
+    p.nc[d] = n < 1 ? 1 : n;
+    nb *= p.nc[d];
+    p.o[d] = (float)c.domain_min[d];
+    p.dmax[d] = (float)c.domain_max[d];
+    p.g[d] = (float)c.gravity[d];
+  }
+  (void)nwcap;
+  p.nb = (int32_t)nb;
+  p.inv_e = (float)(1.0 / c.block_edge);
+  p.r2f = (float)(c.support * c.support);
+  p.h = (float)c.h;
+  p.inv_h = (float)(1.0 / c.h);
+  const double sigma = 1.0 / (M_PI * c.h * c.h * c.h);
+  p.sigma = (float)sigma;
+  mass = c.mass > 0.0 ? c.mass : c.rho0 / lattice_w_sum(c);
+  p.mass = (float)mass;
+  p.rho0 = (float)c.rho0;
+  const double cc = c.rho0 / (mass * sigma) - 1.0;
+  p.c_hi = (float)cc;
+  p.c_lo = (float)(cc - (double)p.c_hi);
+  p.kms = (float)(mass * sigma / c.rho0);
+  B = c.B > 0.0 ? c.B : c.rho0 * c.c0 * c.c0 / c.gamma;
+  p.B = (float)B;
+  p.visc_num = (float)(2.0 * c.visc_alpha * c.h * c.c0);
+  p.visc_eps_h2 = (float)(c.visc_eps * c.h * c.h);
+  const double rc = r_crit_of(c);
+  dtb = c.dt_base > 0.0 ? c.dt_base : c.lambda_v * rc / c.c0;   // Eq. 1
+  p.dt_base = (float)dtb;
+  p.dt_cfl = c.lambda_v * rc / c.c0;
+  p.lf2r = c.lambda_f * c.lambda_f * rc;
+  int lmax = c.n_levels - 1;
+  if (c.level_cap < lmax) lmax = c.level_cap < 0 ? 0 : c.level_cap;
+  if (c.mode != RTS_MODE_RTS) lmax = 0;
+  p.lmax = lmax;
+  p.mode = c.mode;
+  p.serna_correct = c.serna_correct;
+  p.clamp_p = c.clamp_p;
+  // Level l steps 2^l base steps and takes beta of rank l + 1 (Section 3.1:
+  // beta_1 = infinity, beta_n = beta2 * ratio^(n-2)):
+  //   Eq. 3:  |v|^2 <= (alpha beta_{l+1} r / (2^l dt))^2
+  //   Eq. 2:  |a|^2 <= (lambda_f^2 r / (2^l dt)^2)^2
+  for (int l = 0; l < kMaxLevels; ++l) {
+    double dtl = ldexp(dtb, l);
+    double bet = (l + 1 <= 1) ? INFINITY : c.beta2 * pow(c.beta_ratio, (double)(l + 1 - 2));
+    double vl = isinf(bet) ? INFINITY : c.alpha_rts * bet * rc / dtl;
+    double al = c.lambda_f * c.lambda_f * rc / (dtl * dtl);
+    p.TV[l] = (float)(vl * vl);
+    p.TA[l] = (float)(al * al);
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carves the workspace; with base == nullptr only the size is computed.
+size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtrs *d) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char * {
+    char *q = base ? base + off : nullptr;
+    off += align256(bytes > 0 ? bytes : 1);
+    return q;
+  };
+  const size_t n = (size_t)(ncap > 0 ? ncap : 1);
+  const size_t nw = (size_t)(nwcap > 0 ? nwcap : 1);
+  const size_t nb = (size_t)p.nb;
+  const size_t ntiles = (nb + kScanTile - 1) / kScanTile;
+  DevPtrs t;
+  memset(&t, 0, sizeof(t));
+  for (int b = 0; b < 2; ++b) {
+    t.P[b] = (float4 *)take(n * 16);
+    t.V[b] = (float4 *)take(n * 16);
+    t.A[b] = (float4 *)take(n * 16);
+    t.M[b] = (uint32_t *)take(n * 4);
+    t.ID[b] = (uint32_t *)take(n * 4);
+  }
+  t.ANEW = (float4 *)take(n * 16);
+  t.PRES = (float *)take(n * 4);
+  t.KEY = (uint32_t *)take(n * 4);
+  t.KEYOLD = (uint32_t *)take(n * 4);
+  t.RANK = (uint32_t *)take(n * 4);
+  t.TMP = (uint32_t *)take(n * 4);
+  t.PERM = (uint32_t *)take(n * 4);
+  t.NNB = (uint32_t *)take(n * 4);
+  t.ACT = (uint32_t *)take(n * 4);
+  t.NBR = (uint32_t *)take(n * (size_t)p.kcap * 4);
+  t.COUNT = (uint32_t *)take(nb * 4);
+  t.CELL_START = (uint32_t *)take((nb + 1) * 4);
+  t.LRAW = (uint8_t *)take(nb);
+  t.LVL = (uint8_t *)take(nb);
+  t.WP = (float4 *)take(nw * 16);
+  t.WID = (uint32_t *)take(nw * 4);
+  t.WCELL_START = (uint32_t *)take((nb + 1) * 4);
+  t.WKEY = (uint32_t *)take(nw * 4);
+  t.WRANK = (uint32_t *)take(nw * 4);
+  t.WTMP = (uint32_t *)take(nw * 4);
+  t.TILES = (unsigned long long *)take(ntiles * 8);
+  t.CTRL = (DevCtrl *)take(sizeof(DevCtrl));
+  t.S = (DevScalars *)take(sizeof(DevScalars));
+  if (d) *d = t;
+  return off;
+}
+
+void destroy_graphs(rts_ctx *c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+  c->graph_ok = false;
+}
+
+// The kernels of one base step, reading buffer `cur` and leaving the state in
+// buffer cur ^ 1.
+void enqueue_step(rts_ctx *c, int cur, hipStream_t st) {
+  const DevParams &p = c->prm;
+  const DevPtrs &d = c->d;
+  const int nx = cur ^ 1;
+  launch_key_hist(p, d, cur, st);
+  launch_scan(p, d.COUNT, d.CELL_START, p.nb, d.TILES, d.CTRL, d.S, st);
+  launch_scatter(p, d, st);
+  launch_cell_gather(p, d, cur, st);
+  launch_rmin_flags(p, d, nx, 1, st);
+  launch_search_density(p, d, nx, c->grid_persist, st);
+  launch_force(p, d, nx, c->grid_persist, st);
+  launch_correct_predict(p, d, nx, st);
+}
+
+rts_status build_graphs(rts_ctx *c) {
+  destroy_graphs(c);
+  for (int k = 0; k < 2; ++k) {
+    HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    enqueue_step(c, k, c->cap_stream);
+    HIP_OK(c, hipStreamEndCapture(c->cap_stream, &c->graph[k]));
+    HIP_OK(c, hipGraphInstantiate(&c->gexec[k], c->graph[k], nullptr, nullptr, 0));
+  }
+  c->graph_ok = true;
+  return RTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rts_default_config(rts_config *c) {
+  memset(c, 0, sizeof(*c));
+  c->solver = RTS_WCSPH;
+  c->mode = RTS_MODE_RTS;
+  c->n_levels = 4;
+  c->level_cap = 3;
+  c->clamp_p = 1;
+  c->serna_correct = 1;
+  c->nbr_cap = 384;
+  c->use_graph = 1;
+  c->spacing = 0.01;
+  c->h = 0.02;
+  c->support = 0.04;
+  c->block_edge = 0.04;
+  c->r_crit = 0.02;
+  c->rho0 = 1000.0;
+  c->mass = 0.0;
+  c->c0 = 44.29446918;
+  c->gamma = 7.0;
+  c->B = 0.0;
+  c->visc_alpha = 0.05;
+  c->visc_eps = 0.01;
+  c->gravity[1] = -9.81;
+  for (int d = 0; d < 3; ++d) { c->domain_min[d] = -0.04; c->domain_max[d] = 1.04; }
+  c->domain_max[0] = 2.04;
+  c->dt_base = 0.0;
+  c->lambda_v = 0.4;
+  c->lambda_f = 0.25;
+  c->alpha_rts = 0.4;
+  c->beta2 = 0.4;
+  c->beta_ratio = 0.2;
+}
+
+const char *rts_status_string(rts_status s) {
+  switch (s) {
+    case RTS_OK: return "ok";
+    case RTS_E_INVALID: return "invalid argument";
+    case RTS_E_CAPACITY: return "capacity exceeded";
+    case RTS_E_DEVICE: return "device error";
+    case RTS_E_NUMERICAL: return "numerical failure";
+    case RTS_E_STATE: return "invalid state";
+    case RTS_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown";
+}
+
+const char *rts_last_error(const rts_ctx *c) { return c ? c->err : "no context"; }
+
+rts_status rts_workspace_size(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
+                              size_t *bytes) {
+  char msg[256];
+  rts_status s = validate(cfg, msg, sizeof(msg));
+  if (s) return s;
+  if (!bytes || n_fluid_max < 0 || n_wall_max < 0 || n_fluid_max > 0x7FFFFFFF ||
+      n_wall_max > 0x7FFFFFFF)
+    return RTS_E_INVALID;
+  DevParams p;
+  double m, B, dt;
+  derive(*cfg, n_fluid_max, n_wall_max, p, m, B, dt);
+  *bytes = carve(p, n_fluid_max, n_wall_max, nullptr, nullptr);
+  return RTS_OK;
+}
+
+rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
+                      void *d_workspace, size_t bytes, void *hip_stream, rts_ctx **out) {
+  if (!out) return RTS_E_INVALID;
+  *out = nullptr;
+  char msg[256];
+  rts_status s = validate(cfg, msg, sizeof(msg));
+  if (s) return s;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255u) || n_fluid_max < 0 || n_wall_max < 0 ||
+      n_fluid_max > 0x7FFFFFFF || n_wall_max > 0x7FFFFFFF)
+    return RTS_E_INVALID;
+  rts_ctx *c = new (std::nothrow) rts_ctx();
+  if (!c) return RTS_E_DEVICE;
+  c->cfg = *cfg;
+  c->ncap = n_fluid_max;
+  c->nwcap = n_wall_max;
+  derive(*cfg, n_fluid_max, n_wall_max, c->prm, c->mass, c->B, c->dt_base);
+  size_t need = carve(c->prm, n_fluid_max, n_wall_max, nullptr, nullptr);
+  if (bytes < need) {
+    delete c;
+    return RTS_E_CAPACITY;
+  }
+  carve(c->prm, n_fluid_max, n_wall_max, (char *)d_workspace, &c->d);
+  c->stream = (hipStream_t)hip_stream;
+  c->cur = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete c;
+    return RTS_E_DEVICE;
+  }
+  int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  int64_t want = (n_fluid_max + 255) / 256;
+  int64_t cap = (int64_t)cus * 8;
+  c->grid_persist = (int)(want < 1 ? 1 : (want < cap ? want : cap));
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return RTS_E_DEVICE;
+  }
+  // counts must start at zero; everything else is written before it is read
+  hipError_t e = hipMemsetAsync(c->d.COUNT, 0, (size_t)c->prm.nb * 4, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d.TILES, 0,
+                                          ((size_t)c->prm.nb + kScanTile - 1) / kScanTile * 8,
+                                          c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d.NNB, 0, (size_t)(n_fluid_max > 0 ? n_fluid_max : 1) * 4, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d.WCELL_START, 0, ((size_t)c->prm.nb + 1) * 4, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d.CTRL, 0, sizeof(DevCtrl), c->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return RTS_E_DEVICE;
+  }
+  launch_reset_scalars(c->d.S, c->stream);
+  *out = c;
+  return RTS_OK;
+}
+
+void rts_destroy(rts_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+rts_status rts_set_walls(rts_ctx *c, const float *d_pos, int64_t nw) {
+  if (!c) return RTS_E_INVALID;
+  if (nw < 0 || nw > c->nwcap) return fail(c, RTS_E_CAPACITY, "nw %lld exceeds capacity %lld", (long long)nw, (long long)c->nwcap);
+  if (nw > 0 && !d_pos) return fail(c, RTS_E_INVALID, "wall positions are NULL");
+  c->prm.nw = (int32_t)nw;
+  launch_wall_sort(c->prm, c->d, d_pos, c->stream);
+  HIP_OK(c, hipGetLastError());
+  destroy_graphs(c);
+  return RTS_OK;
+}
+
+rts_status rts_set_state(rts_ctx *c, const float *d_pos, const float *d_vel, int64_t n) {
+  if (!c) return RTS_E_INVALID;
+  if (n < 0 || n > c->ncap) return fail(c, RTS_E_CAPACITY, "n %lld exceeds capacity %lld", (long long)n, (long long)c->ncap);
+  if (n > 0 && !d_pos) return fail(c, RTS_E_INVALID, "positions are NULL");
+  c->prm.n = (int32_t)n;
+  c->cur = 0;
+  launch_reset_scalars(c->d.S, c->stream);
+  launch_set_state(c->prm, c->d, 0, d_pos, d_vel, c->stream);
+  HIP_OK(c, hipGetLastError());
+  destroy_graphs(c);
+  c->has_state = true;
+  c->poisoned = false;
+  return RTS_OK;
+}
+
+rts_status rts_assign_levels(rts_ctx *c, int32_t *h_hist) {
+  if (!c) return RTS_E_INVALID;
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  const DevParams &p = c->prm;
+  const int cur = c->cur;
+  launch_key_hist(p, c->d, cur, c->stream);
+  launch_scan(p, c->d.COUNT, c->d.CELL_START, p.nb, c->d.TILES, c->d.CTRL, c->d.S, c->stream);
+  launch_scatter(p, c->d, c->stream);
+  launch_cell_gather(p, c->d, cur, c->stream);
+  launch_rmin_flags(p, c->d, cur ^ 1, 0, c->stream);
+  HIP_OK(c, hipGetLastError());
+  c->cur = cur ^ 1;
+  if (h_hist) {
+    uint8_t *lv = (uint8_t *)malloc((size_t)p.nb);
+    if (!lv) return RTS_E_DEVICE;
+    hipError_t e = hipMemcpyAsync(lv, c->d.LVL, (size_t)p.nb, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      free(lv);
+      return fail(c, RTS_E_DEVICE, "copy of block levels failed: %s", hipGetErrorString(e));
+    }
+    for (int l = 0; l < c->cfg.n_levels; ++l) h_hist[l] = 0;
+    for (int64_t b = 0; b < p.nb; ++b)
+      if (lv[b] != kEmpty && lv[b] < c->cfg.n_levels) h_hist[lv[b]]++;
+    free(lv);
+  } else {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  }
+  return RTS_OK;
+}
+
+rts_status rts_advance(rts_ctx *c, int32_t n_steps) {
+  if (!c || n_steps < 0) return RTS_E_INVALID;
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  if (c->poisoned) return fail(c, RTS_E_STATE, "state failed; set or load a state first");
+  if (n_steps == 0) return RTS_OK;
+  if (c->cfg.use_graph && !c->graph_ok) {
+    rts_status s = build_graphs(c);
+    if (s) return s;
+  }
+  for (int32_t k = 0; k < n_steps; ++k) {
+    if (c->graph_ok) {
+      HIP_OK(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
+    } else {
+      enqueue_step(c, c->cur, c->stream);
+      HIP_OK(c, hipGetLastError());
+    }
+    c->cur ^= 1;
+  }
+  return RTS_OK;
+}
+
+rts_status rts_sync(rts_ctx *c, rts_stats *out) {
+  if (!c) return RTS_E_INVALID;
+  DevScalars S;
+  HIP_OK(c, hipMemcpyAsync(&S, c->d.S, sizeof(S), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  const int32_t bad = S.status ? S.bad_index : -1;
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    out->step = S.step;
+    out->time = S.time;
+    out->dt_last = S.dt_next;
+    out->active_last = S.n_act;
+    out->inter_last = (int64_t)S.inter_last;
+    out->active_total = (int64_t)S.active_total;
+    out->inter_total = (int64_t)S.inter_total;
+    memcpy(&out->err_max_last, &S.err_bits_last, 4);
+    memcpy(&out->err_max_run, &S.err_bits_run, 4);
+    for (int l = 0; l < RTS_MAX_LEVELS; ++l) out->level_hist[l] = S.hist[l];
+    out->nbr_max = (int32_t)S.nbr_max;
+    out->status = (int32_t)S.status;
+    out->bad_index = bad;
+  }
+  if (S.status) {
+    c->poisoned = true;
+    return fail(c, (rts_status)S.status, "device reported %s (particle %d)",
+                rts_status_string((rts_status)S.status), bad);
+  }
+  return RTS_OK;
+}
+
+rts_status rts_get_state(rts_ctx *c, float *d_pos, float *d_vel, float *d_acc, float *d_rho,
+                         float *d_p, uint8_t *d_level) {
+  if (!c) return RTS_E_INVALID;
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  launch_get_state(c->prm, c->d, c->cur, d_pos, d_vel, d_acc, d_rho, d_p, d_level, c->stream);
+  HIP_OK(c, hipGetLastError());
+  return RTS_OK;
+}
+
+rts_status rts_state_bytes(rts_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return RTS_E_INVALID;
+  size_t n = (size_t)c->prm.n;
+  *bytes = 64 + n * (16 * 3 + 4 * 3) + sizeof(DevScalars);
+  return RTS_OK;
+}
+
+rts_status rts_save_state(rts_ctx *c, void *d_buf, size_t cap) {
+  if (!c || !d_buf) return RTS_E_INVALID;
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  size_t need;
+  rts_state_bytes(c, &need);
+  if (cap < need) return fail(c, RTS_E_CAPACITY, "buffer holds %zu of %zu bytes", cap, need);
+  size_t n = (size_t)c->prm.n;
+  char *b = (char *)d_buf;
+  int64_t hdr[8] = {0x5254535354415445LL, (int64_t)n, c->prm.nb, 0, 0, 0, 0, 0};
+  HIP_OK(c, hipMemcpyAsync(b, hdr, 64, hipMemcpyHostToDevice, c->stream));
+  size_t off = 64;
+  const int k = c->cur;
+  HIP_OK(c, hipMemcpyAsync(b + off, c->d.P[k], n * 16, hipMemcpyDeviceToDevice, c->stream)); off += n * 16;
+  HIP_OK(c, hipMemcpyAsync(b + off, c->d.V[k], n * 16, hipMemcpyDeviceToDevice, c->stream)); off += n * 16;
+  HIP_OK(c, hipMemcpyAsync(b + off, c->d.A[k], n * 16, hipMemcpyDeviceToDevice, c->stream)); off += n * 16;
+  HIP_OK(c, hipMemcpyAsync(b + off, c->d.M[k], n * 4, hipMemcpyDeviceToDevice, c->stream)); off += n * 4;
+  HIP_OK(c, hipMemcpyAsync(b + off, c->d.ID[k], n * 4, hipMemcpyDeviceToDevice, c->stream)); off += n * 4;
+  HIP_OK(c, hipMemcpyAsync(b + off, c->d.PRES, n * 4, hipMemcpyDeviceToDevice, c->stream)); off += n * 4;
+  HIP_OK(c, hipMemcpyAsync(b + off, c->d.S, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));  // the header lives on this host stack
+  return RTS_OK;
+}
+
+rts_status rts_load_state(rts_ctx *c, const void *d_buf, size_t len) {
+  if (!c || !d_buf || len < 64) return RTS_E_INVALID;
+  int64_t hdr[8];
+  HIP_OK(c, hipMemcpy(hdr, d_buf, 64, hipMemcpyDeviceToHost));
+  if (hdr[0] != 0x5254535354415445LL || hdr[1] < 0 || hdr[1] > c->ncap || hdr[2] != c->prm.nb)
+    return fail(c, RTS_E_INVALID, "buffer does not hold a state for this context");
+  size_t n = (size_t)hdr[1];
+  c->prm.n = (int32_t)n;
+  size_t need;
+  rts_state_bytes(c, &need);
+  if (len < need) return fail(c, RTS_E_INVALID, "buffer too short");
+  const char *b = (const char *)d_buf;
+  size_t off = 64;
+  c->cur = 0;
+  HIP_OK(c, hipMemcpyAsync(c->d.P[0], b + off, n * 16, hipMemcpyDeviceToDevice, c->stream)); off += n * 16;
+  HIP_OK(c, hipMemcpyAsync(c->d.V[0], b + off, n * 16, hipMemcpyDeviceToDevice, c->stream)); off += n * 16;
+  HIP_OK(c, hipMemcpyAsync(c->d.A[0], b + off, n * 16, hipMemcpyDeviceToDevice, c->stream)); off += n * 16;
+  HIP_OK(c, hipMemcpyAsync(c->d.M[0], b + off, n * 4, hipMemcpyDeviceToDevice, c->stream)); off += n * 4;
+  HIP_OK(c, hipMemcpyAsync(c->d.ID[0], b + off, n * 4, hipMemcpyDeviceToDevice, c->stream)); off += n * 4;
+  HIP_OK(c, hipMemcpyAsync(c->d.PRES, b + off, n * 4, hipMemcpyDeviceToDevice, c->stream)); off += n * 4;
+  HIP_OK(c, hipMemcpyAsync(c->d.S, b + off, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
+  destroy_graphs(c);
+  c->has_state = true;
+  c->poisoned = false;
+  return RTS_OK;
+}
+
+rts_status rts_debug_get(rts_ctx *c, int32_t what, void *d_out, size_t cap, size_t *n_out) {
+  if (!c || !d_out) return RTS_E_INVALID;
+  const size_t n = (size_t)c->prm.n, nb = (size_t)c->prm.nb, nw = (size_t)c->prm.nw;
+  const int k = c->cur, pk = c->cur ^ 1;
+  const void *src = nullptr;
+  size_t count = 0, esz = 4;
+  switch (what) {
+    case RTS_DBG_POS: src = c->d.P[k]; count = n; esz = 16; break;
+    case RTS_DBG_VEL: src = c->d.V[k]; count = n; esz = 16; break;
+    case RTS_DBG_ACC: src = c->d.A[k]; count = n; esz = 16; break;
+    case RTS_DBG_ACC_NEW: src = c->d.ANEW; count = n; esz = 16; break;
+    case RTS_DBG_META: src = c->d.M[k]; count = n; break;
+    case RTS_DBG_ID: src = c->d.ID[k]; count = n; break;
+    case RTS_DBG_KEY: src = c->d.KEY; count = n; break;
+    case RTS_DBG_PERM: src = c->d.PERM; count = n; break;
+    case RTS_DBG_CELL_START: src = c->d.CELL_START; count = nb + 1; break;
+    case RTS_DBG_BLK_LEVEL_RAW: src = c->d.LRAW; count = nb; esz = 1; break;
+    case RTS_DBG_BLK_LEVEL: src = c->d.LVL; count = nb; esz = 1; break;
+    case RTS_DBG_NNB: src = c->d.NNB; count = n; break;
+    case RTS_DBG_NBR: src = c->d.NBR; count = (size_t)c->prm.kcap * (size_t)c->ncap; break;
+    case RTS_DBG_PRESSURE: src = c->d.PRES; count = n; break;
+    case RTS_DBG_PRE_POS: src = c->d.P[pk]; count = n; esz = 16; break;
+    case RTS_DBG_PRE_VEL: src = c->d.V[pk]; count = n; esz = 16; break;
+    case RTS_DBG_PRE_ACC: src = c->d.A[pk]; count = n; esz = 16; break;
+    case RTS_DBG_PRE_META: src = c->d.M[pk]; count = n; break;
+    case RTS_DBG_PRE_ID: src = c->d.ID[pk]; count = n; break;
+    case RTS_DBG_WALL_POS: src = c->d.WP; count = nw; esz = 16; break;
+    case RTS_DBG_WALL_ID: src = c->d.WID; count = nw; break;
+    case RTS_DBG_WALL_CELL_START: src = c->d.WCELL_START; count = nb + 1; break;
+    case RTS_DBG_ACTIVE: {
+      DevScalars S;
+      HIP_OK(c, hipMemcpyAsync(&S, c->d.S, sizeof(S), hipMemcpyDeviceToHost, c->stream));
+      HIP_OK(c, hipStreamSynchronize(c->stream));
+      src = c->d.ACT;
+      count = S.n_act;
+      break;
+    }
+    default: return fail(c, RTS_E_INVALID, "unknown debug view %d", what);
+  }
+  if (n_out) *n_out = count;
+  if (count * esz > cap) return fail(c, RTS_E_CAPACITY, "debug view needs %zu bytes", count * esz);
+  if (count) HIP_OK(c, hipMemcpyAsync(d_out, src, count * esz, hipMemcpyDeviceToDevice, c->stream));
+  return RTS_OK;
+}
+
+rts_status rts_grid_info(rts_ctx *c, int32_t *nc3, int64_t *nblocks, double *mass, double *B,
+                         double *dt_base) {
+  if (!c) return RTS_E_INVALID;
+  if (nc3) for (int d = 0; d < 3; ++d) nc3[d] = c->prm.nc[d];
+  if (nblocks) *nblocks = c->prm.nb;
+  if (mass) *mass = c->mass;
+  if (B) *B = c->B;
+  if (dt_base) *dt_base = c->dt_base;
+  return RTS_OK;
+}
+
+}  // extern "C"

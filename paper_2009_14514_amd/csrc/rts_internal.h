@@ -1,0 +1,129 @@
+// Internal declarations of the RTS HIP library: device parameter block,
+// device buffer table, per-run counters and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rts.h"
+
+namespace rts {
+
+constexpr uint32_t kWallBit = 0x80000000u;
+constexpr uint8_t kEmpty = 0xFF;      // level of a block holding no fluid
+constexpr int kMaxLevels = RTS_MAX_LEVELS;
+constexpr int kCellMax = 512;         // particles per block the sort can canonicalise
+constexpr int kScanTile = 1024;       // elements per scan workgroup (256 threads x 4)
+
+// Meta word of a particle: bits 0-3 level, 4 compute, 5-15 age (base steps
+// since the last evaluation), 16-31 validity (int16).
+__host__ __device__ inline uint32_t meta_pack(uint32_t level, uint32_t compute, uint32_t age,
+                                              int32_t validity) {
+  return (level & 0xFu) | ((compute & 1u) << 4) | ((age & 0x7FFu) << 5) |
+         ((uint32_t)(uint16_t)(int16_t)validity << 16);
+}
+__host__ __device__ inline uint32_t meta_level(uint32_t m) { return m & 0xFu; }
+__host__ __device__ inline uint32_t meta_compute(uint32_t m) { return (m >> 4) & 1u; }
+__host__ __device__ inline uint32_t meta_age(uint32_t m) { return (m >> 5) & 0x7FFu; }
+__host__ __device__ inline int32_t meta_validity(uint32_t m) { return (int32_t)(int16_t)(m >> 16); }
+
+// Numbers every kernel needs, derived once on the host in double precision
+// and rounded to float.
+struct DevParams {
+  int32_t n, ncap, nw, kcap;
+  int32_t nc[3];
+  int32_t nb;
+  float o[3];
+  float inv_e, r2f;
+  float h, inv_h, sigma, mass;
+  float dmax[3];         // domain upper corner (particles beyond it are an error)
+  float kms;             // m sigma / rho0
+  float c_hi, c_lo;      // rho0 / (m sigma) - 1 split in two floats (density deviation)
+  float B, rho0;
+  float visc_num;        // 2 alpha h c0
+  float visc_eps_h2;     // eps h^2
+  float g[3];
+  float dt_base;
+  double dt_cfl;         // lambda_v r / c0 (adaptive comparator)
+  double lf2r;           // lambda_f^2 r (adaptive comparator: dt^2 <= lf2r / |a|)
+  int32_t lmax, mode, serna_correct, clamp_p;
+  float TV[kMaxLevels], TA[kMaxLevels];
+};
+
+// Scan control words.  Zeroed once when the context is created and never
+// reset or restored afterwards: the epoch only grows, so look-back words
+// left by an earlier scan can never be mistaken for the current one's.
+struct DevCtrl {
+  uint32_t epoch;
+  uint32_t scan_ticket;
+};
+
+// Counters kept on the device (part of the saved state).
+struct DevScalars {
+  uint32_t status;
+  int32_t bad_index;         // caller index of the particle that raised status, or -1
+  uint32_t n_act;
+  uint32_t pad1;
+  uint32_t pad2;
+  uint32_t nbr_max;
+  uint32_t err_bits_last;    // float bits of the last step's max compression error
+  uint32_t err_bits_run;
+  uint32_t amax2_bits;       // float bits of max |a|^2 over active particles
+  int32_t hist[kMaxLevels];
+  uint32_t pad0;
+  unsigned long long inter_last;
+  unsigned long long active_total;
+  unsigned long long inter_total;
+  long long step;
+  double time;
+  double dt_prev;            // length of the step that ended at this step's start
+  double dt_next;            // length of the step predicted at this step's end
+};
+
+struct DevPtrs {
+  float4 *P[2];      // x, y, z, rho
+  float4 *V[2];      // vx, vy, vz, p / rho^2
+  float4 *A[2];      // stored acceleration
+  uint32_t *M[2];    // meta
+  uint32_t *ID[2];   // caller index
+  float4 *ANEW;      // acceleration evaluated this step
+  float *PRES;       // pressure
+  uint32_t *KEY;     // block of each sorted particle
+  uint32_t *KEYOLD;  // block of each particle in the previous order
+  uint32_t *RANK;    // arrival slot within its block (unordered)
+  uint32_t *TMP;     // block-grouped previous indices, unordered within a block
+  uint32_t *PERM;    // previous index of each sorted particle
+  uint32_t *NNB;
+  uint32_t *NBR;     // kcap x ncap, slot k of particle i at k * ncap + i
+  uint32_t *ACT;     // active particles (sorted indices)
+  uint32_t *COUNT;   // nb, zero between sorts
+  uint32_t *CELL_START;  // nb + 1
+  uint8_t *LRAW, *LVL;   // block level before / after R_min
+  float4 *WP;        // wall particles, sorted
+  uint32_t *WID, *WCELL_START, *WKEY, *WRANK, *WTMP;
+  unsigned long long *TILES;  // scan look-back words
+  DevCtrl *CTRL;
+  DevScalars *S;
+};
+
+// Launchers (rts_kernels.hip).  All enqueue on `st`.
+void launch_key_hist(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_scan(const DevParams &p, uint32_t *count, uint32_t *start, int nb,
+                 unsigned long long *tiles, DevCtrl *ctrl, DevScalars *S, hipStream_t st);
+void launch_prep_scan(DevCtrl *ctrl, hipStream_t st);
+void launch_scatter(const DevParams &p, const DevPtrs &d, hipStream_t st);
+void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags,
+                       hipStream_t st);
+void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid,
+                           hipStream_t st);
+void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st);
+void launch_correct_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_set_state(const DevParams &p, const DevPtrs &d, int cur, const float *pos,
+                      const float *vel, hipStream_t st);
+void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos, float *vel,
+                      float *acc, float *rho, float *pres, uint8_t *level, hipStream_t st);
+void launch_wall_sort(const DevParams &p, const DevPtrs &d, const float *pos, hipStream_t st);
+void launch_reset_scalars(DevScalars *S, hipStream_t st);
+
+}  // namespace rts

@@ -1,0 +1,227 @@
+"""GPU parity of the WCSPH regional-time-stepping base step against the oracle.
+
+Structure (block keys, stable order, block starts, block levels before and
+after R_min, particle flags, neighbour lists) must match bit for bit on the
+same float32 snapshot; density within 1e-5 relative; the force stage, fed the
+GPU's own density and pressure, within 1e-5 (normwise); 10-step trajectories
+within 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_14514_amd import scenes
+from paper_2009_14514_amd.sim import Simulation, decode_meta
+
+from parity import (expected_structure, gpu_lists, oracle_density, oracle_forces_stage,
+                    oracle_lists, snapshot_after_step)
+
+pytestmark = pytest.mark.gpu
+
+DENSITY_TOL = 1e-5     # relative, single step
+FORCE_TOL = 1e-5       # normwise relative, stage-isolated
+TRAJ_TOL = 1e-4        # 10-step trajectories: max|dx|/s and |dv|/|v|
+
+
+def f32(a):
+    return np.asarray(a, np.float32)
+
+
+def rts_scene(counts=(24, 40, 20), seed=3):
+    # a column small enough for the oracle, large enough for several levels
+    return scenes.dam_break_column(counts=counts, spacing=0.01, box=(0.6, 0.5, 0.3), seed=seed)
+
+
+def check_structure(sim, cfg, snap, check_lists=True):
+    exp = expected_structure(cfg, snap)
+    assert np.array_equal(snap["PERM"], exp["perm"]), "stable order differs"
+    assert np.array_equal(snap["KEY"], exp["keys"]), "block keys differ"
+    assert np.array_equal(snap["CELL_START"], exp["cell_start"]), "block starts differ"
+    assert np.array_equal(snap["BLK_LEVEL_RAW"], exp["lraw"]), "block levels differ"
+    assert np.array_equal(snap["BLK_LEVEL"], exp["lvl"]), "R_min levels differ"
+    level, comp, age, val = decode_meta(snap["META"])
+    assert np.array_equal(level, exp["level"])
+    assert np.array_equal(comp, exp["compute"])
+    assert np.array_equal(val, exp["validity"])
+    assert np.array_equal(age, exp["age"])
+    if check_lists:
+        rows = np.nonzero(exp["compute"])[0]
+        onbr, onnb = oracle_lists(cfg, snap, exp["compute"])
+        assert np.array_equal(snap["NNB"][rows], onnb[rows].astype(np.uint32))
+        glists = gpu_lists(sim, snap, rows)
+        for r, g in zip(rows, glists):
+            assert np.array_equal(g, onbr[r, :onnb[r]]), f"neighbour list of {r} differs"
+    return exp
+
+
+def test_structure_first_step_small():
+    sc = scenes.dam_break_small()
+    sim = Simulation(sc)
+    sim.advance(1)
+    sim.sync()
+    snap = snapshot_after_step(sim)
+    cfg = oracle.cfg_from_params(sc.params)
+    exp = check_structure(sim, cfg, snap)
+    assert exp["compute"].all()          # validity 0 at start: everyone active
+
+
+def test_structure_rts_levels_after_steps():
+    sc = rts_scene()
+    sim = Simulation(sc)
+    sim.advance(250)
+    sim.sync()
+    sim.advance(1)
+    st = sim.sync()
+    snap = snapshot_after_step(sim)
+    cfg = oracle.cfg_from_params(sc.params)
+    exp = check_structure(sim, cfg, snap)
+    lv = exp["lvl"][exp["lvl"] != oracle.EMPTY_BLOCK]
+    assert len(np.unique(lv)) >= 2, "scene should hold several levels"
+    assert 0 < st.active_last < sc.n
+
+
+@pytest.mark.parametrize("steps_before", [0, 250])
+def test_density_single_step(steps_before):
+    sc = rts_scene()
+    sim = Simulation(sc)
+    if steps_before:
+        sim.advance(steps_before)
+        sim.sync()
+    sim.advance(1)
+    sim.sync()
+    snap = snapshot_after_step(sim)
+    cfg = oracle.cfg_from_params(sc.params)
+    _, comp, _, _ = decode_meta(snap["META"])
+    rho_o, p_o = oracle_density(cfg, snap, comp)
+    rows = np.nonzero(comp)[0]
+    rho_g = snap["POS"][rows, 3].astype(np.float64)
+    rel = np.abs(rho_g - rho_o[rows]) / rho_o[rows]
+    assert rel.max() <= DENSITY_TOL, rel.max()
+    # pressure against the stiffness scale rho0 c0^2 (a density-equivalent bound)
+    scale = sc.params["rho0"] * sc.params["c0"] ** 2
+    dp = np.abs(snap["PRESSURE"][rows].astype(np.float64) - p_o[rows]) / scale
+    assert dp.max() <= DENSITY_TOL, dp.max()
+
+
+@pytest.mark.parametrize("steps_before", [0, 250])
+def test_forces_stage_isolated(steps_before):
+    sc = rts_scene()
+    sim = Simulation(sc)
+    if steps_before:
+        sim.advance(steps_before)
+        sim.sync()
+    sim.advance(1)
+    sim.sync()
+    snap = snapshot_after_step(sim)
+    cfg = oracle.cfg_from_params(sc.params)
+    _, comp, _, _ = decode_meta(snap["META"])
+    a_o = oracle_forces_stage(cfg, snap, comp)
+    rows = np.nonzero(comp)[0]
+    a_g = snap["ACC_NEW"][rows, :3].astype(np.float64)
+    err = np.linalg.norm(a_g - a_o[rows]) / np.linalg.norm(a_o[rows])
+    assert err <= FORCE_TOL, err
+
+
+def trajectory_errors(sc, steps, **over):
+    sim = Simulation(sc, **over)
+    sim.advance(steps)
+    st = sim.sync()
+    g = sim.state()
+    ref = oracle.WCSPH(sc.params, f32(sc.pos), vel=f32(sc.vel), walls=f32(sc.walls), **over)
+    ref.step(steps)
+    dx = np.abs(g["pos"] - ref.x).max() / sc.params["spacing"]
+    dv = np.linalg.norm(g["vel"] - ref.v) / np.linalg.norm(ref.v)
+    return dx, dv, st, ref
+
+
+def test_trajectory_small_global_10_steps():
+    sc = scenes.dam_break_small()
+    dx, dv, st, ref = trajectory_errors(sc, 10)
+    assert st.active_total == 10 * sc.n
+    assert dx <= TRAJ_TOL and dv <= TRAJ_TOL, (dx, dv)
+
+
+def developed(sc, steps=250):
+    """The scene after `steps` GPU base steps, as a new initial condition, so
+    that a 10-step window starts from a moving flow with several levels."""
+    sim = Simulation(sc)
+    sim.advance(steps)
+    sim.sync()
+    s = sim.state()
+    return scenes.Scene(sc.name, s["pos"], s["vel"], sc.walls, sc.params)
+
+
+@pytest.mark.parametrize("mode", ["rts", "global_fixed", "global_adaptive"])
+def test_trajectory_developed_10_steps(mode):
+    sc = developed(rts_scene())
+    dx, dv, st, ref = trajectory_errors(sc, 10, mode=mode)
+    assert dx <= TRAJ_TOL and dv <= TRAJ_TOL, (dx, dv)
+    assert st.active_total == sum(h["n_active"] for h in ref.history)
+    assert abs(st.time - ref.t) <= 1e-6 * ref.t
+
+
+def test_rts_level_cap_zero_is_global_bitwise():
+    sc = rts_scene()
+    a = Simulation(sc, mode="rts", level_cap=0)
+    b = Simulation(sc, mode="global_fixed")
+    a.advance(12)
+    b.advance(12)
+    a.sync()
+    b.sync()
+    sa, sb = a.state(), b.state()
+    for k in ("pos", "vel", "acc", "rho"):
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_graph_replay_matches_eager_bitwise():
+    sc = rts_scene()
+    a = Simulation(sc, use_graph=1)
+    b = Simulation(sc, use_graph=0)
+    for _ in range(3):
+        a.advance(7)
+        b.advance(7)
+        a.sync()
+        b.sync()
+    sa, sb = a.state(), b.state()
+    for k in ("pos", "vel", "acc", "rho", "level"):
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_runs_are_deterministic():
+    sc = rts_scene()
+    outs = []
+    for _ in range(2):
+        s = Simulation(sc)
+        s.advance(25)
+        s.sync()
+        outs.append(s.state())
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_save_load_continues_bitwise():
+    sc = rts_scene()
+    a = Simulation(sc)
+    a.advance(20)
+    a.sync()
+    b = Simulation(sc)
+    b.advance(10)
+    b.sync()
+    buf = b.save()
+    c = Simulation(sc)
+    c.load(buf)
+    c.advance(10)
+    c.sync()
+    sa, sc_ = a.state(), c.state()
+    for k in sa:
+        assert np.array_equal(sa[k], sc_[k]), k
+
+
+def test_adaptive_time_from_rest_matches_oracle():
+    # from rest the velocities are tiny and their relative error is dominated
+    # by float32 positions seen through the stiff equation of state; the
+    # positions and the simulated time are the checked quantities here
+    sc = rts_scene()
+    dx, dv, st, ref = trajectory_errors(sc, 10, mode="global_adaptive")
+    assert abs(st.time - ref.t) <= 1e-6 * ref.t
+    assert dx <= TRAJ_TOL, dx
