@@ -1,0 +1,234 @@
+"""Benchmark: WCSPH regional time stepping vs global adaptive stepping on one GPU.
+
+Workload: the 250,000-particle dam break (column 0.5 x 1.0 x 0.5 m at spacing
+0.01 m in a 2 x 1 x 1 m box), block levels 0..3, K base steps (default 500).
+A step is one base step of the whole path (grid rebuild, block levels, flags,
+neighbour search + density, forces, corrector/predictor).
+
+Printed: one JSON line.  ``value`` is RTS particle-steps/s (particles x base
+steps / wall seconds, inputs resident in HBM).  The global adaptive
+comparator is timed over the same simulated time.  The dominant kernel's
+roofline comes from an event-bracketed replay of the same K steps; the CPU
+baseline is the FP64 oracle on a bounded window of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, packed FP32 off
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="approximate CPU time spent on the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_traffic(name, n, nb, K, act, inter, cand):
+    """Algorithmic bytes and flops per launch of each kernel (averaged over K steps).
+
+    Bytes count the particle state each kernel must read and write, plus the
+    neighbour-index stream; re-reads of neighbour state served by caches are
+    not counted.  ``act``/``inter``/``cand`` are totals over the K steps.
+    """
+    a, i, c = act / K, inter / K, cand / K
+    table = {
+        "key_hist": (24.0 * n, 10.0 * n),
+        "scan": (14.0 * nb, 4.0 * nb),
+        "scatter": (16.0 * n, 1.0 * n),
+        "cell_gather": (124.0 * n + nb, 16.0 * n),
+        "rmin_flags": (8.0 * n + 27.0 * nb, 8.0 * n),
+        # own position and flags in; 16-bit list, density, p/rho^2, p, counts out
+        "search_density": (36.0 * a + 4.0 * n + 2.0 * i, 9.0 * c + 20.0 * i),
+        # own state, counts and 16-bit list in; acceleration out
+        "force": (56.0 * a + 2.0 * i, 45.0 * i),
+        "step_stats": (30.0 * nb, 12.0 * nb),
+        "correct_predict": (104.0 * n + 16.0 * a, 30.0 * n),
+    }
+    return table[name]
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+
+    from paper_2009_14514_amd import scenes
+    from paper_2009_14514_amd.sim import Simulation
+
+    torch.cuda.set_device(0)
+    sc = scenes.dam_break_column()          # 250,000 particles, levels 0..3
+    K, W = args.steps, args.warmup
+    out = {}
+
+    def timed(sim, steps):
+        st = sim.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        sim.advance(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    # --- RTS ------------------------------------------------------------------
+    rts = Simulation(sc, mode="rts")
+    init = rts.save()
+    if W:
+        rts.advance(W)
+        rts.sync()
+        rts.load(init)
+    ms_rts = timed(rts, K)
+    st_rts = rts.sync()
+    T = st_rts.time
+    print(f"[bench] rts: {K} steps in {ms_rts:.2f} ms, active {st_rts.active_total}, "
+          f"err_max {st_rts.err_max_run:.4f}", file=sys.stderr, flush=True)
+
+    # --- global adaptive comparator over the same simulated time ---------------
+    ga = Simulation(sc, mode="global_adaptive")
+    ga_init = ga.save()
+    if W:
+        ga.advance(W)
+        ga.sync()
+        ga.load(ga_init)
+    ms_ga = timed(ga, K)
+    st_ga = ga.sync()
+    while st_ga.time < T * (1.0 - 1e-9):
+        ms_ga += timed(ga, 10)
+        st_ga = ga.sync()
+    print(f"[bench] global adaptive: {st_ga.step} steps in {ms_ga:.2f} ms, "
+          f"err_max {st_ga.err_max_run:.4f}", file=sys.stderr, flush=True)
+
+    n = sc.n
+    ps_rts = n * K / (ms_rts * 1e-3)
+    ps_ga = n * (st_ga.time / st_rts.dt_last) / (ms_ga * 1e-3)
+    out.update(
+        n=n, nw=sc.nw, K=K, ms_rts=ms_rts, ms_ga=ms_ga, ps_rts=ps_rts, ps_ga=ps_ga,
+        sim_time=T, dt_base=st_rts.dt_last,
+        rts=dict(active_total=st_rts.active_total, inter_total=st_rts.inter_total,
+                 cand_total=st_rts.cand_total, err_max=float(st_rts.err_max_run),
+                 level_hist_last=list(st_rts.level_hist)[:4], nbr_max=st_rts.nbr_max),
+        ga=dict(steps=st_ga.step, active_total=st_ga.active_total,
+                inter_total=st_ga.inter_total, err_max=float(st_ga.err_max_run)),
+        nblocks=rts.info["nblocks"],
+    )
+
+    # --- per-kernel times: the same K steps, kernels bracketed by HIP events -----
+    if not args.no_profile:
+        rts.load(init)
+        prof = rts.profile(K)
+        st_p = rts.sync()
+        out["kernels_ms"] = prof
+        out["prof_counts"] = dict(active=st_p.active_total, inter=st_p.inter_total,
+                                  cand=st_p.cand_total)
+    rts.close()
+    ga.close()
+    return out
+
+
+def run_cpu_baseline(budget_s):
+    """FP64 oracle, RTS mode, on the first steps of the same workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2009_14514_amd import scenes
+
+    sc = scenes.dam_break_column()
+    sim = oracle.WCSPH(sc.params, sc.pos.astype(np.float32), walls=sc.walls.astype(np.float32),
+                       mode="rts")
+    t0 = time.time()
+    steps = 0
+    while True:
+        sim.step()
+        steps += 1
+        el = time.time() - t0
+        if el >= budget_s or steps >= 500:
+            break
+    return dict(value=sc.n * steps / el, unit="particle-steps/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"first {steps} RTS base steps of the 250,000-particle dam break "
+                       f"(FP64, {el:.1f} s)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+    g = run_gpu(args)
+    K = g["K"]
+    line = {
+        "metric": "particle-steps/s RTS vs global dt on 1 MI355X at <=1% density error; HBM GB/s",
+        "value": g["ps_rts"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": g["ms_rts"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "wcsph_rts_dam_break_250k", "n_particles": g["n"],
+                   "n_wall_particles": g["nw"], "spacing_m": 0.01, "h_over_s": 2.0,
+                   "levels": 4, "base_steps": K, "dt_base_s": g["dt_base"]},
+        "global_adaptive": {"value": g["ps_ga"], "unit": "particle-steps/s",
+                            "ms_total": g["ms_ga"], "steps": g["ga"]["steps"],
+                            "density_err_max": g["ga"]["err_max"]},
+        "speedup_vs_global_adaptive": g["ms_ga"] / g["ms_rts"],
+        "density_err_max": g["rts"]["err_max"],
+        "active_fraction": g["rts"]["active_total"] / (g["n"] * K),
+        "neighbour_interactions_per_s": g["rts"]["inter_total"] / (g["ms_rts"] * 1e-3),
+        "simulated_time_s": g["sim_time"],
+    }
+    if "kernels_ms" in g:
+        km = g["kernels_ms"]
+        cnt = g["prof_counts"]
+        rows = {}
+        for name, ms in km.items():
+            b, f = kernel_traffic(name, g["n"], g["nblocks"], K, cnt["active"], cnt["inter"],
+                                  cnt["cand"])
+            avg = ms / K * 1e-3
+            rows[name] = {"avg_us": avg * 1e6, "GBps": b / avg / 1e9 if avg > 0 else 0.0,
+                          "TFLOPs": f / avg / 1e12 if avg > 0 else 0.0}
+        dom = max(km, key=lambda k: km[k])
+        d = rows[dom]
+        if dom == "search_density":
+            roof = {"kernel": dom, "bound": "alu", "achieved": d["TFLOPs"],
+                    "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": d["TFLOPs"] / FP32_VALU_PEAK_TFLOPS, "traffic": None}
+        else:
+            roof = {"kernel": dom, "bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None}
+        line["roofline"] = roof
+        line["kernels"] = rows
+        tn = km["key_hist"] + km["scan"] + km["scatter"] + km["cell_gather"]
+        tp = km["search_density"] + km["force"]
+        tr = km["rmin_flags"] + km["step_stats"]
+        ti = km["correct_predict"]
+        tot = tn + tp + tr + ti
+        line["phase_split"] = {"grid_and_search_share": None,
+                               "T_grid": tn / tot, "T_search_density_force": tp / tot,
+                               "T_rts_flags": tr / tot, "T_integrate": ti / tot}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = run_cpu_baseline(args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

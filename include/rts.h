@@ -55,6 +55,7 @@ typedef enum { RTS_WCSPH = 0, RTS_PCISPH = 1 } rts_solver;
 typedef enum { RTS_MODE_RTS = 0, RTS_MODE_GLOBAL_FIXED = 1, RTS_MODE_GLOBAL_ADAPTIVE = 2 } rts_mode;
 
 #define RTS_MAX_LEVELS 8
+#define RTS_DEBUG_NBR_ROW 1024  /* row width of the RTS_DBG_NBR view */
 
 /* Run configuration.  SI units, double precision so that derived float
  * thresholds are rounded once from the exact configured values.
@@ -66,7 +67,8 @@ typedef struct rts_config {
   int32_t level_cap;     /* highest level a block may take */
   int32_t clamp_p;       /* clamp pressure at zero */
   int32_t serna_correct; /* 1: apply the predictor-corrector correction (Section 4.1) */
-  int32_t nbr_cap;       /* neighbour list capacity per particle */
+  int32_t cand_cap;      /* neighbour candidates per block (27 blocks + walls) the neighbour
+                            bitmasks can describe; multiple of 128, <= 65536 */
   int32_t use_graph;     /* 1: replay each base step as a captured HIP graph */
   double spacing;         /* initial particle spacing s */
   double h;               /* smoothing length of the cubic spline (support 2h) */
@@ -100,6 +102,7 @@ typedef struct rts_stats {
   int64_t inter_last;                /* neighbour pairs of active particles in the last step */
   int64_t active_total;              /* sum over steps of active particles */
   int64_t inter_total;               /* sum over steps of neighbour pairs evaluated */
+  int64_t cand_total;                /* sum over steps of candidate pair tests in the search */
   float err_max_last;                /* max over particles of max(rho - rho0, 0) / rho0, last step */
   float err_max_run;                 /* the same, max over all steps */
   int32_t level_hist[RTS_MAX_LEVELS];/* particles per level after the last step's flags */
@@ -172,28 +175,45 @@ rts_status rts_load_state(rts_ctx *ctx, const void *d_buf, size_t len);
  *   RTS_DBG_PERM: previous sorted position of each sorted particle
  *   RTS_DBG_CELL_START: nblocks + 1 uint32
  *   RTS_DBG_BLK_LEVEL_RAW / BLK_LEVEL: uint8 per block, before / after R_min
- *   RTS_DBG_NNB: uint32 per particle;  RTS_DBG_NBR: nbr_cap x ncap uint32,
- *                 slot k of particle i at k * ncap + i
+ *   RTS_DBG_NNB: uint32 per particle: neighbour count (last step's active)
+ *   RTS_DBG_NBR: n x RTS_DEBUG_NBR_ROW uint32, row i = canonical neighbour
+ *                 list of sorted particle i (ascending sorted index, then walls
+ *                 as wall sorted index | 0x80000000), followed by n uint32 list
+ *                 lengths; rows of particles inactive in the last step are empty
  *   RTS_DBG_PRESSURE: float per sorted slot, valid for the last step's active
  *                 particles only
  *   RTS_DBG_PRE_POS/VEL/ACC/META/ID: the arrays as they were before the last
  *                 step's sort (the step's input), in their previous order
  *   RTS_DBG_WALL_POS: float4 per wall particle, sorted; RTS_DBG_WALL_ID:
  *                 caller index of each sorted wall; RTS_DBG_WALL_CELL_START
- *   RTS_DBG_ACTIVE: sorted indices of the last step's active particles
- *                 (any order). */
+ *   RTS_DBG_OCCUPIED: ascending keys of the blocks holding fluid
+ *   RTS_DBG_BLK_STATS: uint32 x 4 per block, valid for occupied blocks: active
+ *                 particles, neighbour pairs, candidate tests, and max neighbour
+ *                 count | particles << 16, of the last step. */
 typedef enum {
   RTS_DBG_POS = 0, RTS_DBG_VEL, RTS_DBG_ACC, RTS_DBG_ACC_NEW, RTS_DBG_META, RTS_DBG_ID,
   RTS_DBG_KEY, RTS_DBG_PERM, RTS_DBG_CELL_START, RTS_DBG_BLK_LEVEL_RAW, RTS_DBG_BLK_LEVEL,
   RTS_DBG_NNB, RTS_DBG_NBR, RTS_DBG_PRESSURE, RTS_DBG_PRE_POS, RTS_DBG_PRE_VEL,
   RTS_DBG_PRE_ACC, RTS_DBG_PRE_META, RTS_DBG_PRE_ID, RTS_DBG_WALL_POS, RTS_DBG_WALL_ID,
-  RTS_DBG_WALL_CELL_START, RTS_DBG_ACTIVE, RTS_DBG_COUNT_
+  RTS_DBG_WALL_CELL_START, RTS_DBG_OCCUPIED, RTS_DBG_BLK_STATS, RTS_DBG_COUNT_
 } rts_debug_what;
 rts_status rts_debug_get(rts_ctx *ctx, int32_t what, void *d_out, size_t cap_bytes, size_t *n_out);
 
 /* Grid and derived numbers: nc[3], nblocks, particle mass, Tait B, base step. */
 rts_status rts_grid_info(rts_ctx *ctx, int32_t *h_nc3, int64_t *h_nblocks, double *h_mass,
                          double *h_B, double *h_dt_base);
+
+/* Timing aid: advances n_steps base steps like rts_advance, but launches the
+ * kernels one by one with a HIP event between consecutive kernels on the
+ * context's stream, and adds each kernel's time in milliseconds to
+ * h_ms[0..RTS_PROF_COUNT) in the order of rts_prof_kernel.  Waits for the
+ * stream.  The simulation result is identical to rts_advance. */
+typedef enum {
+  RTS_PROF_KEY_HIST = 0, RTS_PROF_SCAN, RTS_PROF_SCATTER, RTS_PROF_CELL_GATHER,
+  RTS_PROF_RMIN_FLAGS, RTS_PROF_SEARCH_DENSITY, RTS_PROF_FORCE, RTS_PROF_STEP_STATS,
+  RTS_PROF_CORRECT_PREDICT, RTS_PROF_COUNT
+} rts_prof_kernel;
+rts_status rts_profile_advance(rts_ctx *ctx, int32_t n_steps, double *h_ms);
 
 const char *rts_last_error(const rts_ctx *ctx);
 const char *rts_status_string(rts_status s);

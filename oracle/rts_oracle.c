@@ -260,8 +260,8 @@ void orc_flags(int32_t n, const uint32_t *key, const uint8_t *blk, int32_t *leve
 }
 
 /* ------------------------------------------------------------------------ */
-/* Neighbour search over the block grid.  Predicate in float:                */
-/*   dx = xj - xi (per axis) ; d2 = (dx*dx + dy*dy) + dz*dz ; d2 < r2f.      */
+/* Neighbour search over the block grid.  Predicate in float, fused:         */
+/*   dx = xj - xi (per axis) ; d2 = fma(dz, dz, fma(dy, dy, dx*dx)) < r2f.   */
 /* Canonical list order: fluid by sorted position ascending (blocks scanned  */
 /* dz, dy, dx ascending), then walls by their sorted position ascending.     */
 /* ------------------------------------------------------------------------ */
@@ -288,9 +288,8 @@ static int near_f(const float *pi, const float *pj, float r2f) {
   float dx = pj[0] - pi[0];
   float dy = pj[1] - pi[1];
   float dz = pj[2] - pi[2];
-  float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-  float s = xx + yy;
-  float d2 = s + zz;
+  float xx = dx * dx;
+  float d2 = fmaf(dz, dz, fmaf(dy, dy, xx));   /* fmaf rounds once per fused step */
   return d2 < r2f;
 }
 

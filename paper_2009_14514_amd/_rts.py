@@ -18,26 +18,29 @@ STATUS_NAMES = {0: "ok", 1: "invalid", 2: "capacity", 3: "device", 4: "numerical
 RTS_WCSPH, RTS_PCISPH = 0, 1
 MODES = {"rts": 0, "global_fixed": 1, "global_adaptive": 2}
 MAX_LEVELS = 8
+DEBUG_NBR_ROW = 1024
 
 DBG = {name: i for i, name in enumerate([
     "POS", "VEL", "ACC", "ACC_NEW", "META", "ID", "KEY", "PERM", "CELL_START", "BLK_LEVEL_RAW",
     "BLK_LEVEL", "NNB", "NBR", "PRESSURE", "PRE_POS", "PRE_VEL", "PRE_ACC", "PRE_META", "PRE_ID",
-    "WALL_POS", "WALL_ID", "WALL_CELL_START", "ACTIVE"])}
+    "WALL_POS", "WALL_ID", "WALL_CELL_START", "OCCUPIED", "BLK_STATS"])}
 
 # exported symbols, in the order include/rts.h declares them
 EXPORTS = [
     "rts_default_config", "rts_workspace_size", "rts_create", "rts_destroy", "rts_set_walls",
     "rts_set_state", "rts_assign_levels", "rts_advance", "rts_sync", "rts_get_state",
     "rts_state_bytes", "rts_save_state", "rts_load_state", "rts_debug_get", "rts_grid_info",
-    "rts_last_error", "rts_status_string",
+    "rts_profile_advance", "rts_last_error", "rts_status_string",
 ]
+PROF_KERNELS = ["key_hist", "scan", "scatter", "cell_gather", "rmin_flags", "search_density",
+                "force", "step_stats", "correct_predict"]
 
 
 class RtsConfig(C.Structure):
     _fields_ = [
         ("solver", C.c_int32), ("mode", C.c_int32), ("n_levels", C.c_int32),
         ("level_cap", C.c_int32), ("clamp_p", C.c_int32), ("serna_correct", C.c_int32),
-        ("nbr_cap", C.c_int32), ("use_graph", C.c_int32),
+        ("cand_cap", C.c_int32), ("use_graph", C.c_int32),
         ("spacing", C.c_double), ("h", C.c_double), ("support", C.c_double),
         ("block_edge", C.c_double), ("r_crit", C.c_double), ("rho0", C.c_double),
         ("mass", C.c_double), ("c0", C.c_double), ("gamma", C.c_double), ("B", C.c_double),
@@ -52,7 +55,8 @@ class RtsStats(C.Structure):
     _fields_ = [
         ("step", C.c_int64), ("time", C.c_double), ("dt_last", C.c_double),
         ("active_last", C.c_int64), ("inter_last", C.c_int64), ("active_total", C.c_int64),
-        ("inter_total", C.c_int64), ("err_max_last", C.c_float), ("err_max_run", C.c_float),
+        ("inter_total", C.c_int64), ("cand_total", C.c_int64), ("err_max_last", C.c_float),
+        ("err_max_run", C.c_float),
         ("level_hist", C.c_int32 * MAX_LEVELS), ("nbr_max", C.c_int32), ("status", C.c_int32),
         ("bad_index", C.c_int32),
     ]
@@ -98,6 +102,7 @@ def lib():
         L.rts_load_state.argtypes = [vp, vp, C.c_size_t]
         L.rts_debug_get.argtypes = [vp, i32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
         L.rts_grid_info.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.rts_profile_advance.argtypes = [vp, i32, C.POINTER(C.c_double)]
         L.rts_last_error.argtypes = [vp]
         L.rts_last_error.restype = C.c_char_p
         L.rts_status_string.argtypes = [C.c_int]
@@ -128,7 +133,7 @@ def config_from_params(p: dict, **over) -> RtsConfig:
     c.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     c.n_levels, c.level_cap = int(q["n_levels"]), int(q["level_cap"])
     c.clamp_p, c.serna_correct = int(q["clamp_p"]), int(q["serna_correct"])
-    c.nbr_cap = int(q.get("nbr_cap", 384))
+    c.cand_cap = int(q.get("cand_cap", 4096))
     c.use_graph = int(q.get("use_graph", 1))
     for k in ("spacing", "h", "support", "block_edge", "rho0", "c0", "gamma", "visc_alpha",
               "visc_eps", "dt_base", "lambda_v", "lambda_f", "alpha_rts", "beta2", "beta_ratio"):
@@ -227,6 +232,13 @@ def grid_info(ctx):
     m, B, dt = C.c_double(0), C.c_double(0), C.c_double(0)
     check(lib().rts_grid_info(ctx, nc, C.byref(nb), C.byref(m), C.byref(B), C.byref(dt)), ctx)
     return dict(nc=list(nc), nblocks=int(nb.value), mass=m.value, B=B.value, dt_base=dt.value)
+
+
+def profile_advance(ctx, n_steps):
+    """Per-kernel milliseconds summed over n_steps eager, event-bracketed steps."""
+    ms = (C.c_double * len(PROF_KERNELS))()
+    check(lib().rts_profile_advance(ctx, int(n_steps), ms), ctx)
+    return dict(zip(PROF_KERNELS, list(ms)))
 
 
 def last_error(ctx):

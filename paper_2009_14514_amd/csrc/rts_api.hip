@@ -23,7 +23,9 @@ struct rts_ctx {
   hipGraph_t graph[2];
   bool graph_ok;
   int64_t ncap, nwcap;
-  int grid_persist;
+  int grid_wave;     // workgroups of the one-wave-per-block kernels (4 waves each)
+  int grid_search;   // workgroups of the search / density kernel
+  int grid_force;    // workgroups of the force kernel
   bool has_state;
   bool poisoned;
   double mass, B, dt_base;
@@ -98,7 +100,11 @@ rts_status validate(const rts_config *c, char *msg, size_t cap) {
     snprintf(msg, cap, "n_levels must be in [1, %d]", RTS_MAX_LEVELS);
     return RTS_E_INVALID;
   }
-  if (c->nbr_cap < 1 || c->nbr_cap > 4096) { snprintf(msg, cap, "nbr_cap must be in [1, 4096]"); return RTS_E_INVALID; }
+  // bitmask words of 32 candidates for each of kSub lanes
+  if (c->cand_cap < 32 * kSub || c->cand_cap > 65536 || c->cand_cap % (32 * kSub)) {
+    snprintf(msg, cap, "cand_cap must be a multiple of %d in [%d, 65536]", 32 * kSub, 32 * kSub);
+    return RTS_E_INVALID;
+  }
   if (!(c->lambda_v > 0 && c->lambda_f > 0 && c->alpha_rts > 0 && c->beta2 > 0 && c->beta_ratio > 0)) {
     snprintf(msg, cap, "time-step coefficients must be positive");
     return RTS_E_INVALID;
@@ -117,7 +123,8 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
             double &B, double &dtb) {
   memset(&p, 0, sizeof(p));
   p.ncap = (int32_t)ncap;
-  p.kcap = c.nbr_cap;
+  p.cand_cap = c.cand_cap;
+  p.wpl = c.cand_cap / (kSub * 32);
   int64_t nb = 1;
   for (int d = 0; d < 3; ++d) {
     int32_t n = (int32_t)ceil((c.domain_max[d] - c.domain_min[d]) / c.block_edge);
@@ -203,12 +210,16 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.TMP = (uint32_t *)take(n * 4);
   t.PERM = (uint32_t *)take(n * 4);
   t.NNB = (uint32_t *)take(n * 4);
-  t.ACT = (uint32_t *)take(n * 4);
-  t.NBR = (uint32_t *)take(n * (size_t)p.kcap * 4);
+  t.MASK = (uint32_t *)take(n * (size_t)(kSub * p.wpl) * 4);
   t.COUNT = (uint32_t *)take(nb * 4);
   t.CELL_START = (uint32_t *)take((nb + 1) * 4);
+  t.OCC = (uint32_t *)take(nb * 4);
   t.LRAW = (uint8_t *)take(nb);
   t.LVL = (uint8_t *)take(nb);
+  t.BLKU = (uint4 *)take(nb * 16);
+  t.BLKERR = (float *)take(nb * 4);
+  t.BLKAMAX = (float *)take(nb * 4);
+  t.PART = (StatPart *)take(sizeof(StatPart) * kStatBlocks);
   t.WP = (float4 *)take(nw * 16);
   t.WID = (uint32_t *)take(nw * 4);
   t.WCELL_START = (uint32_t *)take((nb + 1) * 4);
@@ -216,6 +227,7 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.WRANK = (uint32_t *)take(nw * 4);
   t.WTMP = (uint32_t *)take(nw * 4);
   t.TILES = (unsigned long long *)take(ntiles * 8);
+  t.TILES2 = (unsigned long long *)take(ntiles * 8);
   t.CTRL = (DevCtrl *)take(sizeof(DevCtrl));
   t.S = (DevScalars *)take(sizeof(DevScalars));
   if (d) *d = t;
@@ -239,12 +251,13 @@ void enqueue_step(rts_ctx *c, int cur, hipStream_t st) {
   const DevPtrs &d = c->d;
   const int nx = cur ^ 1;
   launch_key_hist(p, d, cur, st);
-  launch_scan(p, d.COUNT, d.CELL_START, p.nb, d.TILES, d.CTRL, d.S, st);
+  launch_scan(p, d, d.CELL_START, true, st);
   launch_scatter(p, d, st);
-  launch_cell_gather(p, d, cur, st);
-  launch_rmin_flags(p, d, nx, 1, st);
-  launch_search_density(p, d, nx, c->grid_persist, st);
-  launch_force(p, d, nx, c->grid_persist, st);
+  launch_cell_gather(p, d, cur, c->grid_wave, st);
+  launch_rmin_flags(p, d, nx, 1, c->grid_wave, st);
+  launch_search_density(p, d, nx, c->grid_search, st);
+  launch_force(p, d, nx, c->grid_force, st);
+  launch_step_stats(p, d, st);
   launch_correct_predict(p, d, nx, st);
 }
 
@@ -272,7 +285,7 @@ void rts_default_config(rts_config *c) {
   c->level_cap = 3;
   c->clamp_p = 1;
   c->serna_correct = 1;
-  c->nbr_cap = 384;
+  c->cand_cap = 4096;
   c->use_graph = 1;
   c->spacing = 0.01;
   c->h = 0.02;
@@ -358,10 +371,12 @@ rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall
     delete c;
     return RTS_E_DEVICE;
   }
-  int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  int64_t want = (n_fluid_max + 255) / 256;
-  int64_t cap = (int64_t)cus * 8;
-  c->grid_persist = (int)(want < 1 ? 1 : (want < cap ? want : cap));
+  const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  // persistent grids: enough workgroups to fill every CU, each striding over
+  // the occupied blocks (search: 3 per CU fit in LDS; force: 1 per CU)
+  c->grid_wave = cus * 8;
+  c->grid_search = cus * 4;
+  c->grid_force = cus * 2;
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return RTS_E_DEVICE;
@@ -369,6 +384,9 @@ rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall
   // counts must start at zero; everything else is written before it is read
   hipError_t e = hipMemsetAsync(c->d.COUNT, 0, (size_t)c->prm.nb * 4, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->d.TILES, 0,
+                                          ((size_t)c->prm.nb + kScanTile - 1) / kScanTile * 8,
+                                          c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d.TILES2, 0,
                                           ((size_t)c->prm.nb + kScanTile - 1) / kScanTile * 8,
                                           c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->d.NNB, 0, (size_t)(n_fluid_max > 0 ? n_fluid_max : 1) * 4, c->stream);
@@ -424,10 +442,10 @@ rts_status rts_assign_levels(rts_ctx *c, int32_t *h_hist) {
   const DevParams &p = c->prm;
   const int cur = c->cur;
   launch_key_hist(p, c->d, cur, c->stream);
-  launch_scan(p, c->d.COUNT, c->d.CELL_START, p.nb, c->d.TILES, c->d.CTRL, c->d.S, c->stream);
+  launch_scan(p, c->d, c->d.CELL_START, true, c->stream);
   launch_scatter(p, c->d, c->stream);
-  launch_cell_gather(p, c->d, cur, c->stream);
-  launch_rmin_flags(p, c->d, cur ^ 1, 0, c->stream);
+  launch_cell_gather(p, c->d, cur, c->grid_wave, c->stream);
+  launch_rmin_flags(p, c->d, cur ^ 1, 0, c->grid_wave, c->stream);
   HIP_OK(c, hipGetLastError());
   c->cur = cur ^ 1;
   if (h_hist) {
@@ -470,6 +488,52 @@ rts_status rts_advance(rts_ctx *c, int32_t n_steps) {
   return RTS_OK;
 }
 
+rts_status rts_profile_advance(rts_ctx *c, int32_t n_steps, double *h_ms) {
+  if (!c || n_steps < 0 || !h_ms) return RTS_E_INVALID;
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  if (c->poisoned) return fail(c, RTS_E_STATE, "state failed; set or load a state first");
+  hipEvent_t ev[RTS_PROF_COUNT + 1];
+  for (int k = 0; k <= RTS_PROF_COUNT; ++k) HIP_OK(c, hipEventCreate(&ev[k]));
+  rts_status st = RTS_OK;
+  const DevParams &p = c->prm;
+  const DevPtrs &d = c->d;
+  for (int32_t s = 0; s < n_steps && st == RTS_OK; ++s) {
+    const int cur = c->cur, nx = cur ^ 1;
+    hipStream_t q = c->stream;
+    (void)hipEventRecord(ev[0], q);
+    launch_key_hist(p, d, cur, q);
+    (void)hipEventRecord(ev[1], q);
+    launch_scan(p, d, d.CELL_START, true, q);
+    (void)hipEventRecord(ev[2], q);
+    launch_scatter(p, d, q);
+    (void)hipEventRecord(ev[3], q);
+    launch_cell_gather(p, d, cur, c->grid_wave, q);
+    (void)hipEventRecord(ev[4], q);
+    launch_rmin_flags(p, d, nx, 1, c->grid_wave, q);
+    (void)hipEventRecord(ev[5], q);
+    launch_search_density(p, d, nx, c->grid_search, q);
+    (void)hipEventRecord(ev[6], q);
+    launch_force(p, d, nx, c->grid_force, q);
+    (void)hipEventRecord(ev[7], q);
+    launch_step_stats(p, d, q);
+    (void)hipEventRecord(ev[8], q);
+    launch_correct_predict(p, d, nx, q);
+    (void)hipEventRecord(ev[9], q);
+    c->cur = nx;
+    if (hipEventSynchronize(ev[RTS_PROF_COUNT]) != hipSuccess) {
+      st = fail(c, RTS_E_DEVICE, "event synchronisation failed");
+      break;
+    }
+    for (int k = 0; k < RTS_PROF_COUNT; ++k) {
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      h_ms[k] += ms;
+    }
+  }
+  for (int k = 0; k <= RTS_PROF_COUNT; ++k) (void)hipEventDestroy(ev[k]);
+  return st;
+}
+
 rts_status rts_sync(rts_ctx *c, rts_stats *out) {
   if (!c) return RTS_E_INVALID;
   DevScalars S;
@@ -485,8 +549,9 @@ rts_status rts_sync(rts_ctx *c, rts_stats *out) {
     out->inter_last = (int64_t)S.inter_last;
     out->active_total = (int64_t)S.active_total;
     out->inter_total = (int64_t)S.inter_total;
-    memcpy(&out->err_max_last, &S.err_bits_last, 4);
-    memcpy(&out->err_max_run, &S.err_bits_run, 4);
+    out->cand_total = (int64_t)S.cand_total;
+    out->err_max_last = S.err_last;
+    out->err_max_run = S.err_run;
     for (int l = 0; l < RTS_MAX_LEVELS; ++l) out->level_hist[l] = S.hist[l];
     out->nbr_max = (int32_t)S.nbr_max;
     out->status = (int32_t)S.status;
@@ -585,7 +650,16 @@ rts_status rts_debug_get(rts_ctx *c, int32_t what, void *d_out, size_t cap, size
     case RTS_DBG_BLK_LEVEL_RAW: src = c->d.LRAW; count = nb; esz = 1; break;
     case RTS_DBG_BLK_LEVEL: src = c->d.LVL; count = nb; esz = 1; break;
     case RTS_DBG_NNB: src = c->d.NNB; count = n; break;
-    case RTS_DBG_NBR: src = c->d.NBR; count = (size_t)c->prm.kcap * (size_t)c->ncap; break;
+    case RTS_DBG_NBR: {
+      // canonical lists of the last step's active particles, then their counts
+      count = n * ((size_t)RTS_DEBUG_NBR_ROW + 1);
+      if (n_out) *n_out = count;
+      if (count * 4 > cap) return fail(c, RTS_E_CAPACITY, "debug view needs %zu bytes", count * 4);
+      uint32_t *o = (uint32_t *)d_out;
+      launch_debug_lists(c->prm, c->d, k, o, o + n * (size_t)RTS_DEBUG_NBR_ROW, c->stream);
+      HIP_OK(c, hipGetLastError());
+      return RTS_OK;
+    }
     case RTS_DBG_PRESSURE: src = c->d.PRES; count = n; break;
     case RTS_DBG_PRE_POS: src = c->d.P[pk]; count = n; esz = 16; break;
     case RTS_DBG_PRE_VEL: src = c->d.V[pk]; count = n; esz = 16; break;
@@ -595,12 +669,13 @@ rts_status rts_debug_get(rts_ctx *c, int32_t what, void *d_out, size_t cap, size
     case RTS_DBG_WALL_POS: src = c->d.WP; count = nw; esz = 16; break;
     case RTS_DBG_WALL_ID: src = c->d.WID; count = nw; break;
     case RTS_DBG_WALL_CELL_START: src = c->d.WCELL_START; count = nb + 1; break;
-    case RTS_DBG_ACTIVE: {
+    case RTS_DBG_BLK_STATS: src = c->d.BLKU; count = nb; esz = 16; break;
+    case RTS_DBG_OCCUPIED: {
       DevScalars S;
       HIP_OK(c, hipMemcpyAsync(&S, c->d.S, sizeof(S), hipMemcpyDeviceToHost, c->stream));
       HIP_OK(c, hipStreamSynchronize(c->stream));
-      src = c->d.ACT;
-      count = S.n_act;
+      src = c->d.OCC;
+      count = S.n_occ;
       break;
     }
     default: return fail(c, RTS_E_INVALID, "unknown debug view %d", what);

@@ -30,7 +30,9 @@ __host__ __device__ inline int32_t meta_validity(uint32_t m) { return (int32_t)(
 // Numbers every kernel needs, derived once on the host in double precision
 // and rounded to float.
 struct DevParams {
-  int32_t n, ncap, nw, kcap;
+  int32_t n, ncap, nw;
+  int32_t cand_cap;      // candidates per block the neighbour bitmasks can describe
+  int32_t wpl;           // bitmask words per lane: cand_cap / (kSub * 32)
   int32_t nc[3];
   int32_t nb;
   float o[3];
@@ -50,35 +52,52 @@ struct DevParams {
   float TV[kMaxLevels], TA[kMaxLevels];
 };
 
-// Scan control words.  Zeroed once when the context is created and never
-// reset or restored afterwards: the epoch only grows, so look-back words
-// left by an earlier scan can never be mistaken for the current one's.
+// Control words.  Zeroed once when the context is created and never reset
+// or restored afterwards: the scan epoch only grows, so look-back words left
+// by an earlier scan can never be mistaken for the current one's.
 struct DevCtrl {
   uint32_t epoch;
   uint32_t scan_ticket;
+  uint32_t stats_ticket;
+  uint32_t pad;
 };
 
 // Counters kept on the device (part of the saved state).
 struct DevScalars {
   uint32_t status;
   int32_t bad_index;         // caller index of the particle that raised status, or -1
-  uint32_t n_act;
-  uint32_t pad1;
-  uint32_t pad2;
+  uint32_t n_act;            // active particles of the last step
+  uint32_t n_occ;            // occupied blocks of the current grid
   uint32_t nbr_max;
-  uint32_t err_bits_last;    // float bits of the last step's max compression error
-  uint32_t err_bits_run;
-  uint32_t amax2_bits;       // float bits of max |a|^2 over active particles
+  float err_last;            // last step's max compression error
+  float err_run;
+  float amax2;               // max |a|^2 over the last step's active particles
   int32_t hist[kMaxLevels];
-  uint32_t pad0;
   unsigned long long inter_last;
+  unsigned long long cand_last;      // candidate pair tests of the last step
   unsigned long long active_total;
   unsigned long long inter_total;
+  unsigned long long cand_total;
   long long step;
   double time;
   double dt_prev;            // length of the step that ended at this step's start
-  double dt_next;            // length of the step predicted at this step's end
+  double dt_next;            // length of this step (predictor)
 };
+
+// Per-workgroup partial of the per-step statistics reduction.
+struct StatPart {
+  unsigned long long act, inter, cand;
+  uint32_t nmax;
+  float err, amax2;
+  int32_t hist[kMaxLevels];
+};
+constexpr int kStatBlocks = 64;
+
+// Neighbour lists are bitmasks over a block's canonical candidate order:
+// kSub lanes share one particle, lane s owning candidates k = s + kSub * m,
+// one bit per candidate, 32 per word; word w of lane s of particle i is at
+// MASK[i * kSub * wpl + kSub * w + s].
+constexpr int kSub = 8;
 
 struct DevPtrs {
   float4 *P[2];      // x, y, z, rho
@@ -87,37 +106,45 @@ struct DevPtrs {
   uint32_t *M[2];    // meta
   uint32_t *ID[2];   // caller index
   float4 *ANEW;      // acceleration evaluated this step
-  float *PRES;       // pressure
+  float *PRES;       // pressure (last step's active particles)
   uint32_t *KEY;     // block of each sorted particle
   uint32_t *KEYOLD;  // block of each particle in the previous order
   uint32_t *RANK;    // arrival slot within its block (unordered)
   uint32_t *TMP;     // block-grouped previous indices, unordered within a block
   uint32_t *PERM;    // previous index of each sorted particle
-  uint32_t *NNB;
-  uint32_t *NBR;     // kcap x ncap, slot k of particle i at k * ncap + i
-  uint32_t *ACT;     // active particles (sorted indices)
+  uint32_t *NNB;     // neighbour count per particle (last step's active ones)
+  uint32_t *MASK;    // ncap x (kSub * wpl) neighbour bitmask words
   uint32_t *COUNT;   // nb, zero between sorts
   uint32_t *CELL_START;  // nb + 1
+  uint32_t *OCC;     // occupied blocks, ascending
   uint8_t *LRAW, *LVL;   // block level before / after R_min
+  uint4 *BLKU;       // per block: active, pairs, candidate tests, max count | n << 16
+  float *BLKERR;     // per block: max compression error
+  float *BLKAMAX;    // per block: max |a|^2 of active particles
+  StatPart *PART;    // kStatBlocks partials
   float4 *WP;        // wall particles, sorted
   uint32_t *WID, *WCELL_START, *WKEY, *WRANK, *WTMP;
-  unsigned long long *TILES;  // scan look-back words
+  unsigned long long *TILES;   // scan look-back words, counts
+  unsigned long long *TILES2;  // scan look-back words, occupied blocks
   DevCtrl *CTRL;
   DevScalars *S;
 };
 
 // Launchers (rts_kernels.hip).  All enqueue on `st`.
 void launch_key_hist(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
-void launch_scan(const DevParams &p, uint32_t *count, uint32_t *start, int nb,
-                 unsigned long long *tiles, DevCtrl *ctrl, DevScalars *S, hipStream_t st);
+void launch_scan(const DevParams &p, const DevPtrs &d, uint32_t *start, bool fluid,
+                 hipStream_t st);
 void launch_prep_scan(DevCtrl *ctrl, hipStream_t st);
 void launch_scatter(const DevParams &p, const DevPtrs &d, hipStream_t st);
-void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
-void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags,
+void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st);
+void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags, int grid,
                        hipStream_t st);
 void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid,
                            hipStream_t st);
 void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st);
+void launch_step_stats(const DevParams &p, const DevPtrs &d, hipStream_t st);
+void launch_debug_lists(const DevParams &p, const DevPtrs &d, int cur, uint32_t *out, uint32_t *out_n,
+                        hipStream_t st);
 void launch_correct_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
 void launch_set_state(const DevParams &p, const DevPtrs &d, int cur, const float *pos,
                       const float *vel, hipStream_t st);

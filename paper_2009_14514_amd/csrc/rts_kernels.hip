@@ -4,25 +4,40 @@
 // corrector of the step that ends now placed before the predictor of the
 // next one, as the predictor-corrector equations of Section 4.1 require):
 //   key_hist        block key of every particle + per-block arrival counts
-//   scan            exclusive scan of the counts (decoupled look-back)
+//   scan            exclusive scans (decoupled look-back) of the counts and of
+//                   the occupied-block flags: block starts, occupied-block list
 //   scatter         block-grouped previous indices
-//   cell_gather     one wave per block: canonical (stable) order, gather of
-//                   the SoA state, block maxima of |v|^2 and |a|^2, block level
-//                   from Eq. 2-3 (Section 3.1)
-//   rmin_flags      one wave per block: R_min smoothing (Section 4.2), particle
-//                   validity / compute / pre-emption, active-list compaction
-//   search_density  active particles: neighbours from the 27 surrounding
-//                   blocks (list written), density and Tait pressure
-//   force           active particles: pressure + viscosity + gravity
+//   cell_gather     one wave per occupied block: canonical (stable) order, SoA
+//                   gather, block maxima of |v|^2 and |a|^2, block level from
+//                   Eq. 2-3 (Section 3.1)
+//   rmin_flags      one wave per occupied block: R_min smoothing (Section 4.2),
+//                   particle validity / compute / pre-emption (Algorithm 1)
+//   search_density  one workgroup per occupied block: the 27 surrounding
+//                   blocks are staged in LDS once; 4 lanes per active particle
+//                   test interleaved quarters of them, write the neighbour
+//                   sub-lists and sum density; Tait pressure
+//   force           one workgroup per occupied block: candidates' position,
+//                   velocity, density and pressure staged in LDS; pressure +
+//                   viscosity + gravity from the lists
+//   step_stats      per-step counters and the step length
 //   correct_predict all particles: corrector for the active ones, then the
 //                   predictor of the next base step
 //
 // Every float comparison that decides an integer (block key, neighbour
 // predicate, block level) is evaluated with contraction off and a fixed
 // operation order, so the structure is reproducible bit for bit on the CPU.
+// No floating-point atomics are used; same-address integer atomics are
+// limited to one per group of equal keys in a wave.
 #include "rts_internal.h"
 
 namespace rts {
+
+constexpr int kBlockThreads = 512;            // search: 64 particles x kSub lanes
+constexpr int kPartPerPass = kBlockThreads / kSub;
+constexpr int kForceThreads = 512;            // force: 64 particles x kSub lanes
+constexpr int kForcePerPass = kForceThreads / kSub;
+constexpr int kStageCap = 2048;               // candidates staged in LDS (search: 16 B each)
+constexpr int kForceCap = 2048;               // candidates staged in LDS (force: 32 B each)
 
 // ---------------------------------------------------------------------------
 // small device helpers
@@ -60,31 +75,37 @@ __device__ inline float norm2_exact(float x, float y, float z) {
   return s + zz;
 }
 
-// Squared distance with the same fixed order, from xj - xi per axis.
+// Squared distance from xj - xi per axis, as fma(dz, dz, fma(dy, dy, dx*dx)):
+// each fused step is rounded once, so the CPU reproduces it with fmaf.
 __device__ inline float dist2_exact(float xi, float yi, float zi, float xj, float yj, float zj) {
 #pragma clang fp contract(off)
-  float dx = xj - xi, dy = yj - yi, dz = zj - zi;
-  float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-  float s = xx + yy;
-  return s + zz;
+  const float dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  const float xx = dx * dx;
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, xx));
 }
 
-// Cubic spline shape w(q) and its derivative (support q < 2).
+// Cubic spline shape w(q) and its derivative (support q < 2), branch-free:
+// both pieces are evaluated and the right one selected.
 __device__ inline float w_shape(float q) {
-  if (q < 1.0f) return 1.0f + q * q * (-1.5f + 0.75f * q);
-  if (q < 2.0f) {
-    float t = 2.0f - q;
-    return 0.25f * t * t * t;
-  }
-  return 0.0f;
+  const float w1 = 1.0f + q * q * (-1.5f + 0.75f * q);
+  const float t = fmaxf(2.0f - q, 0.0f);
+  const float w2 = 0.25f * t * t * t;
+  return q < 1.0f ? w1 : w2;
 }
 __device__ inline float dw_shape(float q) {
-  if (q < 1.0f) return q * (-3.0f + 2.25f * q);
-  if (q < 2.0f) {
-    float t = 2.0f - q;
-    return -0.75f * t * t;
-  }
-  return 0.0f;
+  const float d1 = q * (-3.0f + 2.25f * q);
+  const float t = fmaxf(2.0f - q, 0.0f);
+  const float d2 = -0.75f * t * t;
+  return q < 1.0f ? d1 : d2;
+}
+
+// Tait pressure from the density deviation d = rho/rho0 - 1, with
+// (1 + d)^7 - 1 expanded in d (gamma = 7) so that nothing cancels.
+__device__ inline float tait_from_dev(const DevParams &p, float d) {
+  float poly = 7.0f + d * (21.0f + d * (35.0f + d * (35.0f + d * (21.0f + d * (7.0f + d)))));
+  float pr = p.B * d * poly;
+  if (p.clamp_p && pr < 0.0f) pr = 0.0f;
+  return pr;
 }
 
 __device__ inline void set_status(DevScalars *S, uint32_t code, int32_t idx) {
@@ -108,6 +129,89 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
+// The candidate set of a block: 9 fluid row ranges (dz outer, dy inner, each
+// row covering x-1..x+1 contiguously in sorted order) followed by the same 9
+// rows of the wall grid.  Range r starts at global index rs and occupies
+// local indices [ro[r], ro[r+1]).  Local order equals the canonical
+// neighbour order (ascending sorted index, fluid before walls).
+__device__ inline void row_range(const DevParams &p, const uint32_t *start,
+                                 const uint32_t *wstart, int3 c, int r, uint32_t &rs,
+                                 uint32_t &len) {
+  const uint32_t *cs = r < 9 ? start : wstart;
+  const int rr = r % 9;
+  const int z = c.z + rr / 3 - 1, y = c.y + rr % 3 - 1;
+  rs = 0;
+  len = 0;
+  if (z < 0 || z >= p.nc[2] || y < 0 || y >= p.nc[1]) return;
+  if (r >= 9 && p.nw == 0) return;
+  const int x0 = max(c.x - 1, 0), x1 = min(c.x + 1, p.nc[0] - 1);
+  const uint32_t row = (uint32_t)p.nc[0] * ((uint32_t)y + (uint32_t)p.nc[1] * (uint32_t)z);
+  rs = cs[row + (uint32_t)x0];
+  const uint32_t re = cs[row + (uint32_t)x1 + 1u];
+  len = re > rs ? re - rs : 0u;
+}
+
+// Global position of local candidate k.
+__device__ inline uint32_t local_to_global(const uint32_t *rs, const uint32_t *ro, uint32_t k,
+                                           bool &wall) {
+  int r = 0;
+  while (r < 17 && k >= ro[r + 1]) ++r;
+  wall = r >= 9;
+  return rs[r] + (k - ro[r]);
+}
+
+// Sets up the candidate ranges of block b in shared memory and their prefix
+// offsets.  Ends with the offsets visible to the whole workgroup.
+__device__ inline void block_ranges_shared(const DevParams &p, const uint32_t *start,
+                                           const uint32_t *wstart, uint32_t b, uint32_t *s_rs,
+                                           uint32_t *s_ro, uint32_t *s_len) {
+  const int tid = threadIdx.x;
+  if (tid < 18) {
+    uint32_t rs, len;
+    row_range(p, start, wstart, coords_of(p, b), tid, rs, len);
+    s_rs[tid] = rs;
+    s_len[tid] = len;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int r = 0; r < 18; ++r) {
+      s_ro[r] = acc;
+      acc += s_len[r];
+    }
+    s_ro[18] = acc;
+  }
+  __syncthreads();
+}
+
+// Copies the block's candidates into shared memory in canonical order, one
+// range at a time so that consecutive threads read consecutive particles;
+// slots from C up to cpad are filled with far-away positions.
+__device__ inline void stage_positions(const uint32_t *s_rs, const uint32_t *s_ro,
+                                       const float4 *__restrict__ P,
+                                       const float4 *__restrict__ WP, float4 *s_pos,
+                                       uint32_t cpad) {
+  constexpr int kPer = (kStageCap + kBlockThreads - 1) / kBlockThreads;
+  const uint32_t C = s_ro[18];
+  float4 v[kPer];
+  // every load is issued before the first shared-memory write
+#pragma unroll
+  for (int it = 0; it < kPer; ++it) {
+    const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kBlockThreads;
+    v[it] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);  // padding: never a neighbour
+    if (k < C) {
+      bool wall;
+      const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
+      v[it] = wall ? WP[j] : P[j];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < kPer; ++it) {
+    const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kBlockThreads;
+    if (k < cpad) s_pos[k] = v[it];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // key + histogram
 // ---------------------------------------------------------------------------
@@ -117,36 +221,53 @@ __global__ void __launch_bounds__(256) k_key_hist(DevParams p, const float4 *__r
                                                  uint32_t *__restrict__ rank,
                                                  uint32_t *__restrict__ count, DevCtrl *ctrl,
                                                  DevScalars *S) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
   if (i == 0) {
-    // per-step control words; every later kernel of the step sees them
-    ctrl->epoch += 1u;
+    ctrl->epoch += 1u;  // a fresh epoch for this step's scan
     ctrl->scan_ticket = 0u;
-    S->n_act = 0u;
-    S->amax2_bits = 0u;
-    S->err_bits_last = 0u;
-    S->inter_last = 0ull;
-    for (int l = 0; l < kMaxLevels; ++l) S->hist[l] = 0;
+    ctrl->stats_ticket = 0u;
     S->dt_prev = S->dt_next;
   }
-  if (i >= p.n) return;
-  float4 x = P[i];
-  bool bad = !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z));
-  // domain check in float against the grid extent
-  bad = bad || x.x < p.o[0] || x.y < p.o[1] || x.z < p.o[2] || x.x > p.dmax[0] ||
-        x.y > p.dmax[1] || x.z > p.dmax[2];
-  if (bad) set_status(S, RTS_E_NUMERICAL, (int32_t)ids[i]);
-  uint32_t k = key_of(p, block_of(p, x.x, x.y, x.z));
-  keyold[i] = k;
-  rank[i] = atomicAdd(&count[k], 1u);
+  const bool live = i < p.n;
+  uint32_t k = 0;
+  if (live) {
+    const float4 x = P[i];
+    bool bad = !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z));
+    bad = bad || x.x < p.o[0] || x.y < p.o[1] || x.z < p.o[2] || x.x > p.dmax[0] ||
+          x.y > p.dmax[1] || x.z > p.dmax[2];
+    if (bad) set_status(S, RTS_E_NUMERICAL, (int32_t)ids[i]);
+    k = key_of(p, block_of(p, x.x, x.y, x.z));
+    keyold[i] = k;
+  }
+  // Particles arrive in the previous sorted order, so a wave holds few
+  // distinct keys: one atomic per distinct key, ranks handed out in-wave.
+  bool done = !live;
+  unsigned long long todo = __ballot(!done);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const uint32_t lk = (uint32_t)__shfl((int)k, leader, 64);
+    const bool mine = !done && k == lk;
+    const unsigned long long same = __ballot(mine);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&count[lk], (uint32_t)__popcll(same));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    if (mine) {
+      rank[i] = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+      done = true;
+    }
+    todo = __ballot(!done);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan, single pass with decoupled look-back
+// exclusive scans, single pass with decoupled look-back
 // (Merrill & Garland, "Single-pass Parallel Prefix Scan with Decoupled
 // Look-back", 2016).  Tiles take tickets in launch order so every tile's
-// predecessors have started; status words carry the step's epoch so they
+// predecessors have started; status words carry the scan's epoch so they
 // never need clearing.  Reading a count also clears it for the next sort.
+// For the fluid grid the same pass scans the occupied-block flags into the
+// occupied-block list and marks the levels of empty blocks.
 // ---------------------------------------------------------------------------
 constexpr unsigned long long kFlagAgg = 1ull, kFlagPre = 2ull;
 __device__ inline unsigned long long pack_status(uint32_t epoch, unsigned long long flag,
@@ -154,34 +275,44 @@ __device__ inline unsigned long long pack_status(uint32_t epoch, unsigned long l
   return ((unsigned long long)(epoch & 0x3FFFFFFFu) << 34) | (flag << 32) | v;
 }
 
-__global__ void __launch_bounds__(256) k_scan(uint32_t *__restrict__ count,
-                                             uint32_t *__restrict__ start, int nb,
-                                             unsigned long long *__restrict__ tiles,
-                                             DevCtrl *ctrl, DevScalars *S) {
-  __shared__ uint32_t s_tile, s_prefix;
-  __shared__ uint32_t s_wave[4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_tile = atomicAdd(&ctrl->scan_ticket, 1u);
-  __syncthreads();
-  const uint32_t tile = s_tile;
-  const uint32_t epoch = ctrl->epoch;
-  const int base = (int)tile * kScanTile + tid * 4;
-  uint32_t v[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int idx = base + k;
-    v[k] = idx < nb ? count[idx] : 0u;
+// Thread 0 of a tile: publish the aggregate, look back, publish the prefix.
+__device__ uint32_t look_back(unsigned long long *tiles, uint32_t tile, uint32_t epoch,
+                              uint32_t total, DevScalars *S) {
+  if (tile == 0) {
+    __hip_atomic_store(&tiles[0], pack_status(epoch, kFlagPre, total), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
   }
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (base + k < nb) count[base + k] = 0u;
-  uint32_t incl[4];
-  incl[0] = v[0];
-  incl[1] = incl[0] + v[1];
-  incl[2] = incl[1] + v[2];
-  incl[3] = incl[2] + v[3];
-  uint32_t t = incl[3];
-  // inclusive scan of per-thread totals across the wave
+  __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagAgg, total), __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t excl = 0;
+  int j = (int)tile - 1;
+  uint32_t spins = 0;
+  while (j >= 0) {
+    const unsigned long long w =
+        __hip_atomic_load(&tiles[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long flag = (w >> 32) & 3ull;
+    const uint32_t ep = (uint32_t)(w >> 34);
+    if (ep != (epoch & 0x3FFFFFFFu) || flag == 0ull) {
+      if (++spins > (1u << 24)) {  // predecessors always finish; this bound is a guard
+        set_status(S, RTS_E_DEVICE, -1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += (uint32_t)(w & 0xFFFFFFFFull);
+    if (flag == kFlagPre) break;
+    --j;
+  }
+  __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagPre, excl + total), __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
+// Block-wide inclusive scan of one value per thread (256 threads).
+__device__ inline uint32_t block_scan_256(uint32_t t, uint32_t *s_wave, uint32_t &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = t;
   for (int o = 1; o < 64; o <<= 1) {
     uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
@@ -189,51 +320,73 @@ __global__ void __launch_bounds__(256) k_scan(uint32_t *__restrict__ count,
   }
   if (lane == 63) s_wave[wave] = x;
   __syncthreads();
-  uint32_t wave_off = 0, total = 0;
+  uint32_t off = 0;
+  total = 0;
   for (int w = 0; w < 4; ++w) {
-    if (w < wave) wave_off += s_wave[w];
+    if (w < wave) off += s_wave[w];
     total += s_wave[w];
   }
-  uint32_t thread_excl = wave_off + x - t;
-  if (tid == 0) {
-    uint32_t excl = 0;
-    if (tile == 0) {
-      __hip_atomic_store(&tiles[0], pack_status(epoch, kFlagPre, total), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagAgg, total), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      int j = (int)tile - 1;
-      uint32_t spins = 0;
-      while (j >= 0) {
-        unsigned long long w =
-            __hip_atomic_load(&tiles[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long flag = (w >> 32) & 3ull;
-        uint32_t ep = (uint32_t)(w >> 34);
-        if (ep != (epoch & 0x3FFFFFFFu) || flag == 0ull) {
-          if (++spins > (1u << 24)) {  // predecessors always finish; this bound is a guard
-            set_status(S, RTS_E_DEVICE, -1);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += (uint32_t)(w & 0xFFFFFFFFull);
-        if (flag == kFlagPre) break;
-        --j;
-      }
-      __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagPre, excl + total),
-                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_prefix = excl;
-  }
+  return off + x;
+}
+
+__global__ void __launch_bounds__(256) k_scan(uint32_t *__restrict__ count,
+                                             uint32_t *__restrict__ start, int nb,
+                                             unsigned long long *__restrict__ tiles,
+                                             unsigned long long *__restrict__ tiles2,
+                                             uint32_t *__restrict__ occ,
+                                             uint8_t *__restrict__ lraw,
+                                             uint8_t *__restrict__ lvl, DevCtrl *ctrl,
+                                             DevScalars *S) {
+  __shared__ uint32_t s_tile, s_prefix, s_prefix2;
+  __shared__ uint32_t s_wave[4], s_wave2[4];
+  const int tid = threadIdx.x;
+  if (tid == 0) s_tile = atomicAdd(&ctrl->scan_ticket, 1u);
   __syncthreads();
-  const uint32_t off = s_prefix + thread_excl;
+  const uint32_t tile = s_tile;
+  const uint32_t epoch = ctrl->epoch;
+  const int base = (int)tile * kScanTile + tid * 4;
+  uint32_t v[4], o[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    int idx = base + k;
-    if (idx < nb) start[idx] = off + incl[k] - v[k];
-    if (idx == nb - 1) start[nb] = off + incl[k];
+    const int idx = base + k;
+    v[k] = idx < nb ? count[idx] : 0u;
+    o[k] = v[k] ? 1u : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + k < nb) count[base + k] = 0u;
+  const uint32_t t = v[0] + v[1] + v[2] + v[3];
+  const uint32_t t2 = o[0] + o[1] + o[2] + o[3];
+  uint32_t total = 0, total2 = 0;
+  const uint32_t incl = block_scan_256(t, s_wave, total);
+  const uint32_t incl2 = occ ? block_scan_256(t2, s_wave2, total2) : 0u;
+  if (tid == 0) {
+    s_prefix = look_back(tiles, tile, epoch, total, S);
+    if (occ) s_prefix2 = look_back(tiles2, tile, epoch, total2, S);
+  }
+  __syncthreads();
+  uint32_t off = s_prefix + incl - t;
+  uint32_t off2 = occ ? s_prefix2 + incl2 - t2 : 0u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int idx = base + k;
+    if (idx < nb) {
+      start[idx] = off;
+      if (occ) {
+        if (v[k]) {
+          occ[off2] = (uint32_t)idx;
+        } else {
+          lraw[idx] = kEmpty;
+          lvl[idx] = kEmpty;
+        }
+      }
+    }
+    off += v[k];
+    off2 += o[k];
+    if (idx == nb - 1) {
+      start[nb] = off;
+      if (occ) S->n_occ = off2;
+    }
   }
 }
 
@@ -249,7 +402,7 @@ __global__ void __launch_bounds__(256) k_scatter(int n, const uint32_t *__restri
                                                 const uint32_t *__restrict__ rank,
                                                 const uint32_t *__restrict__ start,
                                                 uint32_t *__restrict__ tmp, DevScalars *S) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t d = start[keyold[i]] + rank[i];
   if (d < (uint32_t)n)
@@ -258,8 +411,8 @@ __global__ void __launch_bounds__(256) k_scatter(int n, const uint32_t *__restri
     set_status(S, RTS_E_DEVICE, -1);  // inconsistent block starts: never write out of range
 }
 
-// Rank of element k among the n distinct values s[0..n): the stable position
-// of an index inside its block.
+// Rank of val among the n distinct values s[0..n): the stable position of an
+// index inside its block.
 __device__ inline uint32_t rank_in(const uint32_t *s, int n, uint32_t val) {
   uint32_t r = 0;
   for (int m = 0; m < n; ++m) r += (s[m] < val) ? 1u : 0u;
@@ -267,283 +420,560 @@ __device__ inline uint32_t rank_in(const uint32_t *s, int n, uint32_t val) {
 }
 
 // ---------------------------------------------------------------------------
-// one wave per block: canonical order, gather, block maxima, block level
+// one wave per occupied block: canonical order, gather, block maxima, level
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_cell_gather(
-    DevParams p, const uint32_t *__restrict__ start, const uint32_t *__restrict__ tmp,
-    uint32_t *__restrict__ perm, uint32_t *__restrict__ key,
+__global__ void __launch_bounds__(256) k_cell_gather(
+    DevParams p, const uint32_t *__restrict__ occ, const uint32_t *__restrict__ start,
+    const uint32_t *__restrict__ tmp, uint32_t *__restrict__ perm, uint32_t *__restrict__ key,
     const float4 *__restrict__ Pi, const float4 *__restrict__ Vi, const float4 *__restrict__ Ai,
     const uint32_t *__restrict__ Mi, const uint32_t *__restrict__ Ii, float4 *__restrict__ Po,
     float4 *__restrict__ Vo, float4 *__restrict__ Ao, uint32_t *__restrict__ Mo,
     uint32_t *__restrict__ Io, uint8_t *__restrict__ lraw, DevScalars *S) {
-  __shared__ uint32_t s_idx[kCellMax];
-  const int b = blockIdx.x, lane = threadIdx.x;
-  const uint32_t s0 = start[b];
-  const uint32_t s1 = start[b + 1];
-  if (s1 <= s0 || s1 > (uint32_t)p.n) {
-    if (lane == 0) {
-      lraw[b] = kEmpty;
-      if (s1 < s0 || s1 > (uint32_t)p.n) set_status(S, RTS_E_DEVICE, -1);
-    }
-    return;
-  }
-  const int n = (int)(s1 - s0);
-  const bool canon = n <= kCellMax;
-  if (!canon && lane == 0) set_status(S, RTS_E_CAPACITY, -1);
-  if (canon)
-    for (int k = lane; k < n; k += 64) s_idx[k] = tmp[s0 + k];
-  __syncthreads();
-  float v2m = 0.0f, a2m = 0.0f;
-  for (int k = lane; k < n; k += 64) {
-    uint32_t src = canon ? s_idx[k] : tmp[s0 + k];
-    uint32_t dst = s0 + (canon ? rank_in(s_idx, n, src) : (uint32_t)k);
-    if (src >= (uint32_t)p.n) {
-      set_status(S, RTS_E_DEVICE, -1);
+  __shared__ uint32_t s_idx_all[4][kCellMax];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t *s_idx = s_idx_all[wave];
+  const uint32_t nocc = S->n_occ;
+  for (uint32_t q = blockIdx.x * 4 + wave; q < nocc; q += gridDim.x * 4) {
+    const uint32_t b = occ[q];
+    const uint32_t s0 = start[b];
+    const uint32_t s1 = start[b + 1];
+    if (s1 <= s0 || s1 > (uint32_t)p.n) {
+      if (lane == 0) {
+        lraw[b] = kEmpty;
+        set_status(S, RTS_E_DEVICE, -1);
+      }
       continue;
     }
-    perm[dst] = src;
-    key[dst] = (uint32_t)b;
-    float4 x = Pi[src], v = Vi[src], a = Ai[src];
-    Po[dst] = x;
-    Vo[dst] = v;
-    Ao[dst] = a;
-    Mo[dst] = Mi[src];
-    Io[dst] = Ii[src];
-    v2m = fmaxf(v2m, norm2_exact(v.x, v.y, v.z));
-    a2m = fmaxf(a2m, norm2_exact(a.x, a.y, a.z));
-  }
-  v2m = wave_max(v2m);
-  a2m = wave_max(a2m);
-  if (lane == 0) {
-    // Section 3.1: the block takes the largest step whose Eq. 2 and Eq. 3
-    // bounds hold for its fastest and most accelerated particles.
-    int l = 0;
-    while (l + 1 <= p.lmax && v2m <= p.TV[l + 1] && a2m <= p.TA[l + 1]) ++l;
-    lraw[b] = (uint8_t)l;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// one wave per block: R_min, particle flags, active-list compaction
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_rmin_flags(DevParams p, const uint32_t *__restrict__ start,
-                                                  const uint8_t *__restrict__ lraw,
-                                                  uint8_t *__restrict__ lvl,
-                                                  uint32_t *__restrict__ M,
-                                                  uint32_t *__restrict__ act, DevScalars *S,
-                                                  int do_flags) {
-  const int b = blockIdx.x, lane = threadIdx.x;
-  const uint32_t own = lraw[b];
-  if (own == kEmpty) {
-    if (lane == 0) lvl[b] = kEmpty;
-    return;
-  }
-  // R_min (Section 4.2): the smaller step of any occupied neighbour wins.
-  uint32_t l = own;
-  if (lane < 27) {
-    int3 c = coords_of(p, (uint32_t)b);
-    int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
-    int x = c.x + dx, y = c.y + dy, z = c.z + dz;
-    if (x >= 0 && y >= 0 && z >= 0 && x < p.nc[0] && y < p.nc[1] && z < p.nc[2])
-      l = lraw[(uint32_t)(x + p.nc[0] * (y + p.nc[1] * z))];  // 0xFF never wins
-  } else {
-    l = 0xFFu;
-  }
-  l = min(wave_min_u32(l), own);
-  if (lane == 0) lvl[b] = (uint8_t)l;
-  if (!do_flags) return;
-  const uint32_t s0 = start[b];
-  const int n = (int)(start[b + 1] - s0);
-  for (int k0 = 0; k0 < n; k0 += 64) {
-    int k = k0 + lane;
-    bool comp = false;
-    uint32_t i = s0 + (uint32_t)k;
-    if (k < n) {
-      // Algorithm 1: decrement validity; active when it ran out or the
-      // block's step differs (pre-emption); an active particle adopts the
-      // block's step and a validity of 2^level base steps.
-      uint32_t m = M[i];
-      int32_t val = meta_validity(m) - 1;
-      uint32_t lev = meta_level(m);
-      comp = val <= 0 || lev != l;
-      if (comp) {
-        lev = l;
-        val = 1 << l;
+    const int n = (int)(s1 - s0);
+    const bool canon = n <= kCellMax;
+    if (!canon && lane == 0) set_status(S, RTS_E_CAPACITY, -1);
+    if (canon)
+      for (int k = lane; k < n; k += 64) s_idx[k] = tmp[s0 + k];
+    // the wave's LDS writes must be visible to the whole wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float v2m = 0.0f, a2m = 0.0f;
+    for (int k = lane; k < n; k += 64) {
+      const uint32_t src = canon ? s_idx[k] : tmp[s0 + k];
+      const uint32_t dst = s0 + (canon ? rank_in(s_idx, n, src) : (uint32_t)k);
+      if (src >= (uint32_t)p.n) {
+        set_status(S, RTS_E_DEVICE, -1);
+        continue;
       }
-      M[i] = meta_pack(lev, comp ? 1u : 0u, meta_age(m), val);
+      perm[dst] = src;
+      key[dst] = b;
+      const float4 x = Pi[src], v = Vi[src], a = Ai[src];
+      Po[dst] = x;
+      Vo[dst] = v;
+      Ao[dst] = a;
+      Mo[dst] = Mi[src];
+      Io[dst] = Ii[src];
+      v2m = fmaxf(v2m, norm2_exact(v.x, v.y, v.z));
+      a2m = fmaxf(a2m, norm2_exact(a.x, a.y, a.z));
     }
-    unsigned long long mask = __ballot(comp);
-    uint32_t cnt = (uint32_t)__popcll(mask);
-    uint32_t off = 0;
-    if (lane == 0 && cnt) off = atomicAdd(&S->n_act, cnt);
-    off = (uint32_t)__shfl((int)off, 0, 64);
-    if (comp) {
-      unsigned long long below = mask & ((1ull << lane) - 1ull);
-      act[off + (uint32_t)__popcll(below)] = i;
+    v2m = wave_max(v2m);
+    a2m = wave_max(a2m);
+    if (lane == 0) {
+      // Section 3.1: the block takes the largest step whose Eq. 2 and Eq. 3
+      // bounds hold for its fastest and most accelerated particles.
+      int l = 0;
+      while (l + 1 <= p.lmax && v2m <= p.TV[l + 1] && a2m <= p.TA[l + 1]) ++l;
+      lraw[b] = (uint8_t)l;
+    }
+    // s_idx is reused for the next block: all lanes must be done reading it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one wave per occupied block: R_min, particle flags, block active count
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t *__restrict__ occ,
+                                                   const uint32_t *__restrict__ start,
+                                                   const uint8_t *__restrict__ lraw,
+                                                   uint8_t *__restrict__ lvl,
+                                                   uint32_t *__restrict__ M,
+                                                   const float4 *__restrict__ P,
+                                                   uint4 *__restrict__ blku,
+                                                   float *__restrict__ blkerr, DevScalars *S,
+                                                   int do_flags) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t nocc = S->n_occ;
+  for (uint32_t q = blockIdx.x * 4 + wave; q < nocc; q += gridDim.x * 4) {
+    const uint32_t b = occ[q];
+    const uint32_t own = lraw[b];
+    // R_min (Section 4.2): the smaller step of any occupied neighbour wins.
+    uint32_t l = 0xFFu;
+    if (lane < 27) {
+      const int3 c = coords_of(p, b);
+      const int x = c.x + lane % 3 - 1, y = c.y + (lane / 3) % 3 - 1, z = c.z + lane / 9 - 1;
+      if (x >= 0 && y >= 0 && z >= 0 && x < p.nc[0] && y < p.nc[1] && z < p.nc[2])
+        l = lraw[(uint32_t)(x + p.nc[0] * (y + p.nc[1] * z))];  // 0xFF never wins
+    }
+    l = min(wave_min_u32(l), own);
+    if (lane == 0) lvl[b] = (uint8_t)l;
+    if (!do_flags) continue;
+    const uint32_t s0 = start[b];
+    const int n = (int)(start[b + 1] - s0);
+    uint32_t nact = 0;
+    float err = 0.0f;
+    for (int k0 = 0; k0 < n; k0 += 64) {
+      const int k = k0 + lane;
+      bool comp = false;
+      if (k < n) {
+        // Algorithm 1: decrement validity; active when it ran out or the
+        // block's step differs (pre-emption); an active particle adopts the
+        // block's step and a validity of 2^level base steps.
+        const uint32_t i = s0 + (uint32_t)k;
+        const uint32_t m = M[i];
+        int32_t val = meta_validity(m) - 1;
+        uint32_t lev = meta_level(m);
+        comp = val <= 0 || lev != l;
+        if (comp) {
+          lev = l;
+          val = 1 << l;
+        } else {
+          // an inactive particle keeps its last density for this step
+          err = fmaxf(err, (P[i].w - p.rho0) / p.rho0);
+        }
+        M[i] = meta_pack(lev, comp ? 1u : 0u, meta_age(m), val);
+      }
+      nact += (uint32_t)__popcll(__ballot(comp));
+    }
+    err = wave_max(err);
+    if (lane == 0) {
+      blku[b] = make_uint4(nact, 0u, 0u, (uint32_t)n << 16);
+      blkerr[b] = err;
     }
   }
-  if (lane == 0) atomicAdd(&S->hist[l], n);
 }
 
 // ---------------------------------------------------------------------------
-// neighbour search + density + Tait pressure (active particles)
+// neighbour search + density + Tait pressure, one workgroup per block
 // ---------------------------------------------------------------------------
-// Tait pressure from the density deviation d = rho/rho0 - 1, with
-// (1 + d)^7 - 1 expanded in d (gamma = 7) so that nothing cancels.
-__device__ inline float tait_from_dev(const DevParams &p, float d) {
-  float poly = 7.0f + d * (21.0f + d * (35.0f + d * (35.0f + d * (21.0f + d * (7.0f + d)))));
-  float pr = p.B * d * poly;
-  if (p.clamp_p && pr < 0.0f) pr = 0.0f;
-  return pr;
+// Combines two Kahan accumulators (true value = s - c), the rounding of the
+// sum s + s2 being carried into c.
+__device__ inline void kahan_merge(float &s, float &c, float s2, float c2) {
+  const float t = s + s2;
+  const float v = t - s;
+  const float e = (s - (t - v)) + (s2 - v);  // t + e == s + s2 exactly
+  s = t;
+  c = (c + c2) - e;
 }
 
-template <bool kWalls>
-__device__ inline void scan_rows(const DevParams &p, int3 c, uint32_t self, float xi, float yi,
-                                 float zi, const uint32_t *__restrict__ start,
-                                 const float4 *__restrict__ X, uint32_t lim, uint32_t tag,
-                                 uint32_t *__restrict__ nbr, uint32_t i, int &cnt, float &sum,
-                                 float &comp) {
-  const int x0 = max(c.x - 1, 0), x1 = min(c.x + 1, p.nc[0] - 1);
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int z = c.z + dz;
-    if (z < 0 || z >= p.nc[2]) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int y = c.y + dy;
-      if (y < 0 || y >= p.nc[1]) continue;
-      const uint32_t row = (uint32_t)p.nc[0] * ((uint32_t)y + (uint32_t)p.nc[1] * (uint32_t)z);
-      const uint32_t j0 = start[row + (uint32_t)x0];
-      const uint32_t j1 = min(start[row + (uint32_t)x1 + 1u], lim);
-      for (uint32_t j = j0; j < j1; ++j) {
-        if (!kWalls && j == self) continue;
-        float4 q = X[j];
-        float d2 = dist2_exact(xi, yi, zi, q.x, q.y, q.z);
-        if (d2 < p.r2f) {
-          if (cnt < p.kcap) nbr[(size_t)cnt * (size_t)p.ncap + i] = j | tag;
-          ++cnt;
-          float w = w_shape(sqrtf(d2) * p.inv_h);
-          // Kahan-compensated sum of W (in units of sigma)
-          float y2 = w - comp;
-          float t = sum + y2;
-          comp = (t - sum) - y2;
-          sum = t;
+__global__ void __launch_bounds__(kBlockThreads) k_search_density(
+    DevParams p, const uint32_t *__restrict__ occ, const uint32_t *__restrict__ start,
+    const uint32_t *__restrict__ wstart, float4 *__restrict__ P, float4 *__restrict__ V,
+    const uint32_t *__restrict__ M, float *__restrict__ pres, uint32_t *__restrict__ nnb,
+    uint32_t *__restrict__ mask, const float4 *__restrict__ WP, uint4 *__restrict__ blku,
+    float *__restrict__ blkerr, const uint32_t *__restrict__ ids, DevScalars *S) {
+  __shared__ float4 s_pos[kStageCap];
+  __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
+  __shared__ uint16_t s_act[kCellMax];
+  __shared__ uint32_t s_nact;
+  __shared__ float s_err[kBlockThreads / 64];
+  __shared__ uint32_t s_inter[kBlockThreads / 64], s_nmax[kBlockThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sub = tid & (kSub - 1);
+  const uint32_t nocc = S->n_occ;
+  for (uint32_t q = blockIdx.x; q < nocc; q += gridDim.x) {
+    const uint32_t b = occ[q];
+    if (blku[b].x == 0) continue;  // no active particle: nothing to evaluate
+    const uint32_t s0 = start[b];
+    const int n = min((int)(start[b + 1] - s0), kCellMax);
+    if (tid == 0) s_nact = 0;
+    block_ranges_shared(p, start, wstart, b, s_rs, s_ro, s_len);
+    // active particles of the block (their order here does not matter)
+    for (int k = tid; k < n; k += kBlockThreads)
+      if (meta_compute(M[s0 + (uint32_t)k])) s_act[atomicAdd(&s_nact, 1u)] = (uint16_t)k;
+    __syncthreads();
+    const uint32_t nact = s_nact;
+    const uint32_t C = s_ro[18];
+    const uint32_t cpad = (C + 32u * kSub - 1u) / (32u * kSub) * (32u * kSub);
+    const bool staged = cpad <= (uint32_t)kStageCap;
+    if (staged) stage_positions(s_rs, s_ro, P, WP, s_pos, cpad);
+    __syncthreads();
+    const uint32_t self_off = s_ro[4] - s_rs[4];  // local index = sorted index + self_off
+    const uint32_t nslot = (C + kSub - 1) / kSub;     // candidate slots per lane
+    const uint32_t nwords = (nslot + 31) / 32;
+    if (nwords > (uint32_t)p.wpl) {
+      if (tid == 0 && nact > 0) set_status(S, RTS_E_CAPACITY, (int32_t)ids[s0]);
+    }
+    float err = 0.0f;
+    uint32_t inter = 0, nmax = 0;
+    for (uint32_t c0 = 0; c0 < nact && nwords <= (uint32_t)p.wpl; c0 += kPartPerPass) {
+      if (c0 + (uint32_t)(wave * (64 / kSub)) >= nact) break;  // no particle for this wave
+      const uint32_t slot = c0 + (uint32_t)(tid / kSub);
+      const bool live = slot < nact;
+      const uint32_t i = s0 + (live ? (uint32_t)s_act[slot] : 0u);
+      const float4 xi = P[i];
+      const uint32_t selfk = i + self_off;
+      // this lane's words: word w of lane `sub` at mrow[kSub * w]
+      uint32_t *mrow = mask + (size_t)i * (size_t)(kSub * p.wpl) + (size_t)sub;
+      uint32_t cnt = 0;
+      // pass 1: the neighbour predicate over this lane's candidates
+      // k = sub + kSub * m, one bit per candidate, 32 candidates per word
+      for (uint32_t w = 0; w < nwords; ++w) {
+        uint32_t bits = 0;
+        if (staged) {
+          // candidates past C are padded far away in shared memory
+#pragma unroll
+          for (uint32_t t = 0; t < 32; ++t) {
+            const float4 qj = s_pos[(uint32_t)sub + kSub * (32u * w + t)];
+            const float d2 = dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z);
+            bits |= d2 < p.r2f ? (1u << t) : 0u;
+          }
+        } else {
+          for (uint32_t t = 0; t < 32; ++t) {
+            const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
+            if (k >= C) break;
+            bool wall;
+            const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
+            const float4 qj = wall ? WP[j] : P[j];
+            const float d2 = dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z);
+            bits |= d2 < p.r2f ? (1u << t) : 0u;
+          }
+        }
+        if ((selfk & (kSub - 1)) == (uint32_t)sub && (selfk / kSub) / 32u == w)
+          bits &= ~(1u << ((selfk / kSub) & 31u));  // a particle is not its own neighbour
+        if (live) mrow[kSub * w] = bits;
+        cnt += (uint32_t)__popc(bits);
+      }
+      if (!live) cnt = 0;
+      // pass 2: density over this lane's hits, walking the set bits in order
+      // (Kahan-compensated sum of the kernel shape)
+      float sum = 0.0f, comp = 0.0f;
+      {
+        // walk the set bits word by word, the next word always in flight
+        uint32_t w = 0;
+        uint32_t bits = (live && nwords) ? mrow[0] : 0u;
+        uint32_t nxt = (live && nwords > 1u) ? mrow[kSub] : 0u;
+        for (uint32_t e = 0; e < cnt; ++e) {
+          while (bits == 0u) {
+            bits = nxt;
+            ++w;
+            nxt = (w + 1u < nwords) ? mrow[kSub * (w + 1u)] : 0u;
+          }
+          const uint32_t t = (uint32_t)(__ffs(bits) - 1);
+          bits &= bits - 1u;
+          const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
+          float4 qj;
+          if (staged) {
+            qj = s_pos[k];
+          } else {
+            bool wall;
+            const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
+            qj = wall ? WP[j] : P[j];
+          }
+          const float d2 = dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z);
+          const float wk = w_shape(__builtin_amdgcn_sqrtf(d2) * p.inv_h);
+          const float y2 = wk - comp;
+          const float tt = sum + y2;
+          comp = (tt - sum) - y2;
+          sum = tt;
         }
       }
+      // the kSub lanes of a particle are adjacent: merge sums and counts
+      uint32_t total = cnt;
+      for (int o = 1; o < kSub; o <<= 1) {
+        const float s2 = __shfl_xor(sum, o, 64), c2 = __shfl_xor(comp, o, 64);
+        kahan_merge(sum, comp, s2, c2);
+        total += (uint32_t)__shfl_xor((int)total, o, 64);
+      }
+      if (live && sub == 0) {
+        // rho/rho0 - 1 = (m sigma / rho0) (sum - C) with C = rho0/(m sigma) - 1,
+        // sum = neighbour sum of the kernel shape (self excluded), carried as
+        // sum - comp; the difference is formed before any rounding to rho.
+        const float dev = p.kms * ((sum - p.c_hi) - (comp + p.c_lo));
+        const float rho = p.rho0 + p.rho0 * dev;
+        const float pr = tait_from_dev(p, dev);
+        reinterpret_cast<float *>(&P[i])[3] = rho;
+        reinterpret_cast<float *>(&V[i])[3] = pr / (rho * rho);
+        pres[i] = pr;
+        nnb[i] = total;
+        err = fmaxf(err, dev);
+        inter += total;
+        nmax = max(nmax, total);
+      }
     }
-  }
-}
-
-__global__ void __launch_bounds__(256) k_search_density(
-    DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ key,
-    const uint32_t *__restrict__ start, float4 *__restrict__ P, float4 *__restrict__ V,
-    float *__restrict__ pres, uint32_t *__restrict__ nnb, uint32_t *__restrict__ nbr,
-    const uint32_t *__restrict__ wstart, const float4 *__restrict__ WP,
-    const uint32_t *__restrict__ ids, DevScalars *S) {
-  const uint32_t nact = S->n_act;
-  const int lane = threadIdx.x & 63;
-  uint32_t inter = 0, cmax = 0;
-  for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x;
-       slot - lane < nact;  // whole waves iterate together
-       slot += gridDim.x * blockDim.x) {
-    const bool live = slot < nact;
-    if (live) {
-      const uint32_t i = act[slot];
-      const float4 xi = P[i];
-      const int3 c = coords_of(p, key[i]);
-      int cnt = 0;
-      float sum = 0.0f, comp = 0.0f;
-      scan_rows<false>(p, c, i, xi.x, xi.y, xi.z, start, P, (uint32_t)p.n, 0u, nbr, i, cnt, sum,
-                       comp);
-      if (p.nw > 0)
-        scan_rows<true>(p, c, 0xFFFFFFFFu, xi.x, xi.y, xi.z, wstart, WP, (uint32_t)p.nw, kWallBit,
-                        nbr, i, cnt, sum, comp);
-      if (cnt > p.kcap) set_status(S, RTS_E_CAPACITY, (int32_t)ids[i]);
-      // rho/rho0 - 1 = (m sigma / rho0) (sum - C) with C = rho0/(m sigma) - 1,
-      // sum = neighbour sum of the kernel shape (self excluded), carried as
-      // sum - comp; the difference is formed before any rounding to rho.
-      const float dev = p.kms * ((sum - p.c_hi) - (comp + p.c_lo));
-      const float rho = p.rho0 + p.rho0 * dev;
-      const float pr = tait_from_dev(p, dev);
-      reinterpret_cast<float *>(&P[i])[3] = rho;
-      reinterpret_cast<float *>(&V[i])[3] = pr / (rho * rho);
-      pres[i] = pr;
-      nnb[i] = (uint32_t)min(cnt, p.kcap);
-      inter += (uint32_t)cnt;
-      cmax = max(cmax, (uint32_t)cnt);
+    err = wave_max(err);
+    inter = wave_sum_u32(inter);
+    nmax = wave_max_u32(nmax);
+    if (lane == 0) {
+      s_err[wave] = err;
+      s_inter[wave] = inter;
+      s_nmax[wave] = nmax;
     }
-  }
-  inter = wave_sum_u32(inter);
-  cmax = wave_max_u32(cmax);
-  if (lane == 0) {
-    if (inter) atomicAdd(&S->inter_last, (unsigned long long)inter);
-    atomicMax(&S->nbr_max, cmax);
+    __syncthreads();
+    if (tid == 0) {
+      float e = blkerr[b];  // inactive particles, from the flags pass
+      uint32_t it = 0, nm = 0;
+      for (int w = 0; w < kBlockThreads / 64; ++w) {
+        e = fmaxf(e, s_err[w]);
+        it += s_inter[w];
+        nm = max(nm, s_nmax[w]);
+      }
+      blku[b] = make_uint4(nact, it, nact * C, nm | ((uint32_t)n << 16));
+      blkerr[b] = e;
+    }
+    __syncthreads();  // shared memory is reused by the next block
   }
 }
 
 // ---------------------------------------------------------------------------
-// forces (active particles)
+// forces, one workgroup per block
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_force(DevParams p, const uint32_t *__restrict__ act,
-                                              const float4 *__restrict__ P,
-                                              const float4 *__restrict__ V,
-                                              const uint32_t *__restrict__ nnb,
-                                              const uint32_t *__restrict__ nbr,
-                                              const float4 *__restrict__ WP,
-                                              float4 *__restrict__ anew, DevScalars *S) {
-  const uint32_t nact = S->n_act;
-  const int lane = threadIdx.x & 63;
-  float a2max = 0.0f;
+__global__ void __launch_bounds__(kForceThreads) k_force(
+    DevParams p, const uint32_t *__restrict__ occ, const uint32_t *__restrict__ start,
+    const uint32_t *__restrict__ wstart, const float4 *__restrict__ P,
+    const float4 *__restrict__ V, const uint32_t *__restrict__ M,
+    const uint32_t *__restrict__ nnb, const uint32_t *__restrict__ mask,
+    const float4 *__restrict__ WP, float4 *__restrict__ anew, const uint4 *__restrict__ blku,
+    float *__restrict__ blkamax, DevScalars *S) {
+  __shared__ float4 s_p[kForceCap];
+  __shared__ float4 s_v[kForceCap];
+  __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
+  __shared__ uint16_t s_act[kCellMax];
+  __shared__ uint32_t s_nact;
+  __shared__ float s_amax[kForceThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sub = tid & (kSub - 1);
   const float coefg = p.sigma * p.inv_h;  // dW/dr = sigma / h * w'(q)
-  for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x; slot - lane < nact;
-       slot += gridDim.x * blockDim.x) {
-    if (slot < nact) {
-      const uint32_t i = act[slot];
+  const uint32_t nocc = S->n_occ;
+  for (uint32_t q = blockIdx.x; q < nocc; q += gridDim.x) {
+    const uint32_t b = occ[q];
+    if (blku[b].x == 0) {  // no active particle in this block
+      if (tid == 0) blkamax[b] = 0.0f;
+      continue;
+    }
+    const uint32_t s0 = start[b];
+    const int n = min((int)(start[b + 1] - s0), kCellMax);
+    if (tid == 0) s_nact = 0;
+    block_ranges_shared(p, start, wstart, b, s_rs, s_ro, s_len);
+    for (int k = tid; k < n; k += kForceThreads)
+      if (meta_compute(M[s0 + (uint32_t)k])) s_act[atomicAdd(&s_nact, 1u)] = (uint16_t)k;
+    __syncthreads();
+    const uint32_t nact = s_nact;
+    const uint32_t C = s_ro[18], Cf = s_ro[9];
+    const uint32_t nwords = ((C + kSub - 1) / kSub + 31) / 32;
+    const bool staged = C <= (uint32_t)kForceCap;
+    if (staged) {
+      constexpr int kPer = (kForceCap + kForceThreads - 1) / kForceThreads;
+      uint32_t src[kPer];
+      float4 buf[kPer];
+      // positions (walls included), then velocities: all loads of a phase
+      // are issued before its shared-memory writes
+#pragma unroll
+      for (int it = 0; it < kPer; ++it) {
+        const uint32_t k = (uint32_t)tid + (uint32_t)it * kForceThreads;
+        src[it] = 0xFFFFFFFFu;
+        if (k < C) {
+          bool wall;
+          const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
+          buf[it] = wall ? WP[j] : P[j];
+          src[it] = wall ? 0xFFFFFFFFu : j;
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < kPer; ++it) {
+        const uint32_t k = (uint32_t)tid + (uint32_t)it * kForceThreads;
+        if (k < C) s_p[k] = buf[it];
+      }
+#pragma unroll
+      for (int it = 0; it < kPer; ++it)
+        if (src[it] != 0xFFFFFFFFu) buf[it] = V[src[it]];
+#pragma unroll
+      for (int it = 0; it < kPer; ++it) {
+        const uint32_t k = (uint32_t)tid + (uint32_t)it * kForceThreads;
+        if (src[it] != 0xFFFFFFFFu) s_v[k] = buf[it];
+      }
+    }
+    __syncthreads();
+    float a2max = 0.0f;
+    for (uint32_t c0 = 0; c0 < nact && nwords <= (uint32_t)p.wpl; c0 += kForcePerPass) {
+      if (c0 + (uint32_t)(wave * (64 / kSub)) >= nact) break;
+      const uint32_t slot = c0 + (uint32_t)(tid / kSub);
+      const bool live = slot < nact;
+      const uint32_t i = s0 + (live ? (uint32_t)s_act[slot] : 0u);
       const float4 pi = P[i], vi = V[i];
       const float rhoi = pi.w, pri = vi.w;
+      const float inv_rhoi = __builtin_amdgcn_rcpf(rhoi);
       float ax = 0.0f, ay = 0.0f, az = 0.0f;
-      const int cnt = (int)nnb[i];
-      for (int k = 0; k < cnt; ++k) {
-        const uint32_t j = nbr[(size_t)k * (size_t)p.ncap + i];
-        float xj, yj, zj, vxj, vyj, vzj, rhoj, prj;
-        if (j & kWallBit) {
-          // static wall particle: at rest, density mirrored, pressure mirrored
-          // plus the hydrostatic difference, clamped at zero
-          const float4 q = WP[j & ~kWallBit];
-          xj = q.x; yj = q.y; zj = q.z;
-          vxj = vyj = vzj = 0.0f;
-          rhoj = rhoi;
-          const float gd = p.g[0] * (xj - pi.x) + p.g[1] * (yj - pi.y) + p.g[2] * (zj - pi.z);
-          prj = fmaxf(pri + gd / rhoi, 0.0f);
-        } else {
-          const float4 q = P[j], u = V[j];
-          xj = q.x; yj = q.y; zj = q.z; rhoj = q.w;
-          vxj = u.x; vyj = u.y; vzj = u.z; prj = u.w;
+      const uint32_t *mrow = mask + (size_t)i * (size_t)(kSub * p.wpl) + (size_t)sub;
+      // walk the set bits word by word, the next word always in flight
+      uint32_t w = 0;
+      const uint32_t left = live ? nwords : 0u;
+      uint32_t bits = left ? mrow[0] : 0u;
+      uint32_t nxt = left > 1u ? mrow[kSub] : 0u;
+      while (true) {
+        while (bits == 0u && w + 1u < left) {
+          bits = nxt;
+          ++w;
+          nxt = (w + 1u < left) ? mrow[kSub * (w + 1u)] : 0u;
         }
-        const float dx = pi.x - xj, dy = pi.y - yj, dz = pi.z - zj;
+        if (bits == 0u) break;
+        const uint32_t t = (uint32_t)(__ffs(bits) - 1);
+        bits &= bits - 1u;
+        const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
+        float4 qj, uj;
+        const bool wall = k >= Cf;
+        if (staged) {
+          qj = s_p[k];
+          uj = wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : s_v[k];
+        } else {
+          bool w2;
+          const uint32_t j = local_to_global(s_rs, s_ro, k, w2);
+          qj = wall ? WP[j] : P[j];
+          uj = wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[j];
+        }
+        // a static wall particle is at rest and mirrors the density and the
+        // pressure of the fluid particle, plus the hydrostatic difference,
+        // clamped at zero
+        const float gd = p.g[0] * (qj.x - pi.x) + p.g[1] * (qj.y - pi.y) + p.g[2] * (qj.z - pi.z);
+        const float rhoj = wall ? rhoi : qj.w;
+        const float prj = wall ? fmaxf(pri + gd * inv_rhoi, 0.0f) : uj.w;
+        const float dx = pi.x - qj.x, dy = pi.y - qj.y, dz = pi.z - qj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 <= 0.0f) continue;
-        const float rinv = rsqrtf(r2);
+        const float rinv = __builtin_amdgcn_rsqf(r2);
         const float r = r2 * rinv;
         const float f = coefg * dw_shape(r * p.inv_h) * rinv;  // gradW = f * x_ij
-        float coef = pri + prj;
-        const float vx = (vi.x - vxj) * dx + (vi.y - vyj) * dy + (vi.z - vzj) * dz;
-        if (vx < 0.0f) {
-          const float nu = p.visc_num / (rhoi + rhoj);
-          coef -= nu * vx / (r2 + p.visc_eps_h2);
-        }
-        const float s = -p.mass * coef * f;
-        ax += s * dx;
-        ay += s * dy;
-        az += s * dz;
+        const float vx = (vi.x - uj.x) * dx + (vi.y - uj.y) * dy + (vi.z - uj.z) * dz;
+        // artificial viscosity -nu vx / (r^2 + eps h^2), nu = 2 alpha h c0 / (rho_i + rho_j)
+        const float visc = -p.visc_num * vx *
+                           __builtin_amdgcn_rcpf((rhoi + rhoj) * (r2 + p.visc_eps_h2));
+        const float coef = pri + prj + (vx < 0.0f ? visc : 0.0f);
+        const float sc = r2 > 0.0f ? -p.mass * coef * f : 0.0f;
+        ax += sc * dx;
+        ay += sc * dy;
+        az += sc * dz;
       }
-      ax += p.g[0];
-      ay += p.g[1];
-      az += p.g[2];
-      anew[i] = make_float4(ax, ay, az, 0.0f);
-      a2max = fmaxf(a2max, ax * ax + ay * ay + az * az);
+      for (int o = 1; o < kSub; o <<= 1) {
+        ax += __shfl_xor(ax, o, 64);
+        ay += __shfl_xor(ay, o, 64);
+        az += __shfl_xor(az, o, 64);
+      }
+      if (live && sub == 0) {
+        ax += p.g[0];
+        ay += p.g[1];
+        az += p.g[2];
+        anew[i] = make_float4(ax, ay, az, 0.0f);
+        a2max = fmaxf(a2max, ax * ax + ay * ay + az * az);
+      }
+    }
+    a2max = wave_max(a2max);
+    if (lane == 0) s_amax[wave] = a2max;
+    __syncthreads();
+    if (tid == 0) {
+      float m = 0.0f;
+      for (int w2 = 0; w2 < kForceThreads / 64; ++w2) m = fmaxf(m, s_amax[w2]);
+      blkamax[b] = m;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-step statistics and the step length (kStatBlocks workgroups; the last
+// one to finish folds the partials)
+// ---------------------------------------------------------------------------
+__device__ inline void part_add(StatPart &t, const StatPart &u) {
+  t.act += u.act;
+  t.inter += u.inter;
+  t.cand += u.cand;
+  t.nmax = max(t.nmax, u.nmax);
+  t.err = fmaxf(t.err, u.err);
+  t.amax2 = fmaxf(t.amax2, u.amax2);
+  for (int k = 0; k < kMaxLevels; ++k) t.hist[k] += u.hist[k];
+}
+
+__global__ void __launch_bounds__(256) k_step_stats(DevParams p, const uint32_t *__restrict__ occ,
+                                                   const uint4 *__restrict__ blku,
+                                                   const float *__restrict__ blkerr,
+                                                   const float *__restrict__ blkamax,
+                                                   const uint8_t *__restrict__ lvl,
+                                                   StatPart *__restrict__ part, DevCtrl *ctrl,
+                                                   DevScalars *S) {
+  __shared__ StatPart s_w[4];
+  __shared__ uint32_t s_last;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t nocc = S->n_occ;
+  StatPart t = {};
+  for (uint32_t q = blockIdx.x * blockDim.x + tid; q < nocc; q += gridDim.x * blockDim.x) {
+    const uint32_t b = occ[q];
+    const uint4 u = blku[b];
+    t.act += u.x;
+    t.inter += u.y;
+    t.cand += u.z;
+    t.nmax = max(t.nmax, u.w & 0xFFFFu);
+    t.err = fmaxf(t.err, blkerr[b]);
+    t.amax2 = fmaxf(t.amax2, blkamax[b]);
+    const uint32_t l = lvl[b];
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k)
+      t.hist[k] += (l == (uint32_t)k) ? (int32_t)(u.w >> 16) : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    t.act += __shfl_xor(t.act, o, 64);
+    t.inter += __shfl_xor(t.inter, o, 64);
+    t.cand += __shfl_xor(t.cand, o, 64);
+    t.nmax = max(t.nmax, (uint32_t)__shfl_xor((int)t.nmax, o, 64));
+    t.err = fmaxf(t.err, __shfl_xor(t.err, o, 64));
+    t.amax2 = fmaxf(t.amax2, __shfl_xor(t.amax2, o, 64));
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) t.hist[k] += __shfl_xor(t.hist[k], o, 64);
+  }
+  if (lane == 0) s_w[wave] = t;
+  __syncthreads();
+  if (tid == 0) {
+    StatPart w = s_w[0];
+    for (int k = 1; k < 4; ++k) part_add(w, s_w[k]);
+    part[blockIdx.x] = w;
+    __threadfence();
+    s_last = atomicAdd(&ctrl->stats_ticket, 1u) == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_last || wave != 0) return;
+  __threadfence();
+  // one wave folds the partials: lane g reads partial g
+  StatPart a = {};
+  for (unsigned g = (unsigned)lane; g < gridDim.x; g += 64) part_add(a, part[g]);
+  for (int o = 32; o > 0; o >>= 1) {
+    a.act += __shfl_xor(a.act, o, 64);
+    a.inter += __shfl_xor(a.inter, o, 64);
+    a.cand += __shfl_xor(a.cand, o, 64);
+    a.nmax = max(a.nmax, (uint32_t)__shfl_xor((int)a.nmax, o, 64));
+    a.err = fmaxf(a.err, __shfl_xor(a.err, o, 64));
+    a.amax2 = fmaxf(a.amax2, __shfl_xor(a.amax2, o, 64));
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) a.hist[k] += __shfl_xor(a.hist[k], o, 64);
+  }
+  if (lane != 0) return;
+  S->n_act = (uint32_t)a.act;
+  S->inter_last = a.inter;
+  S->cand_last = a.cand;
+  S->active_total += a.act;
+  S->inter_total += a.inter;
+  S->cand_total += a.cand;
+  S->nbr_max = max(S->nbr_max, a.nmax);
+  S->err_last = a.err;
+  S->err_run = fmaxf(S->err_run, a.err);
+  S->amax2 = a.amax2;
+  for (int k = 0; k < kMaxLevels; ++k) S->hist[k] = a.hist[k];
+  // the step length: fixed, or the adaptive comparator's
+  double dtd = p.dt_base;
+  if (p.mode == RTS_MODE_GLOBAL_ADAPTIVE) {
+    dtd = p.dt_cfl;
+    if (a.amax2 > 0.0f) {
+      const double df = sqrt(p.lf2r / sqrt((double)a.amax2));
+      if (df < dtd) dtd = df;
     }
   }
-  a2max = wave_max(a2max);
-  if (lane == 0 && a2max > 0.0f) atomicMax(&S->amax2_bits, __float_as_uint(a2max));
+  S->dt_next = dtd;
+  S->time += dtd;
+  S->step += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -554,75 +984,49 @@ __global__ void __launch_bounds__(256) k_correct_predict(DevParams p, float4 *__
                                                         float4 *__restrict__ A,
                                                         uint32_t *__restrict__ M,
                                                         const float4 *__restrict__ anew,
-                                                        DevScalars *S) {
+                                                        const DevScalars *__restrict__ S) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  // step length: fixed, or the adaptive comparator's
-  double dtd = p.dt_base;
-  if (p.mode == RTS_MODE_GLOBAL_ADAPTIVE) {
-    dtd = p.dt_cfl;
-    const float a2 = __uint_as_float(S->amax2_bits);
-    if (a2 > 0.0f) {
-      const double df = sqrt(p.lf2r / sqrt((double)a2));
-      if (df < dtd) dtd = df;
+  if (i >= p.n) return;
+  const float dt = (float)S->dt_next;
+  float4 x = P[i], v = V[i], a = A[i];
+  const uint32_t m = M[i];
+  uint32_t age = meta_age(m);
+  if (meta_compute(m)) {
+    const float4 an = anew[i];
+    if (p.serna_correct) {
+      const float dtau =
+          p.mode == RTS_MODE_GLOBAL_ADAPTIVE ? (float)S->dt_prev : (float)age * p.dt_base;
+      const float cx = dtau * dtau * (1.0f / 6.0f), cv = dtau * 0.5f;
+      const float dax = an.x - a.x, day = an.y - a.y, daz = an.z - a.z;
+      x.x += dax * cx; x.y += day * cx; x.z += daz * cx;
+      v.x += dax * cv; v.y += day * cv; v.z += daz * cv;
     }
+    a.x = an.x; a.y = an.y; a.z = an.z;
+    age = 0;
   }
-  const float dt = (float)dtd;
-  float err = 0.0f;
-  if (i < p.n) {
-    float4 x = P[i], v = V[i], a = A[i];
-    uint32_t m = M[i];
-    uint32_t age = meta_age(m);
-    if (meta_compute(m)) {
-      const float4 an = anew[i];
-      if (p.serna_correct) {
-        const float dtau = p.mode == RTS_MODE_GLOBAL_ADAPTIVE ? (float)S->dt_prev
-                                                              : (float)age * p.dt_base;
-        const float cx = dtau * dtau * (1.0f / 6.0f), cv = dtau * 0.5f;
-        const float dax = an.x - a.x, day = an.y - a.y, daz = an.z - a.z;
-        x.x += dax * cx; x.y += day * cx; x.z += daz * cx;
-        v.x += dax * cv; v.y += day * cv; v.z += daz * cv;
-      }
-      a.x = an.x; a.y = an.y; a.z = an.z;
-      age = 0;
-    }
-    const float h2 = 0.5f * dt * dt;
-    x.x += v.x * dt + a.x * h2;
-    x.y += v.y * dt + a.y * h2;
-    x.z += v.z * dt + a.z * h2;
-    v.x += a.x * dt;
-    v.y += a.y * dt;
-    v.z += a.z * dt;
-    age = min(age + 1u, 0x7FFu);
-    P[i] = x;
-    V[i] = v;
-    A[i] = a;
-    M[i] = meta_pack(meta_level(m), meta_compute(m), age, meta_validity(m));
-    err = fmaxf((x.w - p.rho0) / p.rho0, 0.0f);
-  }
-  err = wave_max(err);
-  if (lane == 0 && err > 0.0f) {
-    atomicMax(&S->err_bits_last, __float_as_uint(err));
-    atomicMax(&S->err_bits_run, __float_as_uint(err));
-  }
-  if (i == 0) {
-    S->dt_next = dtd;
-    S->time += dtd;
-    S->step += 1;
-    S->active_total += S->n_act;
-    S->inter_total += S->inter_last;
-  }
+  const float h2 = 0.5f * dt * dt;
+  x.x += v.x * dt + a.x * h2;
+  x.y += v.y * dt + a.y * h2;
+  x.z += v.z * dt + a.z * h2;
+  v.x += a.x * dt;
+  v.y += a.y * dt;
+  v.z += a.z * dt;
+  age = min(age + 1u, 0x7FFu);
+  P[i] = x;
+  V[i] = v;
+  A[i] = a;
+  M[i] = meta_pack(meta_level(m), meta_compute(m), age, meta_validity(m));
 }
 
 // ---------------------------------------------------------------------------
-// state in / out, walls
+// state in / out, walls, debug views
 // ---------------------------------------------------------------------------
 __global__ void k_set_state(DevParams p, const float *__restrict__ pos,
                             const float *__restrict__ vel, float4 *P, float4 *V, float4 *A,
                             uint32_t *M, uint32_t *ID, float *pres) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
-  size_t n = (size_t)p.n;
+  const size_t n = (size_t)p.n;
   P[i] = make_float4(pos[i], pos[n + i], pos[2 * n + i], p.rho0);
   V[i] = vel ? make_float4(vel[i], vel[n + i], vel[2 * n + i], 0.0f)
              : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -633,27 +1037,62 @@ __global__ void k_set_state(DevParams p, const float *__restrict__ pos,
 }
 
 __global__ void k_get_state(DevParams p, const float4 *P, const float4 *V, const float4 *A,
-                            const uint32_t *M, const uint32_t *ID, const float *pres, float *pos,
-                            float *vel, float *acc, float *rho, float *po, uint8_t *level) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+                            const uint32_t *M, const uint32_t *ID, float *pos, float *vel,
+                            float *acc, float *rho, float *po, uint8_t *level) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
-  size_t n = (size_t)p.n;
-  uint32_t c = ID[i];
-  float4 x = P[i];
+  const size_t n = (size_t)p.n;
+  const uint32_t c = ID[i];
+  const float4 x = P[i];
   if (pos) { pos[c] = x.x; pos[n + c] = x.y; pos[2 * n + c] = x.z; }
-  if (vel) { float4 v = V[i]; vel[c] = v.x; vel[n + c] = v.y; vel[2 * n + c] = v.z; }
-  if (acc) { float4 a = A[i]; acc[c] = a.x; acc[n + c] = a.y; acc[2 * n + c] = a.z; }
+  if (vel) { const float4 v = V[i]; vel[c] = v.x; vel[n + c] = v.y; vel[2 * n + c] = v.z; }
+  if (acc) { const float4 a = A[i]; acc[c] = a.x; acc[n + c] = a.y; acc[2 * n + c] = a.z; }
   if (rho) rho[c] = x.w;
   if (po) po[c] = V[i].w * x.w * x.w;  // V.w holds p / rho^2
   if (level) level[c] = (uint8_t)meta_level(M[i]);
 }
 
+// Canonical global neighbour lists of the last step's active particles:
+// out[i * kDebugRow + e] = fluid sorted index, or wall sorted index | bit 31.
+__global__ void k_debug_lists(DevParams p, const uint32_t *key, const uint32_t *start,
+                              const uint32_t *wstart, const uint32_t *M, const uint32_t *mask,
+                              uint32_t *out, uint32_t *out_n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  if (!meta_compute(M[i])) {
+    out_n[i] = 0;
+    return;
+  }
+  uint32_t rs[18], ro[19];
+  const int3 c = coords_of(p, key[i]);
+  uint32_t acc = 0;
+  for (int r = 0; r < 18; ++r) {
+    uint32_t len;
+    row_range(p, start, wstart, c, r, rs[r], len);
+    ro[r] = acc;
+    acc += len;
+  }
+  ro[18] = acc;
+  const uint32_t C = acc;
+  const uint32_t *row = mask + (size_t)i * (size_t)(kSub * p.wpl);
+  uint32_t e = 0;
+  for (uint32_t k = 0; k < C && ((k / kSub) / 32u) < (uint32_t)p.wpl; ++k) {
+    const uint32_t sub = k % kSub, m = k / kSub;
+    if (!((row[kSub * (m / 32u) + sub] >> (m & 31u)) & 1u)) continue;
+    bool wall;
+    const uint32_t j = local_to_global(rs, ro, k, wall);
+    if (e < (uint32_t)RTS_DEBUG_NBR_ROW) out[(size_t)i * RTS_DEBUG_NBR_ROW + e] = wall ? (j | kWallBit) : j;
+    ++e;
+  }
+  out_n[i] = e;
+}
+
 __global__ void k_wall_keys(DevParams p, const float *__restrict__ pos, uint32_t *wkey,
                             uint32_t *wrank, uint32_t *count) {
-  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= p.nw) return;
-  size_t n = (size_t)p.nw;
-  uint32_t k = key_of(p, block_of(p, pos[w], pos[n + w], pos[2 * n + w]));
+  const size_t n = (size_t)p.nw;
+  const uint32_t k = key_of(p, block_of(p, pos[w], pos[n + w], pos[2 * n + w]));
   wkey[w] = k;
   wrank[w] = atomicAdd(&count[k], 1u);
 }
@@ -676,10 +1115,10 @@ __global__ void __launch_bounds__(64) k_wall_gather(DevParams p, const uint32_t 
   if (canon)
     for (int k = lane; k < n; k += 64) s_idx[k] = tmp[s0 + k];
   __syncthreads();
-  size_t nw = (size_t)p.nw;
+  const size_t nw = (size_t)p.nw;
   for (int k = lane; k < n; k += 64) {
-    uint32_t src = canon ? s_idx[k] : tmp[s0 + k];
-    uint32_t dst = s0 + (canon ? rank_in(s_idx, n, src) : (uint32_t)k);
+    const uint32_t src = canon ? s_idx[k] : tmp[s0 + k];
+    const uint32_t dst = s0 + (canon ? rank_in(s_idx, n, src) : (uint32_t)k);
     if (src >= (uint32_t)p.nw) {
       set_status(S, RTS_E_DEVICE, -1);
       continue;
@@ -707,41 +1146,53 @@ void launch_key_hist(const DevParams &p, const DevPtrs &d, int cur, hipStream_t 
 void launch_prep_scan(DevCtrl *ctrl, hipStream_t st) {
   hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(1), 0, st, ctrl);
 }
-void launch_scan(const DevParams &p, uint32_t *count, uint32_t *start, int nb,
-                 unsigned long long *tiles, DevCtrl *ctrl, DevScalars *S, hipStream_t st) {
-  (void)p;
-  hipLaunchKernelGGL(k_scan, dim3(blocks_for(nb, kScanTile)), dim3(256), 0, st, count, start, nb,
-                     tiles, ctrl, S);
+void launch_scan(const DevParams &p, const DevPtrs &d, uint32_t *start, bool fluid,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(blocks_for(p.nb, kScanTile)), dim3(256), 0, st, d.COUNT, start,
+                     p.nb, d.TILES, d.TILES2, fluid ? d.OCC : nullptr, d.LRAW, d.LVL, d.CTRL,
+                     d.S);
 }
 void launch_scatter(const DevParams &p, const DevPtrs &d, hipStream_t st) {
   if (p.n == 0) return;
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p.n, d.KEYOLD,
                      d.RANK, d.CELL_START, d.TMP, d.S);
 }
-void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
-  int nx = cur ^ 1;
-  hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)p.nb), dim3(64), 0, st, p, d.CELL_START, d.TMP,
-                     d.PERM, d.KEY, d.P[cur], d.V[cur], d.A[cur], d.M[cur], d.ID[cur], d.P[nx],
-                     d.V[nx], d.A[nx], d.M[nx], d.ID[nx], d.LRAW, d.S);
+void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st) {
+  const int nx = cur ^ 1;
+  hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)grid), dim3(256), 0, st, p, d.OCC,
+                     d.CELL_START, d.TMP, d.PERM, d.KEY, d.P[cur], d.V[cur], d.A[cur], d.M[cur],
+                     d.ID[cur], d.P[nx], d.V[nx], d.A[nx], d.M[nx], d.ID[nx], d.LRAW, d.S);
 }
-void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags,
+void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags, int grid,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_rmin_flags, dim3((unsigned)p.nb), dim3(64), 0, st, p, d.CELL_START,
-                     d.LRAW, d.LVL, d.M[cur], d.ACT, d.S, do_flags);
+  hipLaunchKernelGGL(k_rmin_flags, dim3((unsigned)grid), dim3(256), 0, st, p, d.OCC, d.CELL_START,
+                     d.LRAW, d.LVL, d.M[cur], d.P[cur], d.BLKU, d.BLKERR, d.S, do_flags);
 }
 void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_search_density, dim3((unsigned)grid), dim3(256), 0, st, p, d.ACT, d.KEY,
-                     d.CELL_START, d.P[cur], d.V[cur], d.PRES, d.NNB, d.NBR, d.WCELL_START, d.WP,
-                     d.ID[cur], d.S);
+  hipLaunchKernelGGL(k_search_density, dim3((unsigned)grid), dim3(kBlockThreads), 0, st, p, d.OCC,
+                     d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.PRES, d.NNB,
+                     d.MASK, d.WP, d.BLKU, d.BLKERR, d.ID[cur], d.S);
 }
 void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_force, dim3((unsigned)grid), dim3(256), 0, st, p, d.ACT, d.P[cur],
-                     d.V[cur], d.NNB, d.NBR, d.WP, d.ANEW, d.S);
+  hipLaunchKernelGGL(k_force, dim3((unsigned)grid), dim3(kForceThreads), 0, st, p, d.OCC,
+                     d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.NNB, d.MASK,
+                     d.WP, d.ANEW, d.BLKU, d.BLKAMAX, d.S);
+}
+void launch_step_stats(const DevParams &p, const DevPtrs &d, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_stats, dim3(kStatBlocks), dim3(256), 0, st, p, d.OCC, d.BLKU,
+                     d.BLKERR, d.BLKAMAX, d.LVL, d.PART, d.CTRL, d.S);
 }
 void launch_correct_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
-  hipLaunchKernelGGL(k_correct_predict, dim3(blocks_for(p.n > 0 ? p.n : 1, 256)), dim3(256), 0,
-                     st, p, d.P[cur], d.V[cur], d.A[cur], d.M[cur], d.ANEW, d.S);
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_correct_predict, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
+                     d.V[cur], d.A[cur], d.M[cur], d.ANEW, d.S);
+}
+void launch_debug_lists(const DevParams &p, const DevPtrs &d, int cur, uint32_t *out,
+                        uint32_t *out_n, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_debug_lists, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p, d.KEY,
+                     d.CELL_START, d.WCELL_START, d.M[cur], d.MASK, out, out_n);
 }
 void launch_set_state(const DevParams &p, const DevPtrs &d, int cur, const float *pos,
                       const float *vel, hipStream_t st) {
@@ -753,15 +1204,14 @@ void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos,
                       float *acc, float *rho, float *pres, uint8_t *level, hipStream_t st) {
   if (p.n == 0) return;
   hipLaunchKernelGGL(k_get_state, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
-                     d.V[cur], d.A[cur], d.M[cur], d.ID[cur], d.PRES, pos, vel, acc, rho, pres,
-                     level);
+                     d.V[cur], d.A[cur], d.M[cur], d.ID[cur], pos, vel, acc, rho, pres, level);
 }
 void launch_wall_sort(const DevParams &p, const DevPtrs &d, const float *pos, hipStream_t st) {
   launch_prep_scan(d.CTRL, st);
   if (p.nw > 0)
     hipLaunchKernelGGL(k_wall_keys, dim3(blocks_for(p.nw, 256)), dim3(256), 0, st, p, pos, d.WKEY,
                        d.WRANK, d.COUNT);
-  launch_scan(p, d.COUNT, d.WCELL_START, p.nb, d.TILES, d.CTRL, d.S, st);
+  launch_scan(p, d, d.WCELL_START, false, st);
   if (p.nw > 0) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(p.nw, 256)), dim3(256), 0, st, p.nw, d.WKEY,
                        d.WRANK, d.WCELL_START, d.WTMP, d.S);

@@ -82,6 +82,9 @@ class Simulation:
     def advance(self, n_steps=1):
         _rts.advance(self.ctx, n_steps)
 
+    def profile(self, n_steps):
+        return _rts.profile_advance(self.ctx, n_steps)
+
     def sync(self, raise_on_error=True):
         return _rts.sync(self.ctx, raise_on_error)
 
@@ -124,7 +127,8 @@ class Simulation:
         "NBR": (np.uint32, 1), "PRESSURE": (np.float32, 1), "PRE_POS": (np.float32, 4),
         "PRE_VEL": (np.float32, 4), "PRE_ACC": (np.float32, 4), "PRE_META": (np.uint32, 1),
         "PRE_ID": (np.uint32, 1), "WALL_POS": (np.float32, 4), "WALL_ID": (np.uint32, 1),
-        "WALL_CELL_START": (np.uint32, 1), "ACTIVE": (np.uint32, 1),
+        "WALL_CELL_START": (np.uint32, 1), "OCCUPIED": (np.uint32, 1),
+        "BLK_STATS": (np.uint32, 4),
     }
 
     def debug(self, what: str) -> np.ndarray:
@@ -149,6 +153,13 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+def neighbour_lists(sim):
+    """Canonical lists of the last step's active particles: (rows (n, width), counts)."""
+    raw = sim.debug("NBR")
+    n, w = sim.n, _rts.DEBUG_NBR_ROW
+    return raw[: n * w].reshape(n, w), raw[n * w: n * w + n]
 
 
 def decode_meta(m: np.ndarray):

@@ -5,7 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
-from paper_2009_14514_amd.sim import decode_meta
+from paper_2009_14514_amd.sim import decode_meta, neighbour_lists
 
 
 def snapshot_after_step(sim):
@@ -34,18 +34,12 @@ def expected_structure(cfg, snap):
 
 
 def gpu_lists(sim, snap, rows):
-    """GPU neighbour lists of the given sorted particles, as python lists."""
-    nbr = sim.debug("NBR")
-    ncap = sim.n_fluid_max
-    nnb = snap["NNB"]
-    out = []
-    for i in rows:
-        k = int(nnb[i])
-        out.append(nbr[np.arange(k) * ncap + i].astype(np.uint32))
-    return out
+    """GPU neighbour lists of the given sorted particles, as arrays."""
+    lists, counts = neighbour_lists(sim)
+    return [lists[i, :counts[i]].astype(np.uint32) for i in rows], counts
 
 
-def oracle_lists(cfg, snap, want, cap=512):
+def oracle_lists(cfg, snap, want, cap=1024):
     pos_sorted = snap["PRE_POS"][snap["PERM"], :3]
     wpos = snap["WALL_POS"][:, :3]
     st, nbr, nnb = oracle.neighbors(cfg, pos_sorted, wpos, want=want, cap=cap)

@@ -42,7 +42,7 @@ def test_default_config_and_workspace_size():
     ("block_edge", 0.01, _rts.RTS_E_INVALID),     # block smaller than the support
     ("gamma", 5.0, _rts.RTS_E_UNSUPPORTED),
     ("n_levels", 9, _rts.RTS_E_INVALID),
-    ("nbr_cap", 0, _rts.RTS_E_INVALID),
+    ("cand_cap", 100, _rts.RTS_E_INVALID),       # not a multiple of 128
     ("c0", -1.0, _rts.RTS_E_INVALID),
     ("mode", 7, _rts.RTS_E_INVALID),
 ])

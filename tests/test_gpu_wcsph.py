@@ -47,8 +47,9 @@ def check_structure(sim, cfg, snap, check_lists=True):
     if check_lists:
         rows = np.nonzero(exp["compute"])[0]
         onbr, onnb = oracle_lists(cfg, snap, exp["compute"])
-        assert np.array_equal(snap["NNB"][rows], onnb[rows].astype(np.uint32))
-        glists = gpu_lists(sim, snap, rows)
+        glists, gcounts = gpu_lists(sim, snap, rows)
+        assert np.array_equal(gcounts[rows], onnb[rows].astype(np.uint32))
+        assert np.array_equal(snap["NNB"][rows].astype(np.int64), onnb[rows])
         for r, g in zip(rows, glists):
             assert np.array_equal(g, onbr[r, :onnb[r]]), f"neighbour list of {r} differs"
     return exp

@@ -17,6 +17,16 @@ from paper_2009_14514_amd import scenes
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
 
 
+def fused_d2(d):
+    """Squared distance as the method's float predicate forms it:
+    fma(dz, dz, fma(dy, dy, dx*dx)), each fused step rounded once (emulated
+    through double, where the products of floats are exact)."""
+    d = np.asarray(d, np.float32).astype(np.float64)
+    xx = (d[:, 0] * d[:, 0]).astype(np.float32).astype(np.float64)
+    s = (d[:, 1] * d[:, 1] + xx).astype(np.float32).astype(np.float64)
+    return (d[:, 2] * d[:, 2] + s).astype(np.float32)
+
+
 def params(**over):
     sc = scenes.dam_break_small()
     p = dict(sc.params)
@@ -96,9 +106,8 @@ def test_density_matches_brute_force_sum():
     info = O.derive(c)
     xf = x.astype(np.float32)
     for i in range(0, 300, 7):
-        d = xf - xf[i]
         # neighbour predicate in float, as the method takes structural decisions
-        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        d2 = fused_d2(xf - xf[i])
         nb = np.nonzero((d2 < np.float32(info.r2f)))[0]
         ref = sum(O.kernel_W(c, np.linalg.norm(x[i] - x[j])) for j in nb)
         assert rho[i] == pytest.approx(info.mass * ref, rel=1e-12)
@@ -280,11 +289,9 @@ def test_neighbours_match_brute_force():
     st, nbr, nnb = O.neighbors(c, x, w)
     assert st == 0
     for i in range(0, 700, 11):
-        d = x - x[i]
-        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        d2 = fused_d2(x - x[i])
         f = set(np.nonzero(d2 < info.r2f)[0].tolist()) - {i}
-        dw = w - x[i]
-        d2w = (dw[:, 0] * dw[:, 0] + dw[:, 1] * dw[:, 1]) + dw[:, 2] * dw[:, 2]
+        d2w = fused_d2(w - x[i])
         wl = set((np.nonzero(d2w < info.r2f)[0] | O.WALL_BIT).tolist())
         got = nbr[i, :nnb[i]].tolist()
         assert len(got) == len(set(got))
