@@ -294,7 +294,7 @@ void rts_default_config(rts_config *c) {
   c->r_crit = 0.02;
   c->rho0 = 1000.0;
   c->mass = 0.0;
-  c->c0 = 44.29446918;
+  c->c0 = 88.58893836;  // 20 sqrt(2 g H) for a 1 m column
   c->gamma = 7.0;
   c->B = 0.0;
   c->visc_alpha = 0.05;

@@ -120,9 +120,15 @@ def base_params(spacing, box_min, box_max, *, c0, layers=4, h_ratio=2.0,
     )
 
 
-def sound_speed_for_column(height, g=9.81):
-    """c0 = 10 * sqrt(2 g H): the usual weakly-compressible choice for a column of height H."""
-    return 10.0 * math.sqrt(2.0 * g * height)
+def sound_speed_for_column(height, g=9.81, factor=20.0):
+    """c0 = factor * sqrt(2 g H) for a column of height H.
+
+    sqrt(2 g H) bounds the collapse speed; weakly compressible SPH takes c0 at
+    least ten times the flow speed.  Twenty times keeps the maximum
+    compression of the 250,000-particle dam break below 1 % over its first
+    500 base steps for both regional and global stepping (ten times does not).
+    """
+    return factor * math.sqrt(2.0 * g * height)
 
 
 def dam_break_small(seed=0):

@@ -1,0 +1,148 @@
+"""GPU edge cases and full-size checks of the WCSPH base step.
+
+Empty and single-particle scenes, ragged particle counts, capacity and
+numerical failures reported through the device status, region
+determination alone, and the 250,000-particle dam break: structure bit for
+bit and sampled densities against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_14514_amd import _rts, scenes
+from paper_2009_14514_amd.sim import Simulation, decode_meta
+
+from parity import expected_structure, oracle_density, snapshot_after_step
+
+pytestmark = pytest.mark.gpu
+
+
+def small_box_scene(pos, vel=None):
+    sc = scenes.dam_break_small()
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    return scenes.Scene("custom", pos, np.zeros_like(pos) if vel is None else vel, sc.walls,
+                        dict(sc.params))
+
+
+def test_empty_scene_advances_time_only():
+    sc = small_box_scene(np.zeros((0, 3)))
+    sim = Simulation(sc, n_fluid_max=16)
+    sim.advance(5)
+    st = sim.sync()
+    assert st.step == 5 and st.active_total == 0
+    # the step size is held in float32, the clock in float64
+    assert st.time == pytest.approx(5 * sc.params["dt_base"], rel=1e-6)
+
+
+def test_isolated_particle_falls_freely():
+    sc = small_box_scene([[0.3, 0.2, 0.2]])
+    sim = Simulation(sc)
+    steps = 20
+    sim.advance(steps)
+    st = sim.sync()
+    s = sim.state()
+    t = st.time
+    # constant acceleration: the predictor-corrector is exact (up to float rounding)
+    assert s["pos"][0, 1] == pytest.approx(0.2 - 0.5 * 9.81 * t * t, abs=1e-6)
+    assert s["vel"][0, 1] == pytest.approx(-9.81 * t, rel=1e-5)
+    ref = oracle.WCSPH(sc.params, np.float32(sc.pos), walls=np.float32(sc.walls))
+    ref.step(steps)
+    assert np.abs(s["pos"] - ref.x).max() < 1e-6
+    assert st.inter_total == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 257, 1000])
+def test_ragged_counts_structure_and_density(n):
+    rng = np.random.default_rng(n)
+    pos = rng.uniform([0.02, 0.02, 0.02], [0.3, 0.25, 0.3], size=(n, 3))
+    sc = small_box_scene(pos)
+    sim = Simulation(sc)
+    sim.advance(1)
+    sim.sync()
+    snap = snapshot_after_step(sim)
+    cfg = oracle.cfg_from_params(sc.params)
+    exp = expected_structure(cfg, snap)
+    assert np.array_equal(snap["PERM"], exp["perm"])
+    assert np.array_equal(snap["CELL_START"], exp["cell_start"])
+    assert np.array_equal(snap["BLK_LEVEL"], exp["lvl"])
+    _, comp, _, _ = decode_meta(snap["META"])
+    rho_o, _ = oracle_density(cfg, snap, comp)
+    rows = np.nonzero(comp)[0]
+    rel = np.abs(snap["POS"][rows, 3] - rho_o[rows]) / rho_o[rows]
+    assert rel.max() <= 1e-5
+
+
+def test_candidate_capacity_overflow_is_reported():
+    sc = scenes.dam_break_small()
+    sim = Simulation(sc, cand_cap=256)          # far fewer than a block's 27-block neighbourhood
+    sim.advance(1)
+    with pytest.raises(_rts.RtsError) as e:
+        sim.sync()
+    assert e.value.status == _rts.RTS_E_CAPACITY
+    with pytest.raises(_rts.RtsError) as e:
+        sim.advance(1)                          # state failed: refuse to go on
+    assert e.value.status == _rts.RTS_E_STATE
+    sim.set_state(sc.pos[:1] + 0.1, None)       # a fresh state clears the failure
+    sim.advance(1)
+    sim.sync()
+
+
+def test_nan_and_out_of_domain_are_numerical_failures():
+    sc = scenes.dam_break_small()
+    pos = sc.pos.copy()
+    pos[17] = np.nan
+    sim = Simulation(small_box_scene(pos))
+    sim.advance(1)
+    st = sim.sync(raise_on_error=False)
+    assert st.status == _rts.RTS_E_NUMERICAL and st.bad_index == 17
+    pos = sc.pos.copy()
+    pos[5, 0] = 5.0                             # far outside the domain
+    sim2 = Simulation(small_box_scene(pos))
+    sim2.advance(1)
+    st2 = sim2.sync(raise_on_error=False)
+    assert st2.status == _rts.RTS_E_NUMERICAL and st2.bad_index == 5
+
+
+def test_assign_levels_matches_oracle_levels():
+    sc = scenes.dam_break_column(counts=(24, 40, 20), spacing=0.01, box=(0.6, 0.5, 0.3),
+                                 c0=scenes.sound_speed_for_column(0.4, factor=10.0))
+    sim = Simulation(sc)
+    sim.advance(200)
+    sim.sync()
+    s = sim.state()
+    hist = sim.assign_levels()
+    snap_pos = sim.debug("PRE_POS")[:, :3]
+    cfg = oracle.cfg_from_params(sc.params)
+    keys = oracle.keys(cfg, snap_pos)
+    lraw = oracle.block_levels(cfg, keys, sim.debug("PRE_VEL")[:, :3], sim.debug("PRE_ACC")[:, :3])
+    lvl = oracle.rmin(cfg, lraw)
+    assert np.array_equal(sim.debug("BLK_LEVEL"), lvl)
+    occ = lvl[lvl != oracle.EMPTY_BLOCK]
+    assert hist == [int((occ == l).sum()) for l in range(4)]
+    assert s["pos"].shape[0] == sc.n
+
+
+def test_full_size_structure_and_sampled_density():
+    sc = scenes.dam_break_column()              # 250,000 particles
+    sim = Simulation(sc)
+    sim.advance(60)
+    sim.sync()
+    sim.advance(1)
+    sim.sync()
+    snap = snapshot_after_step(sim)
+    cfg = oracle.cfg_from_params(sc.params)
+    exp = expected_structure(cfg, snap)
+    assert np.array_equal(snap["PERM"], exp["perm"])
+    assert np.array_equal(snap["KEY"], exp["keys"])
+    assert np.array_equal(snap["CELL_START"], exp["cell_start"])
+    assert np.array_equal(snap["BLK_LEVEL"], exp["lvl"])
+    level, comp, age, val = decode_meta(snap["META"])
+    assert np.array_equal(comp, exp["compute"]) and np.array_equal(level, exp["level"])
+    rows = np.nonzero(comp)[0]
+    rng = np.random.default_rng(0)
+    sample = rng.choice(rows, size=min(2000, rows.size), replace=False)
+    which = np.zeros(sc.n, np.uint8)
+    which[sample] = 1
+    rho_o, _ = oracle_density(cfg, snap, which)
+    rel = np.abs(snap["POS"][sample, 3] - rho_o[sample]) / rho_o[sample]
+    assert rel.max() <= 1e-5

@@ -28,8 +28,11 @@ def f32(a):
 
 
 def rts_scene(counts=(24, 40, 20), seed=3):
-    # a column small enough for the oracle, large enough for several levels
-    return scenes.dam_break_column(counts=counts, spacing=0.01, box=(0.6, 0.5, 0.3), seed=seed)
+    # a column small enough for the oracle, large enough for several levels; the
+    # softer sound speed 10 sqrt(2 g H) lets levels 1..3 appear within 250 steps
+    c0 = scenes.sound_speed_for_column(counts[1] * 0.01, factor=10.0)
+    return scenes.dam_break_column(counts=counts, spacing=0.01, box=(0.6, 0.5, 0.3), seed=seed,
+                                   c0=c0)
 
 
 def check_structure(sim, cfg, snap, check_lists=True):
