@@ -37,7 +37,35 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--only-rts", action="store_true",
                     help="time the RTS run only (for profiler runs); prints no JSON line")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run an elementwise copy of 256 MiB three times, the "
+                         "reference kernel for scaling HBM byte counters")
     return ap.parse_args()
+
+
+PROFILE_MD = os.path.join(ROOT, "profiles", "wcsph_rts_dam_break_250k_kernels.md")
+KERNEL_SOURCES = ("paper_2009_14514_amd/csrc/rts_kernels.hip",
+                  "paper_2009_14514_amd/csrc/rts_internal.h")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE_MD).read()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    m = re.search(r"kernel_sources_sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != h.hexdigest():
+        return None
+    m = re.search(r"traffic_bytes_per_launch %s: ([0-9.]+)" % re.escape(kernel), text)
+    return float(m.group(1)) if m else None
 
 
 def kernel_traffic(name, n, nb, K, act, inter, cand):
@@ -76,6 +104,14 @@ def run_gpu(args):
     from paper_2009_14514_amd.sim import Simulation
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # 256 MiB read and 256 MiB written per launch by one elementwise kernel
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     sc = scenes.dam_break_column()          # 250,000 particles, levels 0..3
     K, W = args.steps, args.warmup
     out = {}
@@ -222,10 +258,12 @@ def main():
         if dom in ("search_density", "force"):
             roof = {"kernel": dom, "bound": "alu", "achieved": d["TFLOPs"],
                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": d["TFLOPs"] / FP32_VALU_PEAK_TFLOPS, "traffic": None}
+                    "frac": d["TFLOPs"] / FP32_VALU_PEAK_TFLOPS,
+                    "traffic": measured_traffic(dom)}
         else:
             roof = {"kernel": dom, "bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None}
+                    "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
+                    "traffic": measured_traffic(dom)}
         line["roofline"] = roof
         line["kernels"] = rows
         tn = km["key_hist"] + km["scan"] + km["scatter"] + km["cell_gather"]
