@@ -136,6 +136,7 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   }
   (void)nwcap;
   p.nb = (int32_t)nb;
+  p.act_cap = (int32_t)((nb + kActBuckets - 1) / kActBuckets);
   p.inv_e = (float)(1.0 / c.block_edge);
   p.r2f = (float)(c.support * c.support);
   p.h = (float)c.h;
@@ -214,6 +215,8 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.COUNT = (uint32_t *)take(nb * 4);
   t.CELL_START = (uint32_t *)take((nb + 1) * 4);
   t.OCC = (uint32_t *)take(nb * 4);
+  t.ACT = (uint32_t *)take((size_t)p.act_cap * kActBuckets * 4);
+  t.ACTN = (uint32_t *)take(kActBuckets * 4);
   t.LRAW = (uint8_t *)take(nb);
   t.LVL = (uint8_t *)take(nb);
   t.BLKU = (uint4 *)take(nb * 16);

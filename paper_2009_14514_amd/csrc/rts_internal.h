@@ -35,6 +35,7 @@ struct DevParams {
   int32_t wpl;           // bitmask words per lane: cand_cap / (kSub * 32)
   int32_t nc[3];
   int32_t nb;
+  int32_t act_cap;       // entries per active-block list segment: ceil(nb / kActBuckets)
   float o[3];
   float inv_e, r2f;
   float h, inv_h, sigma, mass;
@@ -54,13 +55,21 @@ struct DevParams {
 
 // Control words.  Zeroed once when the context is created and never reset
 // or restored afterwards: the scan epoch only grows, so look-back words left
-// by an earlier scan can never be mistaken for the current one's.
+// by an earlier scan can never be mistaken for the current one's.  The
+// tickets and the active-block count restart at every step's first kernel.
 struct DevCtrl {
   uint32_t epoch;
   uint32_t scan_ticket;
   uint32_t stats_ticket;
-  uint32_t pad;
+  uint32_t search_ticket;   // next entry of the active-block list (search + density)
+  uint32_t force_ticket;    // next entry of the active-block list (forces)
+  uint32_t pad[3];
 };
+
+// The active-block list is kActBuckets segments of act_cap entries; blocks
+// at occupied positions [r nocc / kActBuckets, (r+1) nocc / kActBuckets)
+// append to segment r, so appends spread over kActBuckets counters.
+constexpr int kActBuckets = 64;
 
 // Counters kept on the device (part of the saved state).
 struct DevScalars {
@@ -117,6 +126,8 @@ struct DevPtrs {
   uint32_t *COUNT;   // nb, zero between sorts
   uint32_t *CELL_START;  // nb + 1
   uint32_t *OCC;     // occupied blocks, ascending
+  uint32_t *ACT;     // blocks holding an active particle this step, kActBuckets segments
+  uint32_t *ACTN;    // kActBuckets segment lengths, zero at every step's start
   uint8_t *LRAW, *LVL;   // block level before / after R_min
   uint4 *BLKU;       // per block: active, pairs, candidate tests, max count | n << 16
   float *BLKERR;     // per block: max compression error

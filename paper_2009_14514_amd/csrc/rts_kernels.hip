@@ -160,6 +160,20 @@ __device__ inline uint32_t local_to_global(const uint32_t *rs, const uint32_t *r
   return rs[r] + (k - ro[r]);
 }
 
+// Position of candidate k (< C) for staging; j = its fluid index, or kNoFluid
+// for a wall particle or a slot past the candidates.
+constexpr uint32_t kNoFluid = 0xFFFFFFFFu;
+__device__ inline float4 stage_load(const uint32_t *rs, const uint32_t *ro,
+                                    const float4 *__restrict__ P, const float4 *__restrict__ WP,
+                                    uint32_t k, uint32_t C, uint32_t &j) {
+  j = kNoFluid;
+  if (k >= C) return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  bool wall;
+  const uint32_t g = local_to_global(rs, ro, k, wall);
+  if (!wall) j = g;
+  return wall ? WP[g] : P[g];
+}
+
 // Sets up the candidate ranges of block b in shared memory and their prefix
 // offsets.  Ends with the offsets visible to the whole workgroup.
 __device__ inline void block_ranges_shared(const DevParams &p, const uint32_t *start,
@@ -220,13 +234,16 @@ __global__ void __launch_bounds__(256) k_key_hist(DevParams p, const float4 *__r
                                                  uint32_t *__restrict__ keyold,
                                                  uint32_t *__restrict__ rank,
                                                  uint32_t *__restrict__ count, DevCtrl *ctrl,
-                                                 DevScalars *S) {
+                                                 uint32_t *__restrict__ actn, DevScalars *S) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
+  if (i < kActBuckets) actn[i] = 0u;
   if (i == 0) {
     ctrl->epoch += 1u;  // a fresh epoch for this step's scan
     ctrl->scan_ticket = 0u;
     ctrl->stats_ticket = 0u;
+    ctrl->search_ticket = 0u;
+    ctrl->force_ticket = 0u;
     S->dt_prev = S->dt_next;
   }
   const bool live = i < p.n;
@@ -276,21 +293,24 @@ __device__ inline unsigned long long pack_status(uint32_t epoch, unsigned long l
 }
 
 // Thread 0 of a tile: publish the aggregate, look back, publish the prefix.
+// A status word carries everything a successor needs (epoch, flag, value),
+// so the words are relaxed device-scope atomics: no cache write-back is
+// needed to publish them.
 __device__ uint32_t look_back(unsigned long long *tiles, uint32_t tile, uint32_t epoch,
                               uint32_t total, DevScalars *S) {
   if (tile == 0) {
-    __hip_atomic_store(&tiles[0], pack_status(epoch, kFlagPre, total), __ATOMIC_RELEASE,
+    __hip_atomic_store(&tiles[0], pack_status(epoch, kFlagPre, total), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     return 0;
   }
-  __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagAgg, total), __ATOMIC_RELEASE,
+  __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagAgg, total), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
   uint32_t excl = 0;
   int j = (int)tile - 1;
   uint32_t spins = 0;
   while (j >= 0) {
     const unsigned long long w =
-        __hip_atomic_load(&tiles[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_load(&tiles[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long flag = (w >> 32) & 3ull;
     const uint32_t ep = (uint32_t)(w >> 34);
     if (ep != (epoch & 0x3FFFFFFFu) || flag == 0ull) {
@@ -305,7 +325,7 @@ __device__ uint32_t look_back(unsigned long long *tiles, uint32_t tile, uint32_t
     if (flag == kFlagPre) break;
     --j;
   }
-  __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagPre, excl + total), __ATOMIC_RELEASE,
+  __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagPre, excl + total), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
   return excl;
 }
@@ -498,7 +518,10 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
                                                    uint32_t *__restrict__ M,
                                                    const float4 *__restrict__ P,
                                                    uint4 *__restrict__ blku,
-                                                   float *__restrict__ blkerr, DevScalars *S,
+                                                   float *__restrict__ blkerr,
+                                                   float *__restrict__ blkamax,
+                                                   uint32_t *__restrict__ act,
+                                                   uint32_t *__restrict__ actn, DevScalars *S,
                                                    int do_flags) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nocc = S->n_occ;
@@ -547,8 +570,49 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
     if (lane == 0) {
       blku[b] = make_uint4(nact, 0u, 0u, (uint32_t)n << 16);
       blkerr[b] = err;
+      // blocks with work join this step's active-block list (their order
+      // there does not change any result); the others report no force
+      if (nact > 0u) {
+        const uint32_t r = (uint32_t)(((unsigned long long)q * kActBuckets) / nocc);
+        act[r * (uint32_t)p.act_cap + atomicAdd(&actn[r], 1u)] = b;
+      } else {
+        blkamax[b] = 0.0f;
+      }
     }
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// active-block work distribution
+// ---------------------------------------------------------------------------
+// Exclusive prefix of the segment lengths in shared memory (pre[kActBuckets]
+// = total).  Called by the whole workgroup; ends with a barrier.
+__device__ inline void active_prefix(const uint32_t *__restrict__ actn, uint32_t *pre) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    static_assert(kActBuckets == 64, "one wave scans the segment lengths");
+    uint32_t v = actn[tid];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = (uint32_t)__shfl_up((int)v, o, 64);
+      if (tid >= o) v += u;
+    }
+    pre[tid + 1] = v;
+    if (tid == 0) pre[0] = 0u;
+  }
+  __syncthreads();
+}
+
+// Block of list entry t (t < pre[kActBuckets]).
+__device__ inline uint32_t active_block(const DevParams &p, const uint32_t *__restrict__ act,
+                                        const uint32_t *pre, uint32_t t) {
+  uint32_t lo = 0, hi = kActBuckets;  // pre[lo] <= t < pre[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= t) lo = mid; else hi = mid;
+  }
+  return act[lo * (uint32_t)p.act_cap + (t - pre[lo])];
 }
 
 // ---------------------------------------------------------------------------
@@ -565,11 +629,12 @@ __device__ inline void kahan_merge(float &s, float &c, float s2, float c2) {
 }
 
 __global__ void __launch_bounds__(kBlockThreads) k_search_density(
-    DevParams p, const uint32_t *__restrict__ occ, const uint32_t *__restrict__ start,
+    DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, float4 *__restrict__ P, float4 *__restrict__ V,
     const uint32_t *__restrict__ M, float *__restrict__ pres, uint32_t *__restrict__ nnb,
     uint32_t *__restrict__ mask, const float4 *__restrict__ WP, uint4 *__restrict__ blku,
-    float *__restrict__ blkerr, const uint32_t *__restrict__ ids, DevScalars *S) {
+    float *__restrict__ blkerr, const uint32_t *__restrict__ ids,
+    const uint32_t *__restrict__ actn, DevCtrl *ctrl, DevScalars *S) {
   __shared__ float4 s_pos[kStageCap];
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
   __shared__ uint16_t s_act[kCellMax];
@@ -578,10 +643,19 @@ __global__ void __launch_bounds__(kBlockThreads) k_search_density(
   __shared__ uint32_t s_inter[kBlockThreads / 64], s_nmax[kBlockThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sub = tid & (kSub - 1);
-  const uint32_t nocc = S->n_occ;
-  for (uint32_t q = blockIdx.x; q < nocc; q += gridDim.x) {
-    const uint32_t b = occ[q];
-    if (blku[b].x == 0) continue;  // no active particle: nothing to evaluate
+  __shared__ uint32_t s_pre[kActBuckets + 1], s_ticket;
+  // blocks with active particles are handed out one at a time (the first
+  // round by workgroup index), so the workgroups finish together however
+  // unevenly the work is spread
+  active_prefix(actn, s_pre);
+  const uint32_t nblk = s_pre[kActBuckets];
+  for (uint32_t round = 0;; ++round) {
+    if (tid == 0)
+      s_ticket = round == 0 ? blockIdx.x : gridDim.x + atomicAdd(&ctrl->search_ticket, 1u);
+    __syncthreads();
+    const uint32_t q = s_ticket;
+    if (q >= nblk) break;
+    const uint32_t b = active_block(p, act, s_pre, q);
     const uint32_t s0 = start[b];
     const int n = min((int)(start[b + 1] - s0), kCellMax);
     if (tid == 0) s_nact = 0;
@@ -727,12 +801,12 @@ __global__ void __launch_bounds__(kBlockThreads) k_search_density(
 // forces, one workgroup per block
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kForceThreads) k_force(
-    DevParams p, const uint32_t *__restrict__ occ, const uint32_t *__restrict__ start,
+    DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, const float4 *__restrict__ P,
     const float4 *__restrict__ V, const uint32_t *__restrict__ M,
     const uint32_t *__restrict__ nnb, const uint32_t *__restrict__ mask,
-    const float4 *__restrict__ WP, float4 *__restrict__ anew, const uint4 *__restrict__ blku,
-    float *__restrict__ blkamax, DevScalars *S) {
+    const float4 *__restrict__ WP, float4 *__restrict__ anew, float *__restrict__ blkamax,
+    const uint32_t *__restrict__ actn, DevCtrl *ctrl) {
   __shared__ float4 s_p[kForceCap];
   __shared__ float4 s_v[kForceCap];
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
@@ -742,13 +816,16 @@ __global__ void __launch_bounds__(kForceThreads) k_force(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sub = tid & (kSub - 1);
   const float coefg = p.sigma * p.inv_h;  // dW/dr = sigma / h * w'(q)
-  const uint32_t nocc = S->n_occ;
-  for (uint32_t q = blockIdx.x; q < nocc; q += gridDim.x) {
-    const uint32_t b = occ[q];
-    if (blku[b].x == 0) {  // no active particle in this block
-      if (tid == 0) blkamax[b] = 0.0f;
-      continue;
-    }
+  __shared__ uint32_t s_pre[kActBuckets + 1], s_ticket;
+  active_prefix(actn, s_pre);
+  const uint32_t nblk = s_pre[kActBuckets];
+  for (uint32_t round = 0;; ++round) {
+    if (tid == 0)
+      s_ticket = round == 0 ? blockIdx.x : gridDim.x + atomicAdd(&ctrl->force_ticket, 1u);
+    __syncthreads();
+    const uint32_t q = s_ticket;
+    if (q >= nblk) break;
+    const uint32_t b = active_block(p, act, s_pre, q);
     const uint32_t s0 = start[b];
     const int n = min((int)(start[b + 1] - s0), kCellMax);
     if (tid == 0) s_nact = 0;
@@ -761,35 +838,28 @@ __global__ void __launch_bounds__(kForceThreads) k_force(
     const uint32_t nwords = ((C + kSub - 1) / kSub + 31) / 32;
     const bool staged = C <= (uint32_t)kForceCap;
     if (staged) {
-      constexpr int kPer = (kForceCap + kForceThreads - 1) / kForceThreads;
-      uint32_t src[kPer];
-      float4 buf[kPer];
-      // positions (walls included), then velocities: all loads of a phase
-      // are issued before its shared-memory writes
-#pragma unroll
-      for (int it = 0; it < kPer; ++it) {
-        const uint32_t k = (uint32_t)tid + (uint32_t)it * kForceThreads;
-        src[it] = 0xFFFFFFFFu;
-        if (k < C) {
-          bool wall;
-          const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
-          buf[it] = wall ? WP[j] : P[j];
-          src[it] = wall ? 0xFFFFFFFFu : j;
-        }
-      }
-#pragma unroll
-      for (int it = 0; it < kPer; ++it) {
-        const uint32_t k = (uint32_t)tid + (uint32_t)it * kForceThreads;
-        if (k < C) s_p[k] = buf[it];
-      }
-#pragma unroll
-      for (int it = 0; it < kPer; ++it)
-        if (src[it] != 0xFFFFFFFFu) buf[it] = V[src[it]];
-#pragma unroll
-      for (int it = 0; it < kPer; ++it) {
-        const uint32_t k = (uint32_t)tid + (uint32_t)it * kForceThreads;
-        if (src[it] != 0xFFFFFFFFu) s_v[k] = buf[it];
-      }
+      // positions (walls included), then velocities: the four loads of a
+      // phase are issued before its shared-memory writes.  Named registers,
+      // not an array, so nothing lands in private memory.
+      static_assert(kForceCap == 4 * kForceThreads, "staging assumes four slots per thread");
+      const uint32_t k0 = (uint32_t)tid, k1 = k0 + kForceThreads, k2 = k1 + kForceThreads,
+                     k3 = k2 + kForceThreads;
+      uint32_t j0, j1, j2, j3;
+      const float4 b0 = stage_load(s_rs, s_ro, P, WP, k0, C, j0);
+      const float4 b1 = stage_load(s_rs, s_ro, P, WP, k1, C, j1);
+      const float4 b2 = stage_load(s_rs, s_ro, P, WP, k2, C, j2);
+      const float4 b3 = stage_load(s_rs, s_ro, P, WP, k3, C, j3);
+      if (k0 < C) s_p[k0] = b0;
+      if (k1 < C) s_p[k1] = b1;
+      if (k2 < C) s_p[k2] = b2;
+      if (k3 < C) s_p[k3] = b3;
+      const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      const float4 u0 = j0 != kNoFluid ? V[j0] : z, u1 = j1 != kNoFluid ? V[j1] : z;
+      const float4 u2 = j2 != kNoFluid ? V[j2] : z, u3 = j3 != kNoFluid ? V[j3] : z;
+      if (j0 != kNoFluid) s_v[k0] = u0;
+      if (j1 != kNoFluid) s_v[k1] = u1;
+      if (j2 != kNoFluid) s_v[k2] = u2;
+      if (j3 != kNoFluid) s_v[k3] = u3;
     }
     __syncthreads();
     float a2max = 0.0f;
@@ -1141,7 +1211,7 @@ static inline unsigned blocks_for(int n, int t) { return (unsigned)((n + t - 1) 
 
 void launch_key_hist(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
   hipLaunchKernelGGL(k_key_hist, dim3(blocks_for(p.n > 0 ? p.n : 1, 256)), dim3(256), 0, st, p,
-                     d.P[cur], d.ID[cur], d.KEYOLD, d.RANK, d.COUNT, d.CTRL, d.S);
+                     d.P[cur], d.ID[cur], d.KEYOLD, d.RANK, d.COUNT, d.CTRL, d.ACTN, d.S);
 }
 void launch_prep_scan(DevCtrl *ctrl, hipStream_t st) {
   hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(1), 0, st, ctrl);
@@ -1166,18 +1236,19 @@ void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, int grid,
 void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags, int grid,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_rmin_flags, dim3((unsigned)grid), dim3(256), 0, st, p, d.OCC, d.CELL_START,
-                     d.LRAW, d.LVL, d.M[cur], d.P[cur], d.BLKU, d.BLKERR, d.S, do_flags);
+                     d.LRAW, d.LVL, d.M[cur], d.P[cur], d.BLKU, d.BLKERR, d.BLKAMAX, d.ACT,
+                     d.ACTN, d.S, do_flags);
 }
 void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_search_density, dim3((unsigned)grid), dim3(kBlockThreads), 0, st, p, d.OCC,
+  hipLaunchKernelGGL(k_search_density, dim3((unsigned)grid), dim3(kBlockThreads), 0, st, p, d.ACT,
                      d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.PRES, d.NNB,
-                     d.MASK, d.WP, d.BLKU, d.BLKERR, d.ID[cur], d.S);
+                     d.MASK, d.WP, d.BLKU, d.BLKERR, d.ID[cur], d.ACTN, d.CTRL, d.S);
 }
 void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_force, dim3((unsigned)grid), dim3(kForceThreads), 0, st, p, d.OCC,
+  hipLaunchKernelGGL(k_force, dim3((unsigned)grid), dim3(kForceThreads), 0, st, p, d.ACT,
                      d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.NNB, d.MASK,
-                     d.WP, d.ANEW, d.BLKU, d.BLKAMAX, d.S);
+                     d.WP, d.ANEW, d.BLKAMAX, d.ACTN, d.CTRL);
 }
 void launch_step_stats(const DevParams &p, const DevPtrs &d, hipStream_t st) {
   hipLaunchKernelGGL(k_step_stats, dim3(kStatBlocks), dim3(256), 0, st, p, d.OCC, d.BLKU,
