@@ -91,6 +91,23 @@ typedef struct rts_config {
   double alpha_rts;       /* Eq. 3 alpha (paper: 0.4 WCSPH, 1 PCISPH) */
   double beta2;           /* beta_2 of Eq. 3 (paper: 0.4) */
   double beta_ratio;      /* beta_{n+1} / beta_n (paper: 0.2) */
+  /* PCISPH with regional iteration counts (Section 5, Algorithms 2-3).
+   * Regions R_1..R_4 are block levels 0..3; region n steps n base steps in
+   * Eq. 2-3 (Eq. 1 is not applied).  One rts_advance step is one minor
+   * step of length dt_base; a major step is n_minor minor steps. */
+  int32_t n_minor;        /* minor steps per major step (paper: 4) */
+  int32_t it_min;         /* correction iterations per minor step, at least (3) */
+  int32_t it_max;         /* ... and at most (50) */
+  int32_t expand_layers;  /* regions 1 and 2 grow by this many block layers (4) */
+  int32_t local_fail;     /* local iterations before reverting to global ones (3) */
+  int32_t global_limit;   /* global iterations in one minor step that end the major step (6) */
+  int32_t short_majors;   /* clean major steps before the long major step returns (10) */
+  int32_t nbr_cap;        /* neighbour-list entries per particle (PCISPH) */
+  double eta;             /* allowed maximum compression (paper: 1 %) */
+  double eta_T;           /* average compression above which extra iterations are global */
+  double delta;           /* pressure coefficient (<= 0: from the full rest-lattice
+                             neighbourhood, standard PCISPH) */
+  double r_list;          /* neighbour-list radius (<= 0: block_edge, the 1.1 r grid) */
 } rts_config;
 
 /* Per-run counters, filled by rts_sync. */
@@ -109,6 +126,18 @@ typedef struct rts_stats {
   int32_t nbr_max;                   /* largest neighbour count seen */
   int32_t status;                    /* device status (rts_status) */
   int32_t bad_index;                 /* particle (caller order) that raised the status, or -1 */
+  /* PCISPH, last minor step */
+  int32_t pci_iters;                 /* correction iterations */
+  int32_t pci_global_iters;          /* of which with the schedule (global) */
+  int32_t pci_resets;                /* restarts of the schedule (average error too high) */
+  int32_t pci_reverts;               /* local phases abandoned, pressure restored */
+  int32_t pci_early_end;             /* 1: the major step ended early after this step */
+  int32_t pci_lists;                 /* neighbour lists rebuilt */
+  int32_t pci_major_len;             /* current major-step length in minor steps */
+  int32_t pci_minor_in_major;        /* minor steps done in the current major step */
+  double pci_errmax;                 /* max compression after the last iteration */
+  double pci_avg;                    /* mean compression after the last iteration */
+  int64_t pci_iters_total;           /* iterations summed over all minor steps */
 } rts_stats;
 
 typedef struct rts_ctx rts_ctx;
@@ -143,11 +172,20 @@ rts_status rts_set_state(rts_ctx *ctx, const float *d_pos, const float *d_vel, i
 /* Region determination only (Section 3.1 and R_min of Section 4.2): rebuilds
  * the block grid, takes block maxima and levels and smooths them, without
  * touching particle flags or physics.  h_level_hist[n_levels]: number of
- * occupied blocks per level.  Waits for the stream. */
+ * occupied blocks per level.  Waits for the stream.
+ * PCISPH: the set-up of a major step (Algorithm 2): grid of edge block_edge,
+ * regions from Eq. 2-3, dilation of regions 1 and 2, R_min, observed blocks,
+ * particle regions and flags; the next rts_advance continues that major
+ * step instead of starting one. */
 rts_status rts_assign_levels(rts_ctx *ctx, int32_t *h_level_hist);
 
 /* Advances n_steps base steps of Algorithm 1 (or of the global comparator
- * chosen by cfg.mode).  Asynchronous. */
+ * chosen by cfg.mode).  Asynchronous.
+ * PCISPH: n_steps minor steps of Algorithm 2 with the density correction of
+ * Algorithm 3; each correction iteration waits for the stream to read the
+ * error reductions that decide the next one, so the call returns after the
+ * work is done.  RTS_MODE_GLOBAL_FIXED runs standard PCISPH (grid and lists
+ * every step, every particle in every iteration) as the comparator. */
 rts_status rts_advance(rts_ctx *ctx, int32_t n_steps);
 
 /* Waits for the stream and copies the counters to *h_out (may be NULL).
@@ -160,7 +198,8 @@ rts_status rts_get_state(rts_ctx *ctx, float *d_pos, float *d_vel, float *d_acc,
                          float *d_p, uint8_t *d_level);
 
 /* Saves / restores the complete particle state and counters, so that a
- * restored run continues bit for bit.  d_buf: device memory. */
+ * restored run continues bit for bit.  d_buf: device memory.
+ * PCISPH contexts return RTS_E_UNSUPPORTED. */
 rts_status rts_state_bytes(rts_ctx *ctx, size_t *bytes);
 rts_status rts_save_state(rts_ctx *ctx, void *d_buf, size_t cap);
 rts_status rts_load_state(rts_ctx *ctx, const void *d_buf, size_t len);
@@ -195,7 +234,18 @@ typedef enum {
   RTS_DBG_KEY, RTS_DBG_PERM, RTS_DBG_CELL_START, RTS_DBG_BLK_LEVEL_RAW, RTS_DBG_BLK_LEVEL,
   RTS_DBG_NNB, RTS_DBG_NBR, RTS_DBG_PRESSURE, RTS_DBG_PRE_POS, RTS_DBG_PRE_VEL,
   RTS_DBG_PRE_ACC, RTS_DBG_PRE_META, RTS_DBG_PRE_ID, RTS_DBG_WALL_POS, RTS_DBG_WALL_ID,
-  RTS_DBG_WALL_CELL_START, RTS_DBG_OCCUPIED, RTS_DBG_BLK_STATS, RTS_DBG_COUNT_
+  RTS_DBG_WALL_CELL_START, RTS_DBG_OCCUPIED, RTS_DBG_BLK_STATS,
+  /* PCISPH (block order of the current major step) */
+  RTS_DBG_PCI_XS,        /* float4: predicted position x*, 0 */
+  RTS_DBG_PCI_PV,        /* float4: pressure, relative density error, pressure backup, rho* */
+  RTS_DBG_PCI_FVG,       /* float4: non-pressure acceleration (gravity + viscosity), 0 */
+  RTS_DBG_PCI_FP,        /* float4: pressure acceleration, 0 */
+  RTS_DBG_PCI_SE,        /* uint8 per particle: member of S_e */
+  RTS_DBG_PCI_OB,        /* uint8 per block: observed (borders a smaller region) */
+  RTS_DBG_PCI_DILATED,   /* uint8 per block: levels after dilation, before R_min */
+  RTS_DBG_PCI_LISTS,     /* uint32: n rows of nbr_cap entries (fluid sorted index,
+                            walls | 0x80000000), then the n counts */
+  RTS_DBG_COUNT_
 } rts_debug_what;
 rts_status rts_debug_get(rts_ctx *ctx, int32_t what, void *d_out, size_t cap_bytes, size_t *n_out);
 

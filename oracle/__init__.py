@@ -32,6 +32,10 @@ class OrcCfg(C.Structure):
         ("beta2", C.c_double), ("beta_ratio", C.c_double),
         ("n_levels", C.c_int32), ("level_cap", C.c_int32), ("mode", C.c_int32),
         ("clamp_p", C.c_int32), ("serna_correct", C.c_int32), ("nbr_cap", C.c_int32),
+        ("solver", C.c_int32), ("n_minor", C.c_int32), ("it_min", C.c_int32),
+        ("it_max", C.c_int32), ("expand_layers", C.c_int32), ("local_fail", C.c_int32),
+        ("global_limit", C.c_int32), ("short_majors", C.c_int32), ("pad_", C.c_int32),
+        ("eta", C.c_double), ("eta_T", C.c_double), ("delta", C.c_double), ("r_list", C.c_double),
     ]
 
 
@@ -41,6 +45,7 @@ class OrcInfo(C.Structure):
         ("inv_e", C.c_float), ("r2f", C.c_float), ("mass", C.c_double), ("B", C.c_double),
         ("sigma", C.c_double), ("dt_base", C.c_double),
         ("TV", C.c_float * MAX_LEVELS), ("TA", C.c_float * MAX_LEVELS), ("lmax", C.c_int32),
+        ("r2l", C.c_float), ("delta", C.c_double),
     ]
 
 
@@ -55,6 +60,26 @@ class OrcState(C.Structure):
         ("t", C.c_double), ("dt_prev", C.c_double), ("step", C.c_int64),
         ("n_active", C.c_int32), ("n_inter", C.c_int64), ("err_max", C.c_double),
         ("hist", C.c_int32 * MAX_LEVELS),
+    ]
+
+
+class OrcPciState(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("nw", C.c_int32),
+        ("x", C.c_void_p), ("v", C.c_void_p), ("fvg", C.c_void_p), ("fp", C.c_void_p),
+        ("p", C.c_void_p), ("rho", C.c_void_p), ("err", C.c_void_p),
+        ("region", C.c_void_p), ("validity", C.c_void_p),
+        ("compute", C.c_void_p), ("in_se", C.c_void_p), ("id", C.c_void_p), ("key", C.c_void_p),
+        ("nbr", C.c_void_p), ("nnb", C.c_void_p),
+        ("cell_start", C.c_void_p), ("blk_level", C.c_void_p), ("blk_ob", C.c_void_p),
+        ("wx", C.c_void_p), ("wcell_start", C.c_void_p),
+        ("major_len", C.c_int32), ("minor_in_major", C.c_int32), ("clean_majors", C.c_int32),
+        ("major_excess", C.c_int32),
+        ("minor_steps", C.c_int64), ("t", C.c_double),
+        ("last_iters", C.c_int32), ("last_global_iters", C.c_int32), ("last_resets", C.c_int32),
+        ("last_reverts", C.c_int32), ("last_early_end", C.c_int32), ("last_lists", C.c_int32),
+        ("evals_density", C.c_int64), ("evals_force", C.c_int64),
+        ("last_errmax", C.c_double), ("last_avg", C.c_double), ("hist", C.c_int32 * 4),
     ]
 
 
@@ -99,6 +124,21 @@ def _declare(L):
     L.orc_serna_correct.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]
     L.orc_wcsph_step.argtypes = [cfgp, _p(OrcState)]
+    vp = C.c_void_p
+    L.orc_pci_delta.argtypes = [cfgp]
+    L.orc_pci_delta.restype = C.c_double
+    L.orc_pci_regions.argtypes = [cfgp, C.c_int32, vp, vp, vp, vp, vp, vp]
+    L.orc_pci_dilate.argtypes = [cfgp, vp, vp, C.c_int, C.c_int]
+    L.orc_pci_observed.argtypes = [cfgp, vp, vp]
+    L.orc_pci_lists.argtypes = [cfgp, C.c_int32, vp, vp, vp, C.c_int32, vp, vp, vp, vp, C.c_int32,
+                                vp, vp]
+    L.orc_pci_density.argtypes = [cfgp, C.c_int32, vp, vp, vp, vp, vp, vp]
+    L.orc_pci_pressure_force.argtypes = [cfgp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_pci_nonpressure.argtypes = [cfgp, C.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_pci_turn.argtypes = [C.c_int32, C.c_int32]
+    L.orc_pci_turn.restype = C.c_uint32
+    L.orc_pci_step.argtypes = [cfgp, _p(OrcPciState)]
+    L.orc_pci_major_begin.argtypes = [cfgp, _p(OrcPciState)]
     L.orc_num_threads.restype = C.c_int
 
 
@@ -122,6 +162,13 @@ def cfg_from_params(p: dict, **over) -> OrcCfg:
     c.mode = MODES[q["mode"]] if isinstance(q["mode"], str) else int(q["mode"])
     c.clamp_p, c.serna_correct = q["clamp_p"], q["serna_correct"]
     c.nbr_cap = q.get("nbr_cap", 512)
+    c.solver = 1 if q.get("solver", "wcsph") == "pcisph" else 0
+    c.n_minor, c.it_min, c.it_max = q.get("n_minor", 4), q.get("it_min", 3), q.get("it_max", 50)
+    c.expand_layers = q.get("expand_layers", 4)
+    c.local_fail, c.global_limit = q.get("local_fail", 3), q.get("global_limit", 6)
+    c.short_majors = q.get("short_majors", 10)
+    c.eta, c.eta_T = q.get("eta", 0.01), q.get("eta_T", 0.0025)
+    c.delta, c.r_list = q.get("delta", 0.0), q.get("r_list", 0.0)
     return c
 
 
@@ -303,3 +350,183 @@ class WCSPH:
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+# ---------------------------------------------------------------------------
+# PCISPH with regional iteration counts
+# ---------------------------------------------------------------------------
+def pci_delta(cfg):
+    return lib().orc_pci_delta(C.byref(cfg))
+
+
+def pci_turn(col, row):
+    return int(lib().orc_pci_turn(int(col), int(row)))
+
+
+def pci_regions(cfg, key, vel_f32, acc_f32):
+    """(raw, lvl, observed) block arrays of a major step's region determination."""
+    info = derive(cfg)
+    key = np.ascontiguousarray(key, np.uint32)
+    v = np.ascontiguousarray(vel_f32, np.float32).reshape(-1, 3)
+    a = np.ascontiguousarray(acc_f32, np.float32).reshape(-1, 3)
+    raw = np.zeros(info.nblocks, np.uint8)
+    lvl = np.zeros(info.nblocks, np.uint8)
+    ob = np.zeros(info.nblocks, np.uint8)
+    lib().orc_pci_regions(C.byref(cfg), key.shape[0], _ptr(key), _ptr(v), _ptr(a), _ptr(raw),
+                          _ptr(lvl), _ptr(ob))
+    return raw, lvl, ob
+
+
+def pci_dilate(cfg, lvl, level, layers):
+    lvl = np.ascontiguousarray(lvl, np.uint8)
+    out = np.zeros_like(lvl)
+    lib().orc_pci_dilate(C.byref(cfg), _ptr(lvl), _ptr(out), int(level), int(layers))
+    return out
+
+
+def pci_observed(cfg, lvl):
+    lvl = np.ascontiguousarray(lvl, np.uint8)
+    out = np.zeros_like(lvl)
+    lib().orc_pci_observed(C.byref(cfg), _ptr(lvl), _ptr(out))
+    return out
+
+
+def pci_lists(cfg, pos_f32, cell_start, key, wpos_f32, wcell_start, want=None, rings=None,
+              cap=None):
+    """Lists of sorted particles against a stored grid: (nbr (n, cap), nnb)."""
+    pos = np.ascontiguousarray(pos_f32, np.float32).reshape(-1, 3)
+    n = pos.shape[0]
+    wpos = np.ascontiguousarray(wpos_f32, np.float32).reshape(-1, 3)
+    cap = int(cap or cfg.nbr_cap)
+    nbr = np.zeros((n, cap), np.uint32)
+    nnb = np.zeros(n, np.int32)
+    cs = np.ascontiguousarray(cell_start, np.uint32)
+    ws = np.ascontiguousarray(wcell_start, np.uint32)
+    key = np.ascontiguousarray(key, np.uint32)
+    w = None if want is None else np.ascontiguousarray(want, np.uint8)
+    r = None if rings is None else np.ascontiguousarray(rings, np.uint8)
+    st = lib().orc_pci_lists(C.byref(cfg), n, _ptr(pos), _ptr(cs), _ptr(key), wpos.shape[0],
+                             _ptr(wpos), _ptr(ws), _ptr(w) if w is not None else None,
+                             _ptr(r) if r is not None else None, cap, _ptr(nbr), _ptr(nnb))
+    return st, nbr, nnb
+
+
+def _lists_arg(cfg, nbr, nnb):
+    nbr = np.ascontiguousarray(nbr, np.uint32)
+    assert nbr.shape[1] == cfg.nbr_cap
+    return nbr, np.ascontiguousarray(nnb, np.int32)
+
+
+def pci_density(cfg, xs, wx, nbr, nnb, which=None):
+    xs = np.ascontiguousarray(xs, np.float64).reshape(-1, 3)
+    wx = np.ascontiguousarray(wx, np.float64).reshape(-1, 3)
+    nbr, nnb = _lists_arg(cfg, nbr, nnb)
+    rho = np.zeros(xs.shape[0])
+    w = None if which is None else np.ascontiguousarray(which, np.uint8)
+    lib().orc_pci_density(C.byref(cfg), xs.shape[0], _ptr(xs), _ptr(wx), _ptr(nbr), _ptr(nnb),
+                          _ptr(w) if w is not None else None, _ptr(rho))
+    return rho
+
+
+def pci_pressure_force(cfg, xs, wx, p, rho, nbr, nnb, which=None):
+    xs = np.ascontiguousarray(xs, np.float64).reshape(-1, 3)
+    wx = np.ascontiguousarray(wx, np.float64).reshape(-1, 3)
+    p = np.ascontiguousarray(p, np.float64)
+    rho = np.ascontiguousarray(rho, np.float64)
+    nbr, nnb = _lists_arg(cfg, nbr, nnb)
+    fp = np.zeros_like(xs)
+    w = None if which is None else np.ascontiguousarray(which, np.uint8)
+    lib().orc_pci_pressure_force(C.byref(cfg), xs.shape[0], _ptr(xs), _ptr(wx), _ptr(p), _ptr(rho),
+                                 _ptr(nbr), _ptr(nnb), _ptr(w) if w is not None else None,
+                                 _ptr(fp))
+    return fp
+
+
+def pci_nonpressure(cfg, x, v, wx, nbr, nnb, which=None):
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    v = np.ascontiguousarray(v, np.float64).reshape(-1, 3)
+    wx = np.ascontiguousarray(wx, np.float64).reshape(-1, 3)
+    nbr, nnb = _lists_arg(cfg, nbr, nnb)
+    out = np.zeros_like(x)
+    w = None if which is None else np.ascontiguousarray(which, np.uint8)
+    lib().orc_pci_nonpressure(C.byref(cfg), x.shape[0], _ptr(x), _ptr(v), _ptr(wx), _ptr(nbr),
+                              _ptr(nnb), _ptr(w) if w is not None else None, _ptr(out))
+    return out
+
+
+def sorted_walls(cfg, walls):
+    """Walls in their grid order (stable) and their block starts."""
+    w32 = np.ascontiguousarray(walls, np.float32).reshape(-1, 3)
+    info = derive(cfg)
+    k = keys(cfg, w32)
+    perm, start = sort(info.nblocks, k)
+    return np.asarray(walls, np.float64).reshape(-1, 3)[perm], start, perm
+
+
+class PCISPH:
+    """FP64 oracle run of Algorithm 2 / 3 on one scene (arrays in block order)."""
+
+    def __init__(self, params: dict, pos, vel=None, walls=None, **over):
+        self.cfg = cfg_from_params(params, **over)
+        self.info = derive(self.cfg)
+        n = int(np.asarray(pos).reshape(-1, 3).shape[0])
+        nb = int(self.info.nblocks)
+        cap = int(self.cfg.nbr_cap)
+        self.x = np.array(np.asarray(pos, np.float64).reshape(-1, 3), copy=True)
+        self.v = np.zeros((n, 3)) if vel is None else np.array(np.asarray(vel, np.float64).reshape(-1, 3))
+        self.fvg = np.zeros((n, 3))
+        self.fp = np.zeros((n, 3))
+        self.p = np.zeros(n)
+        self.rho = np.full(n, self.cfg.rho0)
+        self.err = np.zeros(n)
+        self.region = np.ones(n, np.int32)
+        self.validity = np.zeros(n, np.int32)
+        self.compute = np.ones(n, np.uint8)
+        self.in_se = np.zeros(n, np.uint8)
+        self.id = np.arange(n, dtype=np.uint32)
+        self.key = np.zeros(n, np.uint32)
+        self.nbr = np.zeros((max(n, 1), cap), np.uint32)
+        self.nnb = np.zeros(max(n, 1), np.int32)
+        self.cell_start = np.zeros(nb + 1, np.uint32)
+        self.blk_level = np.full(nb, EMPTY_BLOCK, np.uint8)
+        self.blk_ob = np.zeros(nb, np.uint8)
+        walls = np.zeros((0, 3)) if walls is None else np.asarray(walls, np.float64).reshape(-1, 3)
+        self.wx, self.wcell_start, self.wperm = sorted_walls(self.cfg, walls)
+        self.wx = np.ascontiguousarray(self.wx)
+        self.state = OrcPciState()
+        s = self.state
+        s.n, s.nw = n, self.wx.shape[0]
+        for name in ("x", "v", "fvg", "fp", "p", "rho", "err", "region", "validity", "compute",
+                     "in_se", "id", "key", "nbr", "nnb", "cell_start", "blk_level", "blk_ob",
+                     "wx", "wcell_start"):
+            setattr(s, name, _ptr(getattr(self, name)))
+        s.major_len = int(self.cfg.n_minor)
+        self.history = []
+
+    def step(self, n=1):
+        for _ in range(n):
+            st = lib().orc_pci_step(C.byref(self.cfg), C.byref(self.state))
+            if st:
+                raise RuntimeError(f"oracle PCISPH step status {st}")
+            s = self.state
+            self.history.append(dict(
+                t=s.t, iters=s.last_iters, global_iters=s.last_global_iters,
+                resets=s.last_resets, reverts=s.last_reverts, early_end=s.last_early_end,
+                lists=s.last_lists, evals_density=s.evals_density, evals_force=s.evals_force,
+                errmax=s.last_errmax, avg=s.last_avg, hist=list(s.hist),
+                major_len=s.major_len, minor_in_major=s.minor_in_major))
+        return self
+
+    def major_begin(self):
+        st = lib().orc_pci_major_begin(C.byref(self.cfg), C.byref(self.state))
+        if st:
+            raise RuntimeError(f"oracle major step set-up status {st}")
+
+    @property
+    def t(self):
+        return self.state.t
+
+    def in_caller_order(self, a):
+        out = np.empty_like(a)
+        out[self.id] = a
+        return out

@@ -117,16 +117,23 @@ int orc_derive(const orc_cfg *c, orc_info *o) {
   if (c->level_cap < lmax) lmax = c->level_cap < 0 ? 0 : c->level_cap;
   if (c->mode != ORC_MODE_RTS) lmax = 0;
   o->lmax = lmax;
-  /* Level l steps 2^l base steps and is ranked n = l + 1 for beta (Eq. 3):
-   *   Eq. 3:  2^l dt |v| / r <= alpha beta_{l+1}  ->  |v|^2 <= TV[l]
-   *   Eq. 2:  2^l dt <= lambda_f sqrt(r / |a|)    ->  |a|^2 <= TA[l]   */
+  /* WCSPH level l steps 2^l base steps; PCISPH level l is region n = l + 1,
+   * stepping n base steps (Section 5).  Either way l is ranked n = l + 1
+   * for beta (Eq. 3):
+   *   Eq. 3:  dt_l |v| / r <= alpha beta_{l+1}  ->  |v|^2 <= TV[l]
+   *   Eq. 2:  dt_l <= lambda_f sqrt(r / |a|)    ->  |a|^2 <= TA[l]   */
   for (int l = 0; l < ORC_MAX_LEVELS; ++l) {
-    double dtl = ldexp(o->dt_base, l);
+    double dtl = c->solver == ORC_PCISPH ? o->dt_base * (double)(l + 1) : ldexp(o->dt_base, l);
     double b = beta_n(c, l + 1);
     double vl = isinf(b) ? INFINITY : c->alpha_rts * b * r_crit(c) / dtl;
     double al = c->lambda_f * c->lambda_f * r_crit(c) / (dtl * dtl);
     o->TV[l] = (float)(vl * vl);
     o->TA[l] = (float)(al * al);
+  }
+  if (c->solver == ORC_PCISPH) {
+    double rl = c->r_list > 0.0 ? c->r_list : c->block_edge;
+    o->r2l = (float)(rl * rl);
+    o->delta = c->delta > 0.0 ? c->delta : orc_pci_delta(c);
   }
   return ORC_OK;
 }
@@ -619,4 +626,578 @@ int orc_wcsph_step(const orc_cfg *c, orc_state *s) {
   free(vf); free(af); free(lraw); free(lvl); free(anew); free(dtau);
   ctx_close(&X);
   return status;
+}
+
+/* ======================================================================== */
+/* PCISPH with regional iteration counts (Section 5, Algorithms 2 and 3).    */
+/* Regions R_n, n = 1..4, are block levels l = n - 1; a region-n block is     */
+/* corrected according to the schedule and its particles' neighbourhoods are */
+/* refreshed every n minor steps (n <= 2) or once per major step (n >= 3).   */
+/* ======================================================================== */
+
+/* gradient of W at x_ij = x_i - x_j, |x_ij| = d > 0 */
+static void grad_w(const orc_cfg *c, const double *xij, double d, double *g) {
+  double f = d > 0.0 ? orc_kernel_dWdr(c, d) / d : 0.0;
+  g[0] = f * xij[0]; g[1] = f * xij[1]; g[2] = f * xij[2];
+}
+
+/* a19.  The PCISPH pressure coefficient of Solenthaler & Pajarola (the
+ * standard PCISPH the paper builds on): delta = -1 / (beta (-S.S - Q)) with
+ * S = sum_j gradW_ij, Q = sum_j gradW_ij . gradW_ij over a particle with a
+ * full rest-lattice neighbourhood and beta = 2 (m dt / rho0)^2. */
+double orc_pci_delta(const orc_cfg *c) {
+  double s = c->spacing, r = c->support;
+  double m = c->mass > 0.0 ? c->mass : c->rho0 / orc_lattice_sum(c);
+  double dt = base_dt(c);
+  int K = (int)ceil(r / s) + 1;
+  double S[3] = {0.0, 0.0, 0.0}, Q = 0.0;
+  for (int k = -K; k <= K; ++k)
+    for (int j = -K; j <= K; ++j)
+      for (int i = -K; i <= K; ++i) {
+        if (i == 0 && j == 0 && k == 0) continue;
+        double xij[3] = {-i * s, -j * s, -k * s};   /* particle at the origin, j at +(i,j,k)s */
+        double d = sqrt(xij[0] * xij[0] + xij[1] * xij[1] + xij[2] * xij[2]);
+        if (d >= r) continue;
+        double g[3];
+        grad_w(c, xij, d, g);
+        S[0] += g[0]; S[1] += g[1]; S[2] += g[2];
+        Q += g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+      }
+  double beta = 2.0 * (m * dt / c->rho0) * (m * dt / c->rho0);
+  return -1.0 / (beta * (-(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]) - Q));
+}
+
+static void coords_of_key(const orc_info *I, uint32_t k, int32_t b[3]) {
+  b[0] = (int32_t)(k % (uint32_t)I->nc[0]);
+  uint32_t t = k / (uint32_t)I->nc[0];
+  b[1] = (int32_t)(t % (uint32_t)I->nc[1]);
+  b[2] = (int32_t)(t / (uint32_t)I->nc[1]);
+}
+static int in_grid(const orc_info *I, const int32_t q[3]) {
+  return q[0] >= 0 && q[1] >= 0 && q[2] >= 0 && q[0] < I->nc[0] && q[1] < I->nc[1] &&
+         q[2] < I->nc[2];
+}
+
+/* Section 5, "Extra Correction Iterations": regions 1 and 2 grow by a few
+ * block layers before a major step, so fast particles stay in them. */
+static void dilate_info(const orc_info *I, const uint8_t *in, uint8_t *out, int level,
+                        int layers) {
+  for (int32_t z = 0; z < I->nc[2]; ++z)
+    for (int32_t y = 0; y < I->nc[1]; ++y)
+      for (int32_t x = 0; x < I->nc[0]; ++x) {
+        int32_t b[3] = {x, y, z};
+        uint32_t k = key_of(I, b);
+        uint8_t l = in[k];
+        if (l != ORC_EMPTY_BLOCK && l > level) {
+          int hit = 0;
+          for (int dz = -layers; dz <= layers && !hit; ++dz)
+            for (int dy = -layers; dy <= layers && !hit; ++dy)
+              for (int dx = -layers; dx <= layers && !hit; ++dx) {
+                int32_t q[3] = {x + dx, y + dy, z + dz};
+                if (in_grid(I, q) && in[key_of(I, q)] == level) hit = 1;
+              }
+          if (hit) l = (uint8_t)level;
+        }
+        out[k] = l;
+      }
+}
+void orc_pci_dilate(const orc_cfg *c, const uint8_t *in, uint8_t *out, int level, int layers) {
+  orc_info I;
+  orc_derive(c, &I);
+  dilate_info(&I, in, out, level, layers);
+}
+
+/* Figure "regions": observed blocks border a region with a smaller step. */
+static void observed_info(const orc_info *I, const uint8_t *lvl, uint8_t *ob) {
+  for (int64_t k = 0; k < I->nblocks; ++k) {
+    ob[k] = 0;
+    if (lvl[k] == ORC_EMPTY_BLOCK) continue;
+    int32_t b[3];
+    coords_of_key(I, (uint32_t)k, b);
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int32_t q[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
+          if (in_grid(I, q) && lvl[key_of(I, q)] < lvl[k]) ob[k] = 1;
+        }
+  }
+}
+void orc_pci_observed(const orc_cfg *c, const uint8_t *lvl, uint8_t *ob) {
+  orc_info I;
+  orc_derive(c, &I);
+  observed_info(&I, lvl, ob);
+}
+
+/* a13: Eq. 2 and Eq. 3 per block (Eq. 1 omitted, alpha = 1 via the
+ * configuration), dilation of regions 1 then 2, R_min, observed blocks. */
+void orc_pci_regions(const orc_cfg *c, int32_t n, const uint32_t *key, const float *vel,
+                     const float *acc, uint8_t *raw, uint8_t *lvl, uint8_t *ob) {
+  orc_info I;
+  orc_derive(c, &I);
+  uint8_t *t1 = (uint8_t *)malloc((size_t)I.nblocks), *t2 = (uint8_t *)malloc((size_t)I.nblocks);
+  orc_block_levels(c, n, key, vel, acc, raw);
+  dilate_info(&I, raw, t1, 0, c->expand_layers);
+  dilate_info(&I, t1, t2, 1, c->expand_layers);
+  orc_rmin(c, t2, lvl);
+  observed_info(&I, lvl, ob);
+  free(t1); free(t2);
+}
+
+/* a14: neighbours of sorted particle i within the list radius, found in the
+ * blocks up to `rings` layers around its block of the stored grid. */
+static int32_t pci_list_one(const orc_info *I, int32_t i, const float *pos,
+                            const uint32_t *cell_start, const uint32_t *key, const float *wpos,
+                            const uint32_t *wcell_start, int32_t rings, int32_t cap,
+                            uint32_t *out) {
+  int32_t b[3], cnt = 0;
+  coords_of_key(I, key[i], b);
+  const float *pi = pos + 3 * (int64_t)i;
+  for (int pass = 0; pass < 2; ++pass) {
+    const uint32_t *st = pass == 0 ? cell_start : wcell_start;
+    const float *P = pass == 0 ? pos : wpos;
+    if (!st) continue;
+    for (int dz = -rings; dz <= rings; ++dz)
+      for (int dy = -rings; dy <= rings; ++dy)
+        for (int dx = -rings; dx <= rings; ++dx) {
+          int32_t q[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
+          if (!in_grid(I, q)) continue;
+          uint32_t k = key_of(I, q);
+          for (uint32_t j = st[k]; j < st[k + 1]; ++j) {
+            if (pass == 0 && (int32_t)j == i) continue;
+            if (!near_f(pi, P + 3 * (int64_t)j, I->r2l)) continue;
+            if (cnt >= cap) return -1;
+            out[cnt++] = pass == 0 ? j : (ORC_WALL_BIT | j);
+          }
+        }
+  }
+  return cnt;
+}
+
+int orc_pci_lists(const orc_cfg *c, int32_t n, const float *pos, const uint32_t *cell_start,
+                  const uint32_t *key, int32_t nw, const float *wpos,
+                  const uint32_t *wcell_start, const uint8_t *want, const uint8_t *rings,
+                  int32_t cap, uint32_t *nbr, int32_t *nnb) {
+  orc_info I;
+  if (orc_derive(c, &I)) return ORC_E_INVALID;
+  int status = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t i = 0; i < n; ++i) {
+    if (want && !want[i]) continue;
+    int32_t k = pci_list_one(&I, i, pos, cell_start, key, wpos, nw > 0 ? wcell_start : NULL,
+                             rings ? rings[i] : 1, cap, nbr + (int64_t)i * cap);
+    if (k < 0) {
+#pragma omp atomic write
+      status = ORC_E_CAPACITY;
+      k = 0;
+    }
+    nnb[i] = k;
+  }
+  return status;
+}
+
+static const double *pci_other(const double *x, const double *wx, uint32_t j) {
+  return (j & ORC_WALL_BIT) ? wx + 3 * (int64_t)(j & ~ORC_WALL_BIT) : x + 3 * (int64_t)j;
+}
+
+void orc_pci_density(const orc_cfg *c, int32_t n, const double *xs, const double *wx,
+                     const uint32_t *nbr, const int32_t *nnb, const uint8_t *which,
+                     double *rho) {
+  int32_t cap = c->nbr_cap;
+  double m = c->mass > 0.0 ? c->mass : c->rho0 / orc_lattice_sum(c);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t i = 0; i < n; ++i) {
+    if (which && !which[i]) continue;
+    const double *xi = xs + 3 * (int64_t)i;
+    double sum = orc_kernel_W(c, 0.0);
+    const uint32_t *L = nbr + (int64_t)i * cap;
+    for (int32_t k = 0; k < nnb[i]; ++k) {
+      const double *xj = pci_other(xs, wx, L[k]);
+      double d0 = xi[0] - xj[0], d1 = xi[1] - xj[1], d2 = xi[2] - xj[2];
+      sum += orc_kernel_W(c, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+    }
+    rho[i] = m * sum;
+  }
+}
+
+void orc_pci_pressure_force(const orc_cfg *c, int32_t n, const double *xs, const double *wx,
+                            const double *p, const double *rho, const uint32_t *nbr,
+                            const int32_t *nnb, const uint8_t *which, double *fp) {
+  int32_t cap = c->nbr_cap;
+  double m = c->mass > 0.0 ? c->mass : c->rho0 / orc_lattice_sum(c);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t i = 0; i < n; ++i) {
+    if (which && !which[i]) continue;
+    const double *xi = xs + 3 * (int64_t)i;
+    double pi = p[i] / (rho[i] * rho[i]);
+    double a[3] = {0.0, 0.0, 0.0};
+    const uint32_t *L = nbr + (int64_t)i * cap;
+    for (int32_t k = 0; k < nnb[i]; ++k) {
+      uint32_t j = L[k];
+      const double *xj = pci_other(xs, wx, j);
+      double xij[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+      double d = sqrt(xij[0] * xij[0] + xij[1] * xij[1] + xij[2] * xij[2]);
+      if (!(d > 0.0) || d >= c->support) continue;
+      double pj = (j & ORC_WALL_BIT) ? pi : p[j] / (rho[j] * rho[j]);
+      double g[3];
+      grad_w(c, xij, d, g);
+      for (int e = 0; e < 3; ++e) a[e] -= m * (pi + pj) * g[e];
+    }
+    for (int e = 0; e < 3; ++e) fp[3 * (int64_t)i + e] = a[e];
+  }
+}
+
+void orc_pci_nonpressure(const orc_cfg *c, int32_t n, const double *x, const double *v,
+                         const double *wx, const uint32_t *nbr, const int32_t *nnb,
+                         const uint8_t *which, double *fvg) {
+  int32_t cap = c->nbr_cap;
+  double m = c->mass > 0.0 ? c->mass : c->rho0 / orc_lattice_sum(c);
+  double nu = c->visc_alpha * c->h * c->c0 / c->rho0;
+  double eps_h2 = c->visc_eps * c->h * c->h;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t i = 0; i < n; ++i) {
+    if (which && !which[i]) continue;
+    const double *xi = x + 3 * (int64_t)i, *vi = v + 3 * (int64_t)i;
+    double a[3] = {c->g[0], c->g[1], c->g[2]};
+    const uint32_t *L = nbr + (int64_t)i * cap;
+    for (int32_t k = 0; k < nnb[i]; ++k) {
+      uint32_t j = L[k];
+      const double *xj = pci_other(x, wx, j);
+      double vj[3] = {0.0, 0.0, 0.0};          /* walls are at rest */
+      if (!(j & ORC_WALL_BIT))
+        for (int e = 0; e < 3; ++e) vj[e] = v[3 * (int64_t)j + e];
+      double xij[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+      double d = sqrt(xij[0] * xij[0] + xij[1] * xij[1] + xij[2] * xij[2]);
+      if (!(d > 0.0) || d >= c->support) continue;
+      double vx = (vi[0] - vj[0]) * xij[0] + (vi[1] - vj[1]) * xij[1] + (vi[2] - vj[2]) * xij[2];
+      if (vx >= 0.0) continue;                  /* only approaching pairs are damped */
+      double pi_ij = -nu * vx / (d * d + eps_h2);
+      double g[3];
+      grad_w(c, xij, d, g);
+      for (int e = 0; e < 3; ++e) a[e] -= m * pi_ij * g[e];
+    }
+    for (int e = 0; e < 3; ++e) fvg[3 * (int64_t)i + e] = a[e];
+  }
+}
+
+/* Figure "iterations" (its image is not in the text we work from): a
+ * schedule that meets every stated constraint.  Row 1 holds all regions in
+ * every column; the first column's row 2 holds all regions again; region 1
+ * gets three rows per minor step, region 2 three rows per two minor steps,
+ * regions 3 and 4 fewer per major step (12, 6, 5, 5). */
+uint32_t orc_pci_turn(int32_t col, int32_t row) {
+  static const uint32_t table[3][4] = {
+      {0xF, 0xF, 0xF, 0xF},   /* row 1: R1 R2 R3 R4 */
+      {0xF, 0x1, 0x3, 0x1},   /* row 2 */
+      {0x1, 0x1, 0x1, 0x1},   /* row 3: R1 */
+  };
+  if (row < 1 || row > 3 || col < 0 || col > 3) return 0u;
+  return table[row - 1][col];
+}
+
+static int32_t region_validity(int32_t region, int32_t major_len) {
+  /* Section 5, neighbourhood updates: R1 every minor step, R2 every second,
+   * R3 and R4 at the next major step. */
+  return region <= 2 ? region : major_len;
+}
+
+static void permute_d(double *a, const uint32_t *perm, int32_t n, int w, double *tmp) {
+  for (int32_t i = 0; i < n; ++i)
+    for (int e = 0; e < w; ++e) tmp[(int64_t)w * i + e] = a[(int64_t)w * perm[i] + e];
+  memcpy(a, tmp, sizeof(double) * (size_t)w * (size_t)n);
+}
+static void permute_u32(uint32_t *a, const uint32_t *perm, int32_t n, uint32_t *tmp) {
+  for (int32_t i = 0; i < n; ++i) tmp[i] = a[perm[i]];
+  memcpy(a, tmp, sizeof(uint32_t) * (size_t)n);
+}
+
+static int pci_standard(const orc_cfg *c) { return c->mode != ORC_MODE_RTS; }
+
+/* Algorithm 2, major-step set-up: grid at block edge e, regions, flags. */
+static int pci_major_begin(const orc_cfg *c, const orc_info *I, orc_pci_state *s) {
+  int32_t n = s->n;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  float *pf = (float *)malloc(sizeof(float) * 3 * nn);
+  for (int64_t k = 0; k < 3 * (int64_t)n; ++k) pf[k] = (float)s->x[k];
+  uint32_t *key = (uint32_t *)calloc(nn, sizeof(uint32_t));
+  uint32_t *perm = (uint32_t *)calloc(nn, sizeof(uint32_t));
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t b[3];
+    block_coords(I, pf + 3 * (int64_t)i, b);
+    key[i] = key_of(I, b);
+  }
+  if (orc_sort(I->nblocks, n, key, perm, s->cell_start)) {
+    free(pf); free(key); free(perm);
+    return ORC_E_INVALID;
+  }
+  double *td = (double *)malloc(sizeof(double) * 3 * nn);
+  uint32_t *tw = (uint32_t *)malloc(sizeof(uint32_t) * nn);
+  permute_d(s->x, perm, n, 3, td);
+  permute_d(s->v, perm, n, 3, td);
+  permute_d(s->fvg, perm, n, 3, td);
+  permute_d(s->fp, perm, n, 3, td);
+  permute_d(s->p, perm, n, 1, td);
+  permute_d(s->rho, perm, n, 1, td);
+  permute_d(s->err, perm, n, 1, td);
+  permute_u32(s->id, perm, n, tw);
+  for (int32_t i = 0; i < n; ++i) s->key[i] = key[perm[i]];
+  /* block maxima of the predicted velocity and the total acceleration of
+   * the last minor step, then the regions */
+  float *vf = (float *)malloc(sizeof(float) * 3 * nn), *af = (float *)malloc(sizeof(float) * 3 * nn);
+  for (int64_t k = 0; k < 3 * (int64_t)n; ++k) {
+    vf[k] = (float)s->v[k];
+    af[k] = (float)(s->fvg[k] + s->fp[k]);
+  }
+  uint8_t *raw = (uint8_t *)malloc((size_t)I->nblocks);
+  orc_pci_regions(c, n, s->key, vf, af, raw, s->blk_level, s->blk_ob);
+  int32_t len = pci_standard(c) ? 1 : s->major_len;
+  for (int32_t i = 0; i < n; ++i) {
+    s->region[i] = (int32_t)s->blk_level[s->key[i]] + 1;
+    s->validity[i] = region_validity(s->region[i], len);
+    s->compute[i] = 1;
+  }
+  free(raw); free(vf); free(af);
+  free(pf); free(key); free(perm); free(td); free(tw);
+  return ORC_OK;
+}
+
+int orc_pci_major_begin(const orc_cfg *c, orc_pci_state *s) {
+  orc_info I;
+  if (orc_derive(c, &I)) return ORC_E_INVALID;
+  return pci_major_begin(c, &I, s);
+}
+
+/* blocks holding a particle of S_e, with their 26 neighbours */
+static void mark_near_se(const orc_info *I, const orc_pci_state *s, uint8_t *near) {
+  memset(near, 0, (size_t)I->nblocks);
+  for (int32_t i = 0; i < s->n; ++i) {
+    if (!s->in_se[i]) continue;
+    int32_t b[3];
+    coords_of_key(I, s->key[i], b);
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int32_t q[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
+          if (in_grid(I, q)) near[key_of(I, q)] = 1;
+        }
+  }
+}
+
+int orc_pci_step(const orc_cfg *c, orc_pci_state *s) {
+  orc_info I;
+  if (orc_derive(c, &I)) return ORC_E_INVALID;
+  int32_t n = s->n;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  const int standard = pci_standard(c);
+  if (s->major_len <= 0) s->major_len = c->n_minor;
+  if (standard) s->major_len = 1;
+  if (s->minor_in_major == 0) {
+    int st = pci_major_begin(c, &I, s);
+    if (st) return st;
+    s->major_excess = 0;
+  }
+  const int32_t col = s->minor_in_major;
+  const double dt = I.dt_base, rho0 = c->rho0, eta = c->eta;
+  const int32_t cap = c->nbr_cap;
+
+  /* S1: lists of particles whose validity ran out (Section 5,
+   * neighbourhood updates), two block layers for region 1 */
+  float *pf = (float *)malloc(sizeof(float) * 3 * nn);
+  float *wf = (float *)malloc(sizeof(float) * 3 * (size_t)(s->nw > 0 ? s->nw : 1));
+  for (int64_t k = 0; k < 3 * (int64_t)n; ++k) pf[k] = (float)s->x[k];
+  for (int64_t k = 0; k < 3 * (int64_t)s->nw; ++k) wf[k] = (float)s->wx[k];
+  uint8_t *rings = (uint8_t *)malloc(nn);
+  int32_t lists = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    rings[i] = (uint8_t)((!standard && s->region[i] == 1) ? 2 : 1);
+    lists += s->compute[i] ? 1 : 0;
+  }
+  int st = orc_pci_lists(c, n, pf, s->cell_start, s->key, s->nw, wf, s->wcell_start, s->compute,
+                         rings, cap, s->nbr, s->nnb);
+  free(pf); free(wf); free(rings);
+  if (st) return st;
+
+  /* S2: non-pressure forces of the same particles; S3: p = 0, F^p = 0 */
+  orc_pci_nonpressure(c, n, s->x, s->v, s->wx, s->nbr, s->nnb, s->compute, s->fvg);
+  for (int32_t i = 0; i < n; ++i) {
+    s->p[i] = 0.0;
+    s->fp[3 * (int64_t)i] = s->fp[3 * (int64_t)i + 1] = s->fp[3 * (int64_t)i + 2] = 0.0;
+    s->in_se[i] = 0;
+  }
+
+  /* S4: Algorithm 3 */
+  double *xs = (double *)malloc(sizeof(double) * 3 * nn);
+  double *p_backup = (double *)calloc(nn, sizeof(double));
+  uint8_t *dens = (uint8_t *)malloc(nn), *forc = (uint8_t *)malloc(nn);
+  uint8_t *near = (uint8_t *)malloc((size_t)I.nblocks);
+  memset(near, 0, (size_t)I.nblocks);
+  int32_t iter = 1, row = 1, min_iter = c->it_min, global = 1, local_iters = 0;
+  int32_t global_iters = 0, resets = 0, reverts = 0;
+  int64_t ev_d = 0, ev_f = 0;
+  double errmax = INFINITY, avg = 0.0;
+  while ((iter <= min_iter || errmax >= eta) && iter <= c->it_max) {
+    /* C1: predicted velocity and position of every particle */
+    for (int32_t i = 0; i < n; ++i)
+      for (int e = 0; e < 3; ++e) {
+        int64_t k = 3 * (int64_t)i + e;
+        double vs = s->v[k] + dt * (s->fvg[k] + s->fp[k]);
+        xs[k] = s->x[k] + dt * vs;
+      }
+    /* the particles that have the turn */
+    uint32_t turn = standard ? 0xFu : (global ? orc_pci_turn(col, row) : 0u);
+    for (int32_t i = 0; i < n; ++i) {
+      int t = (turn >> (s->region[i] - 1)) & 1u;
+      int ob = s->blk_ob[s->key[i]] || near[s->key[i]];
+      dens[i] = (uint8_t)(t || s->in_se[i] || ob);
+    }
+    /* C2: predicted density, its error, pressure update */
+    orc_pci_density(c, n, xs, s->wx, s->nbr, s->nnb, dens, s->rho);
+    for (int32_t i = 0; i < n; ++i) {
+      if (!dens[i]) continue;
+      ++ev_d;
+      s->err[i] = (s->rho[i] - rho0) / rho0;
+      double pn = s->p[i] + I.delta * (s->rho[i] - rho0);
+      s->p[i] = pn > 0.0 ? pn : 0.0;
+    }
+    /* C3: S_e gains the particles still over half the allowed error; the
+     * blocks around them join the observed set */
+    for (int32_t i = 0; i < n; ++i)
+      if (dens[i] && s->err[i] > 0.5 * eta) s->in_se[i] = 1;
+    mark_near_se(&I, s, near);
+    /* C4: pressure acceleration of the particles with the turn and of the
+     * updated S_e */
+    for (int32_t i = 0; i < n; ++i)
+      forc[i] = (uint8_t)(((turn >> (s->region[i] - 1)) & 1u) || s->in_se[i]);
+    orc_pci_pressure_force(c, n, xs, s->wx, s->p, s->rho, s->nbr, s->nnb, forc, s->fp);
+    for (int32_t i = 0; i < n; ++i) ev_f += forc[i];
+    /* C5 */
+    if (global) ++global_iters;
+    ++iter;
+    ++row;
+    errmax = 0.0;
+    double sum = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+      double e = s->err[i] > 0.0 ? s->err[i] : 0.0;
+      if (e > errmax) errmax = e;
+      sum += e;
+    }
+    avg = n > 0 ? sum / n : 0.0;
+    /* C6: extra iterations after the three scheduled ones */
+    if (errmax >= eta && iter > 3 && !standard) {
+      ++min_iter;
+      if (avg >= c->eta_T) {                   /* global error: restart the schedule */
+        if (!global) {
+          memcpy(s->p, p_backup, sizeof(double) * nn);
+          ++reverts;
+        }
+        global = 1;
+        row = 1;
+        ++resets;
+      } else if (global) {                     /* local corrections on S_e */
+        memcpy(p_backup, s->p, sizeof(double) * nn);
+        global = 0;
+        local_iters = 0;
+      } else if (++local_iters >= c->local_fail) {
+        memcpy(s->p, p_backup, sizeof(double) * nn);
+        global = 1;
+        row = 1;
+        ++reverts;
+      }
+    } else if (errmax >= eta && iter > 3) {
+      ++min_iter;
+    }
+  }
+  free(xs); free(p_backup); free(dens); free(forc); free(near);
+
+  /* S5: new velocity and position (symplectic Euler) */
+  for (int64_t k = 0; k < 3 * (int64_t)n; ++k) {
+    s->v[k] += dt * (s->fvg[k] + s->fp[k]);
+    s->x[k] += dt * s->v[k];
+  }
+  /* S6: validity */
+  for (int32_t i = 0; i < n; ++i) {
+    s->validity[i] -= 1;
+    if (s->validity[i] <= 0) {
+      s->compute[i] = 1;
+      s->validity[i] = region_validity(s->region[i], s->major_len);
+    } else {
+      s->compute[i] = 0;
+    }
+  }
+  /* S7: a particle that now needs a smaller step takes its block and the 26
+   * around it to that step */
+  if (!standard) {
+    uint8_t *nl = (uint8_t *)malloc((size_t)I.nblocks);
+    memcpy(nl, s->blk_level, (size_t)I.nblocks);
+    int changed = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      float vf[3], af[3];
+      for (int e = 0; e < 3; ++e) {
+        vf[e] = (float)s->v[3 * (int64_t)i + e];
+        af[e] = (float)(s->fvg[3 * (int64_t)i + e] + s->fp[3 * (int64_t)i + e]);
+      }
+      float v2 = norm2f(vf), a2 = norm2f(af);
+      int l = 0;
+      while (l + 1 <= I.lmax && v2 <= I.TV[l + 1] && a2 <= I.TA[l + 1]) ++l;
+      if (l >= s->region[i] - 1) continue;
+      int32_t b[3];
+      coords_of_key(&I, s->key[i], b);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            int32_t q[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
+            if (!in_grid(&I, q)) continue;
+            uint32_t k = key_of(&I, q);
+            if (nl[k] != ORC_EMPTY_BLOCK && nl[k] > l) { nl[k] = (uint8_t)l; changed = 1; }
+          }
+    }
+    if (changed) {
+      for (int32_t i = 0; i < n; ++i) {
+        int32_t r = (int32_t)nl[s->key[i]] + 1;
+        if (r < s->region[i]) {
+          s->region[i] = r;
+          s->compute[i] = 1;
+          s->validity[i] = region_validity(r, s->major_len);
+        }
+      }
+      memcpy(s->blk_level, nl, (size_t)I.nblocks);
+      observed_info(&I, s->blk_level, s->blk_ob);
+    }
+    free(nl);
+  }
+
+  /* statistics and the major-step length (Section 5, extra iterations) */
+  s->last_iters = iter - 1;
+  s->last_global_iters = global_iters;
+  s->last_resets = resets;
+  s->last_reverts = reverts;
+  s->last_lists = lists;
+  s->evals_density = ev_d;
+  s->evals_force = ev_f;
+  s->last_errmax = errmax;
+  s->last_avg = avg;
+  for (int r = 0; r < 4; ++r) s->hist[r] = 0;
+  for (int32_t i = 0; i < n; ++i) s->hist[s->region[i] - 1]++;
+  s->t += dt;
+  s->minor_steps += 1;
+  s->minor_in_major += 1;
+  s->last_early_end = 0;
+  if (!standard && global_iters > c->global_limit) {
+    s->major_excess = 1;
+    if (s->minor_in_major < s->major_len) s->last_early_end = 1;
+  }
+  if (s->minor_in_major >= s->major_len || s->last_early_end) {
+    s->minor_in_major = 0;
+    if (!standard) {
+      if (s->major_excess) {
+        s->major_len = 2 < c->n_minor ? 2 : c->n_minor;
+        s->clean_majors = 0;
+      } else if (s->major_len < c->n_minor && ++s->clean_majors >= c->short_majors) {
+        s->major_len = c->n_minor;
+        s->clean_majors = 0;
+      }
+    }
+  }
+  for (int64_t k = 0; k < 3 * (int64_t)n; ++k)
+    if (!isfinite(s->x[k])) return ORC_E_NUMERICAL;
+  return ORC_OK;
 }

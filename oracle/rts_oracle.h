@@ -24,6 +24,7 @@ extern "C" {
 
 enum { ORC_OK = 0, ORC_E_INVALID = 1, ORC_E_CAPACITY = 2, ORC_E_NUMERICAL = 4 };
 enum { ORC_MODE_RTS = 0, ORC_MODE_GLOBAL_FIXED = 1, ORC_MODE_GLOBAL_ADAPTIVE = 2 };
+enum { ORC_WCSPH = 0, ORC_PCISPH = 1 };
 #define ORC_MAX_LEVELS 8
 #define ORC_WALL_BIT 0x80000000u
 #define ORC_EMPTY_BLOCK 0xFFu
@@ -39,6 +40,18 @@ typedef struct orc_cfg {
   double r_crit;                     /* length r of Eq. 1-3; <= 0: support radius */
   double lambda_v, lambda_f, alpha_rts, beta2, beta_ratio;
   int32_t n_levels, level_cap, mode, clamp_p, serna_correct, nbr_cap;
+  /* PCISPH (solver = ORC_PCISPH) */
+  int32_t solver;
+  int32_t n_minor;                   /* minor steps per major step (4) */
+  int32_t it_min, it_max;            /* correction iterations: at least / at most (3, 50) */
+  int32_t expand_layers;             /* dilation of regions 1 and 2, in blocks (4) */
+  int32_t local_fail;                /* local iterations before reverting to global (3) */
+  int32_t global_limit;              /* global iterations that end a major step early (6) */
+  int32_t short_majors;              /* clean major steps before the long major returns (10) */
+  int32_t pad_;
+  double eta, eta_T;                 /* max / average compression error thresholds */
+  double delta;                      /* <= 0: from the prototype neighbourhood */
+  double r_list;                     /* neighbour-list radius; <= 0: block edge */
 } orc_cfg;
 
 typedef struct orc_info {
@@ -49,6 +62,8 @@ typedef struct orc_info {
   double mass, B, sigma, dt_base;
   float TV[ORC_MAX_LEVELS], TA[ORC_MAX_LEVELS];
   int32_t lmax;
+  float r2l;                         /* PCISPH list radius squared, in float */
+  double delta;                      /* PCISPH pressure coefficient */
 } orc_info;
 
 typedef struct orc_state {
@@ -98,6 +113,79 @@ void orc_serna_correct(int32_t n, double *x, double *v, double *a, const double 
 
 /* one base step of Algorithm 1 (or of a global comparator) */
 int orc_wcsph_step(const orc_cfg *c, orc_state *s);
+
+/* ---------------------------------------------------------------------- */
+/* PCISPH with regional iteration counts (Section 5, Algorithms 2 and 3).   */
+/* Block levels k = 0..3 stand for regions n = k + 1 (step n dt_b).         */
+/* ---------------------------------------------------------------------- */
+typedef struct orc_pci_state {
+  int32_t n, nw;
+  /* particle arrays, in the block order of the current major step */
+  double *x, *v;                     /* 3n */
+  double *fvg, *fp;                  /* 3n: non-pressure / pressure acceleration */
+  double *p, *rho, *err;             /* n: pressure, predicted density, relative error */
+  int32_t *region, *validity;        /* n */
+  uint8_t *compute, *in_se;          /* n */
+  uint32_t *id;                      /* n: caller index held in each slot */
+  uint32_t *key;                     /* n: block of the major step's grid */
+  uint32_t *nbr;                     /* n * nbr_cap: lists (sorted fluid index, walls | bit 31) */
+  int32_t *nnb;                      /* n */
+  /* blocks */
+  uint32_t *cell_start;              /* nb + 1 */
+  uint8_t *blk_level, *blk_ob;       /* nb: level (region - 1, 0xFF empty), observed flag */
+  /* walls, static, in their own block order */
+  const double *wx;                  /* 3nw (sorted by the caller-independent wall grid) */
+  uint32_t *wcell_start;             /* nb + 1 */
+  /* schedule and statistics */
+  int32_t major_len, minor_in_major, clean_majors, major_excess;
+  int64_t minor_steps;
+  double t;
+  int32_t last_iters, last_global_iters, last_resets, last_reverts, last_early_end;
+  int32_t last_lists;                /* lists rebuilt in the last minor step */
+  int64_t evals_density, evals_force; /* particle evaluations in the last minor step */
+  double last_errmax, last_avg;
+  int32_t hist[4];                   /* particles per region at the last minor step */
+} orc_pci_state;
+
+/* a19: delta = -1 / (beta (-sum gradW . sum gradW - sum gradW . gradW)),
+ * beta = 2 (m dt_b / rho0)^2, over the full rest-lattice neighbourhood. */
+double orc_pci_delta(const orc_cfg *c);
+/* a13: block levels from Eq. 2-3 (alpha = 1, no Eq. 1), dilation of levels
+ * 0 and 1 by expand_layers, R_min, observed blocks.  raw, lvl, ob: nb. */
+void orc_pci_regions(const orc_cfg *c, int32_t n, const uint32_t *key, const float *vel,
+                     const float *acc, uint8_t *raw, uint8_t *lvl, uint8_t *ob);
+/* Dilation of one level by `layers` blocks (Chebyshev), occupied blocks only. */
+void orc_pci_dilate(const orc_cfg *c, const uint8_t *in, uint8_t *out, int level, int layers);
+/* Observed blocks: occupied, with an occupied 26-neighbour of smaller level. */
+void orc_pci_observed(const orc_cfg *c, const uint8_t *lvl, uint8_t *ob);
+/* a14: lists of the sorted particles with want[i] set, against the stored
+ * grid: rings[i] block layers around block key[i], float predicate with the
+ * list radius, canonical order (fluid sorted index ascending, then walls). */
+int orc_pci_lists(const orc_cfg *c, int32_t n, const float *pos, const uint32_t *cell_start,
+                  const uint32_t *key, int32_t nw, const float *wpos,
+                  const uint32_t *wcell_start, const uint8_t *want, const uint8_t *rings,
+                  int32_t cap, uint32_t *nbr, int32_t *nnb);
+/* Density predicted at positions xs for particles with which[i] set (walls
+ * at wx): rho = m (W(0) + sum_j W + sum_w W) over the stored lists. */
+void orc_pci_density(const orc_cfg *c, int32_t n, const double *xs, const double *wx,
+                     const uint32_t *nbr, const int32_t *nnb, const uint8_t *which,
+                     double *rho);
+/* Pressure acceleration -m sum_j (p_i/rho_i^2 + p_j/rho_j^2) gradW at xs;
+ * a wall mirrors p_i and rho_i. */
+void orc_pci_pressure_force(const orc_cfg *c, int32_t n, const double *xs, const double *wx,
+                            const double *p, const double *rho, const uint32_t *nbr,
+                            const int32_t *nnb, const uint8_t *which, double *fp);
+/* Gravity plus artificial viscosity (nu = alpha h c0 / rho0) at x, v. */
+void orc_pci_nonpressure(const orc_cfg *c, int32_t n, const double *x, const double *v,
+                         const double *wx, const uint32_t *nbr, const int32_t *nnb,
+                         const uint8_t *which, double *fvg);
+/* Schedule of Figure "iterations": regions (bit n-1 for region n) that take
+ * row `row` (1..3) of minor-step column `col` (0..3). */
+uint32_t orc_pci_turn(int32_t col, int32_t row);
+/* One minor step of Algorithm 2 (a major step begins when due). */
+int orc_pci_step(const orc_cfg *c, orc_pci_state *s);
+/* Major-step set-up alone: sort into the grid, regions, flags. */
+int orc_pci_major_begin(const orc_cfg *c, orc_pci_state *s);
 
 int orc_num_threads(void);
 

@@ -23,7 +23,8 @@ DEBUG_NBR_ROW = 1024
 DBG = {name: i for i, name in enumerate([
     "POS", "VEL", "ACC", "ACC_NEW", "META", "ID", "KEY", "PERM", "CELL_START", "BLK_LEVEL_RAW",
     "BLK_LEVEL", "NNB", "NBR", "PRESSURE", "PRE_POS", "PRE_VEL", "PRE_ACC", "PRE_META", "PRE_ID",
-    "WALL_POS", "WALL_ID", "WALL_CELL_START", "OCCUPIED", "BLK_STATS"])}
+    "WALL_POS", "WALL_ID", "WALL_CELL_START", "OCCUPIED", "BLK_STATS",
+    "PCI_XS", "PCI_PV", "PCI_FVG", "PCI_FP", "PCI_SE", "PCI_OB", "PCI_DILATED", "PCI_LISTS"])}
 
 # exported symbols, in the order include/rts.h declares them
 EXPORTS = [
@@ -48,6 +49,10 @@ class RtsConfig(C.Structure):
         ("domain_min", C.c_double * 3), ("domain_max", C.c_double * 3), ("dt_base", C.c_double),
         ("lambda_v", C.c_double), ("lambda_f", C.c_double), ("alpha_rts", C.c_double),
         ("beta2", C.c_double), ("beta_ratio", C.c_double),
+        ("n_minor", C.c_int32), ("it_min", C.c_int32), ("it_max", C.c_int32),
+        ("expand_layers", C.c_int32), ("local_fail", C.c_int32), ("global_limit", C.c_int32),
+        ("short_majors", C.c_int32), ("nbr_cap", C.c_int32),
+        ("eta", C.c_double), ("eta_T", C.c_double), ("delta", C.c_double), ("r_list", C.c_double),
     ]
 
 
@@ -59,6 +64,10 @@ class RtsStats(C.Structure):
         ("err_max_run", C.c_float),
         ("level_hist", C.c_int32 * MAX_LEVELS), ("nbr_max", C.c_int32), ("status", C.c_int32),
         ("bad_index", C.c_int32),
+        ("pci_iters", C.c_int32), ("pci_global_iters", C.c_int32), ("pci_resets", C.c_int32),
+        ("pci_reverts", C.c_int32), ("pci_early_end", C.c_int32), ("pci_lists", C.c_int32),
+        ("pci_major_len", C.c_int32), ("pci_minor_in_major", C.c_int32),
+        ("pci_errmax", C.c_double), ("pci_avg", C.c_double), ("pci_iters_total", C.c_int64),
     ]
 
     def as_dict(self):
@@ -139,6 +148,15 @@ def config_from_params(p: dict, **over) -> RtsConfig:
               "visc_eps", "dt_base", "lambda_v", "lambda_f", "alpha_rts", "beta2", "beta_ratio"):
         setattr(c, k, float(q[k]))
     c.r_crit = float(q.get("r_crit", 0.0))
+    for k in ("n_minor", "it_min", "it_max", "expand_layers", "local_fail", "global_limit",
+              "short_majors"):
+        if k in q:
+            setattr(c, k, int(q[k]))
+    if c.solver == RTS_PCISPH:
+        c.nbr_cap = int(q.get("nbr_cap", c.nbr_cap))
+    for k in ("eta", "eta_T", "delta", "r_list"):
+        if k in q:
+            setattr(c, k, float(q[k]))
     c.mass = float(q.get("mass", 0.0))
     c.B = float(q.get("B", 0.0))
     for d in range(3):

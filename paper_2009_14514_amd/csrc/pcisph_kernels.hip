@@ -1,0 +1,561 @@
+// HIP kernels of PCISPH with regional iteration counts on gfx950 (Goswami &
+// Batty, Section 5, Algorithms 2 and 3).
+//
+// A major step sorts the particles into a grid of edge 1.1 r once (the sort
+// kernels of the WCSPH path), assigns regions R_1..R_4 (block levels 0..3)
+// from Eq. 2-3, grows regions 1 and 2 by a few block layers, smooths with
+// R_min and marks the observed blocks.  Each minor step then
+//   lists        rebuilds the neighbour lists of particles whose validity ran
+//                out, against the grid of the major step (two block layers
+//                for region 1)
+//   nonpressure  gravity + viscosity of the same particles
+//   reset        p = 0, F^p = 0, S_e empty
+//   per iteration (the host reads the error reductions between iterations):
+//     predict    v* = v + dt (a_vg + a_p), x* = x + dt v*   (all)
+//     density    rho*, error, p += delta (rho* - rho0)      (turn, S_e, observed)
+//     mark_se    blocks around S_e particles join the observed set
+//     force      pressure acceleration                      (turn, S_e)
+//     errstats   max and mean compression, region counts
+//   integrate    symplectic Euler, validity, requests for smaller steps
+//   demote       blocks (and their particles) take the requested steps
+//
+// One thread per particle: the lists hold about 45 entries within 1.1 r and
+// neighbouring threads share most of them, so gathers hit the caches.  Sums
+// run in list order and the reductions are folded in a fixed order: runs are
+// deterministic.
+#include "rts_device.h"
+
+namespace rts {
+
+constexpr uint32_t kNoLevel = 0xFFFFFFFFu;
+
+__device__ inline int region_validity(int level, int major_len) {
+  // neighbourhoods: region 1 every minor step, region 2 every second one,
+  // regions 3 and 4 at the next major step
+  return level <= 1 ? level + 1 : major_len;
+}
+
+__device__ inline bool has_turn(uint32_t turn, uint32_t level) { return (turn >> level) & 1u; }
+
+// ---------------------------------------------------------------------------
+// major step: region dilation, observed blocks, particle flags
+// ---------------------------------------------------------------------------
+// Dilation of `level` by a cube of `layers` blocks, separated into x, y, z
+// passes over occupancy masks (exact for the Chebyshev cube).
+__global__ void k_pci_dil_x(DevParams p, const uint8_t *__restrict__ src, uint8_t *__restrict__ m1,
+                            int level, int layers) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.nb) return;
+  const int3 c = coords_of(p, (uint32_t)b);
+  uint8_t hit = 0;
+  for (int dx = -layers; dx <= layers; ++dx) {
+    const int x = c.x + dx;
+    if (x >= 0 && x < p.nc[0] && src[b + dx] == (uint8_t)level) hit = 1;
+  }
+  m1[b] = hit;
+}
+__global__ void k_pci_dil_y(DevParams p, const uint8_t *__restrict__ m1, uint8_t *__restrict__ m2,
+                            int layers) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.nb) return;
+  const int3 c = coords_of(p, (uint32_t)b);
+  uint8_t hit = 0;
+  for (int dy = -layers; dy <= layers; ++dy) {
+    const int y = c.y + dy;
+    if (y >= 0 && y < p.nc[1] && m1[b + dy * p.nc[0]]) hit = 1;
+  }
+  m2[b] = hit;
+}
+__global__ void k_pci_dil_z(DevParams p, const uint8_t *__restrict__ m2,
+                            const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, int level,
+                            int layers) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.nb) return;
+  const int3 c = coords_of(p, (uint32_t)b);
+  const int plane = p.nc[0] * p.nc[1];
+  uint8_t hit = 0;
+  for (int dz = -layers; dz <= layers; ++dz) {
+    const int z = c.z + dz;
+    if (z >= 0 && z < p.nc[2] && m2[b + dz * plane]) hit = 1;
+  }
+  const uint8_t l = src[b];
+  dst[b] = (l != kEmpty && l > (uint8_t)level && hit) ? (uint8_t)level : l;
+}
+
+// Observed blocks (Section 5, local density correction): occupied blocks
+// with an occupied neighbour of a smaller region.
+__global__ void k_pci_observed(DevParams p, const uint32_t *__restrict__ occ,
+                               const uint8_t *__restrict__ lvl, uint8_t *__restrict__ ob,
+                               const DevScalars *__restrict__ S) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= S->n_occ) return;
+  const uint32_t b = occ[q];
+  const int3 c = coords_of(p, b);
+  const uint8_t own = lvl[b];
+  uint8_t o = 0;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = c.x + dx, y = c.y + dy, z = c.z + dz;
+        if (x < 0 || y < 0 || z < 0 || x >= p.nc[0] || y >= p.nc[1] || z >= p.nc[2]) continue;
+        if (lvl[(uint32_t)(x + p.nc[0] * (y + p.nc[1] * z))] < own) o = 1;
+      }
+  ob[b] = o;
+}
+
+// Algorithm 2: every particle takes its block's region and rebuilds its
+// neighbourhood at the start of a major step.
+__global__ void k_pci_major_flags(DevParams p, const uint32_t *__restrict__ key,
+                                  const uint8_t *__restrict__ lvl, uint32_t *__restrict__ M,
+                                  int major_len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const uint32_t l = lvl[key[i]];
+  M[i] = meta_pack(l, 1u, 0u, region_validity((int)l, major_len));
+}
+
+// ---------------------------------------------------------------------------
+// minor step
+// ---------------------------------------------------------------------------
+// Neighbour lists against the grid of the major step (Section 5,
+// neighbourhood computation): blocks up to `rings` layers around the
+// particle's block, float predicate with the list radius, canonical order
+// (fluid by sorted index, then walls by wall sorted index | bit 31).
+__global__ void __launch_bounds__(256) k_pci_lists(
+    DevParams p, const float4 *__restrict__ P, const uint32_t *__restrict__ M,
+    const uint32_t *__restrict__ key, const uint32_t *__restrict__ start,
+    const float4 *__restrict__ WP, const uint32_t *__restrict__ wstart,
+    uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb, const uint32_t *__restrict__ ids,
+    DevScalars *S) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const uint32_t m = M[i];
+  if (!meta_compute(m)) return;
+  const int rings = (p.mode == RTS_MODE_RTS && meta_level(m) == 0u) ? 2 : 1;
+  const float4 xi = P[i];
+  const int3 c = coords_of(p, key[i]);
+  uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;
+  uint32_t cnt = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 && p.nw == 0) break;
+    const uint32_t *cs = pass == 0 ? start : wstart;
+    const float4 *X = pass == 0 ? P : WP;
+    const uint32_t tag = pass == 0 ? 0u : kWallBit;
+    for (int dz = -rings; dz <= rings; ++dz) {
+      const int z = c.z + dz;
+      if (z < 0 || z >= p.nc[2]) continue;
+      for (int dy = -rings; dy <= rings; ++dy) {
+        const int y = c.y + dy;
+        if (y < 0 || y >= p.nc[1]) continue;
+        const int x0 = max(c.x - rings, 0), x1 = min(c.x + rings, p.nc[0] - 1);
+        const uint32_t row = (uint32_t)p.nc[0] * ((uint32_t)y + (uint32_t)p.nc[1] * (uint32_t)z);
+        const uint32_t s0 = cs[row + (uint32_t)x0], s1 = cs[row + (uint32_t)x1 + 1u];
+        for (uint32_t j = s0; j < s1; ++j) {
+          if (pass == 0 && j == (uint32_t)i) continue;
+          const float4 q = X[j];
+          if (!(dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2l)) continue;
+          if (cnt < (uint32_t)p.nbr_cap) L[cnt] = j | tag;
+          ++cnt;
+        }
+      }
+    }
+  }
+  if (cnt > (uint32_t)p.nbr_cap) {
+    set_status(S, RTS_E_CAPACITY, (int32_t)ids[i]);
+    cnt = (uint32_t)p.nbr_cap;
+  }
+  nnb[i] = cnt;
+}
+
+// dW/dr / r, so that grad W(x_ij) = f * x_ij
+__device__ inline float grad_factor(const DevParams &p, float r2) {
+  const float r = __builtin_sqrtf(r2);
+  return p.sigma * p.inv_h * dw_shape(r * p.inv_h) / r;
+}
+
+// Gravity plus artificial viscosity (approaching pairs only; walls at rest).
+__global__ void __launch_bounds__(256) k_pci_nonpressure(
+    DevParams p, const float4 *__restrict__ P, const float4 *__restrict__ V,
+    const uint32_t *__restrict__ M, const uint32_t *__restrict__ nbr,
+    const uint32_t *__restrict__ nnb, const float4 *__restrict__ WP, float4 *__restrict__ fvg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n || !meta_compute(M[i])) return;
+  const float4 xi = P[i], vi = V[i];
+  const uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;
+  const uint32_t n = nnb[i];
+  const float rs2 = p.support * p.support;
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t j = L[k];
+    const bool wall = (j & kWallBit) != 0u;
+    const float4 q = wall ? WP[j & ~kWallBit] : P[j];
+    const float4 u = wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[j];
+    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float vx = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
+    if (!(r2 > 0.0f) || r2 >= rs2 || !(vx < 0.0f)) continue;
+    const float pij = -p.pci_nu * vx / (r2 + p.visc_eps_h2);
+    const float s = -p.mass * pij * grad_factor(p, r2);
+    ax += s * dx;
+    ay += s * dy;
+    az += s * dz;
+  }
+  fvg[i] = make_float4(p.g[0] + ax, p.g[1] + ay, p.g[2] + az, 0.0f);
+}
+
+__global__ void k_pci_reset(DevParams p, float4 *__restrict__ pv, float4 *__restrict__ fp,
+                            float *__restrict__ pq, uint8_t *__restrict__ se,
+                            uint8_t *__restrict__ nearse) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < p.n) {
+    pv[i] = make_float4(0.0f, 0.0f, 0.0f, p.rho0);
+    fp[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    pq[i] = 0.0f;
+    se[i] = 0;
+  }
+  if (i < p.nb) nearse[i] = 0;
+}
+
+__global__ void k_pci_predict(DevParams p, const float4 *__restrict__ P,
+                              const float4 *__restrict__ V, const float4 *__restrict__ fvg,
+                              const float4 *__restrict__ fp, float4 *__restrict__ xs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const float4 x = P[i], v = V[i], a = fvg[i], b = fp[i];
+  const float dt = p.dt_base;
+  const float vx = v.x + dt * (a.x + b.x), vy = v.y + dt * (a.y + b.y), vz = v.z + dt * (a.z + b.z);
+  xs[i] = make_float4(x.x + dt * vx, x.y + dt * vy, x.z + dt * vz, 0.0f);
+}
+
+// Algorithm 3, density prediction: particles with the turn, S_e and the
+// observed blocks.  rho* = m (W(0) + sum_j W + sum_walls W); the relative
+// excess is formed as (m sigma / rho0) ((sum - c_hi) - (comp + c_lo)) with
+// c = rho0 / (m sigma) - 1, before any rounding to rho*.
+__global__ void __launch_bounds__(256) k_pci_density(
+    DevParams p, const float4 *__restrict__ xs, float4 *__restrict__ pv, float *__restrict__ pq,
+    const uint32_t *__restrict__ M, const uint32_t *__restrict__ key,
+    const uint8_t *__restrict__ ob, const uint8_t *__restrict__ nearse,
+    uint8_t *__restrict__ se, const uint32_t *__restrict__ nbr, const uint32_t *__restrict__ nnb,
+    const float4 *__restrict__ WP, uint32_t turn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const uint32_t b = key[i];
+  const bool in_se = se[i] != 0;
+  if (!(has_turn(turn, meta_level(M[i])) || in_se || ob[b] || nearse[b])) return;
+  const float4 xi = xs[i];
+  const uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;
+  const uint32_t n = nnb[i];
+  float sum = 0.0f, comp = 0.0f;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t j = L[k];
+    const float4 q = (j & kWallBit) ? WP[j & ~kWallBit] : xs[j];
+    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float w = w_shape(__builtin_sqrtf(r2) * p.inv_h);
+    const float y = w - comp;
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+  }
+  const float dev = p.kms * ((sum - p.c_hi) - (comp + p.c_lo));
+  const float rho = p.rho0 + p.rho0 * dev;
+  float4 s = pv[i];
+  const float pn = s.x + p.delta * (p.rho0 * dev);
+  s.x = pn > 0.0f ? pn : 0.0f;
+  s.y = dev;
+  s.w = rho;
+  pv[i] = s;
+  pq[i] = s.x / (rho * rho);
+  if (dev > p.eta_half) se[i] = 1;
+}
+
+// S_ob gains the blocks holding or bordering an S_e particle.
+__global__ void k_pci_mark_se(DevParams p, const uint8_t *__restrict__ se,
+                              const uint32_t *__restrict__ key, uint8_t *__restrict__ nearse) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n || !se[i]) return;
+  const int3 c = coords_of(p, key[i]);
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = c.x + dx, y = c.y + dy, z = c.z + dz;
+        if (x < 0 || y < 0 || z < 0 || x >= p.nc[0] || y >= p.nc[1] || z >= p.nc[2]) continue;
+        nearse[(uint32_t)(x + p.nc[0] * (y + p.nc[1] * z))] = 1;
+      }
+}
+
+// Pressure acceleration -m sum_j (p_i/rho_i^2 + p_j/rho_j^2) grad W(x*_ij);
+// a wall particle mirrors p_i and rho_i.
+__global__ void __launch_bounds__(256) k_pci_force(
+    DevParams p, const float4 *__restrict__ xs, const float *__restrict__ pq,
+    const uint32_t *__restrict__ M, const uint8_t *__restrict__ se,
+    const uint32_t *__restrict__ nbr, const uint32_t *__restrict__ nnb,
+    const float4 *__restrict__ WP, float4 *__restrict__ fp, uint32_t turn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  if (!(has_turn(turn, meta_level(M[i])) || se[i])) return;
+  const float4 xi = xs[i];
+  const float qi = pq[i];
+  const uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;
+  const uint32_t n = nnb[i];
+  const float rs2 = p.support * p.support;
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t j = L[k];
+    const bool wall = (j & kWallBit) != 0u;
+    const float4 q = wall ? WP[j & ~kWallBit] : xs[j];
+    const float qj = wall ? qi : pq[j];
+    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 > 0.0f) || r2 >= rs2) continue;
+    const float s = -p.mass * (qi + qj) * grad_factor(p, r2);
+    ax += s * dx;
+    ay += s * dy;
+    az += s * dz;
+  }
+  fp[i] = make_float4(ax, ay, az, 0.0f);
+}
+
+// Max and mean compression over all particles (each keeps its latest
+// error) and particles per region; per-workgroup partials folded in a fixed
+// order by the last workgroup.
+__global__ void __launch_bounds__(256) k_pci_errstats(DevParams p, const float4 *__restrict__ pv,
+                                                     const uint32_t *__restrict__ M,
+                                                     PciPart *__restrict__ part, DevPci *pci) {
+  __shared__ PciPart s_w[4];
+  __shared__ uint32_t s_last;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float mx = 0.0f;
+  double sum = 0.0;
+  int32_t hist[4] = {0, 0, 0, 0}, ncomp = 0;
+  for (int i = blockIdx.x * blockDim.x + tid; i < p.n; i += gridDim.x * blockDim.x) {
+    const float e = fmaxf(pv[i].y, 0.0f);
+    mx = fmaxf(mx, e);
+    sum += (double)e;
+    const uint32_t m = M[i], l = meta_level(m);
+    ncomp += (int32_t)meta_compute(m);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hist[k] += l == (uint32_t)k ? 1 : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    sum += __shfl_xor(sum, o, 64);
+    ncomp += __shfl_xor(ncomp, o, 64);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hist[k] += __shfl_xor(hist[k], o, 64);
+  }
+  if (lane == 0) {
+    s_w[wave].errmax = mx;
+    s_w[wave].sum = sum;
+    s_w[wave].ncomp = ncomp;
+    for (int k = 0; k < 4; ++k) s_w[wave].hist[k] = hist[k];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    PciPart t = s_w[0];
+    for (int w = 1; w < 4; ++w) {
+      t.errmax = fmaxf(t.errmax, s_w[w].errmax);
+      t.sum += s_w[w].sum;
+      t.ncomp += s_w[w].ncomp;
+      for (int k = 0; k < 4; ++k) t.hist[k] += s_w[w].hist[k];
+    }
+    part[blockIdx.x] = t;
+    __threadfence();
+    s_last = atomicAdd(&pci->ticket, 1u) == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_last || tid != 0) return;
+  __threadfence();
+  PciPart a = part[0];
+  for (unsigned g = 1; g < gridDim.x; ++g) {
+    const PciPart u = part[g];
+    a.errmax = fmaxf(a.errmax, u.errmax);
+    a.sum += u.sum;
+    a.ncomp += u.ncomp;
+    for (int k = 0; k < 4; ++k) a.hist[k] += u.hist[k];
+  }
+  pci->ncomp = a.ncomp;
+  pci->errmax = a.errmax;
+  pci->avg = p.n > 0 ? a.sum / (double)p.n : 0.0;
+  for (int k = 0; k < 4; ++k) pci->hist[k] = a.hist[k];
+  pci->ticket = 0u;
+}
+
+// Pressure snapshot before local iterations, or its restoration.
+__global__ void k_pci_pressure_copy(DevParams p, float4 *__restrict__ pv, float *__restrict__ pq,
+                                    int to_backup) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  float4 s = pv[i];
+  if (to_backup) {
+    s.z = s.x;
+  } else {
+    s.x = s.z;
+    pq[i] = s.x / (s.w * s.w);
+  }
+  pv[i] = s;
+}
+
+// Algorithm 2 after the correction: new velocity and position, validity,
+// and the request of a smaller step for a particle whose speed or
+// acceleration no longer fits its region (its block and the 26 around it).
+__global__ void k_pci_integrate(DevParams p, float4 *__restrict__ P, float4 *__restrict__ V,
+                                float4 *__restrict__ A, uint32_t *__restrict__ M,
+                                const float4 *__restrict__ fvg, const float4 *__restrict__ fp,
+                                const float4 *__restrict__ pv, const float *__restrict__ pq,
+                                const uint32_t *__restrict__ key, uint32_t *__restrict__ dem,
+                                int major_len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const float dt = p.dt_base;
+  const float4 a0 = fvg[i], a1 = fp[i];
+  const float ax = a0.x + a1.x, ay = a0.y + a1.y, az = a0.z + a1.z;
+  float4 v = V[i], x = P[i];
+  v.x += dt * ax;
+  v.y += dt * ay;
+  v.z += dt * az;
+  x.x += dt * v.x;
+  x.y += dt * v.y;
+  x.z += dt * v.z;
+  x.w = pv[i].w;
+  v.w = pq[i];
+  P[i] = x;
+  V[i] = v;
+  A[i] = make_float4(ax, ay, az, 0.0f);
+  const uint32_t m = M[i];
+  const uint32_t l = meta_level(m);
+  int32_t val = meta_validity(m) - 1;
+  uint32_t comp = 0u;
+  if (val <= 0) {
+    comp = 1u;
+    val = region_validity((int)l, major_len);
+  }
+  M[i] = meta_pack(l, comp, 0u, val);
+  if (p.mode != RTS_MODE_RTS) return;
+  const float v2 = norm2_exact(v.x, v.y, v.z), a2 = norm2_exact(ax, ay, az);
+  uint32_t need = 0;
+  while ((int)need + 1 <= p.lmax && v2 <= p.TV[need + 1] && a2 <= p.TA[need + 1]) ++need;
+  if (need >= l) return;
+  const int3 c = coords_of(p, key[i]);
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int bx = c.x + dx, by = c.y + dy, bz = c.z + dz;
+        if (bx < 0 || by < 0 || bz < 0 || bx >= p.nc[0] || by >= p.nc[1] || bz >= p.nc[2])
+          continue;
+        atomicMin(&dem[(uint32_t)(bx + p.nc[0] * (by + p.nc[1] * bz))], need);
+      }
+}
+
+// Occupied blocks take the smallest requested level; every request is
+// cleared for the next minor step.
+__global__ void k_pci_demote_blocks(DevParams p, uint8_t *__restrict__ lvl,
+                                    uint32_t *__restrict__ dem) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.nb) return;
+  const uint32_t r = dem[b];
+  if (r == kNoLevel) return;
+  const uint8_t l = lvl[b];
+  if (l != kEmpty && r < (uint32_t)l) lvl[b] = (uint8_t)r;
+  dem[b] = kNoLevel;
+}
+__global__ void k_pci_demote_particles(DevParams p, const uint32_t *__restrict__ key,
+                                       const uint8_t *__restrict__ lvl, uint32_t *__restrict__ M,
+                                       int major_len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const uint32_t l = lvl[key[i]];
+  const uint32_t m = M[i];
+  if (l < meta_level(m)) M[i] = meta_pack(l, 1u, 0u, region_validity((int)l, major_len));
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+unsigned grid_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+}  // namespace
+
+void launch_pci_dilate(const DevParams &p, const DevPtrs &d, const uint8_t *src, uint8_t *dst,
+                       int level, int layers, hipStream_t st) {
+  const unsigned g = grid_of(p.nb, 256);
+  hipLaunchKernelGGL(k_pci_dil_x, dim3(g), dim3(256), 0, st, p, src, d.DIL1, level, layers);
+  hipLaunchKernelGGL(k_pci_dil_y, dim3(g), dim3(256), 0, st, p, d.DIL1, d.DIL2, layers);
+  hipLaunchKernelGGL(k_pci_dil_z, dim3(g), dim3(256), 0, st, p, d.DIL2, src, dst, level, layers);
+}
+void launch_pci_major_flags(const DevParams &p, const DevPtrs &d, int cur, int major_len,
+                            hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_major_flags, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.KEY,
+                     d.LVL, d.M[cur], major_len);
+}
+void launch_pci_observed(const DevParams &p, const DevPtrs &d, hipStream_t st) {
+  hipLaunchKernelGGL(k_pci_observed, dim3(grid_of(p.nb, 256)), dim3(256), 0, st, p, d.OCC, d.LVL,
+                     d.OB, d.S);
+}
+void launch_pci_lists(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_lists, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
+                     d.M[cur], d.KEY, d.CELL_START, d.WP, d.WCELL_START, d.NBRL, d.NNB, d.ID[cur],
+                     d.S);
+}
+void launch_pci_nonpressure(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_nonpressure, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
+                     d.V[cur], d.M[cur], d.NBRL, d.NNB, d.WP, d.FVG);
+}
+void launch_pci_reset(const DevParams &p, const DevPtrs &d, hipStream_t st) {
+  const int64_t m = p.n > p.nb ? p.n : p.nb;
+  hipLaunchKernelGGL(k_pci_reset, dim3(grid_of(m, 256)), dim3(256), 0, st, p, d.PV, d.FP, d.PQ,
+                     d.SE, d.NEARSE);
+}
+void launch_pci_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_predict, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
+                     d.V[cur], d.FVG, d.FP, d.XS);
+}
+void launch_pci_density(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
+                        hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_density, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.XS, d.PV,
+                     d.PQ, d.M[cur], d.KEY, d.OB, d.NEARSE, d.SE, d.NBRL, d.NNB, d.WP, turn);
+}
+void launch_pci_mark_se(const DevParams &p, const DevPtrs &d, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_mark_se, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.SE, d.KEY,
+                     d.NEARSE);
+}
+void launch_pci_force(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
+                      hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_force, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.XS, d.PQ,
+                     d.M[cur], d.SE, d.NBRL, d.NNB, d.WP, d.FP, turn);
+}
+void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
+  hipLaunchKernelGGL(k_pci_errstats, dim3(kPciStatBlocks), dim3(256), 0, st, p, d.PV, d.M[cur],
+                     d.PPART, d.PCI);
+}
+void launch_pci_pressure_copy(const DevParams &p, const DevPtrs &d, int to_backup,
+                              hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_pressure_copy, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.PV,
+                     d.PQ, to_backup);
+}
+void launch_pci_integrate(const DevParams &p, const DevPtrs &d, int cur, int major_len,
+                          hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_integrate, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
+                     d.V[cur], d.A[cur], d.M[cur], d.FVG, d.FP, d.PV, d.PQ, d.KEY, d.DEM,
+                     major_len);
+}
+void launch_pci_demote(const DevParams &p, const DevPtrs &d, int cur, int major_len,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_pci_demote_blocks, dim3(grid_of(p.nb, 256)), dim3(256), 0, st, p, d.LVL,
+                     d.DEM);
+  if (p.n > 0)
+    hipLaunchKernelGGL(k_pci_demote_particles, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p,
+                       d.KEY, d.LVL, d.M[cur], major_len);
+  launch_pci_observed(p, d, st);
+}
+
+}  // namespace rts

@@ -29,6 +29,14 @@ struct rts_ctx {
   bool has_state;
   bool poisoned;
   double mass, B, dt_base;
+  // PCISPH schedule state (host side: the correction loop is driven from here)
+  int pci_major_len, pci_minor_in_major, pci_clean, pci_excess;
+  bool pci_ready;        // the current major step has been set up
+  int64_t pci_steps, pci_iters_total;
+  double pci_time;
+  int32_t pci_last[6];   // iters, global iters, resets, reverts, early end, lists
+  double pci_errmax, pci_avg;
+  int32_t pci_hist[4];
   char err[512];
 };
 
@@ -79,10 +87,73 @@ double lattice_w_sum(const rts_config &c) {
 
 double r_crit_of(const rts_config &c) { return c.r_crit > 0.0 ? c.r_crit : c.support; }
 
+// Cubic spline shape derivative d w / d q.
+double dw_shape_d(double q) {
+  if (q < 1.0) return -3.0 * q + 2.25 * q * q;
+  if (q < 2.0) {
+    double t = 2.0 - q;
+    return -0.75 * t * t;
+  }
+  return 0.0;
+}
+
+// The PCISPH pressure coefficient of standard PCISPH (Solenthaler &
+// Pajarola), evaluated once over a particle with a full rest-lattice
+// neighbourhood: with g_j the kernel gradient towards lattice neighbour j,
+// G = sum_j g_j and Q = sum_j |g_j|^2, delta = 1 / (beta (|G|^2 + Q)),
+// beta = 2 (m dt / rho0)^2.
+double pci_delta(const rts_config &c, double mass, double dt) {
+  const double s = c.spacing, r = c.support;
+  const int m = (int)ceil(r / s) + 1;
+  double G[3] = {0.0, 0.0, 0.0}, Q = 0.0;
+  for (int k = -m; k <= m; ++k)
+    for (int j = -m; j <= m; ++j)
+      for (int i = -m; i <= m; ++i) {
+        if (!i && !j && !k) continue;
+        const double x[3] = {i * s, j * s, k * s};
+        const double d = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        if (d >= r) continue;
+        const double f = dw_shape_d(d / c.h) / (M_PI * c.h * c.h * c.h * c.h) / d;
+        for (int e = 0; e < 3; ++e) G[e] += f * x[e];
+        Q += f * f * d * d;
+      }
+  const double beta = 2.0 * (mass * dt / c.rho0) * (mass * dt / c.rho0);
+  return 1.0 / (beta * (G[0] * G[0] + G[1] * G[1] + G[2] * G[2] + Q));
+}
+
 rts_status validate(const rts_config *c, char *msg, size_t cap) {
   if (!c) { snprintf(msg, cap, "config is NULL"); return RTS_E_INVALID; }
-  if (c->solver != RTS_WCSPH) { snprintf(msg, cap, "solver %d not built", c->solver); return RTS_E_UNSUPPORTED; }
+  if (c->solver != RTS_WCSPH && c->solver != RTS_PCISPH) {
+    snprintf(msg, cap, "unknown solver %d", c->solver);
+    return RTS_E_INVALID;
+  }
   if (c->mode < 0 || c->mode > 2) { snprintf(msg, cap, "bad mode %d", c->mode); return RTS_E_INVALID; }
+  if (c->solver == RTS_PCISPH) {
+    if (c->mode == RTS_MODE_GLOBAL_ADAPTIVE) {
+      snprintf(msg, cap, "PCISPH runs regional (rts) or standard (global_fixed) stepping");
+      return RTS_E_UNSUPPORTED;
+    }
+    if (c->n_levels != 4) { snprintf(msg, cap, "PCISPH has 4 regions"); return RTS_E_INVALID; }
+    if (c->n_minor < 1 || c->n_minor > 16 || c->it_min < 1 || c->it_max < c->it_min ||
+        c->it_max > 1000 || c->expand_layers < 0 || c->expand_layers > 16 ||
+        c->local_fail < 1 || c->global_limit < 1 || c->short_majors < 1) {
+      snprintf(msg, cap, "PCISPH schedule parameters out of range");
+      return RTS_E_INVALID;
+    }
+    if (c->nbr_cap < 8 || c->nbr_cap > 4096) {
+      snprintf(msg, cap, "nbr_cap must be in [8, 4096]");
+      return RTS_E_INVALID;
+    }
+    if (!(c->eta > 0 && c->eta_T > 0 && c->dt_base > 0)) {
+      snprintf(msg, cap, "PCISPH needs eta, eta_T and dt_base > 0");
+      return RTS_E_INVALID;
+    }
+    const double rl = c->r_list > 0 ? c->r_list : c->block_edge;
+    if (!(rl >= c->support && rl <= c->block_edge)) {
+      snprintf(msg, cap, "r_list must lie in [support, block_edge]");
+      return RTS_E_INVALID;
+    }
+  }
   if (!(c->spacing > 0 && c->h > 0 && c->support > 0 && c->rho0 > 0 && c->c0 > 0)) {
     snprintf(msg, cap, "spacing, h, support, rho0 and c0 must be positive");
     return RTS_E_INVALID;
@@ -170,13 +241,25 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   // beta_1 = infinity, beta_n = beta2 * ratio^(n-2)):
   //   Eq. 3:  |v|^2 <= (alpha beta_{l+1} r / (2^l dt))^2
   //   Eq. 2:  |a|^2 <= (lambda_f^2 r / (2^l dt)^2)^2
+  // PCISPH region n = l + 1 steps n base steps instead (Section 5).
   for (int l = 0; l < kMaxLevels; ++l) {
-    double dtl = ldexp(dtb, l);
+    double dtl = c.solver == RTS_PCISPH ? dtb * (double)(l + 1) : ldexp(dtb, l);
     double bet = (l + 1 <= 1) ? INFINITY : c.beta2 * pow(c.beta_ratio, (double)(l + 1 - 2));
     double vl = isinf(bet) ? INFINITY : c.alpha_rts * bet * rc / dtl;
     double al = c.lambda_f * c.lambda_f * rc / (dtl * dtl);
     p.TV[l] = (float)(vl * vl);
     p.TA[l] = (float)(al * al);
+  }
+  p.solver = c.solver;
+  p.support = (float)c.support;
+  if (c.solver == RTS_PCISPH) {
+    p.nbr_cap = c.nbr_cap;
+    const double rl = c.r_list > 0.0 ? c.r_list : c.block_edge;
+    p.r2l = (float)(rl * rl);
+    p.delta = (float)(c.delta > 0.0 ? c.delta : pci_delta(c, mass, dtb));
+    p.eta_half = (float)(0.5 * c.eta);
+    p.pci_nu = (float)(c.visc_alpha * c.h * c.c0 / c.rho0);
+    p.w0m = (float)(mass * sigma);
   }
 }
 
@@ -211,7 +294,7 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.TMP = (uint32_t *)take(n * 4);
   t.PERM = (uint32_t *)take(n * 4);
   t.NNB = (uint32_t *)take(n * 4);
-  t.MASK = (uint32_t *)take(n * (size_t)(kSub * p.wpl) * 4);
+  t.MASK = (uint32_t *)take(p.solver == RTS_PCISPH ? 4 : n * (size_t)(kSub * p.wpl) * 4);
   t.COUNT = (uint32_t *)take(nb * 4);
   t.CELL_START = (uint32_t *)take((nb + 1) * 4);
   t.OCC = (uint32_t *)take(nb * 4);
@@ -233,6 +316,24 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.TILES2 = (unsigned long long *)take(ntiles * 8);
   t.CTRL = (DevCtrl *)take(sizeof(DevCtrl));
   t.S = (DevScalars *)take(sizeof(DevScalars));
+  const bool pci = p.solver == RTS_PCISPH;
+  const size_t np = pci ? n : 1, nbp = pci ? nb : 1;
+  t.XS = (float4 *)take(np * 16);
+  t.PV = (float4 *)take(np * 16);
+  t.FVG = (float4 *)take(np * 16);
+  t.FP = (float4 *)take(np * 16);
+  t.PQ = (float *)take(np * 4);
+  t.SE = (uint8_t *)take(np);
+  t.NBRL = (uint32_t *)take(np * (size_t)(pci ? p.nbr_cap : 1) * 4);
+  t.OB = (uint8_t *)take(nbp);
+  t.NEARSE = (uint8_t *)take(nbp);
+  t.DIL1 = (uint8_t *)take(nbp);
+  t.DIL2 = (uint8_t *)take(nbp);
+  t.DILT = (uint8_t *)take(nbp);
+  t.DILATED = (uint8_t *)take(nbp);
+  t.DEM = (uint32_t *)take(nbp * 4);
+  t.PPART = (PciPart *)take(sizeof(PciPart) * kPciStatBlocks);
+  t.PCI = (DevPci *)take(sizeof(DevPci));
   if (d) *d = t;
   return off;
 }
@@ -276,6 +377,148 @@ rts_status build_graphs(rts_ctx *c) {
   return RTS_OK;
 }
 
+// Figure "iterations" of Section 5 (the image is not part of the text we
+// work from): a schedule meeting every constraint the text states.  Bit l is
+// region l + 1; rows 1-3 of minor-step columns (a)-(d).
+uint32_t pci_turn(int col, int row) {
+  static const uint32_t table[3][4] = {{0xF, 0xF, 0xF, 0xF}, {0xF, 0x1, 0x3, 0x1},
+                                       {0x1, 0x1, 0x1, 0x1}};
+  if (row < 1 || row > 3 || col < 0 || col > 3) return 0u;
+  return table[row - 1][col];
+}
+
+// Algorithm 2, set-up of a major step: sort into the grid, regions from
+// Eq. 2-3, dilation of regions 1 and 2, R_min, observed blocks, flags.
+rts_status pci_major_begin(rts_ctx *c) {
+  const DevParams &p = c->prm;
+  const DevPtrs &d = c->d;
+  hipStream_t st = c->stream;
+  const int cur = c->cur, nx = cur ^ 1;
+  launch_key_hist(p, d, cur, st);
+  launch_scan(p, d, d.CELL_START, true, st);
+  launch_scatter(p, d, st);
+  launch_cell_gather(p, d, cur, c->grid_wave, st);
+  launch_pci_dilate(p, d, d.LRAW, d.DILT, 0, c->cfg.expand_layers, st);
+  launch_pci_dilate(p, d, d.DILT, d.DILATED, 1, c->cfg.expand_layers, st);
+  launch_rmin_flags(p, d, nx, 0, c->grid_wave, st, d.DILATED);
+  launch_pci_observed(p, d, st);
+  launch_pci_major_flags(p, d, nx, c->pci_major_len, st);
+  HIP_OK(c, hipGetLastError());
+  c->cur = nx;
+  c->pci_ready = true;
+  c->pci_excess = 0;
+  return RTS_OK;
+}
+
+rts_status pci_read(rts_ctx *c, DevPci *h) {
+  HIP_OK(c, hipMemcpyAsync(h, c->d.PCI, sizeof(DevPci), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return RTS_OK;
+}
+
+// One minor step of Algorithm 2 with the density correction of Algorithm 3.
+rts_status pci_minor_step(rts_ctx *c) {
+  const bool standard = c->cfg.mode != RTS_MODE_RTS;
+  if (standard) c->pci_major_len = 1;
+  if (!c->pci_ready) {
+    rts_status s = pci_major_begin(c);
+    if (s) return s;
+  }
+  const DevParams &p = c->prm;
+  const DevPtrs &d = c->d;
+  hipStream_t st = c->stream;
+  const int cur = c->cur, col = c->pci_minor_in_major;
+  int32_t lists = 0;
+  launch_pci_lists(p, d, cur, st);
+  launch_pci_nonpressure(p, d, cur, st);
+  launch_pci_reset(p, d, st);
+  HIP_OK(c, hipGetLastError());
+  int iter = 1, row = 1, min_iter = c->cfg.it_min, global = 1, local_iters = 0;
+  int global_iters = 0, resets = 0, reverts = 0;
+  double errmax = INFINITY, avg = 0.0;
+  const double eta = c->cfg.eta;
+  DevPci h;
+  while ((iter <= min_iter || errmax >= eta) && iter <= c->cfg.it_max) {
+    const uint32_t turn = standard ? 0xFu : (global ? pci_turn(col, row) : 0u);
+    launch_pci_predict(p, d, cur, st);
+    launch_pci_density(p, d, cur, turn, st);
+    launch_pci_mark_se(p, d, st);
+    launch_pci_force(p, d, cur, turn, st);
+    launch_pci_errstats(p, d, cur, st);
+    HIP_OK(c, hipGetLastError());
+    rts_status s = pci_read(c, &h);
+    if (s) return s;
+    if (iter == 1) lists = h.ncomp;   // compute flags are those of this minor step
+    if (global) ++global_iters;
+    ++iter;
+    ++row;
+    errmax = (double)h.errmax;
+    avg = h.avg;
+    // extra iterations after the three scheduled ones (Section 5)
+    if (errmax >= eta && iter > 3) {
+      ++min_iter;
+      if (standard) continue;
+      if (avg >= c->cfg.eta_T) {            // global error: restart the schedule
+        if (!global) {
+          launch_pci_pressure_copy(p, d, 0, st);
+          ++reverts;
+        }
+        global = 1;
+        row = 1;
+        ++resets;
+      } else if (global) {                  // local corrections on S_e
+        launch_pci_pressure_copy(p, d, 1, st);
+        global = 0;
+        local_iters = 0;
+      } else if (++local_iters >= c->cfg.local_fail) {
+        launch_pci_pressure_copy(p, d, 0, st);
+        global = 1;
+        row = 1;
+        ++reverts;
+      }
+    }
+  }
+  launch_pci_integrate(p, d, cur, c->pci_major_len, st);
+  if (!standard) launch_pci_demote(p, d, cur, c->pci_major_len, st);
+  launch_pci_errstats(p, d, cur, st);
+  HIP_OK(c, hipGetLastError());
+  rts_status s = pci_read(c, &h);
+  if (s) return s;
+  for (int k = 0; k < 4; ++k) c->pci_hist[k] = h.hist[k];
+  c->pci_last[0] = iter - 1;
+  c->pci_last[1] = global_iters;
+  c->pci_last[2] = resets;
+  c->pci_last[3] = reverts;
+  c->pci_last[5] = lists;
+  c->pci_errmax = errmax;
+  c->pci_avg = avg;
+  c->pci_iters_total += iter - 1;
+  c->pci_time += c->dt_base;
+  c->pci_steps += 1;
+  c->pci_minor_in_major += 1;
+  int early = 0;
+  if (!standard && global_iters > c->cfg.global_limit) {
+    c->pci_excess = 1;
+    if (c->pci_minor_in_major < c->pci_major_len) early = 1;
+  }
+  c->pci_last[4] = early;
+  if (c->pci_minor_in_major >= c->pci_major_len || early) {
+    c->pci_minor_in_major = 0;
+    c->pci_ready = false;
+    if (!standard) {
+      const int shortened = c->cfg.n_minor < 2 ? c->cfg.n_minor : 2;
+      if (c->pci_excess) {
+        c->pci_major_len = shortened;
+        c->pci_clean = 0;
+      } else if (c->pci_major_len < c->cfg.n_minor && ++c->pci_clean >= c->cfg.short_majors) {
+        c->pci_major_len = c->cfg.n_minor;
+        c->pci_clean = 0;
+      }
+    }
+  }
+  return RTS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -311,6 +554,18 @@ void rts_default_config(rts_config *c) {
   c->alpha_rts = 0.4;
   c->beta2 = 0.4;
   c->beta_ratio = 0.2;
+  c->n_minor = 4;
+  c->it_min = 3;
+  c->it_max = 50;
+  c->expand_layers = 4;
+  c->local_fail = 3;
+  c->global_limit = 6;
+  c->short_majors = 10;
+  c->nbr_cap = 128;
+  c->eta = 0.01;
+  c->eta_T = 0.0025;
+  c->delta = 0.0;
+  c->r_list = 0.0;
 }
 
 const char *rts_status_string(rts_status s) {
@@ -395,6 +650,12 @@ rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall
   if (e == hipSuccess) e = hipMemsetAsync(c->d.NNB, 0, (size_t)(n_fluid_max > 0 ? n_fluid_max : 1) * 4, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->d.WCELL_START, 0, ((size_t)c->prm.nb + 1) * 4, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->d.CTRL, 0, sizeof(DevCtrl), c->stream);
+  if (e == hipSuccess && cfg->solver == RTS_PCISPH) {
+    e = hipMemsetAsync(c->d.DEM, 0xFF, (size_t)c->prm.nb * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d.PCI, 0, sizeof(DevPci), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d.OB, 0, (size_t)c->prm.nb, c->stream);
+  }
+  c->pci_major_len = cfg->mode == RTS_MODE_RTS ? cfg->n_minor : 1;
   if (e != hipSuccess) {
     (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -430,6 +691,14 @@ rts_status rts_set_state(rts_ctx *c, const float *d_pos, const float *d_vel, int
   if (n > 0 && !d_pos) return fail(c, RTS_E_INVALID, "positions are NULL");
   c->prm.n = (int32_t)n;
   c->cur = 0;
+  c->pci_major_len = c->cfg.mode == RTS_MODE_RTS ? c->cfg.n_minor : 1;
+  c->pci_minor_in_major = 0;
+  c->pci_clean = 0;
+  c->pci_excess = 0;
+  c->pci_ready = false;
+  c->pci_steps = 0;
+  c->pci_iters_total = 0;
+  c->pci_time = 0.0;
   launch_reset_scalars(c->d.S, c->stream);
   launch_set_state(c->prm, c->d, 0, d_pos, d_vel, c->stream);
   HIP_OK(c, hipGetLastError());
@@ -443,14 +712,21 @@ rts_status rts_assign_levels(rts_ctx *c, int32_t *h_hist) {
   if (!c) return RTS_E_INVALID;
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
   const DevParams &p = c->prm;
-  const int cur = c->cur;
-  launch_key_hist(p, c->d, cur, c->stream);
-  launch_scan(p, c->d, c->d.CELL_START, true, c->stream);
-  launch_scatter(p, c->d, c->stream);
-  launch_cell_gather(p, c->d, cur, c->grid_wave, c->stream);
-  launch_rmin_flags(p, c->d, cur ^ 1, 0, c->grid_wave, c->stream);
-  HIP_OK(c, hipGetLastError());
-  c->cur = cur ^ 1;
+  if (c->cfg.solver == RTS_PCISPH) {
+    if (c->cfg.mode != RTS_MODE_RTS) c->pci_major_len = 1;
+    rts_status s = pci_major_begin(c);
+    if (s) return s;
+    c->pci_minor_in_major = 0;
+  } else {
+    const int cur = c->cur;
+    launch_key_hist(p, c->d, cur, c->stream);
+    launch_scan(p, c->d, c->d.CELL_START, true, c->stream);
+    launch_scatter(p, c->d, c->stream);
+    launch_cell_gather(p, c->d, cur, c->grid_wave, c->stream);
+    launch_rmin_flags(p, c->d, cur ^ 1, 0, c->grid_wave, c->stream);
+    HIP_OK(c, hipGetLastError());
+    c->cur = cur ^ 1;
+  }
   if (h_hist) {
     uint8_t *lv = (uint8_t *)malloc((size_t)p.nb);
     if (!lv) return RTS_E_DEVICE;
@@ -475,6 +751,13 @@ rts_status rts_advance(rts_ctx *c, int32_t n_steps) {
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
   if (c->poisoned) return fail(c, RTS_E_STATE, "state failed; set or load a state first");
   if (n_steps == 0) return RTS_OK;
+  if (c->cfg.solver == RTS_PCISPH) {
+    for (int32_t k = 0; k < n_steps; ++k) {
+      rts_status s = pci_minor_step(c);
+      if (s) return s;
+    }
+    return RTS_OK;
+  }
   if (c->cfg.use_graph && !c->graph_ok) {
     rts_status s = build_graphs(c);
     if (s) return s;
@@ -493,6 +776,8 @@ rts_status rts_advance(rts_ctx *c, int32_t n_steps) {
 
 rts_status rts_profile_advance(rts_ctx *c, int32_t n_steps, double *h_ms) {
   if (!c || n_steps < 0 || !h_ms) return RTS_E_INVALID;
+  if (c->cfg.solver == RTS_PCISPH)
+    return fail(c, RTS_E_UNSUPPORTED, "per-kernel profiling covers the WCSPH step");
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
   if (c->poisoned) return fail(c, RTS_E_STATE, "state failed; set or load a state first");
   hipEvent_t ev[RTS_PROF_COUNT + 1];
@@ -559,6 +844,24 @@ rts_status rts_sync(rts_ctx *c, rts_stats *out) {
     out->nbr_max = (int32_t)S.nbr_max;
     out->status = (int32_t)S.status;
     out->bad_index = bad;
+    if (c->cfg.solver == RTS_PCISPH) {
+      out->step = c->pci_steps;
+      out->time = c->pci_time;
+      out->dt_last = c->dt_base;
+      out->err_max_last = (float)c->pci_errmax;
+      for (int l = 0; l < RTS_MAX_LEVELS; ++l) out->level_hist[l] = l < 4 ? c->pci_hist[l] : 0;
+      out->pci_iters = c->pci_last[0];
+      out->pci_global_iters = c->pci_last[1];
+      out->pci_resets = c->pci_last[2];
+      out->pci_reverts = c->pci_last[3];
+      out->pci_early_end = c->pci_last[4];
+      out->pci_lists = c->pci_last[5];
+      out->pci_major_len = c->pci_major_len;
+      out->pci_minor_in_major = c->pci_minor_in_major;
+      out->pci_errmax = c->pci_errmax;
+      out->pci_avg = c->pci_avg;
+      out->pci_iters_total = c->pci_iters_total;
+    }
   }
   if (S.status) {
     c->poisoned = true;
@@ -586,6 +889,8 @@ rts_status rts_state_bytes(rts_ctx *c, size_t *bytes) {
 
 rts_status rts_save_state(rts_ctx *c, void *d_buf, size_t cap) {
   if (!c || !d_buf) return RTS_E_INVALID;
+  if (c->cfg.solver == RTS_PCISPH)
+    return fail(c, RTS_E_UNSUPPORTED, "save/load covers the WCSPH state");
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
   size_t need;
   rts_state_bytes(c, &need);
@@ -609,6 +914,8 @@ rts_status rts_save_state(rts_ctx *c, void *d_buf, size_t cap) {
 
 rts_status rts_load_state(rts_ctx *c, const void *d_buf, size_t len) {
   if (!c || !d_buf || len < 64) return RTS_E_INVALID;
+  if (c->cfg.solver == RTS_PCISPH)
+    return fail(c, RTS_E_UNSUPPORTED, "save/load covers the WCSPH state");
   int64_t hdr[8];
   HIP_OK(c, hipMemcpy(hdr, d_buf, 64, hipMemcpyDeviceToHost));
   if (hdr[0] != 0x5254535354415445LL || hdr[1] < 0 || hdr[1] > c->ncap || hdr[2] != c->prm.nb)
@@ -638,6 +945,7 @@ rts_status rts_debug_get(rts_ctx *c, int32_t what, void *d_out, size_t cap, size
   if (!c || !d_out) return RTS_E_INVALID;
   const size_t n = (size_t)c->prm.n, nb = (size_t)c->prm.nb, nw = (size_t)c->prm.nw;
   const int k = c->cur, pk = c->cur ^ 1;
+  const bool pci = c->cfg.solver == RTS_PCISPH;
   const void *src = nullptr;
   size_t count = 0, esz = 4;
   switch (what) {
@@ -673,6 +981,25 @@ rts_status rts_debug_get(rts_ctx *c, int32_t what, void *d_out, size_t cap, size
     case RTS_DBG_WALL_ID: src = c->d.WID; count = nw; break;
     case RTS_DBG_WALL_CELL_START: src = c->d.WCELL_START; count = nb + 1; break;
     case RTS_DBG_BLK_STATS: src = c->d.BLKU; count = nb; esz = 16; break;
+    case RTS_DBG_PCI_XS: src = c->d.XS; count = pci ? n : 0; esz = 16; break;
+    case RTS_DBG_PCI_PV: src = c->d.PV; count = pci ? n : 0; esz = 16; break;
+    case RTS_DBG_PCI_FVG: src = c->d.FVG; count = pci ? n : 0; esz = 16; break;
+    case RTS_DBG_PCI_FP: src = c->d.FP; count = pci ? n : 0; esz = 16; break;
+    case RTS_DBG_PCI_SE: src = c->d.SE; count = pci ? n : 0; esz = 1; break;
+    case RTS_DBG_PCI_OB: src = c->d.OB; count = pci ? nb : 0; esz = 1; break;
+    case RTS_DBG_PCI_DILATED: src = c->d.DILATED; count = pci ? nb : 0; esz = 1; break;
+    case RTS_DBG_PCI_LISTS: {
+      const size_t w = pci ? (size_t)c->prm.nbr_cap : 0;
+      count = pci ? n * (w + 1) : 0;
+      if (n_out) *n_out = count;
+      if (count * 4 > cap) return fail(c, RTS_E_CAPACITY, "debug view needs %zu bytes", count * 4);
+      if (count) {
+        HIP_OK(c, hipMemcpyAsync(d_out, c->d.NBRL, n * w * 4, hipMemcpyDeviceToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync((uint32_t *)d_out + n * w, c->d.NNB, n * 4,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      }
+      return RTS_OK;
+    }
     case RTS_DBG_OCCUPIED: {
       DevScalars S;
       HIP_OK(c, hipMemcpyAsync(&S, c->d.S, sizeof(S), hipMemcpyDeviceToHost, c->stream));

@@ -51,7 +51,33 @@ struct DevParams {
   double lf2r;           // lambda_f^2 r (adaptive comparator: dt^2 <= lf2r / |a|)
   int32_t lmax, mode, serna_correct, clamp_p;
   float TV[kMaxLevels], TA[kMaxLevels];
+  // PCISPH
+  int32_t solver;
+  int32_t nbr_cap;       // list entries per particle
+  float support;         // kernel support r
+  float r2l;             // list radius squared
+  float delta;           // pressure per unit density excess
+  float eta_half;        // S_e threshold: half the allowed compression
+  float pci_nu;          // artificial viscosity alpha h c0 / rho0
+  float w0m;             // m W(0), the self term of the density
 };
+
+// Reductions of one PCISPH correction iteration, read by the host.
+struct DevPci {
+  float errmax;          // max over particles of max(err, 0)
+  uint32_t ticket;       // last-workgroup detection of the fold (back to 0 after it)
+  double avg;            // mean over particles of max(err, 0)
+  int32_t hist[4];       // particles per region
+  int32_t ncomp;         // particles with the compute flag
+  int32_t pad;
+};
+struct PciPart {
+  float errmax;
+  int32_t ncomp;
+  double sum;
+  int32_t hist[4];
+};
+constexpr int kPciStatBlocks = 64;
 
 // Control words.  Zeroed once when the context is created and never reset
 // or restored afterwards: the scan epoch only grows, so look-back words left
@@ -139,6 +165,21 @@ struct DevPtrs {
   unsigned long long *TILES2;  // scan look-back words, occupied blocks
   DevCtrl *CTRL;
   DevScalars *S;
+  // PCISPH (one entry when the solver is WCSPH)
+  float4 *XS;        // predicted position x*
+  float4 *PV;        // pressure, relative density error, pressure backup, rho*
+  float4 *FVG;       // gravity + viscosity acceleration
+  float4 *FP;        // pressure acceleration
+  float *PQ;         // p / rho*^2
+  uint8_t *SE;       // member of S_e
+  uint32_t *NBRL;    // n x nbr_cap neighbour lists
+  uint8_t *OB;       // per block: observed
+  uint8_t *NEARSE;   // per block: holds or borders an S_e particle
+  uint8_t *DIL1, *DIL2;  // per block: dilation masks
+  uint8_t *DILT, *DILATED;  // per block: levels after the first / both dilations
+  uint32_t *DEM;     // per block: smallest level requested this minor step
+  PciPart *PPART;    // kPciStatBlocks partials
+  DevPci *PCI;
 };
 
 // Launchers (rts_kernels.hip).  All enqueue on `st`.
@@ -149,7 +190,7 @@ void launch_prep_scan(DevCtrl *ctrl, hipStream_t st);
 void launch_scatter(const DevParams &p, const DevPtrs &d, hipStream_t st);
 void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st);
 void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags, int grid,
-                       hipStream_t st);
+                       hipStream_t st, const uint8_t *src = nullptr);
 void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid,
                            hipStream_t st);
 void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st);
@@ -163,5 +204,28 @@ void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos,
                       float *acc, float *rho, float *pres, uint8_t *level, hipStream_t st);
 void launch_wall_sort(const DevParams &p, const DevPtrs &d, const float *pos, hipStream_t st);
 void launch_reset_scalars(DevScalars *S, hipStream_t st);
+
+// PCISPH launchers (pcisph_kernels.hip)
+void launch_pci_dilate(const DevParams &p, const DevPtrs &d, const uint8_t *src, uint8_t *dst,
+                       int level, int layers, hipStream_t st);
+void launch_pci_major_flags(const DevParams &p, const DevPtrs &d, int cur, int major_len,
+                            hipStream_t st);
+void launch_pci_observed(const DevParams &p, const DevPtrs &d, hipStream_t st);
+void launch_pci_lists(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_pci_nonpressure(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_pci_reset(const DevParams &p, const DevPtrs &d, hipStream_t st);
+void launch_pci_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_pci_density(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
+                        hipStream_t st);
+void launch_pci_mark_se(const DevParams &p, const DevPtrs &d, hipStream_t st);
+void launch_pci_force(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
+                      hipStream_t st);
+void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_pci_pressure_copy(const DevParams &p, const DevPtrs &d, int to_backup,
+                              hipStream_t st);
+void launch_pci_integrate(const DevParams &p, const DevPtrs &d, int cur, int major_len,
+                          hipStream_t st);
+void launch_pci_demote(const DevParams &p, const DevPtrs &d, int cur, int major_len,
+                       hipStream_t st);
 
 }  // namespace rts

@@ -110,13 +110,14 @@ def base_params(spacing, box_min, box_max, *, c0, layers=4, h_ratio=2.0,
         box_min=tuple(float(b) for b in box_min), box_max=tuple(float(b) for b in box_max),
         domain_min=tuple(float(b) - margin for b in box_min),
         domain_max=tuple(float(b) + margin for b in box_max),
-        dt_base=float(dt_base), r_crit=h, lambda_v=0.4, lambda_f=0.25,
+        dt_base=float(dt_base), r_crit=2.0 * spacing, lambda_v=0.4, lambda_f=0.25,
         alpha_rts=0.4 if solver == "wcsph" else 1.0, beta2=0.4, beta_ratio=0.2,
         n_levels=n_levels, level_cap=level_cap, clamp_p=1, serna_correct=1,
         wall_layers=layers,
         # PCISPH settings (unused by WCSPH)
         eta=0.01, eta_T=0.0025, it_min=3, it_max=50, n_minor=4, expand_layers=4,
-        local_fail_limit=3, global_reset_limit=6, clean_major_revert=10,
+        local_fail=3, global_limit=6, short_majors=10, delta=0.0, r_list=0.0,
+        nbr_cap=512,
     )
 
 
@@ -159,6 +160,18 @@ def dam_break_column(counts=(50, 100, 50), spacing=0.01, box=(2.0, 1.0, 1.0), se
                  box_walls(bmin, bmax, spacing, p["wall_layers"]), p)
 
 
+def pcisph_params(spacing, bmin, bmax, height, dt_base, mode="rts"):
+    """PCISPH runs take the paper's kernel support r = 2s (h = s) on a grid of
+    block edge 1.1 r = 2.2s, with two wall layers.  (At support 4s the
+    standard prototype-neighbourhood delta over-corrects and the iteration
+    diverges.)  c0 only scales the artificial viscosity."""
+    p = base_params(spacing, bmin, bmax, c0=sound_speed_for_column(height), layers=2,
+                    h_ratio=1.0, support_ratio=2.0, edge_ratio=1.1, dt_base=dt_base,
+                    solver="pcisph", level_cap=3, mode=mode)
+    p["nbr_cap"] = 128      # about 45 neighbours within 2.2s at rest
+    return p
+
+
 def double_dam_break(spacing=0.4 / 63, col=(0.4, 0.8, 0.4), box=(2.0, 1.0, 1.0), seed=0,
                      jitter_frac=0.005, dt_base=1e-3):
     """PCISPH double dam break: two columns at both x-ends of a 2 x 1 x 1 m box.
@@ -171,9 +184,36 @@ def double_dam_break(spacing=0.4 / 63, col=(0.4, 0.8, 0.4), box=(2.0, 1.0, 1.0),
     b = lattice_column(n, spacing, (box[0] - n[0] * spacing, 0.0, 0.0),
                        jitter=jitter_frac * spacing, seed=seed, first_index=a.shape[0])
     pos = np.concatenate([a, b], axis=0)
-    p = base_params(spacing, bmin, bmax, c0=sound_speed_for_column(col[1]), dt_base=dt_base,
-                    solver="pcisph", edge_ratio=1.1, level_cap=3)
+    p = pcisph_params(spacing, bmin, bmax, col[1], dt_base)
     return Scene(f"double_dam_break_{pos.shape[0]}", pos, np.zeros_like(pos),
+                 box_walls(bmin, bmax, spacing, p["wall_layers"]), p)
+
+
+def pcisph_dam_break_small(counts=(10, 20, 10), spacing=0.02, box=(0.8, 0.5, 0.3), seed=0,
+                           dt_base=1e-3, mode="rts", v0=0.0):
+    """Small PCISPH double dam break: two ``counts`` columns at both x-ends of
+    the box (4,000 particles by default), thrown at each other with speed
+    ``v0`` (m/s) along x."""
+    bmin, bmax = (0.0, 0.0, 0.0), tuple(float(b) for b in box)
+    a = lattice_column(counts, spacing, (0.0, 0.0, 0.0), jitter=0.005 * spacing, seed=seed)
+    b = lattice_column(counts, spacing, (box[0] - counts[0] * spacing, 0.0, 0.0),
+                       jitter=0.005 * spacing, seed=seed, first_index=a.shape[0])
+    pos = np.concatenate([a, b], axis=0)
+    vel = np.zeros_like(pos)
+    vel[: a.shape[0], 0] = v0
+    vel[a.shape[0]:, 0] = -v0
+    p = pcisph_params(spacing, bmin, bmax, counts[1] * spacing, dt_base, mode)
+    return Scene(f"pcisph_double_dam_break_{pos.shape[0]}", pos, vel,
+                 box_walls(bmin, bmax, spacing, p["wall_layers"]), p)
+
+
+def pcisph_column(counts=(8, 12, 8), spacing=0.02, box=(0.16, 0.5, 0.16), seed=0,
+                  dt_base=1e-3, mode="rts"):
+    """One PCISPH column at the x = 0 corner of the box."""
+    bmin, bmax = (0.0, 0.0, 0.0), tuple(float(b) for b in box)
+    pos = lattice_column(counts, spacing, bmin, jitter=0.005 * spacing, seed=seed)
+    p = pcisph_params(spacing, bmin, bmax, counts[1] * spacing, dt_base, mode)
+    return Scene(f"pcisph_column_{pos.shape[0]}", pos, np.zeros_like(pos),
                  box_walls(bmin, bmax, spacing, p["wall_layers"]), p)
 
 

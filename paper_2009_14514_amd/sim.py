@@ -129,6 +129,9 @@ class Simulation:
         "PRE_ID": (np.uint32, 1), "WALL_POS": (np.float32, 4), "WALL_ID": (np.uint32, 1),
         "WALL_CELL_START": (np.uint32, 1), "OCCUPIED": (np.uint32, 1),
         "BLK_STATS": (np.uint32, 4),
+        "PCI_XS": (np.float32, 4), "PCI_PV": (np.float32, 4), "PCI_FVG": (np.float32, 4),
+        "PCI_FP": (np.float32, 4), "PCI_SE": (np.uint8, 1), "PCI_OB": (np.uint8, 1),
+        "PCI_DILATED": (np.uint8, 1), "PCI_LISTS": (np.uint32, 1),
     }
 
     def debug(self, what: str) -> np.ndarray:
@@ -159,6 +162,13 @@ def neighbour_lists(sim):
     """Canonical lists of the last step's active particles: (rows (n, width), counts)."""
     raw = sim.debug("NBR")
     n, w = sim.n, _rts.DEBUG_NBR_ROW
+    return raw[: n * w].reshape(n, w), raw[n * w: n * w + n]
+
+
+def pcisph_lists(sim):
+    """PCISPH neighbour lists: (rows (n, nbr_cap), counts)."""
+    raw = sim.debug("PCI_LISTS")
+    n, w = sim.n, int(sim.cfg.nbr_cap)
     return raw[: n * w].reshape(n, w), raw[n * w: n * w + n]
 
 

@@ -1,0 +1,178 @@
+"""GPU parity of PCISPH with regional iteration counts against the oracle.
+
+Structure (keys, order, regions before and after dilation and R_min,
+observed blocks, flags, neighbour lists) is compared bit for bit on the same
+snapshot; the stages of a correction iteration (prediction, density,
+pressure, pressure force, non-pressure force) within 1e-5; short runs by
+their iteration counts and positions.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_14514_amd import scenes
+from paper_2009_14514_amd.sim import Simulation, decode_meta, pcisph_lists
+
+pytestmark = pytest.mark.gpu
+
+
+def scene(**kw):
+    return scenes.pcisph_dam_break_small(**kw)
+
+
+def developed(sim, steps):
+    sim.advance(steps)
+    sim.sync()
+
+
+def region_validity(level, major_len):
+    return np.where(level <= 1, level + 1, major_len)
+
+
+def expected_major(cfg, sim):
+    info = oracle.derive(cfg)
+    pre_pos = sim.debug("PRE_POS")[:, :3]
+    keys_old = oracle.keys(cfg, pre_pos)
+    perm, start = oracle.sort(info.nblocks, keys_old)
+    raw, lvl, ob = oracle.pci_regions(cfg, keys_old, sim.debug("PRE_VEL")[:, :3],
+                                      sim.debug("PRE_ACC")[:, :3])
+    t1 = oracle.pci_dilate(cfg, raw, 0, cfg.expand_layers)
+    dil = oracle.pci_dilate(cfg, t1, 1, cfg.expand_layers)
+    return dict(perm=perm, start=start, keys=keys_old[perm], raw=raw, dil=dil, lvl=lvl, ob=ob)
+
+
+@pytest.mark.parametrize("steps", [0, 40, 120])
+def test_major_step_setup_is_bit_exact(steps):
+    sc = scene()
+    sim = Simulation(sc)
+    if steps:
+        developed(sim, steps)
+    sim.assign_levels()
+    cfg = oracle.cfg_from_params(sc.params)
+    exp = expected_major(cfg, sim)
+    assert np.array_equal(sim.debug("PERM"), exp["perm"])
+    assert np.array_equal(sim.debug("KEY"), exp["keys"])
+    assert np.array_equal(sim.debug("CELL_START"), exp["start"])
+    assert np.array_equal(sim.debug("BLK_LEVEL_RAW"), exp["raw"])
+    assert np.array_equal(sim.debug("PCI_DILATED"), exp["dil"])
+    assert np.array_equal(sim.debug("BLK_LEVEL"), exp["lvl"])
+    occ = np.unique(exp["keys"])
+    assert np.array_equal(sim.debug("PCI_OB")[occ], exp["ob"][occ])
+    level, comp, _, val = decode_meta(sim.debug("META"))
+    want_level = exp["lvl"][exp["keys"]].astype(np.int32)
+    assert np.array_equal(level, want_level)
+    assert np.all(comp == 1)
+    major_len = sim.sync().pci_major_len
+    assert np.array_equal(val, region_validity(want_level, major_len))
+
+
+def first_iteration(v0):
+    """One minor step with exactly one correction iteration from a major-step
+    set-up, so that every particle is evaluated once from the stored
+    snapshot.  Columns thrown at v0 = 10 m/s put every block in region 1
+    (two-layer search); at 1.5 m/s the blocks take regions 2-3."""
+    sc = scene(v0=v0)
+    over = dict(it_min=1, it_max=1)
+    sim = Simulation(sc, **over)
+    sim.assign_levels()
+    before = {k: sim.debug(k) for k in ("POS", "VEL", "META", "KEY", "CELL_START")}
+    sim.advance(1)
+    sim.sync()
+    cfg = oracle.cfg_from_params(sc.params, **over)
+    return sc, sim, cfg, before
+
+
+@pytest.mark.parametrize("v0", [1.5, 10.0])
+def test_lists_match_the_oracle_on_the_stored_grid(v0):
+    sc, sim, cfg, before = first_iteration(v0)
+    rows, counts = pcisph_lists(sim)
+    level, comp, _, _ = decode_meta(before["META"])
+    rings = np.where(level == 0, 2, 1).astype(np.uint8)
+    wpos = sim.debug("WALL_POS")[:, :3]
+    st, nbr, nnb = oracle.pci_lists(cfg, before["POS"][:, :3], before["CELL_START"], before["KEY"],
+                                    wpos, sim.debug("WALL_CELL_START"), want=comp, rings=rings)
+    assert st == 0
+    assert np.array_equal(counts, nnb.astype(np.uint32))
+    for i in range(sim.n):
+        assert np.array_equal(rows[i, :counts[i]], nbr[i, :nnb[i]]), f"list of particle {i}"
+    assert np.all(level == 0) if v0 > 8.0 else not np.any(level == 0)
+
+
+@pytest.mark.parametrize("v0", [1.5, 10.0])
+def test_iteration_stages_match_the_oracle(v0):
+    sc, sim, cfg, before = first_iteration(v0)
+    info = oracle.derive(cfg)
+    rows, counts = pcisph_lists(sim)
+    nbr = np.zeros((sim.n, cfg.nbr_cap), np.uint32)
+    nbr[:, :] = rows
+    nnb = counts.astype(np.int32)
+    wx = sim.debug("WALL_POS")[:, :3].astype(np.float64)
+    x0 = before["POS"][:, :3].astype(np.float64)
+    u0 = before["VEL"][:, :3].astype(np.float64)
+    fvg = sim.debug("PCI_FVG")[:, :3].astype(np.float64)
+    # non-pressure acceleration from the snapshot
+    want = oracle.pci_nonpressure(cfg, x0, u0, wx, nbr, nnb)
+    g = np.asarray(cfg.g)
+    scale = np.abs(want - g).max() + 1e-3
+    assert np.abs(fvg - want).max() <= 1e-5 * max(scale, np.abs(g).max())
+    # prediction (iteration 1: no pressure acceleration yet)
+    xs = sim.debug("PCI_XS")[:, :3].astype(np.float64)
+    dt = info.dt_base
+    want_xs = x0 + dt * (u0 + dt * fvg)
+    assert np.abs(xs - want_xs).max() <= 1e-6 * np.abs(x0).max()
+    # density at the GPU's predicted positions
+    pv = sim.debug("PCI_PV").astype(np.float64)
+    rho = oracle.pci_density(cfg, xs, wx, nbr, nnb)
+    assert np.abs(pv[:, 3] - rho).max() / cfg.rho0 <= 1e-5
+    # pressure update from the GPU density (p was reset to zero)
+    p_want = np.maximum(0.0, info.delta * (pv[:, 3] - cfg.rho0))
+    assert np.abs(pv[:, 0] - p_want).max() <= 1e-5 * max(p_want.max(), 1.0)
+    # pressure acceleration from the GPU's x*, p, rho*
+    fp = sim.debug("PCI_FP")[:, :3].astype(np.float64)
+    want_fp = oracle.pci_pressure_force(cfg, xs, wx, pv[:, 0], pv[:, 3], nbr, nnb)
+    mag = np.linalg.norm(want_fp, axis=1)
+    assert np.abs(fp - want_fp).max() <= 1e-5 * max(mag.max(), 1.0)
+
+
+@pytest.mark.parametrize("mode", ["rts", "global_fixed"])
+def test_short_runs_follow_the_oracle(mode):
+    sc = scene(mode=mode)
+    sim = Simulation(sc)
+    ref = oracle.PCISPH(sc.params, sc.pos.astype(np.float32), vel=sc.vel,
+                        walls=sc.walls.astype(np.float32))
+    for k in range(12):
+        sim.advance(1)
+        st = sim.sync()
+        ref.step()
+        h = ref.history[-1]
+        assert st.pci_iters == h["iters"], f"step {k}: iterations {st.pci_iters} vs {h['iters']}"
+        assert st.pci_lists == h["lists"], f"step {k}"
+        assert list(st.level_hist)[:4] == h["hist"], f"step {k}"
+        assert st.pci_major_len == h["major_len"] and st.pci_minor_in_major == h["minor_in_major"]
+    x_gpu = sim.state()["pos"]
+    x_ref = ref.in_caller_order(ref.x)
+    assert np.abs(x_gpu - x_ref).max() <= 1e-4 * sc.params["spacing"]
+
+
+def test_regions_develop_and_errors_stay_bounded():
+    sc = scene()
+    sim = Simulation(sc)
+    seen = set()
+    for k in range(40):
+        sim.advance(4)
+        st = sim.sync()
+        seen |= {l for l in range(4) if st.level_hist[l] > 0}
+        assert st.pci_errmax < sc.params["eta"] or st.pci_iters == sc.params["it_max"]
+    assert len(seen) >= 3
+    s = sim.state()
+    assert np.all(np.isfinite(s["pos"]))
+
+
+def test_density_error_of_a_resting_column_stays_below_eta():
+    sc = scenes.pcisph_column()
+    sim = Simulation(sc)
+    for k in range(12):
+        sim.advance(1)
+        st = sim.sync()
+        assert st.pci_iters >= 3
+        assert st.pci_errmax < sc.params["eta"]
