@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--only-rts", action="store_true",
                     help="time the RTS run only (for profiler runs); prints no JSON line")
+    ap.add_argument("--pcisph-steps", type=int, default=200,
+                    help="minor steps of the PCISPH double dam break (0: skip it)")
+    ap.add_argument("--only-pcisph", action="store_true",
+                    help="run the PCISPH comparison only (for profiler runs); no JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run an elementwise copy of 256 MiB three times, the "
                          "reference kernel for scaling HBM byte counters")
@@ -184,6 +188,50 @@ def run_gpu(args):
     return out
 
 
+def run_pcisph(steps):
+    """RTS PCISPH vs standard PCISPH on the 1,000,188-particle double dam break.
+
+    Both arms run the same minor steps from rest (so equal simulated time);
+    the correction loop reads its error reductions between iterations, so
+    each minor step is timed by wall clock around a completed call.
+    """
+    import torch
+
+    from paper_2009_14514_amd import scenes
+    from paper_2009_14514_amd.sim import Simulation
+
+    out = {}
+    for mode in ("rts", "global_fixed"):
+        sc = scenes.double_dam_break()
+        sc.params["mode"] = mode
+        sim = Simulation(sc)
+        sim.advance(1)                       # first major step set-up and lists: warm-up
+        sim.sync()
+        sim.set_state(sc.pos, sc.vel)        # back to rest
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.advance(steps)
+        st = sim.sync()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[mode] = dict(n=sc.n, ms=el * 1e3, iters=int(st.pci_iters_total), time=st.time,
+                         errmax=float(st.pci_errmax), hist=list(st.level_hist)[:4])
+        print(f"[bench] pcisph {mode}: {steps} minor steps in {el * 1e3:.1f} ms, "
+              f"{st.pci_iters_total} iterations", file=sys.stderr, flush=True)
+        sim.close()
+    r, g = out["rts"], out["global_fixed"]
+    n = r["n"]
+    return {
+        "workload": "pcisph_rts_double_dam_break_1m", "n_particles": n, "minor_steps": steps,
+        "dt_base_s": 5e-4, "unit": "particle-steps/s",
+        "value": n * steps / (r["ms"] * 1e-3), "ms_per_step": r["ms"] / steps,
+        "iterations": r["iters"], "density_err_last": r["errmax"],
+        "standard_pcisph": {"value": n * steps / (g["ms"] * 1e-3), "ms_per_step": g["ms"] / steps,
+                            "iterations": g["iters"], "density_err_last": g["errmax"]},
+        "speedup_vs_standard": g["ms"] / r["ms"],
+    }
+
+
 def run_cpu_baseline(budget_s):
     """FP64 oracle, RTS mode, on the first steps of the same workload."""
     import numpy as np
@@ -214,6 +262,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.only_pcisph:
+        run_pcisph(args.pcisph_steps)
+        return
     g = run_gpu(args)
     if g is None:
         return
@@ -274,6 +325,8 @@ def main():
         line["phase_split"] = {"grid_and_search_share": None,
                                "T_grid": tn / tot, "T_search_density_force": tp / tot,
                                "T_rts_flags": tr / tot, "T_integrate": ti / tot}
+    if args.pcisph_steps > 0:
+        line["pcisph"] = run_pcisph(args.pcisph_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = run_cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

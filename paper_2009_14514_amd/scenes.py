@@ -173,10 +173,13 @@ def pcisph_params(spacing, bmin, bmax, height, dt_base, mode="rts"):
 
 
 def double_dam_break(spacing=0.4 / 63, col=(0.4, 0.8, 0.4), box=(2.0, 1.0, 1.0), seed=0,
-                     jitter_frac=0.005, dt_base=1e-3):
+                     jitter_frac=0.005, dt_base=5e-4):
     """PCISPH double dam break: two columns at both x-ends of a 2 x 1 x 1 m box.
 
     At spacing 0.4/63 m each column is 63 x 126 x 63 (1,000,188 particles total).
+    The base step is 5e-4 s: at 1e-3 s standard PCISPH itself diverges at
+    this spacing within 0.1 s (the column sinks into the two-layer floor),
+    while 5e-4 s keeps both standard and regional PCISPH below 1 %.
     """
     n = tuple(int(round(c / spacing)) for c in col)
     bmin, bmax = (0.0, 0.0, 0.0), tuple(float(b) for b in box)
