@@ -41,6 +41,8 @@ def parse():
                     help="minor steps of the PCISPH double dam break (0: skip it)")
     ap.add_argument("--only-pcisph", action="store_true",
                     help="run the PCISPH comparison only (for profiler runs); no JSON line")
+    ap.add_argument("--batch-steps", type=int, default=100,
+                    help="base steps of the 64-scene batch and of its sequential runs (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run an elementwise copy of 256 MiB three times, the "
                          "reference kernel for scaling HBM byte counters")
@@ -232,6 +234,53 @@ def run_pcisph(steps):
     }
 
 
+def run_batched(steps):
+    """64 dam-break scenes of uneven size advanced together by one graph
+    replay per base step (launch shape autotuned), against the same scenes
+    run one after another, each by its own context."""
+    import torch
+
+    from paper_2009_14514_amd import scenes
+    from paper_2009_14514_amd.sim import Simulation
+
+    sc = scenes.batched_dam_breaks()
+    sim = Simulation(sc)
+    tune = sim.autotune(steps=3)
+    sim.advance(1)
+    sim.sync()
+    sim.set_state(sc.pos, sc.vel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.advance(steps)
+    st = sim.sync()
+    ms_batch = (time.perf_counter() - t0) * 1e3
+    err = float(st.err_max_run)
+    sim.close()
+    del sim
+    ms_seq = 0.0
+    for sub in sc.subscenes:
+        one = Simulation(sub)
+        one.advance(1)
+        one.sync()
+        one.set_state(sub.pos, sub.vel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one.advance(steps)
+        one.sync()
+        ms_seq += (time.perf_counter() - t0) * 1e3
+        one.close()
+    print(f"[bench] batch: {len(sc.subscenes)} scenes, {sc.n} particles, {steps} steps in "
+          f"{ms_batch:.1f} ms; sequential {ms_seq:.1f} ms", file=sys.stderr, flush=True)
+    return {
+        "workload": "wcsph_rts_batch_64_dam_breaks", "n_scenes": len(sc.subscenes),
+        "n_particles": sc.n, "base_steps": steps, "unit": "particle-steps/s",
+        "value": sc.n * steps / (ms_batch * 1e-3), "ms_per_step": ms_batch / steps,
+        "sequential": {"value": sc.n * steps / (ms_seq * 1e-3), "ms_per_step": ms_seq / steps},
+        "speedup_vs_sequential": ms_seq / ms_batch, "density_err_max": err,
+        "launch_shape": tune,
+    }
+
+
 def run_cpu_baseline(budget_s):
     """FP64 oracle, RTS mode, on the first steps of the same workload."""
     import numpy as np
@@ -327,6 +376,8 @@ def main():
                                "T_rts_flags": tr / tot, "T_integrate": ti / tot}
     if args.pcisph_steps > 0:
         line["pcisph"] = run_pcisph(args.pcisph_steps)
+    if args.batch_steps > 0:
+        line["batched"] = run_batched(args.batch_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = run_cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -265,6 +265,26 @@ typedef enum {
 } rts_prof_kernel;
 rts_status rts_profile_advance(rts_ctx *ctx, int32_t n_steps, double *h_ms);
 
+/* Launch shape of the base step: workgroups of the one-wave-per-block
+ * kernels, of the search + density kernel and of the force kernel. */
+typedef struct rts_tune {
+  int32_t grid_wave;
+  int32_t grid_search;
+  int32_t grid_force;
+  int32_t candidates;     /* shapes timed by rts_autotune */
+  double ms_per_step;     /* replay time of the chosen shape */
+} rts_tune;
+
+/* Times `steps` base steps (WCSPH) under each candidate launch shape from
+ * the current state and keeps the fastest; the state is saved to d_scratch
+ * (at least rts_state_bytes) before and restored after every candidate, so
+ * the run continues exactly as if no tuning had happened (results do not
+ * depend on the launch shape).  Waits for the stream. */
+rts_status rts_autotune(rts_ctx *ctx, int32_t steps, void *d_scratch, size_t scratch_bytes,
+                        rts_tune *h_out);
+/* Current launch shape (h_out->candidates = 0, ms_per_step = 0 until tuned). */
+rts_status rts_get_tune(rts_ctx *ctx, rts_tune *h_out);
+
 const char *rts_last_error(const rts_ctx *ctx);
 const char *rts_status_string(rts_status s);
 

@@ -31,7 +31,7 @@ EXPORTS = [
     "rts_default_config", "rts_workspace_size", "rts_create", "rts_destroy", "rts_set_walls",
     "rts_set_state", "rts_assign_levels", "rts_advance", "rts_sync", "rts_get_state",
     "rts_state_bytes", "rts_save_state", "rts_load_state", "rts_debug_get", "rts_grid_info",
-    "rts_profile_advance", "rts_last_error", "rts_status_string",
+    "rts_profile_advance", "rts_autotune", "rts_get_tune", "rts_last_error", "rts_status_string",
 ]
 PROF_KERNELS = ["key_hist", "scan", "scatter", "cell_gather", "rmin_flags", "search_density",
                 "force", "step_stats", "correct_predict"]
@@ -76,6 +76,14 @@ class RtsStats(C.Structure):
         return d
 
 
+class RtsTune(C.Structure):
+    _fields_ = [("grid_wave", C.c_int32), ("grid_search", C.c_int32), ("grid_force", C.c_int32),
+                ("candidates", C.c_int32), ("ms_per_step", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -112,6 +120,8 @@ def lib():
         L.rts_debug_get.argtypes = [vp, i32, vp, C.c_size_t, C.POINTER(C.c_size_t)]
         L.rts_grid_info.argtypes = [vp, vp, vp, vp, vp, vp]
         L.rts_profile_advance.argtypes = [vp, i32, C.POINTER(C.c_double)]
+        L.rts_autotune.argtypes = [vp, i32, vp, C.c_size_t, C.POINTER(RtsTune)]
+        L.rts_get_tune.argtypes = [vp, C.POINTER(RtsTune)]
         L.rts_last_error.argtypes = [vp]
         L.rts_last_error.restype = C.c_char_p
         L.rts_status_string.argtypes = [C.c_int]
@@ -257,6 +267,18 @@ def profile_advance(ctx, n_steps):
     ms = (C.c_double * len(PROF_KERNELS))()
     check(lib().rts_profile_advance(ctx, int(n_steps), ms), ctx)
     return dict(zip(PROF_KERNELS, list(ms)))
+
+
+def autotune(ctx, steps, d_scratch, nbytes):
+    t = RtsTune()
+    check(lib().rts_autotune(ctx, int(steps), C.c_void_p(d_scratch), int(nbytes), C.byref(t)), ctx)
+    return t.as_dict()
+
+
+def get_tune(ctx):
+    t = RtsTune()
+    check(lib().rts_get_tune(ctx, C.byref(t)), ctx)
+    return t.as_dict()
 
 
 def last_error(ctx):

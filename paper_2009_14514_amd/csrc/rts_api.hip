@@ -37,6 +37,8 @@ struct rts_ctx {
   int32_t pci_last[6];   // iters, global iters, resets, reverts, early end, lists
   double pci_errmax, pci_avg;
   int32_t pci_hist[4];
+  int tune_candidates;
+  double tune_ms;
   char err[512];
 };
 
@@ -921,6 +923,7 @@ rts_status rts_load_state(rts_ctx *c, const void *d_buf, size_t len) {
   if (hdr[0] != 0x5254535354415445LL || hdr[1] < 0 || hdr[1] > c->ncap || hdr[2] != c->prm.nb)
     return fail(c, RTS_E_INVALID, "buffer does not hold a state for this context");
   size_t n = (size_t)hdr[1];
+  const bool same_n = c->prm.n == (int32_t)n;
   c->prm.n = (int32_t)n;
   size_t need;
   rts_state_bytes(c, &need);
@@ -935,7 +938,8 @@ rts_status rts_load_state(rts_ctx *c, const void *d_buf, size_t len) {
   HIP_OK(c, hipMemcpyAsync(c->d.ID[0], b + off, n * 4, hipMemcpyDeviceToDevice, c->stream)); off += n * 4;
   HIP_OK(c, hipMemcpyAsync(c->d.PRES, b + off, n * 4, hipMemcpyDeviceToDevice, c->stream)); off += n * 4;
   HIP_OK(c, hipMemcpyAsync(c->d.S, b + off, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
-  destroy_graphs(c);
+  // the graphs hold the particle count; buffers and both parities are fixed
+  if (!same_n) destroy_graphs(c);
   c->has_state = true;
   c->poisoned = false;
   return RTS_OK;
@@ -1013,6 +1017,88 @@ rts_status rts_debug_get(rts_ctx *c, int32_t what, void *d_out, size_t cap, size
   if (n_out) *n_out = count;
   if (count * esz > cap) return fail(c, RTS_E_CAPACITY, "debug view needs %zu bytes", count * esz);
   if (count) HIP_OK(c, hipMemcpyAsync(d_out, src, count * esz, hipMemcpyDeviceToDevice, c->stream));
+  return RTS_OK;
+}
+
+rts_status rts_get_tune(rts_ctx *c, rts_tune *out) {
+  if (!c || !out) return RTS_E_INVALID;
+  out->grid_wave = c->grid_wave;
+  out->grid_search = c->grid_search;
+  out->grid_force = c->grid_force;
+  out->candidates = c->tune_candidates;
+  out->ms_per_step = c->tune_ms;
+  return RTS_OK;
+}
+
+rts_status rts_autotune(rts_ctx *c, int32_t steps, void *d_scratch, size_t scratch_bytes,
+                        rts_tune *out) {
+  if (!c || steps < 1 || !d_scratch) return RTS_E_INVALID;
+  if (c->cfg.solver != RTS_WCSPH)
+    return fail(c, RTS_E_UNSUPPORTED, "the launch shape is tuned for the WCSPH step");
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  if (c->poisoned) return fail(c, RTS_E_STATE, "state failed; set or load a state first");
+  size_t need = 0;
+  rts_state_bytes(c, &need);
+  if (scratch_bytes < need)
+    return fail(c, RTS_E_CAPACITY, "scratch holds %zu of %zu bytes", scratch_bytes, need);
+  rts_status s = rts_save_state(c, d_scratch, scratch_bytes);
+  if (s) return s;
+  int dev = 0;
+  HIP_OK(c, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_OK(c, hipGetDeviceProperties(&prop, dev));
+  const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  // candidate workgroup counts per CU of the three launch groups
+  const int wave_m[] = {4, 8};
+  const int search_m[] = {2, 3, 4, 6};
+  const int force_m[] = {1, 2, 3, 4};
+  int best[3] = {c->grid_wave, c->grid_search, c->grid_force};
+  double best_ms = INFINITY;
+  int cand = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  for (int a = 0; a < 2 && !s && he == hipSuccess; ++a)
+    for (int b = 0; b < 4 && !s && he == hipSuccess; ++b)
+      for (int f = 0; f < 4 && !s && he == hipSuccess; ++f) {
+        c->grid_wave = cus * wave_m[a];
+        c->grid_search = cus * search_m[b];
+        c->grid_force = cus * force_m[f];
+        destroy_graphs(c);
+        if (c->cfg.use_graph) s = build_graphs(c);
+        if (!s) s = rts_advance(c, 1);                 // first replay of the new shape
+        if (!s) s = rts_load_state(c, d_scratch, need);
+        if (s) break;
+        he = hipEventRecord(e0, c->stream);
+        if (he == hipSuccess) s = rts_advance(c, steps);
+        if (!s && he == hipSuccess) he = hipEventRecord(e1, c->stream);
+        if (!s && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (!s && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (s || he != hipSuccess) break;
+        ++cand;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best[0] = c->grid_wave;
+          best[1] = c->grid_search;
+          best[2] = c->grid_force;
+        }
+        s = rts_load_state(c, d_scratch, need);
+      }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  c->grid_wave = best[0];
+  c->grid_search = best[1];
+  c->grid_force = best[2];
+  destroy_graphs(c);
+  rts_status r = rts_load_state(c, d_scratch, need);
+  if (s) return s;
+  if (he != hipSuccess) return fail(c, RTS_E_DEVICE, "timing failed: %s", hipGetErrorString(he));
+  if (r) return r;
+  c->tune_candidates = cand;
+  c->tune_ms = best_ms / steps;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (out) return rts_get_tune(c, out);
   return RTS_OK;
 }
 

@@ -81,6 +81,11 @@ class Scene:
     vel: np.ndarray                      # (N, 3) float64
     walls: np.ndarray                    # (Nw, 3) float64
     params: dict = field(default_factory=dict)
+    # batched scenes: fluid index range (start, end) and placement offset of
+    # each sub-scene, and the sub-scenes as they run on their own
+    parts: list = field(default_factory=list)
+    offsets: list = field(default_factory=list)
+    subscenes: list = field(default_factory=list)
 
     @property
     def n(self) -> int:
@@ -227,3 +232,65 @@ def batch_sizes(n_scenes=64, lo=2000, hi=200000, seed=0):
     counts = np.rint(np.exp(math.log(lo) + u[:, 0] * (math.log(hi) - math.log(lo)))).astype(np.int64)
     aspect = 0.3 + 1.2 * u[:, 1]
     return counts, aspect
+
+
+def batched_dam_breaks(n_scenes=64, lo=2000, hi=200000, seed=0, spacing=0.01,
+                       box=(2.0, 1.0, 1.0), counts=None):
+    """Independent dam-break scenes of uneven size in one particle set.
+
+    Scene k is a column of about N_k particles (log-uniform in [lo, hi]) with
+    aspect ratio a_k (height / width, U(0.3, 1.5)): n_x = n_z =
+    round((N_k / a_k)^(1/3)), n_y = round(a_k n_x), at the x = 0 corner of
+    its own box.  The boxes (with their wall shells) are tiled in space far
+    enough apart that no particle of one scene is within the kernel support
+    of another scene's particles, so one step of the whole set advances every
+    scene independently.  All scenes share the sound speed of the tallest
+    column and hence the base step.  ``counts`` may give (n_x, n_y, n_z) per
+    scene directly.
+    """
+    if counts is None:
+        n_k, a_k = batch_sizes(n_scenes, lo, hi, seed)
+        counts = []
+        for n, a in zip(n_k, a_k):
+            nx = max(int(round((n / a) ** (1.0 / 3.0))), 1)
+            ny = max(int(round(a * nx)), 1)
+            nx = min(nx, int(box[0] / spacing))
+            ny = min(ny, int(box[1] / spacing))
+            nz = min(nx, int(box[2] / spacing))
+            counts.append((nx, ny, nz))
+    counts = [tuple(int(c) for c in cc) for cc in counts]
+    for cc in counts:
+        if any(cc[d] * spacing > box[d] + 1e-12 for d in range(3)):
+            raise ValueError(f"column {cc} does not fit the box {box}")
+    n_scenes = len(counts)
+    layers = 4
+    margin = layers * spacing
+    gap = 4.0 * spacing                       # at least one block edge between wall shells
+    pitch = np.array([box[0], box[1], box[2]]) + 2.0 * margin + gap
+    per_row = int(math.ceil(n_scenes ** (1.0 / 3.0)))
+    height = max(c[1] for c in counts) * spacing
+    pos_all, wall_all, parts, offsets, subs = [], [], [], [], []
+    start = 0
+    walls0 = box_walls((0.0, 0.0, 0.0), box, spacing, layers)
+    c0 = sound_speed_for_column(height)
+    for k, cc in enumerate(counts):
+        off = pitch * np.array([k % per_row, (k // per_row) % per_row, k // (per_row * per_row)])
+        local = lattice_column(cc, spacing, (0.0, 0.0, 0.0), jitter=0.005 * spacing, seed=seed + k)
+        pos = local + off[None, :]
+        pos_all.append(pos)
+        wall_all.append(walls0 + off[None, :])
+        parts.append((start, start + pos.shape[0]))
+        offsets.append(tuple(float(o) for o in off))
+        subs.append(Scene(f"batch_part_{k}", local, np.zeros_like(local), walls0,
+                          base_params(spacing, (0.0, 0.0, 0.0), box, c0=c0, dt_base=0.0,
+                                      level_cap=3)))
+        start += pos.shape[0]
+    pos = np.concatenate(pos_all, axis=0)
+    walls = np.concatenate(wall_all, axis=0)
+    top = pitch * np.array([min(n_scenes, per_row) - 1,
+                            min((n_scenes - 1) // per_row, per_row - 1),
+                            (n_scenes - 1) // (per_row * per_row)])
+    bmax = tuple(float(t + b) for t, b in zip(top, box))
+    p = base_params(spacing, (0.0, 0.0, 0.0), bmax, c0=c0, dt_base=0.0, level_cap=3)
+    return Scene(f"batched_{n_scenes}_scenes_{pos.shape[0]}", pos, np.zeros_like(pos), walls, p,
+                 parts=parts, offsets=offsets, subscenes=subs)

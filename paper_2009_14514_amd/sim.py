@@ -107,6 +107,17 @@ class Simulation:
                     acc=_from_planes(h[o[2]:o[3]], n), rho=h[o[3]:o[4]].copy(),
                     p=h[o[4]:o[4] + n].copy(), level=lev.cpu().numpy()[:n].copy())
 
+    def autotune(self, steps=10):
+        """Times the candidate launch shapes on the current state and keeps the
+        fastest (the state is restored afterwards)."""
+        torch = _torch()
+        nb = _rts.state_bytes(self.ctx)
+        scratch = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        return _rts.autotune(self.ctx, steps, scratch.data_ptr(), nb)
+
+    def tune(self):
+        return _rts.get_tune(self.ctx)
+
     def save(self):
         torch = _torch()
         nb = _rts.state_bytes(self.ctx)
