@@ -139,6 +139,10 @@ def _declare(L):
     L.orc_pci_turn.restype = C.c_uint32
     L.orc_pci_step.argtypes = [cfgp, _p(OrcPciState)]
     L.orc_pci_major_begin.argtypes = [cfgp, _p(OrcPciState)]
+    L.orc_diff_run.argtypes = [cfgp, C.c_int32, vp, vp, C.c_int32, vp, C.c_double, C.c_double,
+                               C.c_double, C.c_int32, vp, vp]
+    L.orc_diff_grad.argtypes = [cfgp, C.c_int32, vp, vp, C.c_int32, vp, C.c_double, C.c_double,
+                                C.c_double, C.c_int32, vp, vp, vp, vp, vp, vp]
     L.orc_num_threads.restype = C.c_int
 
 
@@ -530,3 +534,34 @@ class PCISPH:
         out = np.empty_like(a)
         out[self.id] = a
         return out
+
+
+# ---------------------------------------------------------------------------
+# differentiable WCSPH substeps
+# ---------------------------------------------------------------------------
+def diff_run(cfg, x0, v0, walls, B, alpha, dt, n_sub):
+    x0 = np.ascontiguousarray(x0, np.float64).reshape(-1, 3)
+    v0 = np.ascontiguousarray(v0, np.float64).reshape(-1, 3)
+    w = np.ascontiguousarray(walls, np.float64).reshape(-1, 3)
+    xo, vo = np.zeros_like(x0), np.zeros_like(v0)
+    st = lib().orc_diff_run(C.byref(cfg), x0.shape[0], _ptr(x0), _ptr(v0), w.shape[0], _ptr(w),
+                            float(B), float(alpha), float(dt), int(n_sub), _ptr(xo), _ptr(vo))
+    if st:
+        raise RuntimeError(f"oracle differentiable run status {st}")
+    return xo, vo
+
+
+def diff_grad(cfg, x0, v0, walls, B, alpha, dt, n_sub, xhat):
+    """Loss mean_i |x_i(T) - xhat_i|^2 and its gradients (x0, v0, B, alpha)."""
+    x0 = np.ascontiguousarray(x0, np.float64).reshape(-1, 3)
+    v0 = np.ascontiguousarray(v0, np.float64).reshape(-1, 3)
+    w = np.ascontiguousarray(walls, np.float64).reshape(-1, 3)
+    xh = np.ascontiguousarray(xhat, np.float64).reshape(-1, 3)
+    gx, gv = np.zeros_like(x0), np.zeros_like(v0)
+    loss, gB, ga = C.c_double(0), C.c_double(0), C.c_double(0)
+    st = lib().orc_diff_grad(C.byref(cfg), x0.shape[0], _ptr(x0), _ptr(v0), w.shape[0], _ptr(w),
+                             float(B), float(alpha), float(dt), int(n_sub), _ptr(xh),
+                             C.byref(loss), _ptr(gx), _ptr(gv), C.byref(gB), C.byref(ga))
+    if st:
+        raise RuntimeError(f"oracle differentiable gradient status {st}")
+    return loss.value, gx, gv, gB.value, ga.value

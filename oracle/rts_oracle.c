@@ -1201,3 +1201,281 @@ int orc_pci_step(const orc_cfg *c, orc_pci_state *s) {
     if (!isfinite(s->x[k])) return ORC_E_NUMERICAL;
   return ORC_OK;
 }
+
+/* ======================================================================== */
+/* Differentiable WCSPH substep and its adjoint (reverse accumulation in     */
+/* scatter form: each ordered neighbour pair pushes its partial derivatives  */
+/* to both particles).                                                       */
+/* ======================================================================== */
+static double d2w_shape(double q) { /* d^2 w_shape / dq^2 */
+  if (q < 1.0) return -3.0 + 4.5 * q;
+  if (q < 2.0) return 1.5 * (2.0 - q);
+  return 0.0;
+}
+
+typedef struct {
+  double *x, *v, *rho, *p;   /* state at the substep's start, and its density and pressure */
+  uint32_t *nbr;
+  int32_t *nnb;
+  int32_t cap;
+} diff_frame;
+
+static int diff_lists(const orc_cfg *c, int32_t n, const double *x, int32_t nw, const double *wx,
+                      diff_frame *f) {
+  ctx_t X;
+  if (ctx_open(&X, c, n, x, nw, wx)) return ORC_E_INVALID;
+  int st = ctx_lists(&X, NULL);
+  f->cap = X.cap;
+  memcpy(f->nbr, X.nbr, sizeof(uint32_t) * (size_t)X.cap * (size_t)(n > 0 ? n : 1));
+  memcpy(f->nnb, X.nnb, sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  ctx_close(&X);
+  return st;
+}
+
+/* one forward substep from f->x, f->v (lists, rho, p filled in f) */
+static void diff_substep(const orc_cfg *c, const orc_info *I, int32_t n, const double *wx,
+                         double B, double alpha, double dt, diff_frame *f, double *x1,
+                         double *v1) {
+  const double m = I->mass, h = c->h, e = c->visc_eps * h * h, rho0 = c->rho0;
+  for (int32_t i = 0; i < n; ++i) {
+    const double *xi = f->x + 3 * (int64_t)i;
+    double sum = orc_kernel_W(c, 0.0);
+    const uint32_t *L = f->nbr + (int64_t)i * f->cap;
+    for (int32_t k = 0; k < f->nnb[i]; ++k) {
+      const double *xj = pci_other(f->x, wx, L[k]);
+      double d0 = xi[0] - xj[0], d1 = xi[1] - xj[1], d2 = xi[2] - xj[2];
+      sum += orc_kernel_W(c, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+    }
+    f->rho[i] = m * sum;
+    f->p[i] = B * (pow(f->rho[i] / rho0, 7.0) - 1.0);
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    const double *xi = f->x + 3 * (int64_t)i, *vi = f->v + 3 * (int64_t)i;
+    const double ri = f->rho[i], Pi_ = f->p[i] / (ri * ri);
+    double a[3] = {c->g[0], c->g[1], c->g[2]};
+    const uint32_t *L = f->nbr + (int64_t)i * f->cap;
+    for (int32_t k = 0; k < f->nnb[i]; ++k) {
+      const uint32_t j = L[k];
+      const int wall = (j & ORC_WALL_BIT) != 0;
+      const double *xj = pci_other(f->x, wx, j);
+      double vj[3] = {0.0, 0.0, 0.0};
+      double coef, nu;
+      if (wall) {
+        coef = 2.0 * Pi_;
+        nu = alpha * h * c->c0 / ri;
+      } else {
+        for (int d = 0; d < 3; ++d) vj[d] = f->v[3 * (int64_t)j + d];
+        const double rj = f->rho[j];
+        coef = Pi_ + f->p[j] / (rj * rj);
+        nu = 2.0 * alpha * h * c->c0 / (ri + rj);
+      }
+      double xij[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+      double r2 = xij[0] * xij[0] + xij[1] * xij[1] + xij[2] * xij[2];
+      double r = sqrt(r2);
+      if (!(r > 0.0) || r >= c->support) continue;
+      double s = (vi[0] - vj[0]) * xij[0] + (vi[1] - vj[1]) * xij[1] + (vi[2] - vj[2]) * xij[2];
+      if (s < 0.0) coef += -nu * s / (r2 + e);
+      double F = orc_kernel_dWdr(c, r) / r;
+      for (int d = 0; d < 3; ++d) a[d] -= m * coef * F * xij[d];
+    }
+    for (int d = 0; d < 3; ++d) {
+      int64_t q = 3 * (int64_t)i + d;
+      v1[q] = vi[d] + dt * a[d];
+      x1[q] = xi[d] + dt * v1[q];
+    }
+  }
+}
+
+static int diff_forward(const orc_cfg *c, int32_t n, const double *x0, const double *v0,
+                        int32_t nw, const double *wx, double B, double alpha, double dt,
+                        int32_t n_sub, diff_frame *frames, double *x_out, double *v_out) {
+  orc_info I;
+  if (orc_derive(c, &I)) return ORC_E_INVALID;
+  size_t sz = sizeof(double) * 3 * (size_t)n;
+  memcpy(frames[0].x, x0, sz);
+  memcpy(frames[0].v, v0, sz);
+  for (int32_t k = 0; k < n_sub; ++k) {
+    diff_frame *f = &frames[k];
+    int st = diff_lists(c, n, f->x, nw, wx, f);
+    if (st) return st;
+    double *x1 = k + 1 < n_sub ? frames[k + 1].x : x_out;
+    double *v1 = k + 1 < n_sub ? frames[k + 1].v : v_out;
+    diff_substep(c, &I, n, wx, B, alpha, dt, f, x1, v1);
+  }
+  return ORC_OK;
+}
+
+static diff_frame *frames_new(int32_t n, int32_t n_sub, int32_t cap) {
+  diff_frame *fr = (diff_frame *)calloc((size_t)n_sub, sizeof(diff_frame));
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  for (int32_t k = 0; k < n_sub; ++k) {
+    fr[k].x = (double *)malloc(sizeof(double) * 3 * nn);
+    fr[k].v = (double *)malloc(sizeof(double) * 3 * nn);
+    fr[k].rho = (double *)malloc(sizeof(double) * nn);
+    fr[k].p = (double *)malloc(sizeof(double) * nn);
+    fr[k].nbr = (uint32_t *)malloc(sizeof(uint32_t) * nn * (size_t)cap);
+    fr[k].nnb = (int32_t *)malloc(sizeof(int32_t) * nn);
+  }
+  return fr;
+}
+static void frames_free(diff_frame *fr, int32_t n_sub) {
+  for (int32_t k = 0; k < n_sub; ++k) {
+    free(fr[k].x); free(fr[k].v); free(fr[k].rho); free(fr[k].p); free(fr[k].nbr);
+    free(fr[k].nnb);
+  }
+  free(fr);
+}
+
+int orc_diff_run(const orc_cfg *c, int32_t n, const double *x0, const double *v0, int32_t nw,
+                 const double *wx, double B, double alpha, double dt, int32_t n_sub,
+                 double *x_out, double *v_out) {
+  if (n_sub < 1) return ORC_E_INVALID;
+  int32_t cap = c->nbr_cap > 0 ? c->nbr_cap : 512;
+  diff_frame *fr = frames_new(n, n_sub, cap);
+  int st = diff_forward(c, n, x0, v0, nw, wx, B, alpha, dt, n_sub, fr, x_out, v_out);
+  frames_free(fr, n_sub);
+  return st;
+}
+
+int orc_diff_grad(const orc_cfg *c, int32_t n, const double *x0, const double *v0, int32_t nw,
+                  const double *wx, double B, double alpha, double dt, int32_t n_sub,
+                  const double *xhat, double *loss, double *g_x0, double *g_v0, double *g_B,
+                  double *g_alpha) {
+  if (n_sub < 1 || n < 1) return ORC_E_INVALID;
+  orc_info I;
+  if (orc_derive(c, &I)) return ORC_E_INVALID;
+  int32_t cap = c->nbr_cap > 0 ? c->nbr_cap : 512;
+  diff_frame *fr = frames_new(n, n_sub, cap);
+  size_t n3 = 3 * (size_t)n;
+  double *xT = (double *)malloc(sizeof(double) * n3), *vT = (double *)malloc(sizeof(double) * n3);
+  int st = diff_forward(c, n, x0, v0, nw, wx, B, alpha, dt, n_sub, fr, xT, vT);
+  if (st) { frames_free(fr, n_sub); free(xT); free(vT); return st; }
+  const double m = I.mass, h = c->h, e = c->visc_eps * h * h, rho0 = c->rho0;
+  double L = 0.0;
+  double *xb = (double *)calloc(n3, sizeof(double)), *vb = (double *)calloc(n3, sizeof(double));
+  for (size_t q = 0; q < n3; ++q) {
+    double d = xT[q] - xhat[q];
+    L += d * d;
+    xb[q] = 2.0 * d / n;
+  }
+  *loss = L / n;
+  double Bb = 0.0, ab_alpha = 0.0;
+  double *ab = (double *)malloc(sizeof(double) * n3);
+  double *xn = (double *)malloc(sizeof(double) * n3), *vn = (double *)malloc(sizeof(double) * n3);
+  double *Pb = (double *)malloc(sizeof(double) * (size_t)n), *rb = (double *)malloc(sizeof(double) * (size_t)n);
+  for (int32_t k = n_sub - 1; k >= 0; --k) {
+    diff_frame *f = &fr[k];
+    /* x' = x + dt v',  v' = v + dt a */
+    for (size_t q = 0; q < n3; ++q) {
+      double vt = vb[q] + dt * xb[q];
+      ab[q] = dt * vt;
+      xn[q] = xb[q];
+      vn[q] = vt;
+    }
+    memset(Pb, 0, sizeof(double) * (size_t)n);
+    memset(rb, 0, sizeof(double) * (size_t)n);
+    /* forces: a_i -= t_ij, t = m c G(x_ij); the upstream gradient of t is -ab_i */
+    for (int32_t i = 0; i < n; ++i) {
+      const double *xi = f->x + 3 * (int64_t)i, *vi = f->v + 3 * (int64_t)i;
+      const double ri = f->rho[i], Pi_ = f->p[i] / (ri * ri);
+      const double u[3] = {-ab[3 * (int64_t)i], -ab[3 * (int64_t)i + 1], -ab[3 * (int64_t)i + 2]};
+      const uint32_t *Lst = f->nbr + (int64_t)i * f->cap;
+      for (int32_t kk = 0; kk < f->nnb[i]; ++kk) {
+        const uint32_t j = Lst[kk];
+        const int wall = (j & ORC_WALL_BIT) != 0;
+        const double *xj = pci_other(f->x, wx, j);
+        double vj[3] = {0.0, 0.0, 0.0}, rj = ri, coef, nu;
+        if (wall) {
+          coef = 2.0 * Pi_;
+          nu = alpha * h * c->c0 / ri;
+        } else {
+          for (int d = 0; d < 3; ++d) vj[d] = f->v[3 * (int64_t)j + d];
+          rj = f->rho[j];
+          coef = Pi_ + f->p[j] / (rj * rj);
+          nu = 2.0 * alpha * h * c->c0 / (ri + rj);
+        }
+        double x[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+        double vv[3] = {vi[0] - vj[0], vi[1] - vj[1], vi[2] - vj[2]};
+        double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        double r = sqrt(r2);
+        if (!(r > 0.0) || r >= c->support) continue;
+        double s = vv[0] * x[0] + vv[1] * x[1] + vv[2] * x[2];
+        const int visc = s < 0.0;
+        const double den = r2 + e;
+        if (visc) coef += -nu * s / den;
+        const double q = r / h, sig = 1.0 / (M_PI * h * h * h);
+        const double W1 = sig * dw_shape(q) / h, W2 = sig * d2w_shape(q) / (h * h);
+        const double F = W1 / r, dF = (W2 * r - W1) / r2;
+        const double G[3] = {F * x[0], F * x[1], F * x[2]};
+        const double Gu = G[0] * u[0] + G[1] * u[1] + G[2] * u[2];
+        const double xu = x[0] * u[0] + x[1] * u[1] + x[2] * u[2];
+        double gx[3], gv[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < 3; ++d) gx[d] = m * coef * (F * u[d] + dF / r * x[d] * xu);
+        if (visc) {
+          for (int d = 0; d < 3; ++d) {
+            const double dcdx = -nu * (vv[d] / den - 2.0 * s * x[d] / (den * den));
+            gx[d] += dcdx * m * Gu;
+            gv[d] = -nu * x[d] / den * m * Gu;
+          }
+          const double nub = -s / den * m * Gu;
+          ab_alpha += nub * nu / alpha;
+          if (wall) {
+            rb[i] += nub * (-nu / ri);
+          } else {
+            rb[i] += nub * (-nu / (ri + rj));
+            rb[j] += nub * (-nu / (ri + rj));
+          }
+        }
+        for (int d = 0; d < 3; ++d) {
+          xn[3 * (int64_t)i + d] += gx[d];
+          vn[3 * (int64_t)i + d] += gv[d];
+        }
+        if (wall) {
+          Pb[i] += 2.0 * m * Gu;
+        } else {
+          Pb[i] += m * Gu;
+          Pb[j] += m * Gu;
+          for (int d = 0; d < 3; ++d) {
+            xn[3 * (int64_t)j + d] -= gx[d];
+            vn[3 * (int64_t)j + d] -= gv[d];
+          }
+        }
+      }
+    }
+    /* P = p / rho^2, EOS */
+    for (int32_t i = 0; i < n; ++i) {
+      const double ri = f->rho[i], pi = f->p[i];
+      const double pb = Pb[i] / (ri * ri);
+      rb[i] += Pb[i] * (-2.0 * pi / (ri * ri * ri));
+      rb[i] += pb * 7.0 * B * pow(ri / rho0, 6.0) / rho0;
+      Bb += pb * (pow(ri / rho0, 7.0) - 1.0);
+    }
+    /* density: rho_i = m sum_j W(|x_i - x_j|) */
+    for (int32_t i = 0; i < n; ++i) {
+      const double *xi = f->x + 3 * (int64_t)i;
+      const uint32_t *Lst = f->nbr + (int64_t)i * f->cap;
+      for (int32_t kk = 0; kk < f->nnb[i]; ++kk) {
+        const uint32_t j = Lst[kk];
+        const double *xj = pci_other(f->x, wx, j);
+        double x[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+        double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        if (!(r > 0.0) || r >= c->support) continue;
+        const double F = orc_kernel_dWdr(c, r) / r;
+        for (int d = 0; d < 3; ++d) {
+          const double g = m * F * x[d] * rb[i];
+          xn[3 * (int64_t)i + d] += g;
+          if (!(j & ORC_WALL_BIT)) xn[3 * (int64_t)j + d] -= g;
+        }
+      }
+    }
+    memcpy(xb, xn, sizeof(double) * n3);
+    memcpy(vb, vn, sizeof(double) * n3);
+  }
+  memcpy(g_x0, xb, sizeof(double) * n3);
+  memcpy(g_v0, vb, sizeof(double) * n3);
+  *g_B = Bb;
+  *g_alpha = ab_alpha;
+  free(xb); free(vb); free(ab); free(xn); free(vn); free(Pb); free(rb); free(xT); free(vT);
+  frames_free(fr, n_sub);
+  return ORC_OK;
+}

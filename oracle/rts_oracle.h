@@ -187,6 +187,25 @@ int orc_pci_step(const orc_cfg *c, orc_pci_state *s);
 /* Major-step set-up alone: sort into the grid, regions, flags. */
 int orc_pci_major_begin(const orc_cfg *c, orc_pci_state *s);
 
+/* ---------------------------------------------------------------------- */
+/* Differentiable WCSPH substep (every particle active, symplectic Euler):  */
+/*   rho_i = m (W(0) + sum_j W_ij + sum_w W_iw)                             */
+/*   p_i   = B ((rho_i / rho0)^7 - 1)            (no clamp)                 */
+/*   a_i   = g - sum_j m (P_i + P_j + Pi_ij) gradW_ij                       */
+/*             - sum_w m (2 P_i + Pi_iw) gradW_iw,   P = p / rho^2           */
+/*   Pi_ij = -nu_ij (v_ij . x_ij) / (r^2 + eps h^2) if v_ij . x_ij < 0,      */
+/*   nu_ij = 2 alpha h c0 / (rho_i + rho_j), nu_iw = alpha h c0 / rho_i      */
+/*   v' = v + dt a ;  x' = x + dt v'                                         */
+/* and its adjoint for L = mean_i |x_i(T) - xhat_i|^2.                      */
+/* ---------------------------------------------------------------------- */
+int orc_diff_run(const orc_cfg *c, int32_t n, const double *x0, const double *v0, int32_t nw,
+                 const double *wx, double B, double alpha, double dt, int32_t n_sub,
+                 double *x_out, double *v_out);
+int orc_diff_grad(const orc_cfg *c, int32_t n, const double *x0, const double *v0, int32_t nw,
+                  const double *wx, double B, double alpha, double dt, int32_t n_sub,
+                  const double *xhat, double *loss, double *g_x0, double *g_v0, double *g_B,
+                  double *g_alpha);
+
 int orc_num_threads(void);
 
 #ifdef __cplusplus

@@ -294,3 +294,37 @@ def batched_dam_breaks(n_scenes=64, lo=2000, hi=200000, seed=0, spacing=0.01,
     p = base_params(spacing, (0.0, 0.0, 0.0), bmax, c0=c0, dt_base=0.0, level_cap=3)
     return Scene(f"batched_{n_scenes}_scenes_{pos.shape[0]}", pos, np.zeros_like(pos), walls, p,
                  parts=parts, offsets=offsets, subscenes=subs)
+
+
+def normal01(seed: int, idx: np.ndarray) -> np.ndarray:
+    """Standard normal draws by Box-Muller on pairs of SplitMix64 outputs
+    (2k, 2k + 1) of the stream."""
+    idx = np.asarray(idx, np.uint64)
+    u1 = uniform01(seed, 2 * idx)
+    u2 = uniform01(seed, 2 * idx + np.uint64(1))
+    u1 = np.maximum(u1, 2.0 ** -25)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def diff_scene(counts=(8, 8, 8), spacing=0.01, box=(0.3, 0.3, 0.3), seed=0, v_scale=0.2,
+               dt=1e-4, n_sub=16, target_sigma=0.005):
+    """Differentiable dam break: a column with seeded initial velocities
+    U(-v_scale, v_scale) per component; run for n_sub substeps of dt.  The
+    target of the loss is the nominal final positions plus N(0, sigma^2) per
+    coordinate (drawn from stream seed + 1 over index 3 i + c); it is
+    produced by the caller from its own nominal run."""
+    bmin = (0.0, 0.0, 0.0)
+    pos = lattice_column(counts, spacing, bmin, jitter=0.005 * spacing, seed=seed)
+    k = np.arange(pos.shape[0] * 3, dtype=np.uint64) + np.uint64(1 << 40)
+    vel = (v_scale * (2.0 * uniform01(seed, k) - 1.0)).reshape(-1, 3)
+    height = max(counts[1] * spacing, 0.5)
+    p = base_params(spacing, bmin, box, c0=sound_speed_for_column(height), dt_base=dt,
+                    level_cap=0, mode="global_fixed")
+    p.update(diff_dt=dt, diff_substeps=n_sub, target_sigma=target_sigma, clamp_p=0)
+    return Scene(f"diff_dam_break_{pos.shape[0]}", pos, vel,
+                 box_walls(bmin, box, spacing, p["wall_layers"]), p)
+
+
+def target_noise(n, sigma=0.005, seed=0):
+    """N(0, sigma^2) offsets per coordinate for the loss target."""
+    return sigma * normal01(seed + 1, np.arange(3 * n, dtype=np.uint64)).reshape(n, 3)
