@@ -285,6 +285,45 @@ rts_status rts_autotune(rts_ctx *ctx, int32_t steps, void *d_scratch, size_t scr
 /* Current launch shape (h_out->candidates = 0, ms_per_step = 0 until tuned). */
 rts_status rts_get_tune(rts_ctx *ctx, rts_tune *h_out);
 
+/* Differentiable WCSPH substeps (every particle active, symplectic Euler)
+ * and their adjoint, for gradient-based inverse problems:
+ *   rho_i = m (W(0) + sum_j W_ij + sum_w W_iw),  p_i = B ((rho_i/rho0)^7 - 1)
+ *   a_i = g - sum_j m (P_i + P_j + Pi_ij) gradW_ij - sum_w m (2 P_i + Pi_iw) gradW_iw
+ *   v' = v + dt a,  x' = x + dt v'
+ * with P = p / rho^2, Monaghan viscosity Pi_ij = -nu (v_ij . x_ij) /
+ * (r^2 + eps h^2) for approaching pairs, nu = 2 alpha h c0 / (rho_i + rho_j)
+ * (walls: at rest, mirrored density and pressure, nu = alpha h c0 / rho_i).
+ * The pressure is not clamped.  The forward run keeps the state every
+ * ckpt_every substeps in the caller's tape; the backward run recomputes each
+ * segment from its checkpoint and runs the adjoint kernels in reverse.
+ * These calls use the context's particle buffers as scratch: the context's
+ * own simulation state is lost (set a state again before rts_advance). */
+typedef struct rts_diff_desc {
+  int32_t n_sub;          /* substeps */
+  int32_t ckpt_every;     /* substeps between checkpoints */
+  int32_t list_cap;       /* neighbour entries per particle (fluid + walls) */
+  int32_t pad;
+  double dt;              /* substep length */
+  double B;               /* Tait stiffness (differentiated) */
+  double alpha;           /* viscosity alpha (differentiated) */
+} rts_diff_desc;
+
+/* Device bytes of the tape for n particles. */
+rts_status rts_diff_tape_bytes(rts_ctx *ctx, const rts_diff_desc *desc, int64_t n, size_t *bytes);
+/* Runs the substeps from d_x0, d_v0 (planes, 3n floats) and writes the final
+ * state to d_xT, d_vT (planes).  Asynchronous. */
+rts_status rts_diff_forward(rts_ctx *ctx, const rts_diff_desc *desc, int64_t n, const float *d_x0,
+                            const float *d_v0, float *d_xT, float *d_vT, void *d_tape,
+                            size_t tape_bytes);
+/* Given dL/dx(T) and dL/dv(T) (planes; d_vT_bar may be NULL for zero),
+ * writes dL/dx(0), dL/dv(0) (planes; either may be NULL) and the host
+ * values dL/dB, dL/dalpha.  Needs the tape of the forward run with the same
+ * desc and n.  Waits for the stream. */
+rts_status rts_diff_backward(rts_ctx *ctx, const rts_diff_desc *desc, int64_t n,
+                             const float *d_xT_bar, const float *d_vT_bar, float *d_x0_bar,
+                             float *d_v0_bar, double *h_B_bar, double *h_alpha_bar, void *d_tape,
+                             size_t tape_bytes);
+
 const char *rts_last_error(const rts_ctx *ctx);
 const char *rts_status_string(rts_status s);
 

@@ -31,7 +31,8 @@ EXPORTS = [
     "rts_default_config", "rts_workspace_size", "rts_create", "rts_destroy", "rts_set_walls",
     "rts_set_state", "rts_assign_levels", "rts_advance", "rts_sync", "rts_get_state",
     "rts_state_bytes", "rts_save_state", "rts_load_state", "rts_debug_get", "rts_grid_info",
-    "rts_profile_advance", "rts_autotune", "rts_get_tune", "rts_last_error", "rts_status_string",
+    "rts_profile_advance", "rts_autotune", "rts_get_tune", "rts_diff_tape_bytes",
+    "rts_diff_forward", "rts_diff_backward", "rts_last_error", "rts_status_string",
 ]
 PROF_KERNELS = ["key_hist", "scan", "scatter", "cell_gather", "rmin_flags", "search_density",
                 "force", "step_stats", "correct_predict"]
@@ -84,6 +85,11 @@ class RtsTune(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RtsDiffDesc(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("ckpt_every", C.c_int32), ("list_cap", C.c_int32),
+                ("pad", C.c_int32), ("dt", C.c_double), ("B", C.c_double), ("alpha", C.c_double)]
+
+
 _lib = None
 
 
@@ -122,6 +128,11 @@ def lib():
         L.rts_profile_advance.argtypes = [vp, i32, C.POINTER(C.c_double)]
         L.rts_autotune.argtypes = [vp, i32, vp, C.c_size_t, C.POINTER(RtsTune)]
         L.rts_get_tune.argtypes = [vp, C.POINTER(RtsTune)]
+        dp = C.POINTER(RtsDiffDesc)
+        L.rts_diff_tape_bytes.argtypes = [vp, dp, i64, C.POINTER(C.c_size_t)]
+        L.rts_diff_forward.argtypes = [vp, dp, i64, vp, vp, vp, vp, vp, C.c_size_t]
+        L.rts_diff_backward.argtypes = [vp, dp, i64, vp, vp, vp, vp, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), vp, C.c_size_t]
         L.rts_last_error.argtypes = [vp]
         L.rts_last_error.restype = C.c_char_p
         L.rts_status_string.argtypes = [C.c_int]
@@ -279,6 +290,34 @@ def get_tune(ctx):
     t = RtsTune()
     check(lib().rts_get_tune(ctx, C.byref(t)), ctx)
     return t.as_dict()
+
+
+def diff_desc(n_sub, ckpt_every, list_cap, dt, B, alpha):
+    d = RtsDiffDesc()
+    d.n_sub, d.ckpt_every, d.list_cap = int(n_sub), int(ckpt_every), int(list_cap)
+    d.dt, d.B, d.alpha = float(dt), float(B), float(alpha)
+    return d
+
+
+def diff_tape_bytes(ctx, desc, n):
+    out = C.c_size_t(0)
+    check(lib().rts_diff_tape_bytes(ctx, C.byref(desc), int(n), C.byref(out)), ctx)
+    return int(out.value)
+
+
+def diff_forward(ctx, desc, n, d_x0, d_v0, d_xT, d_vT, d_tape, nbytes):
+    check(lib().rts_diff_forward(ctx, C.byref(desc), int(n), C.c_void_p(d_x0), C.c_void_p(d_v0),
+                                 C.c_void_p(d_xT), C.c_void_p(d_vT), C.c_void_p(d_tape),
+                                 int(nbytes)), ctx)
+
+
+def diff_backward(ctx, desc, n, d_xT_bar, d_vT_bar, d_x0_bar, d_v0_bar, d_tape, nbytes):
+    gB, ga = C.c_double(0), C.c_double(0)
+    check(lib().rts_diff_backward(ctx, C.byref(desc), int(n), C.c_void_p(d_xT_bar),
+                                  C.c_void_p(d_vT_bar or None), C.c_void_p(d_x0_bar or None),
+                                  C.c_void_p(d_v0_bar or None), C.byref(gB), C.byref(ga),
+                                  C.c_void_p(d_tape), int(nbytes)), ctx)
+    return gB.value, ga.value
 
 
 def last_error(ctx):

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librts.so")
-SOURCES = ["rts_kernels.hip", "pcisph_kernels.hip", "rts_api.hip"]
+SOURCES = ["rts_kernels.hip", "pcisph_kernels.hip", "diff_kernels.hip", "rts_api.hip"]
 
 
 def hipcc() -> str:

@@ -1,0 +1,434 @@
+// HIP kernels of the differentiable WCSPH substep and its adjoint on gfx950.
+//
+// Forward substep (every particle active, symplectic Euler), particles in the
+// caller's order:
+//   rho_i = m (W(0) + sum_j W_ij + sum_w W_iw),  p_i = B ((rho_i/rho0)^7 - 1)
+//   a_i   = g - sum_j m (P_i + P_j + Pi_ij) gradW_ij - sum_w m (2 P_i + Pi_iw) gradW_iw
+//   v' = v + dt a,  x' = x + dt v'
+// with P = p / rho^2 and the Monaghan viscosity Pi (approaching pairs only).
+//
+// The adjoint is in gather form: particle i visits its own list once and
+// collects its share of every pair's partial derivatives, using that the
+// neighbour relation is symmetric and that a pair enters a_i and a_j with
+// opposite signs, so the pair's upstream gradient is abar_j - abar_i.  No
+// thread writes another particle's adjoint, so no atomics are needed and the
+// sums are in list order (deterministic).
+#include "rts_device.h"
+
+namespace rts {
+
+struct DiffArgs {
+  float dt, B, alpha, hc0;  // step, Tait stiffness, viscosity alpha, h c0
+  int32_t n, cap;           // particles, list entries per particle
+};
+
+__device__ inline float d2w_shape(float q) {
+  const float a = -3.0f + 4.5f * q;
+  const float b = 1.5f * fmaxf(2.0f - q, 0.0f);
+  return q < 1.0f ? a : b;
+}
+
+// (1 + d)^7 - 1 and its derivative 7 (1 + d)^6, expanded in d
+__device__ inline float pow7m1(float d) {
+  return d * (7.0f + d * (21.0f + d * (35.0f + d * (35.0f + d * (21.0f + d * (7.0f + d))))));
+}
+__device__ inline float pow6(float d) {
+  const float t = 1.0f + d;
+  const float t3 = t * t * t;
+  return t3 * t3;
+}
+
+__global__ void k_diff_copy_in(DiffArgs a, const float4 *__restrict__ X, float4 *__restrict__ P,
+                               float4 *__restrict__ V, float4 *__restrict__ A,
+                               uint32_t *__restrict__ M, uint32_t *__restrict__ ID) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float4 x = X[i];
+  P[i] = make_float4(x.x, x.y, x.z, 0.0f);
+  V[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  A[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  M[i] = 0u;
+  ID[i] = (uint32_t)i;
+}
+
+// Lists in the canonical order of the sorted grid (rows dz, dy; blocks in x),
+// entries are caller indices (fluid) or wall sorted index | bit 31.
+__global__ void __launch_bounds__(256) k_diff_lists(
+    DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ perm,
+    const uint32_t *__restrict__ start, const float4 *__restrict__ WP,
+    const uint32_t *__restrict__ wstart, uint32_t *__restrict__ L, uint32_t *__restrict__ nn,
+    DevScalars *S) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float4 xi = X[i];
+  const int3 c = block_of(p, xi.x, xi.y, xi.z);
+  uint32_t *row_out = L + (size_t)i * (size_t)a.cap;
+  uint32_t cnt = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 && p.nw == 0) break;
+    const uint32_t *cs = pass == 0 ? start : wstart;
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int z = c.z + dz;
+      if (z < 0 || z >= p.nc[2]) continue;
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int y = c.y + dy;
+        if (y < 0 || y >= p.nc[1]) continue;
+        const int x0 = max(c.x - 1, 0), x1 = min(c.x + 1, p.nc[0] - 1);
+        const uint32_t row = (uint32_t)p.nc[0] * ((uint32_t)y + (uint32_t)p.nc[1] * (uint32_t)z);
+        const uint32_t s0 = cs[row + (uint32_t)x0], s1 = cs[row + (uint32_t)x1 + 1u];
+        for (uint32_t s = s0; s < s1; ++s) {
+          const uint32_t j = pass == 0 ? perm[s] : s;
+          if (pass == 0 && j == (uint32_t)i) continue;
+          const float4 q = pass == 0 ? X[j] : WP[s];
+          if (!(dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2f)) continue;
+          if (cnt < (uint32_t)a.cap) row_out[cnt] = pass == 0 ? j : (s | kWallBit);
+          ++cnt;
+        }
+      }
+    }
+  }
+  if (cnt > (uint32_t)a.cap) {
+    set_status(S, RTS_E_CAPACITY, i);
+    cnt = (uint32_t)a.cap;
+  }
+  nn[i] = cnt;
+}
+
+// Density by summation (compensated) and the unclamped Tait pressure, both
+// from the deviation d = rho/rho0 - 1 formed before rounding to rho.
+__global__ void __launch_bounds__(256) k_diff_density(
+    DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ L,
+    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float *__restrict__ rho,
+    float *__restrict__ prs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float4 xi = X[i];
+  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
+  const uint32_t cnt = nn[i];
+  float sum = 0.0f, comp = 0.0f;
+  for (uint32_t k = 0; k < cnt; ++k) {
+    const uint32_t j = row[k];
+    const float4 q = (j & kWallBit) ? WP[j & ~kWallBit] : X[j];
+    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+    const float w = w_shape(__builtin_sqrtf(dx * dx + dy * dy + dz * dz) * p.inv_h);
+    const float y = w - comp;
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+  }
+  const float dev = p.kms * ((sum - p.c_hi) - (comp + p.c_lo));
+  rho[i] = p.rho0 + p.rho0 * dev;
+  prs[i] = a.B * pow7m1(dev);
+}
+
+__global__ void __launch_bounds__(256) k_diff_force_euler(
+    DevParams p, DiffArgs a, const float4 *__restrict__ X, const float4 *__restrict__ V,
+    const float *__restrict__ rho, const float *__restrict__ prs, const uint32_t *__restrict__ L,
+    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float4 *__restrict__ Xn,
+    float4 *__restrict__ Vn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float4 xi = X[i], vi = V[i];
+  const float ri = rho[i], Pi = prs[i] / (ri * ri);
+  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
+  const uint32_t cnt = nn[i];
+  float ax = p.g[0], ay = p.g[1], az = p.g[2];
+  for (uint32_t k = 0; k < cnt; ++k) {
+    const uint32_t j = row[k];
+    const bool wall = (j & kWallBit) != 0u;
+    float4 q, u = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float coef, nu;
+    if (wall) {
+      q = WP[j & ~kWallBit];
+      coef = 2.0f * Pi;
+      nu = a.alpha * a.hc0 / ri;
+    } else {
+      q = X[j];
+      u = V[j];
+      const float rj = rho[j];
+      coef = Pi + prs[j] / (rj * rj);
+      nu = 2.0f * a.alpha * a.hc0 / (ri + rj);
+    }
+    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 > 0.0f) || r2 >= p.r2f) continue;
+    const float s = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
+    if (s < 0.0f) coef += -nu * s / (r2 + p.visc_eps_h2);
+    const float r = __builtin_sqrtf(r2);
+    const float F = p.sigma * p.inv_h * dw_shape(r * p.inv_h) / r;
+    const float t = p.mass * coef * F;
+    ax -= t * dx;
+    ay -= t * dy;
+    az -= t * dz;
+  }
+  const float vx = vi.x + a.dt * ax, vy = vi.y + a.dt * ay, vz = vi.z + a.dt * az;
+  Vn[i] = make_float4(vx, vy, vz, 0.0f);
+  Xn[i] = make_float4(xi.x + a.dt * vx, xi.y + a.dt * vy, xi.z + a.dt * vz, 0.0f);
+}
+
+// x' = x + dt v', v' = v + dt a: vbar <- vbar' + dt xbar', abar = dt vbar (xbar unchanged)
+__global__ void k_diff_adj_euler(DiffArgs a, const float4 *__restrict__ XB, float4 *__restrict__ VB,
+                                 float4 *__restrict__ AB) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float4 xb = XB[i];
+  float4 vb = VB[i];
+  vb.x += a.dt * xb.x;
+  vb.y += a.dt * xb.y;
+  vb.z += a.dt * xb.z;
+  VB[i] = vb;
+  AB[i] = make_float4(a.dt * vb.x, a.dt * vb.y, a.dt * vb.z, 0.0f);
+}
+
+// Adjoint of the forces, the pressure p / rho^2 and the equation of state.
+__global__ void __launch_bounds__(256) k_diff_adj_force(
+    DevParams p, DiffArgs a, const float4 *__restrict__ X, const float4 *__restrict__ V,
+    const float *__restrict__ rho, const float *__restrict__ prs, const uint32_t *__restrict__ L,
+    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, const float4 *__restrict__ AB,
+    float4 *__restrict__ XB, float4 *__restrict__ VB, float *__restrict__ RB,
+    double *__restrict__ BB, double *__restrict__ AA) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float4 xi = X[i], vi = V[i], abi = AB[i];
+  const float ri = rho[i], pi = prs[i], Pi = pi / (ri * ri);
+  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
+  const uint32_t cnt = nn[i];
+  const float m = p.mass, e = p.visc_eps_h2;
+  const float inv_h2 = p.inv_h * p.inv_h;
+  float gxx = 0.0f, gxy = 0.0f, gxz = 0.0f, gvx = 0.0f, gvy = 0.0f, gvz = 0.0f;
+  float Pb = 0.0f, rb = 0.0f, alb = 0.0f;
+  for (uint32_t k = 0; k < cnt; ++k) {
+    const uint32_t j = row[k];
+    const bool wall = (j & kWallBit) != 0u;
+    float4 q, vj = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float coef, nu, rj = ri, ux, uy, uz;
+    if (wall) {
+      q = WP[j & ~kWallBit];
+      coef = 2.0f * Pi;
+      nu = a.alpha * a.hc0 / ri;
+      ux = -abi.x;
+      uy = -abi.y;
+      uz = -abi.z;
+    } else {
+      q = X[j];
+      vj = V[j];
+      rj = rho[j];
+      coef = Pi + prs[j] / (rj * rj);
+      nu = 2.0f * a.alpha * a.hc0 / (ri + rj);
+      const float4 abj = AB[j];
+      ux = abj.x - abi.x;
+      uy = abj.y - abi.y;
+      uz = abj.z - abi.z;
+    }
+    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 > 0.0f) || r2 >= p.r2f) continue;
+    const float r = __builtin_sqrtf(r2);
+    const float wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
+    const float s = wx * dx + wy * dy + wz * dz;
+    const bool visc = s < 0.0f;
+    const float den = r2 + e;
+    if (visc) coef += -nu * s / den;
+    const float qn = r * p.inv_h;
+    const float W1 = p.sigma * p.inv_h * dw_shape(qn), W2 = p.sigma * inv_h2 * d2w_shape(qn);
+    const float F = W1 / r, dF = (W2 * r - W1) / r2;
+    const float Gu = F * (dx * ux + dy * uy + dz * uz);
+    const float xu = dx * ux + dy * uy + dz * uz;
+    const float c1 = m * coef * F, c2 = m * coef * dF / r * xu;
+    gxx += c1 * ux + c2 * dx;
+    gxy += c1 * uy + c2 * dy;
+    gxz += c1 * uz + c2 * dz;
+    if (visc) {
+      const float mg = m * Gu;
+      const float k1 = -nu / den, k2 = 2.0f * nu * s / (den * den);
+      gxx += (k1 * wx + k2 * dx) * mg;
+      gxy += (k1 * wy + k2 * dy) * mg;
+      gxz += (k1 * wz + k2 * dz) * mg;
+      gvx += k1 * dx * mg;
+      gvy += k1 * dy * mg;
+      gvz += k1 * dz * mg;
+      const float nub = -s / den * mg;
+      if (wall) {
+        rb += nub * (-nu / ri);
+        alb += nub * nu / a.alpha;
+      } else {
+        rb += nub * (-nu / (ri + rj));
+        alb += 0.5f * nub * nu / a.alpha;   // the pair is visited from both ends
+      }
+    }
+    Pb += (wall ? 2.0f : 1.0f) * m * Gu;
+  }
+  // P = p / rho^2 ; p = B ((1 + d)^7 - 1), d = rho / rho0 - 1
+  const float dev = ri / p.rho0 - 1.0f;
+  const float pb = Pb / (ri * ri);
+  rb += Pb * (-2.0f * pi / (ri * ri * ri)) + pb * 7.0f * a.B * pow6(dev) / p.rho0;
+  BB[i] += (double)pb * (double)pow7m1(dev);
+  AA[i] += (double)alb;
+  float4 xb = XB[i], vb = VB[i];
+  xb.x += gxx;
+  xb.y += gxy;
+  xb.z += gxz;
+  vb.x += gvx;
+  vb.y += gvy;
+  vb.z += gvz;
+  XB[i] = xb;
+  VB[i] = vb;
+  RB[i] = rb;
+}
+
+// Adjoint of the density summation: xbar_i += sum_j m gradW_ij (rbar_i + rbar_j).
+__global__ void __launch_bounds__(256) k_diff_adj_density(
+    DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ L,
+    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, const float *__restrict__ RB,
+    float4 *__restrict__ XB) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float4 xi = X[i];
+  const float rbi = RB[i];
+  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
+  const uint32_t cnt = nn[i];
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  for (uint32_t k = 0; k < cnt; ++k) {
+    const uint32_t j = row[k];
+    const bool wall = (j & kWallBit) != 0u;
+    const float4 q = wall ? WP[j & ~kWallBit] : X[j];
+    const float rs = wall ? rbi : rbi + RB[j];
+    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 > 0.0f) || r2 >= p.r2f) continue;
+    const float r = __builtin_sqrtf(r2);
+    const float t = p.mass * p.sigma * p.inv_h * dw_shape(r * p.inv_h) / r * rs;
+    gx += t * dx;
+    gy += t * dy;
+    gz += t * dz;
+  }
+  float4 xb = XB[i];
+  xb.x += gx;
+  xb.y += gy;
+  xb.z += gz;
+  XB[i] = xb;
+}
+
+// planes <-> float4
+__global__ void k_diff_planes_in(int n, const float *__restrict__ src, float4 *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = make_float4(src[i], src[n + i], src[2 * n + i], 0.0f);
+}
+__global__ void k_diff_planes_out(int n, const float4 *__restrict__ src, float *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 v = src[i];
+  dst[i] = v.x;
+  dst[n + i] = v.y;
+  dst[2 * n + i] = v.z;
+}
+__global__ void k_diff_zero(int n, float4 *__restrict__ a, double *__restrict__ b,
+                            double *__restrict__ c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (a) a[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  b[i] = 0.0;
+  c[i] = 0.0;
+}
+
+// One workgroup: fixed-order sums of the two per-particle accumulators.
+__global__ void __launch_bounds__(256) k_diff_reduce(int n, const double *__restrict__ BB,
+                                                    const double *__restrict__ AA,
+                                                    double *__restrict__ out) {
+  __shared__ double s_b[256], s_a[256];
+  const int t = threadIdx.x;
+  double sb = 0.0, sa = 0.0;
+  for (int i = t; i < n; i += 256) {
+    sb += BB[i];
+    sa += AA[i];
+  }
+  s_b[t] = sb;
+  s_a[t] = sa;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s_b[t] += s_b[t + o];
+      s_a[t] += s_a[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = s_b[0];
+    out[1] = s_a[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+unsigned dgrid(int64_t n) { return (unsigned)(n > 0 ? (n + 255) / 256 : 1); }
+DiffArgs dargs(int n, int cap, float dt, float B, float alpha, float hc0) {
+  DiffArgs a;
+  a.dt = dt;
+  a.B = B;
+  a.alpha = alpha;
+  a.hc0 = hc0;
+  a.n = n;
+  a.cap = cap;
+  return a;
+}
+}  // namespace
+
+void launch_diff_planes_in(int n, const float *src, float4 *dst, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_diff_planes_in, dim3(dgrid(n)), dim3(256), 0, st, n, src, dst);
+}
+void launch_diff_planes_out(int n, const float4 *src, float *dst, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_diff_planes_out, dim3(dgrid(n)), dim3(256), 0, st, n, src, dst);
+}
+void launch_diff_zero(int n, float4 *a, double *b, double *c, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_diff_zero, dim3(dgrid(n)), dim3(256), 0, st, n, a, b, c);
+}
+
+// Lists, density and pressure of the state X (caller order): the sort of
+// the WCSPH path supplies the canonical block order.
+void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, float B,
+                       const float4 *X, uint32_t *L, uint32_t *nn, float *rho, float *prs,
+                       int grid_wave, hipStream_t st) {
+  const DiffArgs a = dargs(n, cap, 0.0f, B, 0.0f, 0.0f);
+  if (n > 0)
+    hipLaunchKernelGGL(k_diff_copy_in, dim3(dgrid(n)), dim3(256), 0, st, a, X, d.P[0], d.V[0],
+                       d.A[0], d.M[0], d.ID[0]);
+  launch_key_hist(p, d, 0, st);
+  launch_scan(p, d, d.CELL_START, true, st);
+  launch_scatter(p, d, st);
+  launch_cell_gather(p, d, 0, grid_wave, st);
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_diff_lists, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, d.PERM,
+                     d.CELL_START, d.WP, d.WCELL_START, L, nn, d.S);
+  hipLaunchKernelGGL(k_diff_density, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, L, nn, d.WP, rho,
+                     prs);
+}
+void launch_diff_force_euler(const DevParams &p, const DevPtrs &d, int n, int cap, float dt,
+                             float alpha, float hc0, const float4 *X, const float4 *V,
+                             const float *rho, const float *prs, const uint32_t *L,
+                             const uint32_t *nn, float4 *Xn, float4 *Vn, hipStream_t st) {
+  if (n == 0) return;
+  const DiffArgs a = dargs(n, cap, dt, 0.0f, alpha, hc0);
+  hipLaunchKernelGGL(k_diff_force_euler, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, V, rho, prs, L,
+                     nn, d.WP, Xn, Vn);
+}
+void launch_diff_adjoint(const DevParams &p, const DevPtrs &d, int n, int cap, float dt, float B,
+                         float alpha, float hc0, const float4 *X, const float4 *V,
+                         const float *rho, const float *prs, const uint32_t *L,
+                         const uint32_t *nn, float4 *XB, float4 *VB, float4 *AB, float *RB,
+                         double *BB, double *AA, hipStream_t st) {
+  if (n == 0) return;
+  const DiffArgs a = dargs(n, cap, dt, B, alpha, hc0);
+  hipLaunchKernelGGL(k_diff_adj_euler, dim3(dgrid(n)), dim3(256), 0, st, a, XB, VB, AB);
+  hipLaunchKernelGGL(k_diff_adj_force, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, V, rho, prs, L,
+                     nn, d.WP, AB, XB, VB, RB, BB, AA);
+  hipLaunchKernelGGL(k_diff_adj_density, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, L, nn, d.WP,
+                     RB, XB);
+}
+void launch_diff_reduce(int n, const double *BB, const double *AA, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_diff_reduce, dim3(1), dim3(256), 0, st, n, BB, AA, out);
+}
+
+}  // namespace rts

@@ -1102,6 +1102,193 @@ rts_status rts_autotune(rts_ctx *c, int32_t steps, void *d_scratch, size_t scrat
   return RTS_OK;
 }
 
+namespace {
+// Tape of the differentiable run: checkpoints, the frames of one segment,
+// the adjoint arrays.
+struct DiffTape {
+  float4 *CKX, *CKV;       // checkpoints, n each
+  float4 *FX, *FV;         // segment frames: state at the start of each substep
+  float *FR, *FP;          // density, pressure of each frame
+  uint32_t *FL, *FN;       // lists and counts of each frame
+  float4 *TX, *TV;         // state after the segment's last substep
+  float4 *XB, *VB, *AB;    // adjoints of x, v, a
+  float *RB;               // adjoint of rho
+  double *BB, *AA;         // per-particle parameter adjoints
+  double *RED;             // their sums
+};
+
+size_t diff_carve(const rts_diff_desc &D, int64_t n, char *base, DiffTape *t) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char * {
+    char *q = base ? base + off : nullptr;
+    off += align256(bytes > 0 ? bytes : 1);
+    return q;
+  };
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const size_t nck = (size_t)((D.n_sub + D.ckpt_every - 1) / D.ckpt_every);
+  const size_t nf = (size_t)D.ckpt_every;
+  DiffTape u;
+  u.CKX = (float4 *)take(nck * nn * 16);
+  u.CKV = (float4 *)take(nck * nn * 16);
+  u.FX = (float4 *)take(nf * nn * 16);
+  u.FV = (float4 *)take(nf * nn * 16);
+  u.FR = (float *)take(nf * nn * 4);
+  u.FP = (float *)take(nf * nn * 4);
+  u.FL = (uint32_t *)take(nf * nn * (size_t)D.list_cap * 4);
+  u.FN = (uint32_t *)take(nf * nn * 4);
+  u.TX = (float4 *)take(nn * 16);
+  u.TV = (float4 *)take(nn * 16);
+  u.XB = (float4 *)take(nn * 16);
+  u.VB = (float4 *)take(nn * 16);
+  u.AB = (float4 *)take(nn * 16);
+  u.RB = (float *)take(nn * 4);
+  u.BB = (double *)take(nn * 8);
+  u.AA = (double *)take(nn * 8);
+  u.RED = (double *)take(16);
+  if (t) *t = u;
+  return off;
+}
+
+rts_status diff_check(rts_ctx *c, const rts_diff_desc *D, int64_t n) {
+  if (!c || !D) return RTS_E_INVALID;
+  if (c->cfg.solver != RTS_WCSPH)
+    return fail(c, RTS_E_UNSUPPORTED, "the differentiable substep is WCSPH");
+  if (D->n_sub < 1 || D->ckpt_every < 1 || D->list_cap < 8 || D->list_cap > 4096 ||
+      !(D->dt > 0) || !(D->B > 0) || !(D->alpha > 0))
+    return fail(c, RTS_E_INVALID, "bad differentiable-run description");
+  if (n < 0 || n > c->ncap) return fail(c, RTS_E_CAPACITY, "n %lld exceeds capacity", (long long)n);
+  return RTS_OK;
+}
+
+// Forward substeps k0..k1 from (X0, V0): frames (when kept) and the end state.
+void diff_run_segment(rts_ctx *c, const rts_diff_desc &D, int n, const DiffTape &t,
+                      const float4 *X0, const float4 *V0, int len, bool keep, float4 *Xend,
+                      float4 *Vend) {
+  const float hc0 = (float)(c->cfg.h * c->cfg.c0);
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const float4 *X = X0, *V = V0;
+  for (int k = 0; k < len; ++k) {
+    const size_t f = keep ? (size_t)k : 0;
+    float4 *fx = t.FX + f * nn, *fv = t.FV + f * nn;
+    if (X != fx) {
+      (void)hipMemcpyAsync(fx, X, nn * 16, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(fv, V, nn * 16, hipMemcpyDeviceToDevice, c->stream);
+    }
+    uint32_t *L = t.FL + f * nn * (size_t)D.list_cap, *NN = t.FN + f * nn;
+    float *R = t.FR + f * nn, *P = t.FP + f * nn;
+    launch_diff_setup(c->prm, c->d, n, D.list_cap, (float)D.B, fx, L, NN, R, P, c->grid_wave,
+                      c->stream);
+    // the next state never aliases the frame being read: without kept frames
+    // it goes to TX / TV and is copied into frame 0 by the next substep
+    const bool last = k + 1 == len;
+    float4 *xn = last ? Xend : (keep ? t.FX + (f + 1) * nn : t.TX);
+    float4 *vn = last ? Vend : (keep ? t.FV + (f + 1) * nn : t.TV);
+    launch_diff_force_euler(c->prm, c->d, n, D.list_cap, (float)D.dt, (float)D.alpha, hc0, fx,
+                            fv, R, P, L, NN, xn, vn, c->stream);
+    X = xn;
+    V = vn;
+  }
+}
+
+}  // namespace
+
+rts_status rts_diff_tape_bytes(rts_ctx *c, const rts_diff_desc *D, int64_t n, size_t *bytes) {
+  rts_status s = diff_check(c, D, n);
+  if (s) return s;
+  if (!bytes) return RTS_E_INVALID;
+  *bytes = diff_carve(*D, n, nullptr, nullptr);
+  return RTS_OK;
+}
+
+rts_status rts_diff_forward(rts_ctx *c, const rts_diff_desc *D, int64_t n, const float *d_x0,
+                            const float *d_v0, float *d_xT, float *d_vT, void *d_tape,
+                            size_t tape_bytes) {
+  rts_status s = diff_check(c, D, n);
+  if (s) return s;
+  if (n > 0 && (!d_x0 || !d_v0 || !d_xT || !d_vT)) return fail(c, RTS_E_INVALID, "NULL array");
+  if (!d_tape || tape_bytes < diff_carve(*D, n, nullptr, nullptr) || ((uintptr_t)d_tape & 255u))
+    return fail(c, RTS_E_CAPACITY, "tape too small or not 256-byte aligned");
+  DiffTape t;
+  diff_carve(*D, n, (char *)d_tape, &t);
+  c->prm.n = (int32_t)n;
+  c->cur = 0;
+  c->has_state = false;   // the particle buffers serve as scratch
+  destroy_graphs(c);
+  launch_reset_scalars(c->d.S, c->stream);
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  launch_diff_planes_in((int)n, d_x0, t.CKX, c->stream);
+  launch_diff_planes_in((int)n, d_v0, t.CKV, c->stream);
+  const int nck = (D->n_sub + D->ckpt_every - 1) / D->ckpt_every;
+  for (int q = 0; q < nck; ++q) {
+    const int len = q + 1 < nck ? D->ckpt_every : D->n_sub - q * D->ckpt_every;
+    // the final state goes to the (not yet used) adjoint buffers
+    float4 *xe = q + 1 < nck ? t.CKX + (size_t)(q + 1) * nn : t.XB;
+    float4 *ve = q + 1 < nck ? t.CKV + (size_t)(q + 1) * nn : t.VB;
+    diff_run_segment(c, *D, (int)n, t, t.CKX + (size_t)q * nn, t.CKV + (size_t)q * nn, len, false,
+                     xe, ve);
+    if (q + 1 == nck) {
+      launch_diff_planes_out((int)n, xe, d_xT, c->stream);
+      launch_diff_planes_out((int)n, ve, d_vT, c->stream);
+    }
+  }
+  HIP_OK(c, hipGetLastError());
+  return RTS_OK;
+}
+
+rts_status rts_diff_backward(rts_ctx *c, const rts_diff_desc *D, int64_t n,
+                             const float *d_xT_bar, const float *d_vT_bar, float *d_x0_bar,
+                             float *d_v0_bar, double *h_B_bar, double *h_alpha_bar, void *d_tape,
+                             size_t tape_bytes) {
+  rts_status s = diff_check(c, D, n);
+  if (s) return s;
+  if (n > 0 && !d_xT_bar) return fail(c, RTS_E_INVALID, "NULL dL/dx(T)");
+  if (!d_tape || tape_bytes < diff_carve(*D, n, nullptr, nullptr) || ((uintptr_t)d_tape & 255u))
+    return fail(c, RTS_E_CAPACITY, "tape too small or not 256-byte aligned");
+  DiffTape t;
+  diff_carve(*D, n, (char *)d_tape, &t);
+  c->prm.n = (int32_t)n;
+  c->cur = 0;
+  c->has_state = false;
+  destroy_graphs(c);
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const float hc0 = (float)(c->cfg.h * c->cfg.c0);
+  launch_diff_planes_in((int)n, d_xT_bar, t.XB, c->stream);
+  if (d_vT_bar) {
+    launch_diff_planes_in((int)n, d_vT_bar, t.VB, c->stream);
+    launch_diff_zero((int)n, nullptr, t.BB, t.AA, c->stream);
+  } else {
+    launch_diff_zero((int)n, t.VB, t.BB, t.AA, c->stream);
+  }
+  const int nck = (D->n_sub + D->ckpt_every - 1) / D->ckpt_every;
+  for (int q = nck - 1; q >= 0; --q) {
+    const int len = q + 1 < nck ? D->ckpt_every : D->n_sub - q * D->ckpt_every;
+    // recompute the segment, keeping every frame (the end state is not needed)
+    diff_run_segment(c, *D, (int)n, t, t.CKX + (size_t)q * nn, t.CKV + (size_t)q * nn, len, true,
+                     t.TX, t.TV);
+    for (int k = len - 1; k >= 0; --k) {
+      const size_t f = (size_t)k;
+      launch_diff_adjoint(c->prm, c->d, (int)n, D->list_cap, (float)D->dt, (float)D->B,
+                          (float)D->alpha, hc0, t.FX + f * nn, t.FV + f * nn, t.FR + f * nn,
+                          t.FP + f * nn, t.FL + f * nn * (size_t)D->list_cap, t.FN + f * nn,
+                          t.XB, t.VB, t.AB, t.RB, t.BB, t.AA, c->stream);
+    }
+  }
+  if (d_x0_bar) launch_diff_planes_out((int)n, t.XB, d_x0_bar, c->stream);
+  if (d_v0_bar) launch_diff_planes_out((int)n, t.VB, d_v0_bar, c->stream);
+  launch_diff_reduce((int)n, t.BB, t.AA, t.RED, c->stream);
+  HIP_OK(c, hipGetLastError());
+  double red[2] = {0.0, 0.0};
+  HIP_OK(c, hipMemcpyAsync(red, t.RED, 16, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (h_B_bar) *h_B_bar = red[0];
+  if (h_alpha_bar) *h_alpha_bar = red[1];
+  DevScalars S;
+  HIP_OK(c, hipMemcpy(&S, c->d.S, sizeof(S), hipMemcpyDeviceToHost));
+  if (S.status) return fail(c, (rts_status)S.status, "device reported %s during the run",
+                            rts_status_string((rts_status)S.status));
+  return RTS_OK;
+}
+
 rts_status rts_grid_info(rts_ctx *c, int32_t *nc3, int64_t *nblocks, double *mass, double *B,
                          double *dt_base) {
   if (!c) return RTS_E_INVALID;

@@ -228,4 +228,22 @@ void launch_pci_integrate(const DevParams &p, const DevPtrs &d, int cur, int maj
 void launch_pci_demote(const DevParams &p, const DevPtrs &d, int cur, int major_len,
                        hipStream_t st);
 
+// Differentiable substep launchers (diff_kernels.hip)
+void launch_diff_planes_in(int n, const float *src, float4 *dst, hipStream_t st);
+void launch_diff_planes_out(int n, const float4 *src, float *dst, hipStream_t st);
+void launch_diff_zero(int n, float4 *a, double *b, double *c, hipStream_t st);
+void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, float B,
+                       const float4 *X, uint32_t *L, uint32_t *nn, float *rho, float *prs,
+                       int grid_wave, hipStream_t st);
+void launch_diff_force_euler(const DevParams &p, const DevPtrs &d, int n, int cap, float dt,
+                             float alpha, float hc0, const float4 *X, const float4 *V,
+                             const float *rho, const float *prs, const uint32_t *L,
+                             const uint32_t *nn, float4 *Xn, float4 *Vn, hipStream_t st);
+void launch_diff_adjoint(const DevParams &p, const DevPtrs &d, int n, int cap, float dt, float B,
+                         float alpha, float hc0, const float4 *X, const float4 *V,
+                         const float *rho, const float *prs, const uint32_t *L,
+                         const uint32_t *nn, float4 *XB, float4 *VB, float4 *AB, float *RB,
+                         double *BB, double *AA, hipStream_t st);
+void launch_diff_reduce(int n, const double *BB, const double *AA, double *out, hipStream_t st);
+
 }  // namespace rts
