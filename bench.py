@@ -43,6 +43,8 @@ def parse():
                     help="run the PCISPH comparison only (for profiler runs); no JSON line")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="base steps of the 64-scene batch and of its sequential runs (0: skip)")
+    ap.add_argument("--diff-repeats", type=int, default=3,
+                    help="timed forward+backward runs of the differentiable 101k scene (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run an elementwise copy of 256 MiB three times, the "
                          "reference kernel for scaling HBM byte counters")
@@ -51,6 +53,7 @@ def parse():
 
 PROFILE_MD = os.path.join(ROOT, "profiles", "wcsph_rts_dam_break_250k_kernels.md")
 KERNEL_SOURCES = ("paper_2009_14514_amd/csrc/rts_kernels.hip",
+                  "paper_2009_14514_amd/csrc/rts_device.h",
                   "paper_2009_14514_amd/csrc/rts_internal.h")
 
 
@@ -281,6 +284,46 @@ def run_batched(steps):
     }
 
 
+def run_diff(repeats):
+    """Differentiable WCSPH: 101,306-particle dam break (37 x 74 x 37), 16
+    substeps of 1e-4 s with checkpoints every 4; forward, then the adjoint
+    for L = mean |x(T) - xhat| ^ 2 (gradients in v0, x0, B, alpha)."""
+    import torch
+
+    from paper_2009_14514_amd import scenes
+    from paper_2009_14514_amd.diff import DiffRollout
+
+    sc = scenes.diff_scene(counts=(37, 74, 37), box=(2.0, 1.0, 1.0))
+    model = DiffRollout(sc, n_sub=16, ckpt_every=4)
+    x0 = torch.tensor(sc.pos, dtype=torch.float32, device="cuda")
+    v0 = torch.tensor(sc.vel, dtype=torch.float32, device="cuda")
+    xT, _ = model.forward(x0, v0, model.B0, model.alpha0)      # nominal run: the target
+    xhat = xT + torch.tensor(scenes.target_noise(sc.n, sc.params["target_sigma"]),
+                             dtype=torch.float32, device="cuda")
+    fw, bw = [], []
+    for _ in range(max(repeats, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xT, _ = model.forward(x0, v0, model.B0, model.alpha0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gx, gv, gB, ga = model.backward(2.0 * (xT - xhat) / sc.n)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fw.append(t1 - t0)
+        bw.append(t2 - t1)
+    model.close()
+    f, b = min(fw) * 1e3, min(bw) * 1e3
+    print(f"[bench] differentiable: forward {f:.2f} ms, backward {b:.2f} ms", file=sys.stderr,
+          flush=True)
+    return {"workload": "wcsph_diff_dam_break_101k_16_substeps", "n_particles": sc.n,
+            "substeps": 16, "checkpoint_every": 4, "forward_ms": f, "backward_ms": b,
+            "unit": "particle-substeps/s",
+            "value": sc.n * 16 / ((f + b) * 1e-3),
+            "grad_norms": {"v0": float(gv.norm()), "x0": float(gx.norm()), "B": gB,
+                           "alpha": ga}}
+
+
 def run_cpu_baseline(budget_s):
     """FP64 oracle, RTS mode, on the first steps of the same workload."""
     import numpy as np
@@ -378,6 +421,8 @@ def main():
         line["pcisph"] = run_pcisph(args.pcisph_steps)
     if args.batch_steps > 0:
         line["batched"] = run_batched(args.batch_steps)
+    if args.diff_repeats > 0:
+        line["differentiable"] = run_diff(args.diff_repeats)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = run_cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

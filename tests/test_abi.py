@@ -64,3 +64,46 @@ def test_create_rejects_a_bad_workspace_without_touching_the_device():
     with pytest.raises(_rts.RtsError) as e:
         _rts.create(cfg, sc.n, sc.nw, 4096 + 8, 1 << 30, 0)     # misaligned
     assert e.value.status == _rts.RTS_E_INVALID
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors have the sizes and field offsets the C compiler gives
+    the header's structs."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    checks = {
+        "rts_config": (_rts.RtsConfig, ["n_minor", "nbr_cap", "eta", "r_list", "beta_ratio"]),
+        "rts_stats": (_rts.RtsStats, ["bad_index", "pci_iters", "pci_errmax", "pci_iters_total"]),
+        "rts_tune": (_rts.RtsTune, ["candidates", "ms_per_step"]),
+        "rts_diff_desc": (_rts.RtsDiffDesc, ["list_cap", "dt", "alpha"]),
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rts.h"', "int main(void) {"]
+    for name, (_, fields) in checks.items():
+        lines.append(f'printf("%zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'printf("%zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = []
+    for name, (cls, fields) in checks.items():
+        want.append(C.sizeof(cls))
+        want += [getattr(cls, f).offset for f in fields]
+    assert got == want
+
+
+@pytest.mark.parametrize("field,value", [("n_minor", 0), ("nbr_cap", 4), ("eta", 0.0),
+                                         ("mode", 2), ("r_list", 1.0)])
+def test_invalid_pcisph_configurations_are_rejected(field, value):
+    sc = scenes.pcisph_dam_break_small()
+    cfg = _rts.config_from_params(sc.params)
+    setattr(cfg, field, value)
+    with pytest.raises(_rts.RtsError):
+        _rts.workspace_size(cfg, sc.n, sc.nw)
