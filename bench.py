@@ -43,6 +43,8 @@ def parse():
                     help="run the PCISPH comparison only (for profiler runs); no JSON line")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="base steps of the 64-scene batch and of its sequential runs (0: skip)")
+    ap.add_argument("--more-steps", type=int, default=500,
+                    help="base steps of the double dam break and block drop legs (0: skip)")
     ap.add_argument("--diff-repeats", type=int, default=3,
                     help="timed forward+backward runs of the differentiable 101k scene (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -324,6 +326,49 @@ def run_diff(repeats):
                            "alpha": ga}}
 
 
+def run_more_wcsph(steps):
+    """The paper's other WCSPH scenes as synthetic stand-ins: a double dam
+    break (256,000 particles) and a dam break with a dropped block (177,000);
+    regional vs global adaptive stepping over the same simulated time."""
+    import torch
+
+    from paper_2009_14514_amd import scenes
+    from paper_2009_14514_amd.sim import Simulation
+
+    def run(sim, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.advance(k)
+        st = sim.sync()
+        return (time.perf_counter() - t0) * 1e3, st
+
+    out = {}
+    for name, make in (("wcsph_double_dam_break_256k", scenes.wcsph_double_dam_break),
+                       ("wcsph_block_drop_177k", scenes.block_drop)):
+        sc = make()
+        rts = Simulation(sc, mode="rts")
+        init = rts.save()
+        rts.advance(10)
+        rts.sync()
+        rts.load(init)
+        ms_r, st_r = run(rts, steps)
+        ga = Simulation(sc, mode="global_adaptive")
+        ms_g, st_g = run(ga, steps)
+        while st_g.time < st_r.time * (1.0 - 1e-9):
+            m, st_g = run(ga, 10)
+            ms_g += m
+        out[name] = {"n_particles": sc.n, "base_steps": steps,
+                     "value": sc.n * steps / (ms_r * 1e-3), "unit": "particle-steps/s",
+                     "density_err_max": float(st_r.err_max_run),
+                     "global_adaptive_err_max": float(st_g.err_max_run),
+                     "speedup_vs_global_adaptive": ms_g / ms_r}
+        print(f"[bench] {name}: rts {ms_r:.1f} ms, global adaptive {ms_g:.1f} ms",
+              file=sys.stderr, flush=True)
+        rts.close()
+        ga.close()
+    return out
+
+
 def run_cpu_baseline(budget_s):
     """FP64 oracle, RTS mode, on the first steps of the same workload."""
     import numpy as np
@@ -421,6 +466,8 @@ def main():
         line["pcisph"] = run_pcisph(args.pcisph_steps)
     if args.batch_steps > 0:
         line["batched"] = run_batched(args.batch_steps)
+    if args.more_steps > 0:
+        line["more_wcsph"] = run_more_wcsph(args.more_steps)
     if args.diff_repeats > 0:
         line["differentiable"] = run_diff(args.diff_repeats)
     if not args.no_cpu_baseline:

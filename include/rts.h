@@ -103,6 +103,9 @@ typedef struct rts_config {
   int32_t global_limit;   /* global iterations in one minor step that end the major step (6) */
   int32_t short_majors;   /* clean major steps before the long major step returns (10) */
   int32_t nbr_cap;        /* neighbour-list entries per particle (PCISPH) */
+  int32_t two_ring_levels;/* regions whose lists search two block layers (paper: 1, region 1;
+                             2 adds region 2, the variant of the paper's comparison figure) */
+  int32_t pad;
   double eta;             /* allowed maximum compression (paper: 1 %) */
   double eta_T;           /* average compression above which extra iterations are global */
   double delta;           /* pressure coefficient (<= 0: from the full rest-lattice

@@ -34,7 +34,7 @@ class OrcCfg(C.Structure):
         ("clamp_p", C.c_int32), ("serna_correct", C.c_int32), ("nbr_cap", C.c_int32),
         ("solver", C.c_int32), ("n_minor", C.c_int32), ("it_min", C.c_int32),
         ("it_max", C.c_int32), ("expand_layers", C.c_int32), ("local_fail", C.c_int32),
-        ("global_limit", C.c_int32), ("short_majors", C.c_int32), ("pad_", C.c_int32),
+        ("global_limit", C.c_int32), ("short_majors", C.c_int32), ("two_ring_levels", C.c_int32),
         ("eta", C.c_double), ("eta_T", C.c_double), ("delta", C.c_double), ("r_list", C.c_double),
     ]
 
@@ -171,6 +171,7 @@ def cfg_from_params(p: dict, **over) -> OrcCfg:
     c.expand_layers = q.get("expand_layers", 4)
     c.local_fail, c.global_limit = q.get("local_fail", 3), q.get("global_limit", 6)
     c.short_majors = q.get("short_majors", 10)
+    c.two_ring_levels = q.get("two_ring_levels", 1)
     c.eta, c.eta_T = q.get("eta", 0.01), q.get("eta_T", 0.0025)
     c.delta, c.r_list = q.get("delta", 0.0), q.get("r_list", 0.0)
     return c

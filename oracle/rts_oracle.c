@@ -1007,8 +1007,9 @@ int orc_pci_step(const orc_cfg *c, orc_pci_state *s) {
   for (int64_t k = 0; k < 3 * (int64_t)s->nw; ++k) wf[k] = (float)s->wx[k];
   uint8_t *rings = (uint8_t *)malloc(nn);
   int32_t lists = 0;
+  const int32_t two = c->two_ring_levels > 0 ? c->two_ring_levels : 1;
   for (int32_t i = 0; i < n; ++i) {
-    rings[i] = (uint8_t)((!standard && s->region[i] == 1) ? 2 : 1);
+    rings[i] = (uint8_t)((!standard && s->region[i] <= two) ? 2 : 1);
     lists += s->compute[i] ? 1 : 0;
   }
   int st = orc_pci_lists(c, n, pf, s->cell_start, s->key, s->nw, wf, s->wcell_start, s->compute,

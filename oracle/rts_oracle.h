@@ -48,7 +48,7 @@ typedef struct orc_cfg {
   int32_t local_fail;                /* local iterations before reverting to global (3) */
   int32_t global_limit;              /* global iterations that end a major step early (6) */
   int32_t short_majors;              /* clean major steps before the long major returns (10) */
-  int32_t pad_;
+  int32_t two_ring_levels;           /* regions searching two block layers (<= 0: 1, region 1) */
   double eta, eta_T;                 /* max / average compression error thresholds */
   double delta;                      /* <= 0: from the prototype neighbourhood */
   double r_list;                     /* neighbour-list radius; <= 0: block edge */

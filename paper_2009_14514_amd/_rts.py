@@ -52,7 +52,8 @@ class RtsConfig(C.Structure):
         ("beta2", C.c_double), ("beta_ratio", C.c_double),
         ("n_minor", C.c_int32), ("it_min", C.c_int32), ("it_max", C.c_int32),
         ("expand_layers", C.c_int32), ("local_fail", C.c_int32), ("global_limit", C.c_int32),
-        ("short_majors", C.c_int32), ("nbr_cap", C.c_int32),
+        ("short_majors", C.c_int32), ("nbr_cap", C.c_int32), ("two_ring_levels", C.c_int32),
+        ("pad", C.c_int32),
         ("eta", C.c_double), ("eta_T", C.c_double), ("delta", C.c_double), ("r_list", C.c_double),
     ]
 
@@ -170,7 +171,7 @@ def config_from_params(p: dict, **over) -> RtsConfig:
         setattr(c, k, float(q[k]))
     c.r_crit = float(q.get("r_crit", 0.0))
     for k in ("n_minor", "it_min", "it_max", "expand_layers", "local_fail", "global_limit",
-              "short_majors"):
+              "short_majors", "two_ring_levels"):
         if k in q:
             setattr(c, k, int(q[k]))
     if c.solver == RTS_PCISPH:

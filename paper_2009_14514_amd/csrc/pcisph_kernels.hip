@@ -7,7 +7,7 @@
 // R_min and marks the observed blocks.  Each minor step then
 //   lists        rebuilds the neighbour lists of particles whose validity ran
 //                out, against the grid of the major step (two block layers
-//                for region 1)
+//                for region 1, or regions 1 and 2)
 //   nonpressure  gravity + viscosity of the same particles
 //   reset        p = 0, F^p = 0, S_e empty
 //   per iteration (the host reads the error reductions between iterations):
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(256) k_pci_lists(
   if (i >= p.n) return;
   const uint32_t m = M[i];
   if (!meta_compute(m)) return;
-  const int rings = (p.mode == RTS_MODE_RTS && meta_level(m) == 0u) ? 2 : 1;
+  const int rings = (p.mode == RTS_MODE_RTS && (int)meta_level(m) < p.two_ring_levels) ? 2 : 1;
   const float4 xi = P[i];
   const int3 c = coords_of(p, key[i]);
   uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;

@@ -142,6 +142,10 @@ rts_status validate(const rts_config *c, char *msg, size_t cap) {
       snprintf(msg, cap, "PCISPH schedule parameters out of range");
       return RTS_E_INVALID;
     }
+    if (c->two_ring_levels < 0 || c->two_ring_levels > 4) {
+      snprintf(msg, cap, "two_ring_levels must be in [0, 4]");
+      return RTS_E_INVALID;
+    }
     if (c->nbr_cap < 8 || c->nbr_cap > 4096) {
       snprintf(msg, cap, "nbr_cap must be in [8, 4096]");
       return RTS_E_INVALID;
@@ -256,6 +260,7 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   p.support = (float)c.support;
   if (c.solver == RTS_PCISPH) {
     p.nbr_cap = c.nbr_cap;
+    p.two_ring_levels = c.two_ring_levels > 0 ? c.two_ring_levels : 1;
     const double rl = c.r_list > 0.0 ? c.r_list : c.block_edge;
     p.r2l = (float)(rl * rl);
     p.delta = (float)(c.delta > 0.0 ? c.delta : pci_delta(c, mass, dtb));
@@ -564,6 +569,7 @@ void rts_default_config(rts_config *c) {
   c->global_limit = 6;
   c->short_majors = 10;
   c->nbr_cap = 128;
+  c->two_ring_levels = 1;
   c->eta = 0.01;
   c->eta_T = 0.0025;
   c->delta = 0.0;

@@ -54,6 +54,7 @@ struct DevParams {
   // PCISPH
   int32_t solver;
   int32_t nbr_cap;       // list entries per particle
+  int32_t two_ring_levels;  // regions (levels 0..k-1) whose lists search two block layers
   float support;         // kernel support r
   float r2l;             // list radius squared
   float delta;           // pressure per unit density excess

@@ -75,7 +75,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     checks = {
-        "rts_config": (_rts.RtsConfig, ["n_minor", "nbr_cap", "eta", "r_list", "beta_ratio"]),
+        "rts_config": (_rts.RtsConfig, ["n_minor", "nbr_cap", "two_ring_levels", "eta", "r_list",
+                                        "beta_ratio"]),
         "rts_stats": (_rts.RtsStats, ["bad_index", "pci_iters", "pci_errmax", "pci_iters_total"]),
         "rts_tune": (_rts.RtsTune, ["candidates", "ms_per_step"]),
         "rts_diff_desc": (_rts.RtsDiffDesc, ["list_cap", "dt", "alpha"]),

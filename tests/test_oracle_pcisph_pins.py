@@ -347,3 +347,19 @@ def test_resting_column_stays_within_the_error_bound():
     assert max(h["errmax"] for h in sim.history) < sc.params["eta"]
     # settling of the jitter only: slower than a fall through one spacing
     assert np.linalg.norm(sim.v, axis=1).max() < np.sqrt(2 * 9.81 * sc.params["spacing"])
+
+
+def test_two_layer_variant_searches_region_two_with_two_layers():
+    """With two_ring_levels = 2 a minor step builds region-2 lists over two
+    block layers of the stored grid (brute force on the same snapshot)."""
+    sc = pscene(v0=1.5)
+    sim = O.PCISPH(sc.params, sc.pos, vel=sc.vel, walls=sc.walls, two_ring_levels=2)
+    sim.major_begin()
+    assert np.all(sim.region == 2)
+    x32 = sim.x.astype(np.float32)
+    sim.step()
+    st, nbr, nnb = O.pci_lists(sim.cfg, x32, sim.cell_start, sim.key, sim.wx.astype(np.float32),
+                               sim.wcell_start, rings=np.full(sc.n, 2, np.uint8))
+    assert st == 0
+    assert np.array_equal(sim.nnb[:sc.n], nnb)
+    assert np.array_equal(sim.nbr[:sc.n], nbr)
