@@ -62,7 +62,8 @@ __global__ void __launch_bounds__(256) k_diff_lists(
   if (i >= a.n) return;
   const float4 xi = X[i];
   const int3 c = block_of(p, xi.x, xi.y, xi.z);
-  uint32_t *row_out = L + (size_t)i * (size_t)a.cap;
+  // column-major: entry k of particle i at L[k * n + i]
+  uint32_t *row_out = L + (size_t)i;
   uint32_t cnt = 0;
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1 && p.nw == 0) break;
@@ -81,7 +82,7 @@ __global__ void __launch_bounds__(256) k_diff_lists(
           if (pass == 0 && j == (uint32_t)i) continue;
           const float4 q = pass == 0 ? X[j] : WP[s];
           if (!(dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2f)) continue;
-          if (cnt < (uint32_t)a.cap) row_out[cnt] = pass == 0 ? j : (s | kWallBit);
+          if (cnt < (uint32_t)a.cap) row_out[(size_t)cnt * (size_t)a.n] = pass == 0 ? j : (s | kWallBit);
           ++cnt;
         }
       }
@@ -103,11 +104,12 @@ __global__ void __launch_bounds__(256) k_diff_density(
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const float4 xi = X[i];
-  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
+  const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
   float sum = 0.0f, comp = 0.0f;
+#pragma unroll 4
   for (uint32_t k = 0; k < cnt; ++k) {
-    const uint32_t j = row[k];
+    const uint32_t j = row[(size_t)k * (size_t)a.n];
     const float4 q = (j & kWallBit) ? WP[j & ~kWallBit] : X[j];
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float w = w_shape(__builtin_sqrtf(dx * dx + dy * dy + dz * dz) * p.inv_h);
@@ -130,11 +132,12 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
   if (i >= a.n) return;
   const float4 xi = X[i], vi = V[i];
   const float ri = rho[i], Pi = prs[i] / (ri * ri);
-  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
+  const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
   float ax = p.g[0], ay = p.g[1], az = p.g[2];
+#pragma unroll 4
   for (uint32_t k = 0; k < cnt; ++k) {
-    const uint32_t j = row[k];
+    const uint32_t j = row[(size_t)k * (size_t)a.n];
     const bool wall = (j & kWallBit) != 0u;
     float4 q, u = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float coef, nu;
@@ -191,14 +194,15 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
   if (i >= a.n) return;
   const float4 xi = X[i], vi = V[i], abi = AB[i];
   const float ri = rho[i], pi = prs[i], Pi = pi / (ri * ri);
-  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
+  const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
   const float m = p.mass, e = p.visc_eps_h2;
   const float inv_h2 = p.inv_h * p.inv_h;
   float gxx = 0.0f, gxy = 0.0f, gxz = 0.0f, gvx = 0.0f, gvy = 0.0f, gvz = 0.0f;
   float Pb = 0.0f, rb = 0.0f, alb = 0.0f;
+#pragma unroll 4
   for (uint32_t k = 0; k < cnt; ++k) {
-    const uint32_t j = row[k];
+    const uint32_t j = row[(size_t)k * (size_t)a.n];
     const bool wall = (j & kWallBit) != 0u;
     float4 q, vj = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float coef, nu, rj = ri, ux, uy, uz;
@@ -285,11 +289,12 @@ __global__ void __launch_bounds__(256) k_diff_adj_density(
   if (i >= a.n) return;
   const float4 xi = X[i];
   const float rbi = RB[i];
-  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
+  const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
   float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll 4
   for (uint32_t k = 0; k < cnt; ++k) {
-    const uint32_t j = row[k];
+    const uint32_t j = row[(size_t)k * (size_t)a.n];
     const bool wall = (j & kWallBit) != 0u;
     const float4 q = wall ? WP[j & ~kWallBit] : X[j];
     const float rs = wall ? rbi : rbi + RB[j];

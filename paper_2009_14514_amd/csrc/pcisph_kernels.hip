@@ -134,7 +134,10 @@ __global__ void __launch_bounds__(256) k_pci_lists(
   const int rings = (p.mode == RTS_MODE_RTS && (int)meta_level(m) < p.two_ring_levels) ? 2 : 1;
   const float4 xi = P[i];
   const int3 c = coords_of(p, key[i]);
-  uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;
+  // column-major lists: entry k of particle i at nbr[k * ncap + i], so that
+  // a wave's loads of one entry index are contiguous
+  uint32_t *L = nbr + (size_t)i;
+  const size_t stride = (size_t)p.ncap;
   uint32_t cnt = 0;
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1 && p.nw == 0) break;
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(256) k_pci_lists(
           if (pass == 0 && j == (uint32_t)i) continue;
           const float4 q = X[j];
           if (!(dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2l)) continue;
-          if (cnt < (uint32_t)p.nbr_cap) L[cnt] = j | tag;
+          if (cnt < (uint32_t)p.nbr_cap) L[(size_t)cnt * stride] = j | tag;
           ++cnt;
         }
       }
@@ -181,12 +184,14 @@ __global__ void __launch_bounds__(256) k_pci_nonpressure(
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n || !meta_compute(M[i])) return;
   const float4 xi = P[i], vi = V[i];
-  const uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;
+  const uint32_t *L = nbr + (size_t)i;
+  const size_t stride = (size_t)p.ncap;
   const uint32_t n = nnb[i];
   const float rs2 = p.support * p.support;
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll 4
   for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t j = L[k];
+    const uint32_t j = L[(size_t)k * stride];
     const bool wall = (j & kWallBit) != 0u;
     const float4 q = wall ? WP[j & ~kWallBit] : P[j];
     const float4 u = wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[j];
@@ -243,11 +248,13 @@ __global__ void __launch_bounds__(256) k_pci_density(
   const bool in_se = se[i] != 0;
   if (!(has_turn(turn, meta_level(M[i])) || in_se || ob[b] || nearse[b])) return;
   const float4 xi = xs[i];
-  const uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;
+  const uint32_t *L = nbr + (size_t)i;
+  const size_t stride = (size_t)p.ncap;
   const uint32_t n = nnb[i];
   float sum = 0.0f, comp = 0.0f;
+#pragma unroll 4
   for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t j = L[k];
+    const uint32_t j = L[(size_t)k * stride];
     const float4 q = (j & kWallBit) ? WP[j & ~kWallBit] : xs[j];
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
@@ -296,12 +303,14 @@ __global__ void __launch_bounds__(256) k_pci_force(
   if (!(has_turn(turn, meta_level(M[i])) || se[i])) return;
   const float4 xi = xs[i];
   const float qi = pq[i];
-  const uint32_t *L = nbr + (size_t)i * (size_t)p.nbr_cap;
+  const uint32_t *L = nbr + (size_t)i;
+  const size_t stride = (size_t)p.ncap;
   const uint32_t n = nnb[i];
   const float rs2 = p.support * p.support;
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll 4
   for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t j = L[k];
+    const uint32_t j = L[(size_t)k * stride];
     const bool wall = (j & kWallBit) != 0u;
     const float4 q = wall ? WP[j & ~kWallBit] : xs[j];
     const float qj = wall ? qi : pq[j];
@@ -319,65 +328,72 @@ __global__ void __launch_bounds__(256) k_pci_force(
 // Max and mean compression over all particles (each keeps its latest
 // error) and particles per region; per-workgroup partials folded in a fixed
 // order by the last workgroup.
+__device__ inline void pci_part_add(PciPart &t, const PciPart &u) {
+  t.errmax = fmaxf(t.errmax, u.errmax);
+  t.sum += u.sum;
+  t.ncomp += u.ncomp;
+  for (int k = 0; k < 4; ++k) t.hist[k] += u.hist[k];
+}
+
+// Reduces a 256-thread workgroup's partials (one per thread) in a fixed
+// order: waves by shuffles, then the four wave totals in order.
+__device__ inline PciPart pci_block_reduce(PciPart t, PciPart *s_w) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    t.errmax = fmaxf(t.errmax, __shfl_xor(t.errmax, o, 64));
+    t.sum += __shfl_xor(t.sum, o, 64);
+    t.ncomp += __shfl_xor(t.ncomp, o, 64);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t.hist[k] += __shfl_xor(t.hist[k], o, 64);
+  }
+  if (lane == 0) s_w[wave] = t;
+  __syncthreads();
+  PciPart a = s_w[0];
+  for (int w = 1; w < 4; ++w) pci_part_add(a, s_w[w]);
+  __syncthreads();
+  return a;
+}
+
+// Max and mean compression over all particles (each keeps its latest
+// error), particles per region and with the compute flag; per-workgroup
+// partials folded in a fixed order by the last workgroup.  `first`: the
+// compute count is also kept as this minor step's list count.
 __global__ void __launch_bounds__(256) k_pci_errstats(DevParams p, const float4 *__restrict__ pv,
                                                      const uint32_t *__restrict__ M,
-                                                     PciPart *__restrict__ part, DevPci *pci) {
+                                                     PciPart *__restrict__ part, DevPci *pci,
+                                                     int first) {
   __shared__ PciPart s_w[4];
   __shared__ uint32_t s_last;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  float mx = 0.0f;
-  double sum = 0.0;
-  int32_t hist[4] = {0, 0, 0, 0}, ncomp = 0;
+  const int tid = threadIdx.x;
+  PciPart t = {};
   for (int i = blockIdx.x * blockDim.x + tid; i < p.n; i += gridDim.x * blockDim.x) {
     const float e = fmaxf(pv[i].y, 0.0f);
-    mx = fmaxf(mx, e);
-    sum += (double)e;
+    t.errmax = fmaxf(t.errmax, e);
+    t.sum += (double)e;
     const uint32_t m = M[i], l = meta_level(m);
-    ncomp += (int32_t)meta_compute(m);
+    t.ncomp += (int32_t)meta_compute(m);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) hist[k] += l == (uint32_t)k ? 1 : 0;
+    for (int k = 0; k < 4; ++k) t.hist[k] += l == (uint32_t)k ? 1 : 0;
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-    sum += __shfl_xor(sum, o, 64);
-    ncomp += __shfl_xor(ncomp, o, 64);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) hist[k] += __shfl_xor(hist[k], o, 64);
-  }
-  if (lane == 0) {
-    s_w[wave].errmax = mx;
-    s_w[wave].sum = sum;
-    s_w[wave].ncomp = ncomp;
-    for (int k = 0; k < 4; ++k) s_w[wave].hist[k] = hist[k];
-  }
-  __syncthreads();
+  const PciPart a = pci_block_reduce(t, s_w);
   if (tid == 0) {
-    PciPart t = s_w[0];
-    for (int w = 1; w < 4; ++w) {
-      t.errmax = fmaxf(t.errmax, s_w[w].errmax);
-      t.sum += s_w[w].sum;
-      t.ncomp += s_w[w].ncomp;
-      for (int k = 0; k < 4; ++k) t.hist[k] += s_w[w].hist[k];
-    }
-    part[blockIdx.x] = t;
+    part[blockIdx.x] = a;
     __threadfence();
     s_last = atomicAdd(&pci->ticket, 1u) == gridDim.x - 1 ? 1u : 0u;
   }
   __syncthreads();
-  if (!s_last || tid != 0) return;
+  if (!s_last) return;
   __threadfence();
-  PciPart a = part[0];
-  for (unsigned g = 1; g < gridDim.x; ++g) {
-    const PciPart u = part[g];
-    a.errmax = fmaxf(a.errmax, u.errmax);
-    a.sum += u.sum;
-    a.ncomp += u.ncomp;
-    for (int k = 0; k < 4; ++k) a.hist[k] += u.hist[k];
-  }
-  pci->ncomp = a.ncomp;
-  pci->errmax = a.errmax;
-  pci->avg = p.n > 0 ? a.sum / (double)p.n : 0.0;
-  for (int k = 0; k < 4; ++k) pci->hist[k] = a.hist[k];
+  // the last workgroup folds the partials: thread k takes partials k, k+256, ...
+  PciPart u = {};
+  for (unsigned g = (unsigned)tid; g < gridDim.x; g += 256) pci_part_add(u, part[g]);
+  const PciPart r = pci_block_reduce(u, s_w);
+  if (tid != 0) return;
+  pci->ncomp = r.ncomp;
+  if (first) pci->ncomp_first = r.ncomp;
+  pci->errmax = r.errmax;
+  pci->avg = p.n > 0 ? r.sum / (double)p.n : 0.0;
+  for (int k = 0; k < 4; ++k) pci->hist[k] = r.hist[k];
   pci->ticket = 0u;
 }
 
@@ -469,6 +485,16 @@ __global__ void k_pci_demote_particles(DevParams p, const uint32_t *__restrict__
   if (l < meta_level(m)) M[i] = meta_pack(l, 1u, 0u, region_validity((int)l, major_len));
 }
 
+// Row view of the column-major lists (debug): out[i * cap + k] = nbr[k * ncap + i].
+__global__ void k_pci_lists_rows(DevParams p, const uint32_t *__restrict__ nbr,
+                                 const uint32_t *__restrict__ nnb, uint32_t *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const uint32_t cnt = min(nnb[i], (uint32_t)p.nbr_cap);
+  for (uint32_t k = 0; k < (uint32_t)p.nbr_cap; ++k)
+    out[(size_t)i * (size_t)p.nbr_cap + k] = k < cnt ? nbr[(size_t)k * (size_t)p.ncap + i] : 0u;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -531,9 +557,10 @@ void launch_pci_force(const DevParams &p, const DevPtrs &d, int cur, uint32_t tu
   hipLaunchKernelGGL(k_pci_force, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.XS, d.PQ,
                      d.M[cur], d.SE, d.NBRL, d.NNB, d.WP, d.FP, turn);
 }
-void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
+void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, int first,
+                         hipStream_t st) {
   hipLaunchKernelGGL(k_pci_errstats, dim3(kPciStatBlocks), dim3(256), 0, st, p, d.PV, d.M[cur],
-                     d.PPART, d.PCI);
+                     d.PPART, d.PCI, first);
 }
 void launch_pci_pressure_copy(const DevParams &p, const DevPtrs &d, int to_backup,
                               hipStream_t st) {
@@ -547,6 +574,11 @@ void launch_pci_integrate(const DevParams &p, const DevPtrs &d, int cur, int maj
   hipLaunchKernelGGL(k_pci_integrate, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
                      d.V[cur], d.A[cur], d.M[cur], d.FVG, d.FP, d.PV, d.PQ, d.KEY, d.DEM,
                      major_len);
+}
+void launch_pci_lists_rows(const DevParams &p, const DevPtrs &d, uint32_t *out, hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_pci_lists_rows, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.NBRL,
+                     d.NNB, out);
 }
 void launch_pci_demote(const DevParams &p, const DevPtrs &d, int cur, int major_len,
                        hipStream_t st) {

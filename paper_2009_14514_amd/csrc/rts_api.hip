@@ -435,7 +435,6 @@ rts_status pci_minor_step(rts_ctx *c) {
   const DevPtrs &d = c->d;
   hipStream_t st = c->stream;
   const int cur = c->cur, col = c->pci_minor_in_major;
-  int32_t lists = 0;
   launch_pci_lists(p, d, cur, st);
   launch_pci_nonpressure(p, d, cur, st);
   launch_pci_reset(p, d, st);
@@ -451,14 +450,18 @@ rts_status pci_minor_step(rts_ctx *c) {
     launch_pci_density(p, d, cur, turn, st);
     launch_pci_mark_se(p, d, st);
     launch_pci_force(p, d, cur, turn, st);
-    launch_pci_errstats(p, d, cur, st);
-    HIP_OK(c, hipGetLastError());
-    rts_status s = pci_read(c, &h);
-    if (s) return s;
-    if (iter == 1) lists = h.ncomp;   // compute flags are those of this minor step
     if (global) ++global_iters;
     ++iter;
     ++row;
+    // the reductions decide only whether to stop (after min_iter iterations)
+    // and the extra iterations (after the three scheduled rows): before both,
+    // the loop goes on without waiting for the device
+    const bool need = iter > min_iter || iter > 3;
+    if (iter == 2 || need) launch_pci_errstats(p, d, cur, iter == 2 ? 1 : 0, st);
+    HIP_OK(c, hipGetLastError());
+    if (!need) continue;
+    rts_status s = pci_read(c, &h);
+    if (s) return s;
     errmax = (double)h.errmax;
     avg = h.avg;
     // extra iterations after the three scheduled ones (Section 5)
@@ -487,16 +490,13 @@ rts_status pci_minor_step(rts_ctx *c) {
   }
   launch_pci_integrate(p, d, cur, c->pci_major_len, st);
   if (!standard) launch_pci_demote(p, d, cur, c->pci_major_len, st);
-  launch_pci_errstats(p, d, cur, st);
+  // region counts after the step, read by rts_sync
+  launch_pci_errstats(p, d, cur, 0, st);
   HIP_OK(c, hipGetLastError());
-  rts_status s = pci_read(c, &h);
-  if (s) return s;
-  for (int k = 0; k < 4; ++k) c->pci_hist[k] = h.hist[k];
   c->pci_last[0] = iter - 1;
   c->pci_last[1] = global_iters;
   c->pci_last[2] = resets;
   c->pci_last[3] = reverts;
-  c->pci_last[5] = lists;
   c->pci_errmax = errmax;
   c->pci_avg = avg;
   c->pci_iters_total += iter - 1;
@@ -853,6 +853,11 @@ rts_status rts_sync(rts_ctx *c, rts_stats *out) {
     out->status = (int32_t)S.status;
     out->bad_index = bad;
     if (c->cfg.solver == RTS_PCISPH) {
+      DevPci h;
+      HIP_OK(c, hipMemcpyAsync(&h, c->d.PCI, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+      HIP_OK(c, hipStreamSynchronize(c->stream));
+      for (int k = 0; k < 4; ++k) c->pci_hist[k] = h.hist[k];
+      c->pci_last[5] = h.ncomp_first;
       out->step = c->pci_steps;
       out->time = c->pci_time;
       out->dt_last = c->dt_base;
@@ -1004,7 +1009,8 @@ rts_status rts_debug_get(rts_ctx *c, int32_t what, void *d_out, size_t cap, size
       if (n_out) *n_out = count;
       if (count * 4 > cap) return fail(c, RTS_E_CAPACITY, "debug view needs %zu bytes", count * 4);
       if (count) {
-        HIP_OK(c, hipMemcpyAsync(d_out, c->d.NBRL, n * w * 4, hipMemcpyDeviceToDevice, c->stream));
+        launch_pci_lists_rows(c->prm, c->d, (uint32_t *)d_out, c->stream);
+        HIP_OK(c, hipGetLastError());
         HIP_OK(c, hipMemcpyAsync((uint32_t *)d_out + n * w, c->d.NNB, n * 4,
                                  hipMemcpyDeviceToDevice, c->stream));
       }

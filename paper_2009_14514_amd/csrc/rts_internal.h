@@ -70,7 +70,7 @@ struct DevPci {
   double avg;            // mean over particles of max(err, 0)
   int32_t hist[4];       // particles per region
   int32_t ncomp;         // particles with the compute flag
-  int32_t pad;
+  int32_t ncomp_first;   // the same at the first iteration of the minor step (lists built)
 };
 struct PciPart {
   float errmax;
@@ -78,7 +78,7 @@ struct PciPart {
   double sum;
   int32_t hist[4];
 };
-constexpr int kPciStatBlocks = 64;
+constexpr int kPciStatBlocks = 512;
 
 // Control words.  Zeroed once when the context is created and never reset
 // or restored afterwards: the scan epoch only grows, so look-back words left
@@ -173,7 +173,7 @@ struct DevPtrs {
   float4 *FP;        // pressure acceleration
   float *PQ;         // p / rho*^2
   uint8_t *SE;       // member of S_e
-  uint32_t *NBRL;    // n x nbr_cap neighbour lists
+  uint32_t *NBRL;    // nbr_cap x ncap neighbour lists, column-major (entry k of i at k*ncap+i)
   uint8_t *OB;       // per block: observed
   uint8_t *NEARSE;   // per block: holds or borders an S_e particle
   uint8_t *DIL1, *DIL2;  // per block: dilation masks
@@ -221,13 +221,15 @@ void launch_pci_density(const DevParams &p, const DevPtrs &d, int cur, uint32_t 
 void launch_pci_mark_se(const DevParams &p, const DevPtrs &d, hipStream_t st);
 void launch_pci_force(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
                       hipStream_t st);
-void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, int first,
+                         hipStream_t st);
 void launch_pci_pressure_copy(const DevParams &p, const DevPtrs &d, int to_backup,
                               hipStream_t st);
 void launch_pci_integrate(const DevParams &p, const DevPtrs &d, int cur, int major_len,
                           hipStream_t st);
 void launch_pci_demote(const DevParams &p, const DevPtrs &d, int cur, int major_len,
                        hipStream_t st);
+void launch_pci_lists_rows(const DevParams &p, const DevPtrs &d, uint32_t *out, hipStream_t st);
 
 // Differentiable substep launchers (diff_kernels.hip)
 void launch_diff_planes_in(int n, const float *src, float4 *dst, hipStream_t st);
