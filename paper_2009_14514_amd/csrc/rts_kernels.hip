@@ -12,13 +12,14 @@
 //                   Eq. 2-3 (Section 3.1)
 //   rmin_flags      one wave per occupied block: R_min smoothing (Section 4.2),
 //                   particle validity / compute / pre-emption (Algorithm 1)
-//   search_density  one workgroup per occupied block: the 27 surrounding
-//                   blocks are staged in LDS once; 4 lanes per active particle
-//                   test interleaved quarters of them, write the neighbour
-//                   sub-lists and sum density; Tait pressure
-//   force           one workgroup per occupied block: candidates' position,
+//   search_density  one workgroup per active block: the 27 surrounding
+//                   blocks are staged in LDS once; kSub lanes per active
+//                   particle test interleaved eighths of them, write the
+//                   neighbour bitmask and sum density; Tait pressure
+//   force           one workgroup per active block: candidates' position,
 //                   velocity, density and pressure staged in LDS; pressure +
-//                   viscosity + gravity from the lists
+//                   viscosity + gravity over the bitmask, the hits shared
+//                   evenly by a particle's kSub lanes
 //   step_stats      per-step counters and the step length
 //   correct_predict all particles: corrector for the active ones, then the
 //                   predictor of the next base step
@@ -111,17 +112,18 @@ __device__ inline void block_ranges_shared(const DevParams &p, const uint32_t *s
 // Copies the block's candidates into shared memory in canonical order, one
 // range at a time so that consecutive threads read consecutive particles;
 // slots from C up to cpad are filled with far-away positions.
+template <int kThreads>
 __device__ inline void stage_positions(const uint32_t *s_rs, const uint32_t *s_ro,
                                        const float4 *__restrict__ P,
                                        const float4 *__restrict__ WP, float4 *s_pos,
                                        uint32_t cpad) {
-  constexpr int kPer = (kStageCap + kBlockThreads - 1) / kBlockThreads;
+  constexpr int kPer = (kStageCap + kThreads - 1) / kThreads;
   const uint32_t C = s_ro[18];
   float4 v[kPer];
   // every load is issued before the first shared-memory write
 #pragma unroll
   for (int it = 0; it < kPer; ++it) {
-    const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kBlockThreads;
+    const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kThreads;
     v[it] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);  // padding: never a neighbour
     if (k < C) {
       bool wall;
@@ -131,7 +133,7 @@ __device__ inline void stage_positions(const uint32_t *s_rs, const uint32_t *s_r
   }
 #pragma unroll
   for (int it = 0; it < kPer; ++it) {
-    const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kBlockThreads;
+    const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kThreads;
     if (k < cpad) s_pos[k] = v[it];
   }
 }
@@ -538,6 +540,96 @@ __device__ inline void kahan_merge(float &s, float &c, float s2, float c2) {
   c = (c + c2) - e;
 }
 
+// ---------------------------------------------------------------------------
+// balanced walk over a particle's neighbour bits
+// ---------------------------------------------------------------------------
+// The kSub lanes of a particle own interleaved candidates, so their hit counts
+// differ by several times the square root of the mean, and a walk in which
+// each lane visits its own hits runs as long as the fullest lane of the wave.
+// Here the lanes instead emit their hits in rounds of at most kRound each into
+// a per-particle LDS window, packed in lane order by a prefix over the kSub
+// counts, and then visit that window's entries e = sub, sub + kSub, ...  The
+// visit order depends on the bits alone, so results stay deterministic.
+constexpr uint32_t kRound = 12;             // keeps the force kernel at two workgroups per CU
+constexpr uint32_t kWin = kRound * kSub;   // window entries per particle
+constexpr int kMaxQueueWords = 8;          // words per lane held in registers
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Word queue of one lane: q[0] is the word being walked (index w); popping an
+// exhausted word shifts the rest down, so every access uses a fixed register.
+struct WordQueue {
+  uint32_t q[kMaxQueueWords];
+  uint32_t w;
+  __device__ inline uint32_t count() const {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxQueueWords; ++k) c += (uint32_t)__popc(q[k]);
+    return c;
+  }
+  // next set bit as a bit index m (candidate k = sub + kSub * m); a hit must
+  // remain
+  __device__ inline uint32_t pop() {
+    for (int guard = 0; q[0] == 0u && guard < kMaxQueueWords; ++guard) {
+#pragma unroll
+      for (int k = 0; k + 1 < kMaxQueueWords; ++k) q[k] = q[k + 1];
+      q[kMaxQueueWords - 1] = 0u;
+      ++w;
+    }
+    if (q[0] == 0u) return 0u;  // unreachable while the count is exact
+    const uint32_t t = (uint32_t)(__ffs(q[0]) - 1);
+    q[0] &= q[0] - 1u;
+    return 32u * w + t;
+  }
+};
+
+// Walks the hits of the lane group: `win` is the particle's kWin-entry LDS
+// window, `cnt` this lane's hit count (0 for a lane without a particle).
+// `fetch(k)` loads what candidate k contributes (any k < kStageCap is a valid
+// slot), `use(f)` accumulates it; the next entry is fetched before the
+// current one is used.  Every lane of the wave must call it (the rounds are
+// wave-uniform).
+template <typename Fetch, typename Use>
+__device__ inline void walk_balanced(WordQueue &Q, uint32_t cnt, uint16_t *win, int sub,
+                                     Fetch &&fetch, Use &&use) {
+  // the group's counts, gathered once: each round's packing offsets and
+  // size then follow without further cross-lane traffic
+  uint32_t c[kSub];
+#pragma unroll
+  for (int j = 0; j < kSub; ++j) c[j] = (uint32_t)__shfl((int)cnt, j, kSub);
+  for (uint32_t base = 0; __any(cnt > base); base += kRound) {
+    uint32_t off = 0, total = 0;
+#pragma unroll
+    for (int j = 0; j < kSub; ++j) {
+      const uint32_t t = c[j] > base ? min(c[j] - base, kRound) : 0u;
+      off += j < sub ? t : 0u;
+      total += t;
+    }
+    const uint32_t take = cnt > base ? min(cnt - base, kRound) : 0u;
+    for (uint32_t j = 0; j < take; ++j)
+      win[off + j] = (uint16_t)((uint32_t)sub + (uint32_t)kSub * Q.pop());
+    wave_lds_sync();
+    uint32_t e = (uint32_t)sub;
+    if (e < total) {
+      auto cur = fetch((uint32_t)win[e]);
+      for (;;) {
+        const uint32_t e2 = e + kSub;
+        const bool more = e2 < total;
+        const auto nxt = fetch(more ? (uint32_t)win[e2] : 0u);
+        use(cur);
+        if (!more) break;
+        cur = nxt;
+        e = e2;
+      }
+    }
+    wave_lds_sync();  // the window is refilled by the next round
+  }
+}
+
 __global__ void __launch_bounds__(kBlockThreads) k_search_density(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, float4 *__restrict__ P, float4 *__restrict__ V,
@@ -578,7 +670,7 @@ __global__ void __launch_bounds__(kBlockThreads) k_search_density(
     const uint32_t C = s_ro[18];
     const uint32_t cpad = (C + 32u * kSub - 1u) / (32u * kSub) * (32u * kSub);
     const bool staged = cpad <= (uint32_t)kStageCap;
-    if (staged) stage_positions(s_rs, s_ro, P, WP, s_pos, cpad);
+    if (staged) stage_positions<kBlockThreads>(s_rs, s_ro, P, WP, s_pos, cpad);
     __syncthreads();
     const uint32_t self_off = s_ro[4] - s_rs[4];  // local index = sorted index + self_off
     const uint32_t nslot = (C + kSub - 1) / kSub;     // candidate slots per lane
@@ -710,7 +802,12 @@ __global__ void __launch_bounds__(kBlockThreads) k_search_density(
 // ---------------------------------------------------------------------------
 // forces, one workgroup per block
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kForceThreads) k_force(
+struct StagedPair {
+  float4 q, u;
+  bool wall;
+};
+
+__global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(4))) k_force(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, const float4 *__restrict__ P,
     const float4 *__restrict__ V, const uint32_t *__restrict__ M,
@@ -719,6 +816,8 @@ __global__ void __launch_bounds__(kForceThreads) k_force(
     const uint32_t *__restrict__ actn, DevCtrl *ctrl) {
   __shared__ float4 s_p[kForceCap];
   __shared__ float4 s_v[kForceCap];
+  __shared__ uint16_t s_win[kForceThreads / 64][64 / kSub][kWin];
+  static_assert(kForceCap <= kMaxQueueWords * 32 * kSub, "staged words fit the queue");
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
   __shared__ uint16_t s_act[kCellMax];
   __shared__ uint32_t s_nact;
@@ -766,10 +865,10 @@ __global__ void __launch_bounds__(kForceThreads) k_force(
       const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       const float4 u0 = j0 != kNoFluid ? V[j0] : z, u1 = j1 != kNoFluid ? V[j1] : z;
       const float4 u2 = j2 != kNoFluid ? V[j2] : z, u3 = j3 != kNoFluid ? V[j3] : z;
-      if (j0 != kNoFluid) s_v[k0] = u0;
-      if (j1 != kNoFluid) s_v[k1] = u1;
-      if (j2 != kNoFluid) s_v[k2] = u2;
-      if (j3 != kNoFluid) s_v[k3] = u3;
+      if (k0 < C) s_v[k0] = u0;  // walls: zero velocity
+      if (k1 < C) s_v[k1] = u1;
+      if (k2 < C) s_v[k2] = u2;
+      if (k3 < C) s_v[k3] = u3;
     }
     __syncthreads();
     float a2max = 0.0f;
@@ -782,36 +881,10 @@ __global__ void __launch_bounds__(kForceThreads) k_force(
       const float rhoi = pi.w, pri = vi.w;
       const float inv_rhoi = __builtin_amdgcn_rcpf(rhoi);
       float ax = 0.0f, ay = 0.0f, az = 0.0f;
-      const uint32_t *mrow = mask + (size_t)i * (size_t)(kSub * p.wpl) + (size_t)sub;
-      // walk the set bits word by word, the next word always in flight
-      uint32_t w = 0;
-      const uint32_t left = live ? nwords : 0u;
-      uint32_t bits = left ? mrow[0] : 0u;
-      uint32_t nxt = left > 1u ? mrow[kSub] : 0u;
-      while (true) {
-        while (bits == 0u && w + 1u < left) {
-          bits = nxt;
-          ++w;
-          nxt = (w + 1u < left) ? mrow[kSub * (w + 1u)] : 0u;
-        }
-        if (bits == 0u) break;
-        const uint32_t t = (uint32_t)(__ffs(bits) - 1);
-        bits &= bits - 1u;
-        const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
-        float4 qj, uj;
-        const bool wall = k >= Cf;
-        if (staged) {
-          qj = s_p[k];
-          uj = wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : s_v[k];
-        } else {
-          bool w2;
-          const uint32_t j = local_to_global(s_rs, s_ro, k, w2);
-          qj = wall ? WP[j] : P[j];
-          uj = wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[j];
-        }
-        // a static wall particle is at rest and mirrors the density and the
-        // pressure of the fluid particle, plus the hydrostatic difference,
-        // clamped at zero
+      // a static wall particle is at rest and mirrors the density and the
+      // pressure of the fluid particle, plus the hydrostatic difference,
+      // clamped at zero
+      auto pair = [&](const float4 qj, const float4 uj, bool wall) {
         const float gd = p.g[0] * (qj.x - pi.x) + p.g[1] * (qj.y - pi.y) + p.g[2] * (qj.z - pi.z);
         const float rhoj = wall ? rhoi : qj.w;
         const float prj = wall ? fmaxf(pri + gd * inv_rhoi, 0.0f) : uj.w;
@@ -829,6 +902,40 @@ __global__ void __launch_bounds__(kForceThreads) k_force(
         ax += sc * dx;
         ay += sc * dy;
         az += sc * dz;
+      };
+      const uint32_t *mrow = mask + (size_t)i * (size_t)(kSub * p.wpl) + (size_t)sub;
+      const uint32_t left = live ? nwords : 0u;
+      if (staged) {
+        // at most kForceCap candidates: the lane's words fit the queue
+        WordQueue Q;
+#pragma unroll
+        for (int k = 0; k < kMaxQueueWords; ++k)
+          Q.q[k] = (uint32_t)k < left ? mrow[kSub * k] : 0u;
+        Q.w = 0u;
+        // staged wall slots of s_v hold zero velocity
+        walk_balanced(Q, Q.count(), s_win[wave][lane / kSub], sub,
+                      [&](uint32_t k) { return StagedPair{s_p[k], s_v[k], k >= Cf}; },
+                      [&](const StagedPair &c) { pair(c.q, c.u, c.wall); });
+      } else {
+        // walk the set bits word by word, the next word always in flight
+        uint32_t w = 0;
+        uint32_t bits = left ? mrow[0] : 0u;
+        uint32_t nxt = left > 1u ? mrow[kSub] : 0u;
+        while (true) {
+          while (bits == 0u && w + 1u < left) {
+            bits = nxt;
+            ++w;
+            nxt = (w + 1u < left) ? mrow[kSub * (w + 1u)] : 0u;
+          }
+          if (bits == 0u) break;
+          const uint32_t t = (uint32_t)(__ffs(bits) - 1);
+          bits &= bits - 1u;
+          const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
+          const bool wall = k >= Cf;
+          bool w2;
+          const uint32_t j = local_to_global(s_rs, s_ro, k, w2);
+          pair(wall ? WP[j] : P[j], wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[j], wall);
+        }
       }
       for (int o = 1; o < kSub; o <<= 1) {
         ax += __shfl_xor(ax, o, 64);
