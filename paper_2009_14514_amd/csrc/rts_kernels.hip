@@ -615,14 +615,19 @@ __device__ inline void walk_balanced(WordQueue &Q, uint32_t cnt, uint16_t *win, 
     wave_lds_sync();
     uint32_t e = (uint32_t)sub;
     if (e < total) {
-      auto cur = fetch((uint32_t)win[e]);
+      // two entries in flight, used alternately (no register copies)
+      auto c0 = fetch((uint32_t)win[e]);
       for (;;) {
-        const uint32_t e2 = e + kSub;
-        const bool more = e2 < total;
-        const auto nxt = fetch(more ? (uint32_t)win[e2] : 0u);
-        use(cur);
-        if (!more) break;
-        cur = nxt;
+        const uint32_t e1 = e + kSub;
+        const bool m1 = e1 < total;
+        const auto c1 = fetch(m1 ? (uint32_t)win[e1] : 0u);
+        use(c0);
+        if (!m1) break;
+        const uint32_t e2 = e1 + kSub;
+        const bool m2 = e2 < total;
+        c0 = fetch(m2 ? (uint32_t)win[e2] : 0u);
+        use(c1);
+        if (!m2) break;
         e = e2;
       }
     }
@@ -807,6 +812,11 @@ struct StagedPair {
   bool wall;
 };
 
+// Velocity slot of a wall candidate: at rest, and g . x in place of p / rho^2.
+__device__ inline float4 wall_slot(const DevParams &p, const float4 q) {
+  return make_float4(0.0f, 0.0f, 0.0f, p.g[0] * q.x + p.g[1] * q.y + p.g[2] * q.z);
+}
+
 __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(4))) k_force(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, const float4 *__restrict__ P,
@@ -862,10 +872,11 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
       if (k1 < C) s_p[k1] = b1;
       if (k2 < C) s_p[k2] = b2;
       if (k3 < C) s_p[k3] = b3;
-      const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      const float4 u0 = j0 != kNoFluid ? V[j0] : z, u1 = j1 != kNoFluid ? V[j1] : z;
-      const float4 u2 = j2 != kNoFluid ? V[j2] : z, u3 = j3 != kNoFluid ? V[j3] : z;
-      if (k0 < C) s_v[k0] = u0;  // walls: zero velocity
+      const float4 u0 = j0 != kNoFluid ? V[j0] : wall_slot(p, b0);
+      const float4 u1 = j1 != kNoFluid ? V[j1] : wall_slot(p, b1);
+      const float4 u2 = j2 != kNoFluid ? V[j2] : wall_slot(p, b2);
+      const float4 u3 = j3 != kNoFluid ? V[j3] : wall_slot(p, b3);
+      if (k0 < C) s_v[k0] = u0;
       if (k1 < C) s_v[k1] = u1;
       if (k2 < C) s_v[k2] = u2;
       if (k3 < C) s_v[k3] = u3;
@@ -882,12 +893,12 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
       const float inv_rhoi = __builtin_amdgcn_rcpf(rhoi);
       float ax = 0.0f, ay = 0.0f, az = 0.0f;
       // a static wall particle is at rest and mirrors the density and the
-      // pressure of the fluid particle, plus the hydrostatic difference,
-      // clamped at zero
+      // pressure of the fluid particle, plus the hydrostatic difference
+      // g . (x_j - x_i), clamped at zero; uj.w of a wall holds g . x_j
+      const float gxi = p.g[0] * pi.x + p.g[1] * pi.y + p.g[2] * pi.z;
       auto pair = [&](const float4 qj, const float4 uj, bool wall) {
-        const float gd = p.g[0] * (qj.x - pi.x) + p.g[1] * (qj.y - pi.y) + p.g[2] * (qj.z - pi.z);
         const float rhoj = wall ? rhoi : qj.w;
-        const float prj = wall ? fmaxf(pri + gd * inv_rhoi, 0.0f) : uj.w;
+        const float prj = wall ? fmaxf(pri + (uj.w - gxi) * inv_rhoi, 0.0f) : uj.w;
         const float dx = pi.x - qj.x, dy = pi.y - qj.y, dz = pi.z - qj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float rinv = __builtin_amdgcn_rsqf(r2);
@@ -912,7 +923,7 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
         for (int k = 0; k < kMaxQueueWords; ++k)
           Q.q[k] = (uint32_t)k < left ? mrow[kSub * k] : 0u;
         Q.w = 0u;
-        // staged wall slots of s_v hold zero velocity
+        // staged wall slots of s_v: zero velocity and g . x_j
         walk_balanced(Q, Q.count(), s_win[wave][lane / kSub], sub,
                       [&](uint32_t k) { return StagedPair{s_p[k], s_v[k], k >= Cf}; },
                       [&](const StagedPair &c) { pair(c.q, c.u, c.wall); });
@@ -934,7 +945,8 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
           const bool wall = k >= Cf;
           bool w2;
           const uint32_t j = local_to_global(s_rs, s_ro, k, w2);
-          pair(wall ? WP[j] : P[j], wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[j], wall);
+          const float4 q = wall ? WP[j] : P[j];
+          pair(q, wall ? wall_slot(p, q) : V[j], wall);
         }
       }
       for (int o = 1; o < kSub; o <<= 1) {
