@@ -587,6 +587,13 @@ struct WordQueue {
   }
 };
 
+// Sets word `w` of a queue (w < kMaxQueueWords) without dynamic indexing.
+__device__ inline void queue_set(WordQueue &Q, uint32_t w, uint32_t bits) {
+#pragma unroll
+  for (int k = 0; k < kMaxQueueWords; ++k)
+    if ((uint32_t)k == w) Q.q[k] = bits;
+}
+
 // Walks the hits of the lane group: `win` is the particle's kWin-entry LDS
 // window, `cnt` this lane's hit count (0 for a lane without a particle).
 // `fetch(k)` loads what candidate k contributes (any k < kStageCap is a valid
@@ -643,6 +650,7 @@ __global__ void __launch_bounds__(kBlockThreads) k_search_density(
     float *__restrict__ blkerr, const uint32_t *__restrict__ ids,
     const uint32_t *__restrict__ actn, DevCtrl *ctrl, DevScalars *S) {
   __shared__ float4 s_pos[kStageCap];
+  static_assert(kStageCap <= kMaxQueueWords * 32 * kSub, "staged words fit the queue");
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
   __shared__ uint16_t s_act[kCellMax];
   __shared__ uint32_t s_nact;
@@ -695,6 +703,10 @@ __global__ void __launch_bounds__(kBlockThreads) k_search_density(
       // this lane's words: word w of lane `sub` at mrow[kSub * w]
       uint32_t *mrow = mask + (size_t)i * (size_t)(kSub * p.wpl) + (size_t)sub;
       uint32_t cnt = 0;
+      WordQueue Q;  // the lane's words of a staged block (at most 8)
+#pragma unroll
+      for (int q2 = 0; q2 < kMaxQueueWords; ++q2) Q.q[q2] = 0u;
+      Q.w = 0u;
       // pass 1: the neighbour predicate over this lane's candidates
       // k = sub + kSub * m, one bit per candidate, 32 candidates per word
       for (uint32_t w = 0; w < nwords; ++w) {
@@ -720,14 +732,39 @@ __global__ void __launch_bounds__(kBlockThreads) k_search_density(
         }
         if ((selfk & (kSub - 1)) == (uint32_t)sub && (selfk / kSub) / 32u == w)
           bits &= ~(1u << ((selfk / kSub) & 31u));  // a particle is not its own neighbour
+        if (!live) bits = 0u;
         if (live) mrow[kSub * w] = bits;
+        if (staged) queue_set(Q, w, bits);
         cnt += (uint32_t)__popc(bits);
       }
-      if (!live) cnt = 0;
-      // pass 2: density over this lane's hits, walking the set bits in order
-      // (Kahan-compensated sum of the kernel shape)
+      // pass 2: density over this lane's hits in bit order (Kahan-compensated
+      // sum of the kernel shape)
       float sum = 0.0f, comp = 0.0f;
-      {
+      auto add = [&](const float4 qj) {
+        const float d2 = dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z);
+        const float wk = w_shape(__builtin_amdgcn_sqrtf(d2) * p.inv_h);
+        const float y2 = wk - comp;
+        const float tt = sum + y2;
+        comp = (tt - sum) - y2;
+        sum = tt;
+      };
+      if (staged) {
+        // the words are in registers; two hits in flight, used in turn
+        uint32_t left = cnt;
+        if (left) {
+          float4 c0 = s_pos[(uint32_t)sub + kSub * Q.pop()];
+          for (;;) {
+            const bool m1 = --left > 0u;
+            const float4 c1 = s_pos[m1 ? (uint32_t)sub + kSub * Q.pop() : 0u];
+            add(c0);
+            if (!m1) break;
+            const bool m2 = --left > 0u;
+            c0 = s_pos[m2 ? (uint32_t)sub + kSub * Q.pop() : 0u];
+            add(c1);
+            if (!m2) break;
+          }
+        }
+      } else {
         // walk the set bits word by word, the next word always in flight
         uint32_t w = 0;
         uint32_t bits = (live && nwords) ? mrow[0] : 0u;
@@ -741,20 +778,9 @@ __global__ void __launch_bounds__(kBlockThreads) k_search_density(
           const uint32_t t = (uint32_t)(__ffs(bits) - 1);
           bits &= bits - 1u;
           const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
-          float4 qj;
-          if (staged) {
-            qj = s_pos[k];
-          } else {
-            bool wall;
-            const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
-            qj = wall ? WP[j] : P[j];
-          }
-          const float d2 = dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z);
-          const float wk = w_shape(__builtin_amdgcn_sqrtf(d2) * p.inv_h);
-          const float y2 = wk - comp;
-          const float tt = sum + y2;
-          comp = (tt - sum) - y2;
-          sum = tt;
+          bool wall;
+          const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
+          add(wall ? WP[j] : P[j]);
         }
       }
       // the kSub lanes of a particle are adjacent: merge sums and counts
