@@ -860,7 +860,10 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
   __shared__ float s_amax[kForceThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sub = tid & (kSub - 1);
-  const float coefg = p.sigma * p.inv_h;  // dW/dr = sigma / h * w'(q)
+  // -m grad W(x_ij) = f x_ij with f = -m (sigma / h) w'(q) / r, q = r / h:
+  // f = fA + fB q for q < 1, f = fC (2 - q)^2 / r for 1 <= q < 2
+  const float mcoefg = -p.mass * p.sigma * p.inv_h;
+  const float fA = -3.0f * mcoefg * p.inv_h, fB = 2.25f * mcoefg * p.inv_h, fC = -0.75f * mcoefg;
   __shared__ uint32_t s_pre[kActBuckets + 1], s_ticket;
   active_prefix(actn, s_pre);
   const uint32_t nblk = s_pre[kActBuckets];
@@ -928,14 +931,15 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
         const float dx = pi.x - qj.x, dy = pi.y - qj.y, dz = pi.z - qj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float r = r2 * rinv;
-        const float f = coefg * dw_shape(r * p.inv_h) * rinv;  // gradW = f * x_ij
+        const float q = r2 * rinv * p.inv_h;
+        const float t = fmaxf(2.0f - q, 0.0f);
+        const float f = q < 1.0f ? fmaf(fB, q, fA) : fC * t * t * rinv;  // -m gradW = f x_ij
         const float vx = (vi.x - uj.x) * dx + (vi.y - uj.y) * dy + (vi.z - uj.z) * dz;
         // artificial viscosity -nu vx / (r^2 + eps h^2), nu = 2 alpha h c0 / (rho_i + rho_j)
         const float visc = -p.visc_num * vx *
                            __builtin_amdgcn_rcpf((rhoi + rhoj) * (r2 + p.visc_eps_h2));
         const float coef = pri + prj + (vx < 0.0f ? visc : 0.0f);
-        const float sc = r2 > 0.0f ? -p.mass * coef * f : 0.0f;
+        const float sc = r2 > 0.0f ? coef * f : 0.0f;
         ax += sc * dx;
         ay += sc * dy;
         az += sc * dz;
