@@ -639,9 +639,10 @@ rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall
   }
   const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   // persistent grids: enough workgroups to fill every CU, each striding over
-  // the occupied blocks (search: 3 per CU fit in LDS; force: 1 per CU)
+  // the occupied blocks or taking active blocks by ticket (search and force:
+  // two 512-thread workgroups per CU are resident, limited by registers)
   c->grid_wave = cus * 8;
-  c->grid_search = cus * 4;
+  c->grid_search = cus * 2;
   c->grid_force = cus * 2;
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
