@@ -642,7 +642,7 @@ rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall
   // the occupied blocks or taking active blocks by ticket (search and force:
   // two 512-thread workgroups per CU are resident, limited by registers)
   c->grid_wave = cus * 8;
-  c->grid_search = cus * 2;
+  c->grid_search = cus * 3;
   c->grid_force = cus * 2;
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;

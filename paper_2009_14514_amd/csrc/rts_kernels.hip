@@ -642,7 +642,7 @@ __device__ inline void walk_balanced(WordQueue &Q, uint32_t cnt, uint16_t *win, 
   }
 }
 
-__global__ void __launch_bounds__(kBlockThreads) k_search_density(
+__global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6))) k_search_density(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, float4 *__restrict__ P, float4 *__restrict__ V,
     const uint32_t *__restrict__ M, float *__restrict__ pres, uint32_t *__restrict__ nnb,
