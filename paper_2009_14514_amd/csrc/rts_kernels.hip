@@ -204,41 +204,58 @@ __device__ inline unsigned long long pack_status(uint32_t epoch, unsigned long l
   return ((unsigned long long)(epoch & 0x3FFFFFFFu) << 34) | (flag << 32) | v;
 }
 
-// Thread 0 of a tile: publish the aggregate, look back, publish the prefix.
-// A status word carries everything a successor needs (epoch, flag, value),
-// so the words are relaxed device-scope atomics: no cache write-back is
-// needed to publish them.
+// One wave of a tile: publish the aggregate, look back, publish the prefix.
+// The wave reads the status words of up to 64 predecessors at once (lane l
+// the l-th nearest), takes the run of published words up to the nearest
+// prefix, and moves on past the run when no prefix is in it.  A status word
+// carries everything a successor needs (epoch, flag, value), so the words are
+// relaxed device-scope atomics: no cache write-back is needed to publish
+// them.  Returns the exclusive prefix in every lane.
 __device__ uint32_t look_back(unsigned long long *tiles, uint32_t tile, uint32_t epoch,
                               uint32_t total, DevScalars *S) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t ep30 = epoch & 0x3FFFFFFFu;
   if (tile == 0) {
-    __hip_atomic_store(&tiles[0], pack_status(epoch, kFlagPre, total), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+      __hip_atomic_store(&tiles[0], pack_status(epoch, kFlagPre, total), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     return 0;
   }
-  __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagAgg, total), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0)
+    __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagAgg, total), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   uint32_t excl = 0;
-  int j = (int)tile - 1;
+  int hi = (int)tile - 1;  // nearest predecessor not yet added
   uint32_t spins = 0;
-  while (j >= 0) {
-    const unsigned long long w =
-        __hip_atomic_load(&tiles[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (true) {
+    const int j = hi - lane;
+    // below tile 0 reads as a prefix of zero, so every window ends in one
+    unsigned long long w = pack_status(epoch, kFlagPre, 0u);
+    if (j >= 0) w = __hip_atomic_load(&tiles[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long flag = (w >> 32) & 3ull;
-    const uint32_t ep = (uint32_t)(w >> 34);
-    if (ep != (epoch & 0x3FFFFFFFu) || flag == 0ull) {
-      if (++spins > (1u << 24)) {  // predecessors always finish; this bound is a guard
-        set_status(S, RTS_E_DEVICE, -1);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
+    const bool valid = (uint32_t)(w >> 34) == ep30 && flag != 0ull;
+    const unsigned long long inval = __ballot(!valid);
+    const unsigned long long pre = __ballot(valid && flag == kFlagPre);
+    const int first_inval = inval ? __ffsll((long long)inval) - 1 : 64;
+    const int first_pre = pre ? __ffsll((long long)pre) - 1 : 64;
+    const int take = first_pre < first_inval ? first_pre + 1 : first_inval;
+    if (take > 0) {
+      uint32_t v = lane < take ? (uint32_t)(w & 0xFFFFFFFFull) : 0u;
+      for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+      excl += v;
+      if (first_pre < first_inval) break;
+      hi -= take;
       continue;
     }
-    excl += (uint32_t)(w & 0xFFFFFFFFull);
-    if (flag == kFlagPre) break;
-    --j;
+    if (++spins > (1u << 24)) {  // predecessors always finish; this bound is a guard
+      if (lane == 0) set_status(S, RTS_E_DEVICE, -1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
   }
-  __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagPre, excl + total), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0)
+    __hip_atomic_store(&tiles[tile], pack_status(epoch, kFlagPre, excl + total),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return excl;
 }
 
@@ -292,9 +309,14 @@ __global__ void __launch_bounds__(256) k_scan(uint32_t *__restrict__ count,
   uint32_t total = 0, total2 = 0;
   const uint32_t incl = block_scan_256(t, s_wave, total);
   const uint32_t incl2 = occ ? block_scan_256(t2, s_wave2, total2) : 0u;
-  if (tid == 0) {
-    s_prefix = look_back(tiles, tile, epoch, total, S);
-    if (occ) s_prefix2 = look_back(tiles2, tile, epoch, total2, S);
+  // the two look-backs run in parallel, one wave each
+  const int wave = tid >> 6;
+  if (wave == 0) {
+    const uint32_t pfx = look_back(tiles, tile, epoch, total, S);
+    if (tid == 0) s_prefix = pfx;
+  } else if (wave == 1 && occ) {
+    const uint32_t pfx = look_back(tiles2, tile, epoch, total2, S);
+    if (tid == 64) s_prefix2 = pfx;
   }
   __syncthreads();
   uint32_t off = s_prefix + incl - t;
