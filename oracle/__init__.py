@@ -110,8 +110,7 @@ def _declare(L):
     L.orc_eos.argtypes = [cfgp, C.c_double]
     L.orc_eos.restype = C.c_double
     L.orc_keys.argtypes = [cfgp, C.c_int32, C.c_void_p, C.c_void_p]
-    L.orc_sort.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
-                           C.c_void_p]
+    L.orc_sort.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_block_levels.argtypes = [cfgp, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_rmin.argtypes = [cfgp, C.c_void_p, C.c_void_p]
     L.orc_flags.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -213,16 +212,11 @@ def keys(cfg, pos_f32):
     return out
 
 
-def sort(nblocks, key, x):
-    """Canonical block order: by key, then x (float32), then input position."""
+def sort(nblocks, key):
     key = np.ascontiguousarray(key, np.uint32)
-    x = np.ascontiguousarray(x, np.float32).reshape(-1)
-    if x.shape[0] != key.shape[0]:
-        raise ValueError("one x coordinate per key")
     perm = np.zeros(key.shape[0], np.uint32)
     start = np.zeros(int(nblocks) + 1, np.uint32)
-    st = lib().orc_sort(int(nblocks), key.shape[0], _ptr(key), _ptr(x), 1, _ptr(perm),
-                        _ptr(start))
+    st = lib().orc_sort(int(nblocks), key.shape[0], _ptr(key), _ptr(perm), _ptr(start))
     if st:
         raise ValueError("key out of range")
     return perm, start
@@ -470,7 +464,7 @@ def sorted_walls(cfg, walls):
     w32 = np.ascontiguousarray(walls, np.float32).reshape(-1, 3)
     info = derive(cfg)
     k = keys(cfg, w32)
-    perm, start = sort(info.nblocks, k, w32[:, 0])
+    perm, start = sort(info.nblocks, k)
     return np.asarray(walls, np.float64).reshape(-1, 3)[perm], start, perm
 
 

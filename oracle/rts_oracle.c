@@ -170,24 +170,8 @@ void orc_keys(const orc_cfg *c, int32_t n, const float *pos, uint32_t *key) {
   }
 }
 
-/* Order-preserving image of a float's bits as an unsigned integer: a total
- * order that agrees with < on ordered values (and puts -0 before +0). */
-static uint32_t x_order(float f) {
-  uint32_t u;
-  memcpy(&u, &f, sizeof u);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-static int cmp_u64(const void *a, const void *b) {
-  const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
-  return x < y ? -1 : (x > y ? 1 : 0);
-}
-
-/* Canonical order: perm[new] = old, by block key, then by the x coordinate
- * (float, through x_order), then by input position.  Within a row of blocks
- * along x the particles are then sorted by x.  x[i * xstride] is particle
- * i's x. */
-int orc_sort(int64_t nb, int32_t n, const uint32_t *key, const float *x, int64_t xstride,
-             uint32_t *perm, uint32_t *cell_start) {
+/* Stable counting sort: perm[new] = old, ties kept in input order. */
+int orc_sort(int64_t nb, int32_t n, const uint32_t *key, uint32_t *perm, uint32_t *cell_start) {
   memset(cell_start, 0, sizeof(uint32_t) * (size_t)(nb + 1));
   for (int32_t i = 0; i < n; ++i) {
     if ((int64_t)key[i] >= nb) return ORC_E_INVALID;
@@ -198,18 +182,6 @@ int orc_sort(int64_t nb, int32_t n, const uint32_t *key, const float *x, int64_t
   memcpy(fill, cell_start, sizeof(uint32_t) * (size_t)nb);
   for (int32_t i = 0; i < n; ++i) perm[fill[key[i]]++] = (uint32_t)i;
   free(fill);
-  uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-  for (int64_t b = 0; b < nb; ++b) {
-    const uint32_t s0 = cell_start[b], s1 = cell_start[b + 1];
-    if (s1 - s0 < 2) continue;
-    for (uint32_t k = s0; k < s1; ++k) {
-      const uint32_t i = perm[k];
-      tmp[k - s0] = ((uint64_t)x_order(x[(int64_t)i * xstride]) << 32) | i;
-    }
-    qsort(tmp, s1 - s0, sizeof(uint64_t), cmp_u64);
-    for (uint32_t k = s0; k < s1; ++k) perm[k] = (uint32_t)(tmp[k - s0] & 0xFFFFFFFFu);
-  }
-  free(tmp);
   return ORC_OK;
 }
 
@@ -315,7 +287,7 @@ static int grid_build(const orc_info *I, int32_t n, const float *pos, grid_t *g)
     block_coords(I, pos + 3 * (int64_t)i, b);
     g->key[i] = key_of(I, b);
   }
-  return orc_sort(g->nb, n, g->key, pos, 3, g->perm, g->start);
+  return orc_sort(g->nb, n, g->key, g->perm, g->start);
 }
 static void grid_free(grid_t *g) { free(g->key); free(g->perm); free(g->start); }
 
@@ -953,7 +925,7 @@ static int pci_major_begin(const orc_cfg *c, const orc_info *I, orc_pci_state *s
     block_coords(I, pf + 3 * (int64_t)i, b);
     key[i] = key_of(I, b);
   }
-  if (orc_sort(I->nblocks, n, key, pf, 3, perm, s->cell_start)) {
+  if (orc_sort(I->nblocks, n, key, perm, s->cell_start)) {
     free(pf); free(key); free(perm);
     return ORC_E_INVALID;
   }

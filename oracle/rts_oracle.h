@@ -91,8 +91,7 @@ double orc_eos(const orc_cfg *c, double rho);
 
 /* structural steps, float decisions */
 void orc_keys(const orc_cfg *c, int32_t n, const float *pos, uint32_t *key);
-int  orc_sort(int64_t nb, int32_t n, const uint32_t *key, const float *x, int64_t xstride,
-               uint32_t *perm, uint32_t *cell_start);
+int  orc_sort(int64_t nb, int32_t n, const uint32_t *key, uint32_t *perm, uint32_t *cell_start);
 void orc_block_levels(const orc_cfg *c, int32_t n, const uint32_t *key, const float *vel,
                       const float *acc, uint8_t *lvl);
 void orc_rmin(const orc_cfg *c, const uint8_t *lvl_in, uint8_t *lvl_out);

@@ -365,19 +365,9 @@ __global__ void __launch_bounds__(256) k_scatter(int n, const uint32_t *__restri
     set_status(S, RTS_E_DEVICE, -1);  // inconsistent block starts: never write out of range
 }
 
-// Canonical order inside a block: by x, then by previous position.  x enters
-// through an order-preserving unsigned image of its float bits (a total
-// order; -0 before +0), combined with the previous index into one 64-bit key,
-// so a particle's rank is the number of smaller keys in its block.  A row of
-// blocks along x is then sorted by x, because the block index is monotone
-// in x.
-__device__ inline uint64_t order_key(float x, uint32_t idx) {
-  const uint32_t u = __float_as_uint(x);
-  const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-  return ((uint64_t)o << 32) | idx;
-}
-// Rank of val among the n distinct keys s[0..n).
-__device__ inline uint32_t rank_in(const uint64_t *s, int n, uint64_t val) {
+// Rank of val among the n distinct values s[0..n): the stable position of an
+// index inside its block.
+__device__ inline uint32_t rank_in(const uint32_t *s, int n, uint32_t val) {
   uint32_t r = 0;
   for (int m = 0; m < n; ++m) r += (s[m] < val) ? 1u : 0u;
   return r;
@@ -393,9 +383,9 @@ __global__ void __launch_bounds__(256) k_cell_gather(
     const uint32_t *__restrict__ Mi, const uint32_t *__restrict__ Ii, float4 *__restrict__ Po,
     float4 *__restrict__ Vo, float4 *__restrict__ Ao, uint32_t *__restrict__ Mo,
     uint32_t *__restrict__ Io, uint8_t *__restrict__ lraw, DevScalars *S) {
-  __shared__ uint64_t s_key_all[4][kCellMax];
+  __shared__ uint32_t s_idx_all[4][kCellMax];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint64_t *s_key = s_key_all[wave];
+  uint32_t *s_idx = s_idx_all[wave];
   const uint32_t nocc = S->n_occ;
   for (uint32_t q = blockIdx.x * 4 + wave; q < nocc; q += gridDim.x * 4) {
     const uint32_t b = occ[q];
@@ -412,19 +402,15 @@ __global__ void __launch_bounds__(256) k_cell_gather(
     const bool canon = n <= kCellMax;
     if (!canon && lane == 0) set_status(S, RTS_E_CAPACITY, -1);
     if (canon)
-      for (int k = lane; k < n; k += 64) {
-        const uint32_t src = tmp[s0 + k];
-        s_key[k] = order_key(src < (uint32_t)p.n ? Pi[src].x : 0.0f, src);
-      }
+      for (int k = lane; k < n; k += 64) s_idx[k] = tmp[s0 + k];
     // the wave's LDS writes must be visible to the whole wave
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float v2m = 0.0f, a2m = 0.0f;
     for (int k = lane; k < n; k += 64) {
-      const uint64_t kk = canon ? s_key[k] : 0ull;
-      const uint32_t src = canon ? (uint32_t)(kk & 0xFFFFFFFFull) : tmp[s0 + k];
-      const uint32_t dst = s0 + (canon ? rank_in(s_key, n, kk) : (uint32_t)k);
+      const uint32_t src = canon ? s_idx[k] : tmp[s0 + k];
+      const uint32_t dst = s0 + (canon ? rank_in(s_idx, n, src) : (uint32_t)k);
       if (src >= (uint32_t)p.n) {
         set_status(S, RTS_E_DEVICE, -1);
         continue;
@@ -449,7 +435,7 @@ __global__ void __launch_bounds__(256) k_cell_gather(
       while (l + 1 <= p.lmax && v2m <= p.TV[l + 1] && a2m <= p.TA[l + 1]) ++l;
       lraw[b] = (uint8_t)l;
     }
-    // s_key is reused for the next block: all lanes must be done reading it
+    // s_idx is reused for the next block: all lanes must be done reading it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1266,7 +1252,7 @@ __global__ void __launch_bounds__(64) k_wall_gather(DevParams p, const uint32_t 
                                                    const uint32_t *__restrict__ tmp,
                                                    const float *__restrict__ pos, float4 *WP,
                                                    uint32_t *WID, DevScalars *S) {
-  __shared__ uint64_t s_key[kCellMax];
+  __shared__ uint32_t s_idx[kCellMax];
   const int b = blockIdx.x, lane = threadIdx.x;
   const uint32_t s0 = start[b];
   const uint32_t s1 = start[b + 1];
@@ -1278,16 +1264,12 @@ __global__ void __launch_bounds__(64) k_wall_gather(DevParams p, const uint32_t 
   const bool canon = n <= kCellMax;
   if (!canon && lane == 0) set_status(S, RTS_E_CAPACITY, -1);
   if (canon)
-    for (int k = lane; k < n; k += 64) {
-      const uint32_t src = tmp[s0 + k];
-      s_key[k] = order_key(src < (uint32_t)p.nw ? pos[src] : 0.0f, src);
-    }
+    for (int k = lane; k < n; k += 64) s_idx[k] = tmp[s0 + k];
   __syncthreads();
   const size_t nw = (size_t)p.nw;
   for (int k = lane; k < n; k += 64) {
-    const uint64_t kk = canon ? s_key[k] : 0ull;
-    const uint32_t src = canon ? (uint32_t)(kk & 0xFFFFFFFFull) : tmp[s0 + k];
-    const uint32_t dst = s0 + (canon ? rank_in(s_key, n, kk) : (uint32_t)k);
+    const uint32_t src = canon ? s_idx[k] : tmp[s0 + k];
+    const uint32_t dst = s0 + (canon ? rank_in(s_idx, n, src) : (uint32_t)k);
     if (src >= (uint32_t)p.nw) {
       set_status(S, RTS_E_DEVICE, -1);
       continue;

@@ -22,7 +22,7 @@ def expected_structure(cfg, snap):
     info = oracle.derive(cfg)
     pre_pos = snap["PRE_POS"][:, :3]
     keys_old = oracle.keys(cfg, pre_pos)
-    perm, start = oracle.sort(info.nblocks, keys_old, pre_pos[:, 0])
+    perm, start = oracle.sort(info.nblocks, keys_old)
     lraw = oracle.block_levels(cfg, keys_old, snap["PRE_VEL"][:, :3], snap["PRE_ACC"][:, :3])
     lvl = oracle.rmin(cfg, lraw)
     level0, _, age0, val0 = decode_meta(snap["PRE_META"])

@@ -33,7 +33,7 @@ def expected_major(cfg, sim):
     info = oracle.derive(cfg)
     pre_pos = sim.debug("PRE_POS")[:, :3]
     keys_old = oracle.keys(cfg, pre_pos)
-    perm, start = oracle.sort(info.nblocks, keys_old, pre_pos[:, 0])
+    perm, start = oracle.sort(info.nblocks, keys_old)
     raw, lvl, ob = oracle.pci_regions(cfg, keys_old, sim.debug("PRE_VEL")[:, :3],
                                       sim.debug("PRE_ACC")[:, :3])
     t1 = oracle.pci_dilate(cfg, raw, 0, cfg.expand_layers)

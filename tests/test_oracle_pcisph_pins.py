@@ -210,7 +210,7 @@ def test_lists_match_brute_force_with_a_stale_grid(rings):
     info = O.derive(c)
     x0 = sc.pos.astype(np.float32)
     key0 = O.keys(c, x0)
-    perm, start = O.sort(info.nblocks, key0, x0[:, 0])
+    perm, start = O.sort(info.nblocks, key0)
     xs = x0[perm]
     key = key0[perm]
     # particles move after the grid was built
@@ -248,7 +248,7 @@ def all_lists(c, x, walls=None):
     info = O.derive(c)
     x32 = x.astype(np.float32)
     key0 = O.keys(c, x32)
-    perm, start = O.sort(info.nblocks, key0, x32[:, 0])
+    perm, start = O.sort(info.nblocks, key0)
     w = np.zeros((0, 3)) if walls is None else walls
     wx, wstart, _ = O.sorted_walls(c, w)
     st, nbr, nnb = O.pci_lists(c, x32[perm], start, key0[perm], wx.astype(np.float32), wstart,

@@ -271,35 +271,12 @@ def test_keys_place_each_particle_inside_its_block():
     assert (x >= lo - 1e-6).all() and (x < lo + e + 1e-6).all()
 
 
-def float_order(x):
-    """Order-preserving unsigned image of float32 bits (a total order)."""
-    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
-    return np.where(u >> 31, 0xFFFFFFFF - u, u | 0x80000000)
-
-
-def test_sort_orders_by_key_then_x_then_position():
+def test_sort_is_the_stable_argsort():
     rng = np.random.default_rng(5)
-    n = 2000
-    key = rng.integers(0, 50, size=n).astype(np.uint32)
-    # few distinct x values, so that ties fall back to the input position;
-    # -0 and +0 are distinct in the order
-    x = rng.choice(np.array([-0.5, -0.0, 0.0, 0.25, 0.25, 1.0, 3.5], np.float32), size=n)
-    perm, start = O.sort(50, key, x)
-    want = np.lexsort((np.arange(n), float_order(x), key))
-    assert np.array_equal(perm, want)
+    key = rng.integers(0, 50, size=2000).astype(np.uint32)
+    perm, start = O.sort(50, key)
+    assert np.array_equal(perm, np.argsort(key, kind="stable"))
     assert np.array_equal(start, np.concatenate([[0], np.cumsum(np.bincount(key, minlength=50))]))
-    # a row of blocks along x is sorted by x
-    xs, ks = x[perm], key[perm]
-    for b in range(50):
-        row = xs[ks == b]
-        assert np.all(row[1:] >= row[:-1])
-
-
-def test_sort_of_one_key_is_the_stable_argsort_of_x():
-    rng = np.random.default_rng(9)
-    x = rng.normal(size=500).astype(np.float32)
-    perm, _ = O.sort(1, np.zeros(500, np.uint32), x)
-    assert np.array_equal(perm, np.argsort(x, kind="stable"))
 
 
 def test_neighbours_match_brute_force():
