@@ -1,9 +1,10 @@
 """GPU edge cases and full-size checks of the WCSPH base step.
 
-Empty and single-particle scenes, ragged particle counts, capacity and
-numerical failures reported through the device status, region
-determination alone, and the 250,000-particle dam break: structure bit for
-bit and sampled densities against the oracle.
+Empty and single-particle scenes, ragged particle counts, a dense cluster
+whose candidate sets exceed the LDS staging (search and force then read the
+candidates from memory), capacity and numerical failures reported through
+the device status, region determination alone, and the 250,000-particle
+dam break: structure bit for bit and sampled densities against the oracle.
 """
 import numpy as np
 import pytest
@@ -12,7 +13,8 @@ import oracle
 from paper_2009_14514_amd import _rts, scenes
 from paper_2009_14514_amd.sim import Simulation, decode_meta
 
-from parity import expected_structure, oracle_density, snapshot_after_step
+from parity import (expected_structure, gpu_lists, oracle_density, oracle_forces_stage,
+                    oracle_lists, snapshot_after_step)
 
 pytestmark = pytest.mark.gpu
 
@@ -70,6 +72,46 @@ def test_ragged_counts_structure_and_density(n):
     rows = np.nonzero(comp)[0]
     rel = np.abs(snap["POS"][rows, 3] - rho_o[rows]) / rho_o[rows]
     assert rel.max() <= 1e-5
+
+
+def test_dense_cluster_takes_the_unstaged_path():
+    # a lattice at 0.7 s: about 190 particles per block, so a block's 27-block
+    # neighbourhood (about 5,000 candidates) exceeds the 2,048 LDS slots and
+    # search and force read the candidates from memory instead
+    g = np.arange(0.2, 0.4, 0.014)
+    h = np.arange(0.1, 0.3, 0.014)
+    pos = np.stack(np.meshgrid(g, h, h, indexing="ij"), axis=-1).reshape(-1, 3)
+    pos += np.random.default_rng(4).uniform(-1e-4, 1e-4, pos.shape)
+    sc = small_box_scene(pos)
+    sim = Simulation(sc, cand_cap=8192)
+    sim.advance(1)
+    sim.sync()
+    snap = snapshot_after_step(sim)
+    cfg = oracle.cfg_from_params(sc.params, nbr_cap=1024)  # ~780 neighbours each
+    exp = expected_structure(cfg, snap)
+    assert np.array_equal(snap["PERM"], exp["perm"])
+    assert np.array_equal(snap["CELL_START"], exp["cell_start"])
+    _, comp, _, _ = decode_meta(snap["META"])
+    assert comp.all()
+    # the fluid candidates of the block holding the cluster's centre alone
+    # exceed the LDS slots: the unstaged path is taken
+    nc = list(exp["info"].nc)
+    counts = np.diff(snap["CELL_START"].astype(np.int64)).reshape(nc[2], nc[1], nc[0])
+    b = oracle.keys(cfg, np.array([[0.3, 0.2, 0.2]], np.float32))[0]
+    bx, by, bz = b % nc[0], (b // nc[0]) % nc[1], b // (nc[0] * nc[1])
+    assert counts[bz - 1:bz + 2, by - 1:by + 2, bx - 1:bx + 2].sum() > 2048
+    rows = np.arange(0, sc.n, 37)
+    onbr, onnb = oracle_lists(cfg, snap, comp, cap=1024)
+    glists, gcounts = gpu_lists(sim, snap, rows)
+    assert np.array_equal(gcounts[rows], onnb[rows].astype(np.uint32))
+    for r, gl in zip(rows, glists):
+        assert np.array_equal(gl, onbr[r, :onnb[r]])
+    rho_o, _ = oracle_density(cfg, snap, comp)
+    rel = np.abs(snap["POS"][:, 3] - rho_o) / rho_o
+    assert rel.max() <= 1e-5
+    a_o = oracle_forces_stage(cfg, snap, comp)
+    a_g = snap["ACC_NEW"][:, :3].astype(np.float64)
+    assert np.linalg.norm(a_g - a_o) <= 1e-5 * np.linalg.norm(a_o)
 
 
 def test_candidate_capacity_overflow_is_reported():
