@@ -7,8 +7,8 @@
 // R_min and marks the observed blocks.  Each minor step then
 //   lists        rebuilds the neighbour lists of particles whose validity ran
 //                out, against the grid of the major step (two block layers
-//                for region 1, or regions 1 and 2)
-//   nonpressure  gravity + viscosity of the same particles
+//                for region 1, or regions 1 and 2), and sums their gravity +
+//                viscosity over the hits
 //   reset        p = 0, F^p = 0, S_e empty
 //   per iteration (the host reads the error reductions between iterations):
 //     predict    v* = v + dt (a_vg + a_p), x* = x + dt v*   (all)
@@ -117,22 +117,34 @@ __global__ void k_pci_major_flags(DevParams p, const uint32_t *__restrict__ key,
 // ---------------------------------------------------------------------------
 // minor step
 // ---------------------------------------------------------------------------
+// dW/dr / r, so that grad W(x_ij) = f * x_ij
+__device__ inline float grad_factor(const DevParams &p, float r2) {
+  const float r = __builtin_sqrtf(r2);
+  return p.sigma * p.inv_h * dw_shape(r * p.inv_h) / r;
+}
+
 // Neighbour lists against the grid of the major step (Section 5,
 // neighbourhood computation): blocks up to `rings` layers around the
 // particle's block, float predicate with the list radius, canonical order
-// (fluid by sorted index, then walls by wall sorted index | bit 31).
+// (fluid by sorted index, then walls by wall sorted index | bit 31).  The
+// same pass sums the non-pressure acceleration of Algorithm 2 (gravity plus
+// artificial viscosity of approaching pairs within the support; walls at
+// rest) over the hits in list order, while each neighbour's position is at
+// hand.
 __global__ void __launch_bounds__(256) k_pci_lists(
-    DevParams p, const float4 *__restrict__ P, const uint32_t *__restrict__ M,
-    const uint32_t *__restrict__ key, const uint32_t *__restrict__ start,
-    const float4 *__restrict__ WP, const uint32_t *__restrict__ wstart,
-    uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb, const uint32_t *__restrict__ ids,
-    DevScalars *S) {
+    DevParams p, const float4 *__restrict__ P, const float4 *__restrict__ V,
+    const uint32_t *__restrict__ M, const uint32_t *__restrict__ key,
+    const uint32_t *__restrict__ start, const float4 *__restrict__ WP,
+    const uint32_t *__restrict__ wstart, uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb,
+    float4 *__restrict__ fvg, const uint32_t *__restrict__ ids, DevScalars *S) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   const uint32_t m = M[i];
   if (!meta_compute(m)) return;
   const int rings = (p.mode == RTS_MODE_RTS && (int)meta_level(m) < p.two_ring_levels) ? 2 : 1;
-  const float4 xi = P[i];
+  const float4 xi = P[i], vi = V[i];
+  const float rs2 = p.support * p.support;
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
   const int3 c = coords_of(p, key[i]);
   // column-major lists: entry k of particle i at nbr[k * ncap + i], so that
   // a wave's loads of one entry index are contiguous
@@ -159,6 +171,16 @@ __global__ void __launch_bounds__(256) k_pci_lists(
           if (!(dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2l)) continue;
           if (cnt < (uint32_t)p.nbr_cap) L[(size_t)cnt * stride] = j | tag;
           ++cnt;
+          const float4 u = pass == 0 ? V[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          const float vx = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
+          if (!(r2 > 0.0f) || r2 >= rs2 || !(vx < 0.0f)) continue;
+          const float pij = -p.pci_nu * vx / (r2 + p.visc_eps_h2);
+          const float sc = -p.mass * pij * grad_factor(p, r2);
+          ax += sc * dx;
+          ay += sc * dy;
+          az += sc * dz;
         }
       }
     }
@@ -168,43 +190,6 @@ __global__ void __launch_bounds__(256) k_pci_lists(
     cnt = (uint32_t)p.nbr_cap;
   }
   nnb[i] = cnt;
-}
-
-// dW/dr / r, so that grad W(x_ij) = f * x_ij
-__device__ inline float grad_factor(const DevParams &p, float r2) {
-  const float r = __builtin_sqrtf(r2);
-  return p.sigma * p.inv_h * dw_shape(r * p.inv_h) / r;
-}
-
-// Gravity plus artificial viscosity (approaching pairs only; walls at rest).
-__global__ void __launch_bounds__(256) k_pci_nonpressure(
-    DevParams p, const float4 *__restrict__ P, const float4 *__restrict__ V,
-    const uint32_t *__restrict__ M, const uint32_t *__restrict__ nbr,
-    const uint32_t *__restrict__ nnb, const float4 *__restrict__ WP, float4 *__restrict__ fvg) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n || !meta_compute(M[i])) return;
-  const float4 xi = P[i], vi = V[i];
-  const uint32_t *L = nbr + (size_t)i;
-  const size_t stride = (size_t)p.ncap;
-  const uint32_t n = nnb[i];
-  const float rs2 = p.support * p.support;
-  float ax = 0.0f, ay = 0.0f, az = 0.0f;
-#pragma unroll 4
-  for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t j = L[(size_t)k * stride];
-    const bool wall = (j & kWallBit) != 0u;
-    const float4 q = wall ? WP[j & ~kWallBit] : P[j];
-    const float4 u = wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[j];
-    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    const float vx = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
-    if (!(r2 > 0.0f) || r2 >= rs2 || !(vx < 0.0f)) continue;
-    const float pij = -p.pci_nu * vx / (r2 + p.visc_eps_h2);
-    const float s = -p.mass * pij * grad_factor(p, r2);
-    ax += s * dx;
-    ay += s * dy;
-    az += s * dz;
-  }
   fvg[i] = make_float4(p.g[0] + ax, p.g[1] + ay, p.g[2] + az, 0.0f);
 }
 
@@ -522,13 +507,8 @@ void launch_pci_observed(const DevParams &p, const DevPtrs &d, hipStream_t st) {
 void launch_pci_lists(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
   if (p.n == 0) return;
   hipLaunchKernelGGL(k_pci_lists, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
-                     d.M[cur], d.KEY, d.CELL_START, d.WP, d.WCELL_START, d.NBRL, d.NNB, d.ID[cur],
-                     d.S);
-}
-void launch_pci_nonpressure(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
-  if (p.n == 0) return;
-  hipLaunchKernelGGL(k_pci_nonpressure, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
-                     d.V[cur], d.M[cur], d.NBRL, d.NNB, d.WP, d.FVG);
+                     d.V[cur], d.M[cur], d.KEY, d.CELL_START, d.WP, d.WCELL_START, d.NBRL, d.NNB,
+                     d.FVG, d.ID[cur], d.S);
 }
 void launch_pci_reset(const DevParams &p, const DevPtrs &d, hipStream_t st) {
   const int64_t m = p.n > p.nb ? p.n : p.nb;

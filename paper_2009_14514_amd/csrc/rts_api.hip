@@ -436,7 +436,6 @@ rts_status pci_minor_step(rts_ctx *c) {
   hipStream_t st = c->stream;
   const int cur = c->cur, col = c->pci_minor_in_major;
   launch_pci_lists(p, d, cur, st);
-  launch_pci_nonpressure(p, d, cur, st);
   launch_pci_reset(p, d, st);
   HIP_OK(c, hipGetLastError());
   int iter = 1, row = 1, min_iter = c->cfg.it_min, global = 1, local_iters = 0;

@@ -213,7 +213,6 @@ void launch_pci_major_flags(const DevParams &p, const DevPtrs &d, int cur, int m
                             hipStream_t st);
 void launch_pci_observed(const DevParams &p, const DevPtrs &d, hipStream_t st);
 void launch_pci_lists(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
-void launch_pci_nonpressure(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
 void launch_pci_reset(const DevParams &p, const DevPtrs &d, hipStream_t st);
 void launch_pci_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
 void launch_pci_density(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
