@@ -129,16 +129,23 @@ __device__ inline float grad_factor(const DevParams &p, float r2) {
 // (fluid by sorted index, then walls by wall sorted index | bit 31).  The
 // same pass sums the non-pressure acceleration of Algorithm 2 (gravity plus
 // artificial viscosity of approaching pairs within the support; walls at
-// rest) over the hits in list order, while each neighbour's position is at
-// hand.
+// rest) over the hits, while each neighbour's position is at hand.
+//
+// kPciSub lanes share a particle: they load kPciSub consecutive candidates
+// of a row at once, and a ballot of their hits gives each hit its place in
+// the list, so the list keeps the canonical order.
+constexpr int kPciSub = 8;
 __global__ void __launch_bounds__(256) k_pci_lists(
     DevParams p, const float4 *__restrict__ P, const float4 *__restrict__ V,
     const uint32_t *__restrict__ M, const uint32_t *__restrict__ key,
     const uint32_t *__restrict__ start, const float4 *__restrict__ WP,
     const uint32_t *__restrict__ wstart, uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb,
     float4 *__restrict__ fvg, const uint32_t *__restrict__ ids, DevScalars *S) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
+  const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kPciSub;
+  const uint32_t sub = threadIdx.x & (kPciSub - 1);
+  const uint32_t first = (threadIdx.x & 63u) & ~(uint32_t)(kPciSub - 1);  // group's first lane
+  // the lanes of a particle leave together
+  if (i >= (uint32_t)p.n) return;
   const uint32_t m = M[i];
   if (!meta_compute(m)) return;
   const int rings = (p.mode == RTS_MODE_RTS && (int)meta_level(m) < p.two_ring_levels) ? 2 : 1;
@@ -150,7 +157,7 @@ __global__ void __launch_bounds__(256) k_pci_lists(
   // a wave's loads of one entry index are contiguous
   uint32_t *L = nbr + (size_t)i;
   const size_t stride = (size_t)p.ncap;
-  uint32_t cnt = 0;
+  uint32_t cnt = 0;  // the same in the particle's lanes
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1 && p.nw == 0) break;
     const uint32_t *cs = pass == 0 ? start : wstart;
@@ -165,26 +172,43 @@ __global__ void __launch_bounds__(256) k_pci_lists(
         const int x0 = max(c.x - rings, 0), x1 = min(c.x + rings, p.nc[0] - 1);
         const uint32_t row = (uint32_t)p.nc[0] * ((uint32_t)y + (uint32_t)p.nc[1] * (uint32_t)z);
         const uint32_t s0 = cs[row + (uint32_t)x0], s1 = cs[row + (uint32_t)x1 + 1u];
-        for (uint32_t j = s0; j < s1; ++j) {
-          if (pass == 0 && j == (uint32_t)i) continue;
-          const float4 q = X[j];
-          if (!(dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2l)) continue;
-          if (cnt < (uint32_t)p.nbr_cap) L[(size_t)cnt * stride] = j | tag;
-          ++cnt;
-          const float4 u = pass == 0 ? V[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-          const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
-          const float r2 = dx * dx + dy * dy + dz * dz;
-          const float vx = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
-          if (!(r2 > 0.0f) || r2 >= rs2 || !(vx < 0.0f)) continue;
-          const float pij = -p.pci_nu * vx / (r2 + p.visc_eps_h2);
-          const float sc = -p.mass * pij * grad_factor(p, r2);
-          ax += sc * dx;
-          ay += sc * dy;
-          az += sc * dz;
+        for (uint32_t base = s0; base < s1; base += kPciSub) {
+          const uint32_t j = base + sub;
+          bool hit = false;
+          float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          if (j < s1 && !(pass == 0 && j == i)) {
+            q = X[j];
+            hit = dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2l;
+          }
+          // the group's hits among these candidates, in candidate order
+          const uint32_t mask = (uint32_t)(__ballot(hit) >> first) & ((1u << kPciSub) - 1u);
+          if (hit) {
+            const uint32_t pos = cnt + (uint32_t)__popc(mask & ((1u << sub) - 1u));
+            if (pos < (uint32_t)p.nbr_cap) L[(size_t)pos * stride] = j | tag;
+            const float4 u = pass == 0 ? V[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float vx = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
+            if (r2 > 0.0f && r2 < rs2 && vx < 0.0f) {
+              const float pij = -p.pci_nu * vx / (r2 + p.visc_eps_h2);
+              const float sc = -p.mass * pij * grad_factor(p, r2);
+              ax += sc * dx;
+              ay += sc * dy;
+              az += sc * dz;
+            }
+          }
+          cnt += (uint32_t)__popc(mask);
         }
       }
     }
   }
+  // the group's partial sums, folded in a fixed order
+  for (int o = 1; o < kPciSub; o <<= 1) {
+    ax += __shfl_xor(ax, o, kPciSub);
+    ay += __shfl_xor(ay, o, kPciSub);
+    az += __shfl_xor(az, o, kPciSub);
+  }
+  if (sub != 0) return;
   if (cnt > (uint32_t)p.nbr_cap) {
     set_status(S, RTS_E_CAPACITY, (int32_t)ids[i]);
     cnt = (uint32_t)p.nbr_cap;
@@ -506,7 +530,8 @@ void launch_pci_observed(const DevParams &p, const DevPtrs &d, hipStream_t st) {
 }
 void launch_pci_lists(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL(k_pci_lists, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
+  hipLaunchKernelGGL(k_pci_lists, dim3(grid_of((int64_t)p.n * kPciSub, 256)), dim3(256), 0, st,
+                     p, d.P[cur],
                      d.V[cur], d.M[cur], d.KEY, d.CELL_START, d.WP, d.WCELL_START, d.NBRL, d.NNB,
                      d.FVG, d.ID[cur], d.S);
 }
