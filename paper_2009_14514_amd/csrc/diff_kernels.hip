@@ -53,46 +53,95 @@ __global__ void k_diff_copy_in(DiffArgs a, const float4 *__restrict__ X, float4 
 
 // Lists in the canonical order of the sorted grid (rows dz, dy; blocks in x),
 // entries are caller indices (fluid) or wall sorted index | bit 31.
-__global__ void __launch_bounds__(256) k_diff_lists(
-    DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ perm,
-    const uint32_t *__restrict__ start, const float4 *__restrict__ WP,
-    const uint32_t *__restrict__ wstart, uint32_t *__restrict__ L, uint32_t *__restrict__ nn,
-    DevScalars *S) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const float4 xi = X[i];
-  const int3 c = block_of(p, xi.x, xi.y, xi.z);
-  // column-major: entry k of particle i at L[k * n + i]
-  uint32_t *row_out = L + (size_t)i;
-  uint32_t cnt = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 1 && p.nw == 0) break;
-    const uint32_t *cs = pass == 0 ? start : wstart;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int z = c.z + dz;
-      if (z < 0 || z >= p.nc[2]) continue;
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int y = c.y + dy;
-        if (y < 0 || y >= p.nc[1]) continue;
-        const int x0 = max(c.x - 1, 0), x1 = min(c.x + 1, p.nc[0] - 1);
-        const uint32_t row = (uint32_t)p.nc[0] * ((uint32_t)y + (uint32_t)p.nc[1] * (uint32_t)z);
-        const uint32_t s0 = cs[row + (uint32_t)x0], s1 = cs[row + (uint32_t)x1 + 1u];
-        for (uint32_t s = s0; s < s1; ++s) {
-          const uint32_t j = pass == 0 ? perm[s] : s;
-          if (pass == 0 && j == (uint32_t)i) continue;
-          const float4 q = pass == 0 ? X[j] : WP[s];
-          if (!(dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2f)) continue;
-          if (cnt < (uint32_t)a.cap) row_out[(size_t)cnt * (size_t)a.n] = pass == 0 ? j : (s | kWallBit);
+//
+// One workgroup per occupied block: the block's 27-block candidate set is
+// staged in LDS in canonical order together with each candidate's list entry
+// (caller index, or wall sorted index | bit 31); kSub lanes share a particle
+// and test interleaved candidates, and a ballot of the group's hits over each
+// run of kSub consecutive candidates places them in the canonical order.  A
+// block with more candidates than LDS slots is scanned from memory by one
+// lane per particle.
+constexpr int kDiffListThreads = 512;
+__global__ void __launch_bounds__(kDiffListThreads) k_diff_lists_blocks(
+    DevParams p, DiffArgs a, const float4 *__restrict__ Ps, const uint32_t *__restrict__ perm,
+    const uint32_t *__restrict__ occ, const uint32_t *__restrict__ start,
+    const float4 *__restrict__ WP, const uint32_t *__restrict__ wstart, uint32_t *__restrict__ L,
+    uint32_t *__restrict__ nn, DevScalars *S) {
+  __shared__ float4 s_pos[kStageCap];
+  __shared__ uint32_t s_code[kStageCap];
+  __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t sub = tid & (uint32_t)(kSub - 1);
+  const uint32_t first = (tid & 63u) & ~(uint32_t)(kSub - 1);  // the group's first lane
+  const uint32_t wave_first_slot = (tid / 64u) * (64u / kSub);
+  const uint32_t nocc = S->n_occ;
+  for (uint32_t q = blockIdx.x; q < nocc; q += gridDim.x) {
+    const uint32_t b = occ[q];
+    const uint32_t s0 = start[b];
+    const uint32_t nb = start[b + 1] - s0;
+    block_ranges_shared(p, start, wstart, b, s_rs, s_ro, s_len);
+    const uint32_t C = s_ro[18];
+    const uint32_t cpad = (C + kSub - 1) / kSub * kSub;
+    const bool staged = cpad <= (uint32_t)kStageCap;
+    if (staged)
+      for (uint32_t k = tid; k < cpad; k += kDiffListThreads) {
+        float4 v = make_float4(1e30f, 1e30f, 1e30f, 0.0f);  // padding: never a neighbour
+        uint32_t code = 0u;
+        if (k < C) {
+          bool wall;
+          const uint32_t g = local_to_global(s_rs, s_ro, k, wall);
+          v = wall ? WP[g] : Ps[g];
+          code = wall ? (g | kWallBit) : perm[g];
+        }
+        s_pos[k] = v;
+        s_code[k] = code;
+      }
+    __syncthreads();
+    const uint32_t self_off = s_ro[4] - s_rs[4];  // local index = sorted index + self_off
+    for (uint32_t c0 = 0; c0 < nb; c0 += kDiffListThreads / kSub) {
+      if (c0 + wave_first_slot >= nb) break;  // no particle for this wave
+      const uint32_t slot = c0 + tid / kSub;
+      const bool live = slot < nb;
+      const uint32_t s = s0 + (live ? slot : 0u);
+      const uint32_t i = perm[s];  // caller index
+      const float4 xi = Ps[s];
+      uint32_t *out = L + (size_t)i;
+      uint32_t cnt = 0;  // the same in the group's lanes
+      if (staged) {
+        const uint32_t selfk = s + self_off;
+        for (uint32_t base = 0; base < cpad; base += kSub) {
+          const uint32_t k = base + sub;
+          const float4 qj = s_pos[k];
+          const bool hit =
+              live && k != selfk && dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z) < p.r2f;
+          const uint32_t mask = (uint32_t)(__ballot(hit) >> first) & ((1u << kSub) - 1u);
+          if (hit) {
+            const uint32_t pos = cnt + (uint32_t)__popc(mask & ((1u << sub) - 1u));
+            if (pos < (uint32_t)a.cap) out[(size_t)pos * (size_t)a.n] = s_code[k];
+          }
+          cnt += (uint32_t)__popc(mask);
+        }
+      } else if (live && sub == 0u) {
+        for (uint32_t k = 0; k < C; ++k) {
+          bool wall;
+          const uint32_t g = local_to_global(s_rs, s_ro, k, wall);
+          if (!wall && g == s) continue;
+          const float4 qj = wall ? WP[g] : Ps[g];
+          if (!(dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z) < p.r2f)) continue;
+          if (cnt < (uint32_t)a.cap) out[(size_t)cnt * (size_t)a.n] = wall ? (g | kWallBit) : perm[g];
           ++cnt;
         }
       }
+      if (live && sub == 0u) {
+        if (cnt > (uint32_t)a.cap) {
+          set_status(S, RTS_E_CAPACITY, (int32_t)i);
+          cnt = (uint32_t)a.cap;
+        }
+        nn[i] = cnt;
+      }
     }
+    __syncthreads();  // shared memory is reused by the next block
   }
-  if (cnt > (uint32_t)a.cap) {
-    set_status(S, RTS_E_CAPACITY, i);
-    cnt = (uint32_t)a.cap;
-  }
-  nn[i] = cnt;
 }
 
 // Density by summation (compensated) and the unclamped Tait pressure, both
@@ -405,8 +454,8 @@ void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, flo
   launch_scatter(p, d, st);
   launch_cell_gather(p, d, 0, grid_wave, st);
   if (n == 0) return;
-  hipLaunchKernelGGL(k_diff_lists, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, d.PERM,
-                     d.CELL_START, d.WP, d.WCELL_START, L, nn, d.S);
+  hipLaunchKernelGGL(k_diff_lists_blocks, dim3(1024), dim3(kDiffListThreads), 0, st, p, a,
+                     d.P[1], d.PERM, d.OCC, d.CELL_START, d.WP, d.WCELL_START, L, nn, d.S);
   hipLaunchKernelGGL(k_diff_density, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, L, nn, d.WP, rho,
                      prs);
 }

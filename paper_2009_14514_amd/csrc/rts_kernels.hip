@@ -37,106 +37,6 @@ constexpr int kBlockThreads = 512;            // search: 64 particles x kSub lan
 constexpr int kPartPerPass = kBlockThreads / kSub;
 constexpr int kForceThreads = 512;            // force: 64 particles x kSub lanes
 constexpr int kForcePerPass = kForceThreads / kSub;
-constexpr int kStageCap = 2048;               // candidates staged in LDS (search: 16 B each)
-constexpr int kForceCap = 2048;               // candidates staged in LDS (force: 32 B each)
-
-// The candidate set of a block: 9 fluid row ranges (dz outer, dy inner, each
-// row covering x-1..x+1 contiguously in sorted order) followed by the same 9
-// rows of the wall grid.  Range r starts at global index rs and occupies
-// local indices [ro[r], ro[r+1]).  Local order equals the canonical
-// neighbour order (ascending sorted index, fluid before walls).
-__device__ inline void row_range(const DevParams &p, const uint32_t *start,
-                                 const uint32_t *wstart, int3 c, int r, uint32_t &rs,
-                                 uint32_t &len) {
-  const uint32_t *cs = r < 9 ? start : wstart;
-  const int rr = r % 9;
-  const int z = c.z + rr / 3 - 1, y = c.y + rr % 3 - 1;
-  rs = 0;
-  len = 0;
-  if (z < 0 || z >= p.nc[2] || y < 0 || y >= p.nc[1]) return;
-  if (r >= 9 && p.nw == 0) return;
-  const int x0 = max(c.x - 1, 0), x1 = min(c.x + 1, p.nc[0] - 1);
-  const uint32_t row = (uint32_t)p.nc[0] * ((uint32_t)y + (uint32_t)p.nc[1] * (uint32_t)z);
-  rs = cs[row + (uint32_t)x0];
-  const uint32_t re = cs[row + (uint32_t)x1 + 1u];
-  len = re > rs ? re - rs : 0u;
-}
-
-// Global position of local candidate k.
-__device__ inline uint32_t local_to_global(const uint32_t *rs, const uint32_t *ro, uint32_t k,
-                                           bool &wall) {
-  int r = 0;
-  while (r < 17 && k >= ro[r + 1]) ++r;
-  wall = r >= 9;
-  return rs[r] + (k - ro[r]);
-}
-
-// Position of candidate k (< C) for staging; j = its fluid index, or kNoFluid
-// for a wall particle or a slot past the candidates.
-constexpr uint32_t kNoFluid = 0xFFFFFFFFu;
-__device__ inline float4 stage_load(const uint32_t *rs, const uint32_t *ro,
-                                    const float4 *__restrict__ P, const float4 *__restrict__ WP,
-                                    uint32_t k, uint32_t C, uint32_t &j) {
-  j = kNoFluid;
-  if (k >= C) return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  bool wall;
-  const uint32_t g = local_to_global(rs, ro, k, wall);
-  if (!wall) j = g;
-  return wall ? WP[g] : P[g];
-}
-
-// Sets up the candidate ranges of block b in shared memory and their prefix
-// offsets.  Ends with the offsets visible to the whole workgroup.
-__device__ inline void block_ranges_shared(const DevParams &p, const uint32_t *start,
-                                           const uint32_t *wstart, uint32_t b, uint32_t *s_rs,
-                                           uint32_t *s_ro, uint32_t *s_len) {
-  const int tid = threadIdx.x;
-  if (tid < 18) {
-    uint32_t rs, len;
-    row_range(p, start, wstart, coords_of(p, b), tid, rs, len);
-    s_rs[tid] = rs;
-    s_len[tid] = len;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t acc = 0;
-    for (int r = 0; r < 18; ++r) {
-      s_ro[r] = acc;
-      acc += s_len[r];
-    }
-    s_ro[18] = acc;
-  }
-  __syncthreads();
-}
-
-// Copies the block's candidates into shared memory in canonical order, one
-// range at a time so that consecutive threads read consecutive particles;
-// slots from C up to cpad are filled with far-away positions.
-template <int kThreads>
-__device__ inline void stage_positions(const uint32_t *s_rs, const uint32_t *s_ro,
-                                       const float4 *__restrict__ P,
-                                       const float4 *__restrict__ WP, float4 *s_pos,
-                                       uint32_t cpad) {
-  constexpr int kPer = (kStageCap + kThreads - 1) / kThreads;
-  const uint32_t C = s_ro[18];
-  float4 v[kPer];
-  // every load is issued before the first shared-memory write
-#pragma unroll
-  for (int it = 0; it < kPer; ++it) {
-    const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kThreads;
-    v[it] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);  // padding: never a neighbour
-    if (k < C) {
-      bool wall;
-      const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
-      v[it] = wall ? WP[j] : P[j];
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < kPer; ++it) {
-    const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kThreads;
-    if (k < cpad) s_pos[k] = v[it];
-  }
-}
 
 // ---------------------------------------------------------------------------
 // key + histogram
