@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kDiffListThreads) k_diff_lists_blocks(
 __global__ void __launch_bounds__(256) k_diff_density(
     DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ L,
     const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float *__restrict__ rho,
-    float *__restrict__ prs) {
+    float *__restrict__ prs, float *__restrict__ pq) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const float4 xi = X[i];
@@ -168,19 +168,21 @@ __global__ void __launch_bounds__(256) k_diff_density(
     sum = t;
   }
   const float dev = p.kms * ((sum - p.c_hi) - (comp + p.c_lo));
-  rho[i] = p.rho0 + p.rho0 * dev;
-  prs[i] = a.B * pow7m1(dev);
+  const float r = p.rho0 + p.rho0 * dev, pr = a.B * pow7m1(dev);
+  rho[i] = r;
+  prs[i] = pr;
+  pq[i] = pr / (r * r);  // P = p / rho^2, which the force pass gathers
 }
 
 __global__ void __launch_bounds__(256) k_diff_force_euler(
     DevParams p, DiffArgs a, const float4 *__restrict__ X, const float4 *__restrict__ V,
-    const float *__restrict__ rho, const float *__restrict__ prs, const uint32_t *__restrict__ L,
+    const float *__restrict__ rho, const float *__restrict__ pq, const uint32_t *__restrict__ L,
     const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float4 *__restrict__ Xn,
     float4 *__restrict__ Vn) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const float4 xi = X[i], vi = V[i];
-  const float ri = rho[i], Pi = prs[i] / (ri * ri);
+  const float ri = rho[i], Pi = pq[i];
   const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
   float ax = p.g[0], ay = p.g[1], az = p.g[2];
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
       q = X[j];
       u = V[j];
       const float rj = rho[j];
-      coef = Pi + prs[j] / (rj * rj);
+      coef = Pi + pq[j];
       nu = 2.0f * a.alpha * a.hc0 / (ri + rj);
     }
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
@@ -443,7 +445,7 @@ void launch_diff_zero(int n, float4 *a, double *b, double *c, hipStream_t st) {
 // Lists, density and pressure of the state X (caller order): the sort of
 // the WCSPH path supplies the canonical block order.
 void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, float B,
-                       const float4 *X, uint32_t *L, uint32_t *nn, float *rho, float *prs,
+                       const float4 *X, uint32_t *L, uint32_t *nn, float *rho, float *prs, float *pq,
                        int grid_wave, hipStream_t st) {
   const DiffArgs a = dargs(n, cap, 0.0f, B, 0.0f, 0.0f);
   if (n > 0)
@@ -457,15 +459,15 @@ void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, flo
   hipLaunchKernelGGL(k_diff_lists_blocks, dim3(1024), dim3(kDiffListThreads), 0, st, p, a,
                      d.P[1], d.PERM, d.OCC, d.CELL_START, d.WP, d.WCELL_START, L, nn, d.S);
   hipLaunchKernelGGL(k_diff_density, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, L, nn, d.WP, rho,
-                     prs);
+                     prs, pq);
 }
 void launch_diff_force_euler(const DevParams &p, const DevPtrs &d, int n, int cap, float dt,
                              float alpha, float hc0, const float4 *X, const float4 *V,
-                             const float *rho, const float *prs, const uint32_t *L,
+                             const float *rho, const float *pq, const uint32_t *L,
                              const uint32_t *nn, float4 *Xn, float4 *Vn, hipStream_t st) {
   if (n == 0) return;
   const DiffArgs a = dargs(n, cap, dt, 0.0f, alpha, hc0);
-  hipLaunchKernelGGL(k_diff_force_euler, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, V, rho, prs, L,
+  hipLaunchKernelGGL(k_diff_force_euler, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, V, rho, pq, L,
                      nn, d.WP, Xn, Vn);
 }
 void launch_diff_adjoint(const DevParams &p, const DevPtrs &d, int n, int cap, float dt, float B,

@@ -1121,6 +1121,7 @@ struct DiffTape {
   float4 *CKX, *CKV;       // checkpoints, n each
   float4 *FX, *FV;         // segment frames: state at the start of each substep
   float *FR, *FP;          // density, pressure of each frame
+  float *PQ;               // p / rho^2 of the substep being advanced
   uint32_t *FL, *FN;       // lists and counts of each frame
   float4 *TX, *TV;         // state after the segment's last substep
   float4 *XB, *VB, *AB;    // adjoints of x, v, a
@@ -1148,6 +1149,7 @@ size_t diff_carve(const rts_diff_desc &D, int64_t n, char *base, DiffTape *t) {
   u.FP = (float *)take(nf * nn * 4);
   u.FL = (uint32_t *)take(nf * nn * (size_t)D.list_cap * 4);
   u.FN = (uint32_t *)take(nf * nn * 4);
+  u.PQ = (float *)take(nn * 4);
   u.TX = (float4 *)take(nn * 16);
   u.TV = (float4 *)take(nn * 16);
   u.XB = (float4 *)take(nn * 16);
@@ -1188,15 +1190,15 @@ void diff_run_segment(rts_ctx *c, const rts_diff_desc &D, int n, const DiffTape 
     }
     uint32_t *L = t.FL + f * nn * (size_t)D.list_cap, *NN = t.FN + f * nn;
     float *R = t.FR + f * nn, *P = t.FP + f * nn;
-    launch_diff_setup(c->prm, c->d, n, D.list_cap, (float)D.B, fx, L, NN, R, P, c->grid_wave,
-                      c->stream);
+    launch_diff_setup(c->prm, c->d, n, D.list_cap, (float)D.B, fx, L, NN, R, P, t.PQ,
+                      c->grid_wave, c->stream);
     // the next state never aliases the frame being read: without kept frames
     // it goes to TX / TV and is copied into frame 0 by the next substep
     const bool last = k + 1 == len;
     float4 *xn = last ? Xend : (keep ? t.FX + (f + 1) * nn : t.TX);
     float4 *vn = last ? Vend : (keep ? t.FV + (f + 1) * nn : t.TV);
     launch_diff_force_euler(c->prm, c->d, n, D.list_cap, (float)D.dt, (float)D.alpha, hc0, fx,
-                            fv, R, P, L, NN, xn, vn, c->stream);
+                            fv, R, t.PQ, L, NN, xn, vn, c->stream);
     X = xn;
     V = vn;
   }

@@ -236,10 +236,10 @@ void launch_diff_planes_out(int n, const float4 *src, float *dst, hipStream_t st
 void launch_diff_zero(int n, float4 *a, double *b, double *c, hipStream_t st);
 void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, float B,
                        const float4 *X, uint32_t *L, uint32_t *nn, float *rho, float *prs,
-                       int grid_wave, hipStream_t st);
+                       float *pq, int grid_wave, hipStream_t st);
 void launch_diff_force_euler(const DevParams &p, const DevPtrs &d, int n, int cap, float dt,
                              float alpha, float hc0, const float4 *X, const float4 *V,
-                             const float *rho, const float *prs, const uint32_t *L,
+                             const float *rho, const float *pq, const uint32_t *L,
                              const uint32_t *nn, float4 *Xn, float4 *Vn, hipStream_t st);
 void launch_diff_adjoint(const DevParams &p, const DevPtrs &d, int n, int cap, float dt, float B,
                          float alpha, float hc0, const float4 *X, const float4 *V,
