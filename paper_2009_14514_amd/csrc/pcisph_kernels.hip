@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_pci_lists(
     const uint32_t *__restrict__ start, const float4 *__restrict__ WP,
     const uint32_t *__restrict__ wstart, uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb,
     float4 *__restrict__ fvg, const uint32_t *__restrict__ ids, DevScalars *S) {
-  const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kPciSub;
+  const uint32_t i = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / kPciSub;
   const uint32_t sub = threadIdx.x & (kPciSub - 1);
   const uint32_t first = (threadIdx.x & 63u) & ~(uint32_t)(kPciSub - 1);  // group's first lane
   // the lanes of a particle leave together
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256) k_pci_density(
     const uint8_t *__restrict__ ob, const uint8_t *__restrict__ nearse,
     uint8_t *__restrict__ se, const uint32_t *__restrict__ nbr, const uint32_t *__restrict__ nnb,
     const float4 *__restrict__ WP, uint32_t turn) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
   if (i >= p.n) return;
   const uint32_t b = key[i];
   const bool in_se = se[i] != 0;
@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(256) k_pci_force(
     const uint32_t *__restrict__ M, const uint8_t *__restrict__ se,
     const uint32_t *__restrict__ nbr, const uint32_t *__restrict__ nnb,
     const float4 *__restrict__ WP, float4 *__restrict__ fp, uint32_t turn) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
   if (i >= p.n) return;
   if (!(has_turn(turn, meta_level(M[i])) || se[i])) return;
   const float4 xi = xs[i];
