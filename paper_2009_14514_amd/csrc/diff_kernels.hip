@@ -14,6 +14,7 @@
 // thread writes another particle's adjoint, so no atomics are needed and the
 // sums are in list order (deterministic).
 #include "rts_device.h"
+#include "xcd.h"
 
 namespace rts {
 
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(kDiffListThreads) k_diff_lists_blocks(
   const uint32_t first = (tid & 63u) & ~(uint32_t)(kSub - 1);  // the group's first lane
   const uint32_t wave_first_slot = (tid / 64u) * (64u / kSub);
   const uint32_t nocc = S->n_occ;
-  for (uint32_t q = blockIdx.x; q < nocc; q += gridDim.x) {
+  for (uint32_t q = xcd_block(blockIdx.x, gridDim.x); q < nocc; q += gridDim.x) {
     const uint32_t b = occ[q];
     const uint32_t s0 = start[b];
     const uint32_t nb = start[b + 1] - s0;
@@ -150,7 +151,7 @@ __global__ void __launch_bounds__(256) k_diff_density(
     DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ L,
     const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float *__restrict__ rho,
     float *__restrict__ prs, float *__restrict__ pq) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
   if (i >= a.n) return;
   const float4 xi = X[i];
   const uint32_t *row = L + (size_t)i;
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
     const float *__restrict__ rho, const float *__restrict__ pq, const uint32_t *__restrict__ L,
     const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float4 *__restrict__ Xn,
     float4 *__restrict__ Vn) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
   if (i >= a.n) return;
   const float4 xi = X[i], vi = V[i];
   const float ri = rho[i], Pi = pq[i];
@@ -241,7 +242,7 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
     const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, const float4 *__restrict__ AB,
     float4 *__restrict__ XB, float4 *__restrict__ VB, float *__restrict__ RB,
     double *__restrict__ BB, double *__restrict__ AA) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
   if (i >= a.n) return;
   const float4 xi = X[i], vi = V[i], abi = AB[i];
   const float ri = rho[i], pi = prs[i], Pi = pi / (ri * ri);
@@ -336,7 +337,7 @@ __global__ void __launch_bounds__(256) k_diff_adj_density(
     DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ L,
     const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, const float *__restrict__ RB,
     float4 *__restrict__ XB) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
   if (i >= a.n) return;
   const float4 xi = X[i];
   const float rbi = RB[i];

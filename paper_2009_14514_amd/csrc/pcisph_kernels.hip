@@ -24,6 +24,7 @@
 // run in list order and the reductions are folded in a fixed order: runs are
 // deterministic.
 #include "rts_device.h"
+#include "xcd.h"
 
 namespace rts {
 
