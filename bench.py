@@ -39,6 +39,8 @@ def parse():
                     help="time the RTS run only (for profiler runs); prints no JSON line")
     ap.add_argument("--pcisph-steps", type=int, default=200,
                     help="minor steps of the PCISPH double dam break (0: skip it)")
+    ap.add_argument("--only-diff", action="store_true",
+                    help="run only the differentiable leg (for profiler runs); prints no JSON line")
     ap.add_argument("--only-pcisph", action="store_true",
                     help="run the PCISPH comparison only (for profiler runs); no JSON line")
     ap.add_argument("--batch-steps", type=int, default=100,
@@ -401,6 +403,9 @@ def main():
         sys.exit(2)
     if args.only_pcisph:
         run_pcisph(args.pcisph_steps)
+        return
+    if args.only_diff:
+        run_diff(args.diff_repeats)
         return
     g = run_gpu(args)
     if g is None:
