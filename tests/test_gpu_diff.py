@@ -4,6 +4,8 @@ The forward run and the gradients of L = mean |x(T) - xhat|^2 (initial
 positions and velocities, Tait stiffness, viscosity alpha) are compared
 with the FP64 oracle on the 512-particle scene; checkpoint spacing must
 not change any bit; the autograd wrapper must return the same gradients.
+A dense cluster, whose block neighbourhoods exceed the LDS staging of the
+list build, takes the path that reads candidates from memory.
 """
 import numpy as np
 import pytest
@@ -91,3 +93,27 @@ def test_autograd_function_returns_the_adjoint(case):
     assert np.linalg.norm(v.grad.cpu().numpy() - rgv) <= 1e-3 * np.linalg.norm(rgv)
     assert Bt.grad.item() == pytest.approx(rgB, rel=1e-3)
     assert at.grad.item() == pytest.approx(rga, rel=1e-3)
+
+
+def test_dense_cluster_lists_from_memory():
+    # a lattice at 0.7 s: about 190 particles per block, so a block's
+    # 27-block neighbourhood (about 5,000 candidates) exceeds the 2,048 LDS
+    # slots of the list build; about 780 neighbours per particle
+    from paper_2009_14514_amd.diff import DiffRollout
+    T = torch()
+    base = scenes.diff_scene()
+    g = np.arange(0.1, 0.2, 0.007)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    pos += np.random.default_rng(8).uniform(-1e-4, 1e-4, pos.shape)
+    vel = np.zeros_like(pos)
+    sc = scenes.Scene("dense", pos, vel, base.walls, dict(base.params))
+    model = DiffRollout(sc, n_sub=1, ckpt_every=1, list_cap=1024)
+    x0 = T.tensor(pos, dtype=T.float32, device="cuda")
+    v0 = T.tensor(vel, dtype=T.float32, device="cuda")
+    xT, vT = model.forward(x0, v0, model.B0, model.alpha0)
+    model.close()
+    cfg = oracle.cfg_from_params(sc.params, nbr_cap=1024)
+    x0h = x0.cpu().numpy().astype(np.float64)
+    xr, vr = oracle.diff_run(cfg, x0h, vel, sc.walls, model.B0, model.alpha0, model.dt, 1)
+    assert np.abs(xT.cpu().numpy() - xr).max() <= 1e-4 * sc.params["spacing"]
+    assert np.linalg.norm(vT.cpu().numpy() - vr) <= 1e-4 * np.linalg.norm(vr)
