@@ -12,7 +12,8 @@
 // neighbour relation is symmetric and that a pair enters a_i and a_j with
 // opposite signs, so the pair's upstream gradient is abar_j - abar_i.  No
 // thread writes another particle's adjoint, so no atomics are needed and the
-// sums are in list order (deterministic).
+// sums are in list order (deterministic).  Lists are built per block from
+// LDS-staged candidates; the pair sums run one thread per particle.
 #include "rts_device.h"
 #include "xcd.h"
 

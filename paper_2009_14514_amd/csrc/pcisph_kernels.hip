@@ -19,10 +19,12 @@
 //   integrate    symplectic Euler, validity, requests for smaller steps
 //   demote       blocks (and their particles) take the requested steps
 //
-// One thread per particle: the lists hold about 45 entries within 1.1 r and
-// neighbouring threads share most of them, so gathers hit the caches.  Sums
-// run in list order and the reductions are folded in a fixed order: runs are
-// deterministic.
+// Density and pressure force run one thread per particle: the lists hold
+// about 45 entries within 1.1 r and neighbouring threads share most of them,
+// so gathers hit the caches (each XCD takes one contiguous range of
+// particles, so neighbours share its L2).  The list pass gives a particle
+// eight lanes.  Sums run in list order and the reductions are folded in a
+// fixed order: runs are deterministic.
 #include "rts_device.h"
 #include "xcd.h"
 

@@ -471,7 +471,9 @@ __device__ inline void kahan_merge(float &s, float &c, float s2, float c2) {
 // Here the lanes instead emit their hits in rounds of at most kRound each into
 // a per-particle LDS window, packed in lane order by a prefix over the kSub
 // counts, and then visit that window's entries e = sub, sub + kSub, ...  The
-// visit order depends on the bits alone, so results stay deterministic.
+// visit order depends on the bits alone, so results stay deterministic.  The
+// force pass walks this way; the density pass, with little work per hit,
+// walks each lane's own hits, where the rounds would cost more than they save.
 constexpr uint32_t kRound = 12;             // keeps the force kernel at two workgroups per CU
 constexpr uint32_t kWin = kRound * kSub;   // window entries per particle
 constexpr int kMaxQueueWords = 8;          // words per lane held in registers
