@@ -36,6 +36,8 @@ class OrcCfg(C.Structure):
         ("it_max", C.c_int32), ("expand_layers", C.c_int32), ("local_fail", C.c_int32),
         ("global_limit", C.c_int32), ("short_majors", C.c_int32), ("two_ring_levels", C.c_int32),
         ("eta", C.c_double), ("eta_T", C.c_double), ("delta", C.c_double), ("r_list", C.c_double),
+        ("adapt_dt", C.c_int32), ("grow_iters", C.c_int32), ("dt_min", C.c_double),
+        ("dt_max", C.c_double), ("grow", C.c_double), ("shrink", C.c_double),
     ]
 
 
@@ -80,6 +82,11 @@ class OrcPciState(C.Structure):
         ("last_reverts", C.c_int32), ("last_early_end", C.c_int32), ("last_lists", C.c_int32),
         ("evals_density", C.c_int64), ("evals_force", C.c_int64),
         ("last_errmax", C.c_double), ("last_avg", C.c_double), ("hist", C.c_int32 * 4),
+        ("dt_cur", C.c_double), ("last_dt", C.c_double), ("peak_iters", C.c_int32),
+        ("pad_", C.c_int32), ("last_v2max", C.c_float), ("last_a2max", C.c_float),
+        ("snap", C.c_void_p), ("snap_id", C.c_void_p), ("snap_t", C.c_double),
+        ("snap_steps", C.c_int64), ("snap_major_len", C.c_int32), ("snap_clean", C.c_int32),
+        ("rollbacks", C.c_int32), ("last_rollback", C.c_int32),
     ]
 
 
@@ -138,6 +145,8 @@ def _declare(L):
     L.orc_pci_turn.argtypes = [C.c_int32, C.c_int32]
     L.orc_pci_turn.restype = C.c_uint32
     L.orc_pci_step.argtypes = [cfgp, _p(OrcPciState)]
+    L.orc_pci_next_dt.argtypes = [cfgp, C.c_double, C.c_int32, C.c_int32, C.c_float, C.c_float]
+    L.orc_pci_next_dt.restype = C.c_double
     L.orc_pci_major_begin.argtypes = [cfgp, _p(OrcPciState)]
     L.orc_diff_run.argtypes = [cfgp, C.c_int32, vp, vp, C.c_int32, vp, C.c_double, C.c_double,
                                C.c_double, C.c_int32, vp, vp]
@@ -174,6 +183,9 @@ def cfg_from_params(p: dict, **over) -> OrcCfg:
     c.two_ring_levels = q.get("two_ring_levels", 1)
     c.eta, c.eta_T = q.get("eta", 0.01), q.get("eta_T", 0.0025)
     c.delta, c.r_list = q.get("delta", 0.0), q.get("r_list", 0.0)
+    c.adapt_dt, c.grow_iters = int(q.get("pci_adapt_dt", 0)), int(q.get("pci_grow_iters", 0))
+    c.dt_min, c.dt_max = q.get("pci_dt_min", 0.0), q.get("pci_dt_max", 0.0)
+    c.grow, c.shrink = q.get("pci_grow", 1.1), q.get("pci_shrink", 0.7)
     return c
 
 
@@ -364,6 +376,11 @@ def pci_delta(cfg):
     return lib().orc_pci_delta(C.byref(cfg))
 
 
+def pci_next_dt(cfg, dt, peak_iters, excess, v2max, a2max):
+    return lib().orc_pci_next_dt(C.byref(cfg), float(dt), int(peak_iters), int(excess),
+                                 float(v2max), float(a2max))
+
+
 def pci_turn(col, row):
     return int(lib().orc_pci_turn(int(col), int(row)))
 
@@ -492,6 +509,8 @@ class PCISPH:
         self.key = np.zeros(n, np.uint32)
         self.nbr = np.zeros((max(n, 1), cap), np.uint32)
         self.nnb = np.zeros(max(n, 1), np.int32)
+        self.snap = np.zeros(15 * max(n, 1))
+        self.snap_id = np.zeros(max(n, 1), np.uint32)
         self.cell_start = np.zeros(nb + 1, np.uint32)
         self.blk_level = np.full(nb, EMPTY_BLOCK, np.uint8)
         self.blk_ob = np.zeros(nb, np.uint8)
@@ -503,23 +522,28 @@ class PCISPH:
         s.n, s.nw = n, self.wx.shape[0]
         for name in ("x", "v", "fvg", "fp", "p", "rho", "err", "region", "validity", "compute",
                      "in_se", "id", "key", "nbr", "nnb", "cell_start", "blk_level", "blk_ob",
-                     "wx", "wcell_start"):
+                     "wx", "wcell_start", "snap", "snap_id"):
             setattr(s, name, _ptr(getattr(self, name)))
         s.major_len = int(self.cfg.n_minor)
         self.history = []
 
     def step(self, n=1):
-        for _ in range(n):
+        """n accepted minor steps (a rolled-back major step does not count)."""
+        s = self.state
+        target = s.minor_steps + n
+        while s.minor_steps < target:
             st = lib().orc_pci_step(C.byref(self.cfg), C.byref(self.state))
             if st:
                 raise RuntimeError(f"oracle PCISPH step status {st}")
-            s = self.state
             self.history.append(dict(
                 t=s.t, iters=s.last_iters, global_iters=s.last_global_iters,
                 resets=s.last_resets, reverts=s.last_reverts, early_end=s.last_early_end,
                 lists=s.last_lists, evals_density=s.evals_density, evals_force=s.evals_force,
                 errmax=s.last_errmax, avg=s.last_avg, hist=list(s.hist),
-                major_len=s.major_len, minor_in_major=s.minor_in_major))
+                major_len=s.major_len, minor_in_major=s.minor_in_major, dt=s.last_dt,
+                dt_next=s.dt_cur if s.dt_cur > 0 else self.cfg.dt_base,
+                v2max=s.last_v2max, a2max=s.last_a2max, rollback=s.last_rollback,
+                steps=s.minor_steps))
         return self
 
     def major_begin(self):

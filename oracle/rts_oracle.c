@@ -982,7 +982,43 @@ static void mark_near_se(const orc_info *I, const orc_pci_state *s, uint8_t *nea
   }
 }
 
-int orc_pci_step(const orc_cfg *c, orc_pci_state *s) {
+/* Adaptive base step (the paper leaves adjusting the PCISPH base step in
+ * the manner of global adaptive PCISPH to future work).  Reading taken here:
+ * the correction effort of the major step just ended steers the step (an
+ * overrun of global_limit shrinks it, minor steps that all converged within
+ * grow_iters iterations grow it); the Eq. 2-3 limits of the fastest particle
+ * cap it, Eq. 3 with beta_2 since beta_1 = infinity bounds nothing. */
+static double pci_dt_lo(const orc_cfg *c) { return c->dt_min > 0.0 ? c->dt_min : 0.25 * c->dt_base; }
+
+double orc_pci_next_dt(const orc_cfg *c, double dt, int32_t peak_iters, int32_t excess,
+                       float v2max, float a2max) {
+  const int32_t grow_at = c->grow_iters > 0 ? c->grow_iters : c->it_min + 1;
+  const double lo = pci_dt_lo(c);
+  const double hi = c->dt_max > 0.0 ? c->dt_max : 4.0 * c->dt_base;
+  double next = dt;
+  if (excess)
+    next = dt * c->shrink;
+  else if (peak_iters <= grow_at)
+    next = dt * c->grow;
+  if (next > hi) next = hi;
+  const double r = r_crit(c);
+  if (v2max > 0.0f) {
+    const double b = c->alpha_rts * c->beta2 * r / sqrt((double)v2max);    /* Eq. 3, beta_2 */
+    if (next > b) next = b;
+  }
+  if (a2max > 0.0f) {
+    const double b = c->lambda_f * sqrt(r / sqrt((double)a2max));          /* Eq. 2 */
+    if (next > b) next = b;
+  }
+  if (next < lo) next = lo;
+  return next;
+}
+
+int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
+  /* this major step's base step: the adapted one once there is one */
+  orc_cfg cfg_now = *c_in;
+  if (s->dt_cur > 0.0) cfg_now.dt_base = s->dt_cur;
+  const orc_cfg *c = &cfg_now;
   orc_info I;
   if (orc_derive(c, &I)) return ORC_E_INVALID;
   int32_t n = s->n;
@@ -990,10 +1026,26 @@ int orc_pci_step(const orc_cfg *c, orc_pci_state *s) {
   const int standard = pci_standard(c);
   if (s->major_len <= 0) s->major_len = c->n_minor;
   if (standard) s->major_len = 1;
+  const int adapt = !standard && c_in->adapt_dt && s->snap && s->snap_id;
   if (s->minor_in_major == 0) {
+    if (adapt) {                   /* the state the major step starts from */
+      memcpy(s->snap, s->x, sizeof(double) * 3 * nn);
+      memcpy(s->snap + 3 * nn, s->v, sizeof(double) * 3 * nn);
+      memcpy(s->snap + 6 * nn, s->fvg, sizeof(double) * 3 * nn);
+      memcpy(s->snap + 9 * nn, s->fp, sizeof(double) * 3 * nn);
+      memcpy(s->snap + 12 * nn, s->p, sizeof(double) * nn);
+      memcpy(s->snap + 13 * nn, s->rho, sizeof(double) * nn);
+      memcpy(s->snap + 14 * nn, s->err, sizeof(double) * nn);
+      memcpy(s->snap_id, s->id, sizeof(uint32_t) * nn);
+      s->snap_t = s->t;
+      s->snap_steps = s->minor_steps;
+      s->snap_major_len = s->major_len;
+      s->snap_clean = s->clean_majors;
+    }
     int st = pci_major_begin(c, &I, s);
     if (st) return st;
     s->major_excess = 0;
+    s->peak_iters = 0;
   }
   const int32_t col = s->minor_in_major;
   const double dt = I.dt_base, rho0 = c->rho0, eta = c->eta;
@@ -1178,6 +1230,8 @@ int orc_pci_step(const orc_cfg *c, orc_pci_state *s) {
   s->last_avg = avg;
   for (int r = 0; r < 4; ++r) s->hist[r] = 0;
   for (int32_t i = 0; i < n; ++i) s->hist[s->region[i] - 1]++;
+  if (iter - 1 > s->peak_iters) s->peak_iters = iter - 1;
+  s->last_dt = dt;
   s->t += dt;
   s->minor_steps += 1;
   s->minor_in_major += 1;
@@ -1188,6 +1242,24 @@ int orc_pci_step(const orc_cfg *c, orc_pci_state *s) {
   }
   if (s->minor_in_major >= s->major_len || s->last_early_end) {
     s->minor_in_major = 0;
+    if (adapt) {
+      /* the next major step's base step, from this one's effort and the
+       * fastest particle after it */
+      float v2m = 0.0f, a2m = 0.0f;
+      for (int32_t i = 0; i < n; ++i) {
+        float vf[3], af[3];
+        for (int e = 0; e < 3; ++e) {
+          vf[e] = (float)s->v[3 * (int64_t)i + e];
+          af[e] = (float)(s->fvg[3 * (int64_t)i + e] + s->fp[3 * (int64_t)i + e]);
+        }
+        const float v2 = norm2f(vf), a2 = norm2f(af);
+        if (v2 > v2m) v2m = v2;
+        if (a2 > a2m) a2m = a2;
+      }
+      s->last_v2max = v2m;
+      s->last_a2max = a2m;
+      s->dt_cur = orc_pci_next_dt(c_in, dt, s->peak_iters, s->major_excess, v2m, a2m);
+    }
     if (!standard) {
       if (s->major_excess) {
         s->major_len = 2 < c->n_minor ? 2 : c->n_minor;
@@ -1197,6 +1269,28 @@ int orc_pci_step(const orc_cfg *c, orc_pci_state *s) {
         s->clean_majors = 0;
       }
     }
+  }
+  /* a correction that did not converge: back to the start of the major
+   * step, which restarts with a shorter step */
+  s->last_rollback = 0;
+  if (adapt && errmax >= eta && dt > pci_dt_lo(c_in) && c_in->shrink < 1.0) {
+    memcpy(s->x, s->snap, sizeof(double) * 3 * nn);
+    memcpy(s->v, s->snap + 3 * nn, sizeof(double) * 3 * nn);
+    memcpy(s->fvg, s->snap + 6 * nn, sizeof(double) * 3 * nn);
+    memcpy(s->fp, s->snap + 9 * nn, sizeof(double) * 3 * nn);
+    memcpy(s->p, s->snap + 12 * nn, sizeof(double) * nn);
+    memcpy(s->rho, s->snap + 13 * nn, sizeof(double) * nn);
+    memcpy(s->err, s->snap + 14 * nn, sizeof(double) * nn);
+    memcpy(s->id, s->snap_id, sizeof(uint32_t) * nn);
+    s->t = s->snap_t;
+    s->minor_steps = s->snap_steps;
+    s->major_len = s->snap_major_len;
+    s->clean_majors = s->snap_clean;
+    s->minor_in_major = 0;
+    const double lo = pci_dt_lo(c_in), shrunk = dt * c_in->shrink;
+    s->dt_cur = shrunk > lo ? shrunk : lo;
+    s->rollbacks += 1;
+    s->last_rollback = 1;
   }
   for (int64_t k = 0; k < 3 * (int64_t)n; ++k)
     if (!isfinite(s->x[k])) return ORC_E_NUMERICAL;

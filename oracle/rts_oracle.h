@@ -52,6 +52,12 @@ typedef struct orc_cfg {
   double eta, eta_T;                 /* max / average compression error thresholds */
   double delta;                      /* <= 0: from the prototype neighbourhood */
   double r_list;                     /* neighbour-list radius; <= 0: block edge */
+  /* adaptive base step of regional PCISPH (orc_pci_next_dt) */
+  int32_t adapt_dt;                  /* 1: adapt dt_base between major steps (RTS mode) */
+  int32_t grow_iters;                /* grow after a major step none of whose minor steps
+                                        needed more iterations (<= 0: it_min + 1) */
+  double dt_min, dt_max;             /* bounds of the adapted step (<= 0: dt_base/4, 4 dt_base) */
+  double grow, shrink;               /* factors after an easy / an overrun major step */
 } orc_cfg;
 
 typedef struct orc_info {
@@ -145,6 +151,20 @@ typedef struct orc_pci_state {
   int64_t evals_density, evals_force; /* particle evaluations in the last minor step */
   double last_errmax, last_avg;
   int32_t hist[4];                   /* particles per region at the last minor step */
+  /* adaptive base step */
+  double dt_cur;                     /* step of the current major step (<= 0: cfg dt_base) */
+  double last_dt;                    /* length of the last minor step */
+  int32_t peak_iters;                /* most iterations of a minor step in this major step */
+  int32_t pad_;
+  float last_v2max, last_a2max;      /* speed^2 / acceleration^2 maxima at the last major end */
+  /* roll-back of a major step whose correction failed to converge */
+  double *snap;                      /* 15n: x, v, fvg, fp (3n each), p, rho, err */
+  uint32_t *snap_id;                 /* n */
+  double snap_t;
+  int64_t snap_steps;
+  int32_t snap_major_len, snap_clean;
+  int32_t rollbacks;                 /* major steps rolled back so far */
+  int32_t last_rollback;             /* 1: the last call rolled its major step back */
 } orc_pci_state;
 
 /* a19: delta = -1 / (beta (-sum gradW . sum gradW - sum gradW . gradW)),
@@ -184,6 +204,18 @@ void orc_pci_nonpressure(const orc_cfg *c, int32_t n, const double *x, const dou
 uint32_t orc_pci_turn(int32_t col, int32_t row);
 /* One minor step of Algorithm 2 (a major step begins when due). */
 int orc_pci_step(const orc_cfg *c, orc_pci_state *s);
+/* With adapt_dt, a minor step whose correction still exceeds eta after
+ * it_max iterations rolls its major step back to the state it started from
+ * and restarts it with the step scaled by shrink (not below dt_min): the
+ * call then leaves minor_steps and t as they were before the major step.
+ * Base step of the next major step (adapt_dt): dt scaled by shrink after a
+ * major step that overran global_limit, by grow after one whose minor steps
+ * all needed at most grow_iters iterations, then capped by dt_max and by
+ * Eq. 3 with beta_2 (alpha beta_2 r / V_max) and Eq. 2 (lambda_f
+ * sqrt(r / A_max)) of the fastest particle, and raised to dt_min.
+ * v2max, a2max: squared maxima, in float. */
+double orc_pci_next_dt(const orc_cfg *c, double dt, int32_t peak_iters, int32_t excess,
+                       float v2max, float a2max);
 /* Major-step set-up alone: sort into the grid, regions, flags. */
 int orc_pci_major_begin(const orc_cfg *c, orc_pci_state *s);
 
