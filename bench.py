@@ -238,7 +238,49 @@ def run_pcisph(steps):
         "standard_pcisph": {"value": n * steps / (g["ms"] * 1e-3), "ms_per_step": g["ms"] / steps,
                             "iterations": g["iters"], "density_err_last": g["errmax"]},
         "speedup_vs_standard": g["ms"] / r["ms"],
+        "adaptive_base_step": run_pcisph_adaptive(steps * 5e-4, r["ms"] / (steps * 5e-4)),
     }
+
+
+def run_pcisph_adaptive(sim_time, fixed_ms_per_sim_s):
+    """Regional PCISPH with the adaptive base step over the same simulated
+    time as the fixed-step arms, started from the fixed arms' 5e-4 s and from
+    1e-3 s (where fixed-step PCISPH on this scene diverges).  Compared by wall
+    time per simulated second, since the steps differ in length."""
+    import torch
+
+    from paper_2009_14514_amd import scenes
+    from paper_2009_14514_amd.sim import Simulation
+
+    res = {"sim_time_s": sim_time, "fixed_5e-4_ms_per_sim_s": fixed_ms_per_sim_s}
+    for dt0 in (5e-4, 1e-3):
+        sc = scenes.double_dam_break(dt_base=dt0)
+        sim = Simulation(sc, pci_adapt_dt=1)
+        sim.advance(1)
+        sim.sync()
+        sim.set_state(sc.pos, sc.vel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dts = []
+        while True:
+            sim.advance(4)
+            st = sim.sync()
+            dts.append(st.dt_last)
+            if st.time >= sim_time * (1.0 - 1e-9):
+                break
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[f"from_{dt0:g}"] = dict(
+            ms=el * 1e3, sim_time_s=st.time, ms_per_sim_s=el * 1e3 / st.time,
+            minor_steps=int(st.step), iterations=int(st.pci_iters_total),
+            rollbacks=int(st.pci_rollbacks), dt_min_s=min(dts), dt_max_s=max(dts),
+            density_err_last=float(st.pci_errmax),
+            speed_vs_fixed_5e_4=fixed_ms_per_sim_s / (el * 1e3 / st.time))
+        print(f"[bench] pcisph adaptive from {dt0:g}: {st.time:.4f} s in {el * 1e3:.1f} ms, "
+              f"{st.step} steps, {st.pci_iters_total} iterations, {st.pci_rollbacks} roll-backs",
+              file=sys.stderr, flush=True)
+        sim.close()
+    return res
 
 
 def run_batched(steps):

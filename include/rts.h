@@ -105,12 +105,33 @@ typedef struct rts_config {
   int32_t nbr_cap;        /* neighbour-list entries per particle (PCISPH) */
   int32_t two_ring_levels;/* regions whose lists search two block layers (paper: 1, region 1;
                              2 adds region 2, the variant of the paper's comparison figure) */
-  int32_t pad;
+  int32_t pci_adapt_dt;   /* 1: adaptive base step between major steps (RTS mode; see below) */
   double eta;             /* allowed maximum compression (paper: 1 %) */
   double eta_T;           /* average compression above which extra iterations are global */
   double delta;           /* pressure coefficient (<= 0: from the full rest-lattice
                              neighbourhood, standard PCISPH) */
   double r_list;          /* neighbour-list radius (<= 0: block_edge, the 1.1 r grid) */
+  /* Adaptive base step of regional PCISPH (the paper's conclusions suggest
+   * combining the method with global adaptive stepping).  dt_base is the
+   * first major step's base step.  After each major step the next one's is
+   *   dt * pci_shrink  if a minor step ran more than global_limit global
+   *                    iterations or more than pci_shrink_iters in all,
+   *   dt * pci_grow    else if no minor step ran more than pci_grow_iters,
+   *   dt               otherwise,
+   * capped by pci_dt_max and by Eq. 3 with beta_2 and Eq. 2 for the fastest
+   * particle (alpha beta_2 r / V_max, lambda_f sqrt(r / A_max)), and
+   * raised to pci_dt_min.  A minor step whose correction still exceeds eta
+   * after it_max iterations rolls its major step back to the state the
+   * major step started from and restarts it with max(dt / 2, pci_dt_min),
+   * as long as dt is above pci_dt_min; rts_advance counts accepted minor
+   * steps.  Needs delta <= 0 (delta
+   * follows the step). */
+  int32_t pci_grow_iters; /* (<= 0: it_min) */
+  int32_t pci_shrink_iters; /* (<= 0: it_min) */
+  double pci_dt_min;      /* (<= 0: dt_base / 4) */
+  double pci_dt_max;      /* (<= 0: 4 dt_base) */
+  double pci_grow;        /* >= 1 (1.02) */
+  double pci_shrink;      /* in (0, 1] (0.95) */
 } rts_config;
 
 /* Per-run counters, filled by rts_sync. */
@@ -140,7 +161,11 @@ typedef struct rts_stats {
   int32_t pci_minor_in_major;        /* minor steps done in the current major step */
   double pci_errmax;                 /* max compression after the last iteration */
   double pci_avg;                    /* mean compression after the last iteration */
-  int64_t pci_iters_total;           /* iterations summed over all minor steps */
+  int64_t pci_iters_total;           /* iterations summed over all minor steps, rolled-back
+                                        ones included */
+  int32_t pci_rollbacks;             /* major steps rolled back (adaptive base step) */
+  int32_t pci_pad;
+  double pci_dt_next;                /* base step of the next minor step */
 } rts_stats;
 
 typedef struct rts_ctx rts_ctx;

@@ -36,7 +36,8 @@ class OrcCfg(C.Structure):
         ("it_max", C.c_int32), ("expand_layers", C.c_int32), ("local_fail", C.c_int32),
         ("global_limit", C.c_int32), ("short_majors", C.c_int32), ("two_ring_levels", C.c_int32),
         ("eta", C.c_double), ("eta_T", C.c_double), ("delta", C.c_double), ("r_list", C.c_double),
-        ("adapt_dt", C.c_int32), ("grow_iters", C.c_int32), ("dt_min", C.c_double),
+        ("adapt_dt", C.c_int32), ("grow_iters", C.c_int32), ("shrink_iters", C.c_int32),
+        ("pad_adapt", C.c_int32), ("dt_min", C.c_double),
         ("dt_max", C.c_double), ("grow", C.c_double), ("shrink", C.c_double),
     ]
 
@@ -184,8 +185,9 @@ def cfg_from_params(p: dict, **over) -> OrcCfg:
     c.eta, c.eta_T = q.get("eta", 0.01), q.get("eta_T", 0.0025)
     c.delta, c.r_list = q.get("delta", 0.0), q.get("r_list", 0.0)
     c.adapt_dt, c.grow_iters = int(q.get("pci_adapt_dt", 0)), int(q.get("pci_grow_iters", 0))
+    c.shrink_iters = int(q.get("pci_shrink_iters", 0))
     c.dt_min, c.dt_max = q.get("pci_dt_min", 0.0), q.get("pci_dt_max", 0.0)
-    c.grow, c.shrink = q.get("pci_grow", 1.1), q.get("pci_shrink", 0.7)
+    c.grow, c.shrink = q.get("pci_grow", 1.02), q.get("pci_shrink", 0.95)
     return c
 
 

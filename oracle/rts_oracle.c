@@ -985,18 +985,19 @@ static void mark_near_se(const orc_info *I, const orc_pci_state *s, uint8_t *nea
 /* Adaptive base step (the paper leaves adjusting the PCISPH base step in
  * the manner of global adaptive PCISPH to future work).  Reading taken here:
  * the correction effort of the major step just ended steers the step (an
- * overrun of global_limit shrinks it, minor steps that all converged within
- * grow_iters iterations grow it); the Eq. 2-3 limits of the fastest particle
+ * overrun of global_limit or of shrink_iters shrinks it, minor steps that all
+ * converged within grow_iters iterations grow it); the Eq. 2-3 limits of the fastest particle
  * cap it, Eq. 3 with beta_2 since beta_1 = infinity bounds nothing. */
 static double pci_dt_lo(const orc_cfg *c) { return c->dt_min > 0.0 ? c->dt_min : 0.25 * c->dt_base; }
 
 double orc_pci_next_dt(const orc_cfg *c, double dt, int32_t peak_iters, int32_t excess,
                        float v2max, float a2max) {
-  const int32_t grow_at = c->grow_iters > 0 ? c->grow_iters : c->it_min + 1;
+  const int32_t grow_at = c->grow_iters > 0 ? c->grow_iters : c->it_min;
+  const int32_t shrink_at = c->shrink_iters > 0 ? c->shrink_iters : c->it_min;
   const double lo = pci_dt_lo(c);
   const double hi = c->dt_max > 0.0 ? c->dt_max : 4.0 * c->dt_base;
   double next = dt;
-  if (excess)
+  if (excess || peak_iters > shrink_at)
     next = dt * c->shrink;
   else if (peak_iters <= grow_at)
     next = dt * c->grow;
@@ -1271,9 +1272,9 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
     }
   }
   /* a correction that did not converge: back to the start of the major
-   * step, which restarts with a shorter step */
+   * step, which restarts with half the step */
   s->last_rollback = 0;
-  if (adapt && errmax >= eta && dt > pci_dt_lo(c_in) && c_in->shrink < 1.0) {
+  if (adapt && errmax >= eta && dt > pci_dt_lo(c_in)) {
     memcpy(s->x, s->snap, sizeof(double) * 3 * nn);
     memcpy(s->v, s->snap + 3 * nn, sizeof(double) * 3 * nn);
     memcpy(s->fvg, s->snap + 6 * nn, sizeof(double) * 3 * nn);
@@ -1287,8 +1288,8 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
     s->major_len = s->snap_major_len;
     s->clean_majors = s->snap_clean;
     s->minor_in_major = 0;
-    const double lo = pci_dt_lo(c_in), shrunk = dt * c_in->shrink;
-    s->dt_cur = shrunk > lo ? shrunk : lo;
+    const double lo = pci_dt_lo(c_in), half = 0.5 * dt;
+    s->dt_cur = half > lo ? half : lo;
     s->rollbacks += 1;
     s->last_rollback = 1;
   }

@@ -55,7 +55,10 @@ typedef struct orc_cfg {
   /* adaptive base step of regional PCISPH (orc_pci_next_dt) */
   int32_t adapt_dt;                  /* 1: adapt dt_base between major steps (RTS mode) */
   int32_t grow_iters;                /* grow after a major step none of whose minor steps
-                                        needed more iterations (<= 0: it_min + 1) */
+                                        needed more iterations (<= 0: it_min) */
+  int32_t shrink_iters;              /* shrink after one where a minor step needed more
+                                        (<= 0: it_min) */
+  int32_t pad_adapt;
   double dt_min, dt_max;             /* bounds of the adapted step (<= 0: dt_base/4, 4 dt_base) */
   double grow, shrink;               /* factors after an easy / an overrun major step */
 } orc_cfg;
@@ -206,11 +209,12 @@ uint32_t orc_pci_turn(int32_t col, int32_t row);
 int orc_pci_step(const orc_cfg *c, orc_pci_state *s);
 /* With adapt_dt, a minor step whose correction still exceeds eta after
  * it_max iterations rolls its major step back to the state it started from
- * and restarts it with the step scaled by shrink (not below dt_min): the
+ * and restarts it with half the step (not below dt_min): the
  * call then leaves minor_steps and t as they were before the major step.
  * Base step of the next major step (adapt_dt): dt scaled by shrink after a
- * major step that overran global_limit, by grow after one whose minor steps
- * all needed at most grow_iters iterations, then capped by dt_max and by
+ * major step that overran global_limit or had a minor step needing more than
+ * shrink_iters iterations, else by grow after one whose minor steps all
+ * needed at most grow_iters iterations, then capped by dt_max and by
  * Eq. 3 with beta_2 (alpha beta_2 r / V_max) and Eq. 2 (lambda_f
  * sqrt(r / A_max)) of the fastest particle, and raised to dt_min.
  * v2max, a2max: squared maxima, in float. */

@@ -53,8 +53,10 @@ class RtsConfig(C.Structure):
         ("n_minor", C.c_int32), ("it_min", C.c_int32), ("it_max", C.c_int32),
         ("expand_layers", C.c_int32), ("local_fail", C.c_int32), ("global_limit", C.c_int32),
         ("short_majors", C.c_int32), ("nbr_cap", C.c_int32), ("two_ring_levels", C.c_int32),
-        ("pad", C.c_int32),
+        ("pci_adapt_dt", C.c_int32),
         ("eta", C.c_double), ("eta_T", C.c_double), ("delta", C.c_double), ("r_list", C.c_double),
+        ("pci_grow_iters", C.c_int32), ("pci_shrink_iters", C.c_int32), ("pci_dt_min", C.c_double),
+        ("pci_dt_max", C.c_double), ("pci_grow", C.c_double), ("pci_shrink", C.c_double),
     ]
 
 
@@ -70,6 +72,7 @@ class RtsStats(C.Structure):
         ("pci_reverts", C.c_int32), ("pci_early_end", C.c_int32), ("pci_lists", C.c_int32),
         ("pci_major_len", C.c_int32), ("pci_minor_in_major", C.c_int32),
         ("pci_errmax", C.c_double), ("pci_avg", C.c_double), ("pci_iters_total", C.c_int64),
+        ("pci_rollbacks", C.c_int32), ("pci_pad", C.c_int32), ("pci_dt_next", C.c_double),
     ]
 
     def as_dict(self):
@@ -176,9 +179,13 @@ def config_from_params(p: dict, **over) -> RtsConfig:
             setattr(c, k, int(q[k]))
     if c.solver == RTS_PCISPH:
         c.nbr_cap = int(q.get("nbr_cap", c.nbr_cap))
-    for k in ("eta", "eta_T", "delta", "r_list"):
+    for k in ("eta", "eta_T", "delta", "r_list", "pci_dt_min", "pci_dt_max", "pci_grow",
+              "pci_shrink"):
         if k in q:
             setattr(c, k, float(q[k]))
+    for k in ("pci_adapt_dt", "pci_grow_iters", "pci_shrink_iters"):
+        if k in q:
+            setattr(c, k, int(q[k]))
     c.mass = float(q.get("mass", 0.0))
     c.B = float(q.get("B", 0.0))
     for d in range(3):

@@ -342,6 +342,8 @@ __global__ void __launch_bounds__(256) k_pci_force(
 // order by the last workgroup.
 __device__ inline void pci_part_add(PciPart &t, const PciPart &u) {
   t.errmax = fmaxf(t.errmax, u.errmax);
+  t.v2max = fmaxf(t.v2max, u.v2max);
+  t.a2max = fmaxf(t.a2max, u.a2max);
   t.sum += u.sum;
   t.ncomp += u.ncomp;
   for (int k = 0; k < 4; ++k) t.hist[k] += u.hist[k];
@@ -353,6 +355,8 @@ __device__ inline PciPart pci_block_reduce(PciPart t, PciPart *s_w) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int o = 32; o > 0; o >>= 1) {
     t.errmax = fmaxf(t.errmax, __shfl_xor(t.errmax, o, 64));
+    t.v2max = fmaxf(t.v2max, __shfl_xor(t.v2max, o, 64));
+    t.a2max = fmaxf(t.a2max, __shfl_xor(t.a2max, o, 64));
     t.sum += __shfl_xor(t.sum, o, 64);
     t.ncomp += __shfl_xor(t.ncomp, o, 64);
 #pragma unroll
@@ -369,9 +373,12 @@ __device__ inline PciPart pci_block_reduce(PciPart t, PciPart *s_w) {
 // Max and mean compression over all particles (each keeps its latest
 // error), particles per region and with the compute flag; per-workgroup
 // partials folded in a fixed order by the last workgroup.  `first`: the
-// compute count is also kept as this minor step's list count.
+// compute count is also kept as this minor step's list count.  With V and A
+// given, also the largest |v|^2 and |a|^2 (the adaptive base step's bounds).
 __global__ void __launch_bounds__(256) k_pci_errstats(DevParams p, const float4 *__restrict__ pv,
                                                      const uint32_t *__restrict__ M,
+                                                     const float4 *__restrict__ V,
+                                                     const float4 *__restrict__ A,
                                                      PciPart *__restrict__ part, DevPci *pci,
                                                      int first) {
   __shared__ PciPart s_w[4];
@@ -379,6 +386,11 @@ __global__ void __launch_bounds__(256) k_pci_errstats(DevParams p, const float4 
   const int tid = threadIdx.x;
   PciPart t = {};
   for (int i = blockIdx.x * blockDim.x + tid; i < p.n; i += gridDim.x * blockDim.x) {
+    if (V) {
+      const float4 v = V[i], a = A[i];
+      t.v2max = fmaxf(t.v2max, norm2_exact(v.x, v.y, v.z));
+      t.a2max = fmaxf(t.a2max, norm2_exact(a.x, a.y, a.z));
+    }
     const float e = fmaxf(pv[i].y, 0.0f);
     t.errmax = fmaxf(t.errmax, e);
     t.sum += (double)e;
@@ -406,6 +418,10 @@ __global__ void __launch_bounds__(256) k_pci_errstats(DevParams p, const float4 
   pci->errmax = r.errmax;
   pci->avg = p.n > 0 ? r.sum / (double)p.n : 0.0;
   for (int k = 0; k < 4; ++k) pci->hist[k] = r.hist[k];
+  if (V) {
+    pci->v2max = r.v2max;
+    pci->a2max = r.a2max;
+  }
   pci->ticket = 0u;
 }
 
@@ -566,9 +582,10 @@ void launch_pci_force(const DevParams &p, const DevPtrs &d, int cur, uint32_t tu
                      d.M[cur], d.SE, d.NBRL, d.NNB, d.WP, d.FP, turn);
 }
 void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, int first,
-                         hipStream_t st) {
+                         hipStream_t st, bool motion) {
   hipLaunchKernelGGL(k_pci_errstats, dim3(kPciStatBlocks), dim3(256), 0, st, p, d.PV, d.M[cur],
-                     d.PPART, d.PCI, first);
+                     motion ? d.V[cur] : nullptr, motion ? d.A[cur] : nullptr, d.PPART, d.PCI,
+                     first);
 }
 void launch_pci_pressure_copy(const DevParams &p, const DevPtrs &d, int to_backup,
                               hipStream_t st) {

@@ -37,6 +37,16 @@ struct rts_ctx {
   int32_t pci_last[6];   // iters, global iters, resets, reverts, early end, lists
   double pci_errmax, pci_avg;
   int32_t pci_hist[4];
+  // adaptive base step: the last minor step's length, the most iterations
+  // of a minor step in this major step, and what a roll-back restores (the
+  // particle state itself stays in the sort's source buffers, cur ^ 1,
+  // which the minor steps never write)
+  double dt_last;
+  int pci_peak;
+  int32_t pci_rollbacks;
+  double snap_time;
+  int64_t snap_steps;
+  int snap_major_len, snap_clean;
   int tune_candidates;
   double tune_ms;
   char err[512];
@@ -154,6 +164,17 @@ rts_status validate(const rts_config *c, char *msg, size_t cap) {
       snprintf(msg, cap, "PCISPH needs eta, eta_T and dt_base > 0");
       return RTS_E_INVALID;
     }
+    if (c->pci_adapt_dt) {
+      const double lo = c->pci_dt_min > 0 ? c->pci_dt_min : 0.25 * c->dt_base;
+      const double hi = c->pci_dt_max > 0 ? c->pci_dt_max : 4.0 * c->dt_base;
+      if (c->pci_adapt_dt != 1 || !(c->pci_grow >= 1.0) || !(c->pci_shrink > 0.0) ||
+          !(c->pci_shrink <= 1.0) || !(lo <= c->dt_base && c->dt_base <= hi) ||
+          c->delta > 0.0) {
+        snprintf(msg, cap, "adaptive base step: need pci_grow >= 1, 0 < pci_shrink <= 1, "
+                 "pci_dt_min <= dt_base <= pci_dt_max and delta <= 0");
+        return RTS_E_INVALID;
+      }
+    }
     const double rl = c->r_list > 0 ? c->r_list : c->block_edge;
     if (!(rl >= c->support && rl <= c->block_edge)) {
       snprintf(msg, cap, "r_list must lie in [support, block_edge]");
@@ -196,6 +217,27 @@ rts_status validate(const rts_config *c, char *msg, size_t cap) {
   return RTS_OK;
 }
 
+// What depends on the base step dtb: the step itself, the level thresholds
+// and, for PCISPH, the pressure coefficient.  Level l steps 2^l base steps
+// and takes beta of rank l + 1 (Section 3.1: beta_1 = infinity, beta_n =
+// beta2 * ratio^(n-2)):
+//   Eq. 3:  |v|^2 <= (alpha beta_{l+1} r / (2^l dt))^2
+//   Eq. 2:  |a|^2 <= (lambda_f^2 r / (2^l dt)^2)^2
+// PCISPH region n = l + 1 steps n base steps instead (Section 5).
+void step_params(const rts_config &c, double mass, double dtb, DevParams &p) {
+  const double rc = r_crit_of(c);
+  p.dt_base = (float)dtb;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    double dtl = c.solver == RTS_PCISPH ? dtb * (double)(l + 1) : ldexp(dtb, l);
+    double bet = (l + 1 <= 1) ? INFINITY : c.beta2 * pow(c.beta_ratio, (double)(l + 1 - 2));
+    double vl = isinf(bet) ? INFINITY : c.alpha_rts * bet * rc / dtl;
+    double al = c.lambda_f * c.lambda_f * rc / (dtl * dtl);
+    p.TV[l] = (float)(vl * vl);
+    p.TA[l] = (float)(al * al);
+  }
+  if (c.solver == RTS_PCISPH) p.delta = (float)(c.delta > 0.0 ? c.delta : pci_delta(c, mass, dtb));
+}
+
 void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, double &mass,
             double &B, double &dtb) {
   memset(&p, 0, sizeof(p));
@@ -233,7 +275,6 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   p.visc_eps_h2 = (float)(c.visc_eps * c.h * c.h);
   const double rc = r_crit_of(c);
   dtb = c.dt_base > 0.0 ? c.dt_base : c.lambda_v * rc / c.c0;   // Eq. 1
-  p.dt_base = (float)dtb;
   p.dt_cfl = c.lambda_v * rc / c.c0;
   p.lf2r = c.lambda_f * c.lambda_f * rc;
   int lmax = c.n_levels - 1;
@@ -243,19 +284,6 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   p.mode = c.mode;
   p.serna_correct = c.serna_correct;
   p.clamp_p = c.clamp_p;
-  // Level l steps 2^l base steps and takes beta of rank l + 1 (Section 3.1:
-  // beta_1 = infinity, beta_n = beta2 * ratio^(n-2)):
-  //   Eq. 3:  |v|^2 <= (alpha beta_{l+1} r / (2^l dt))^2
-  //   Eq. 2:  |a|^2 <= (lambda_f^2 r / (2^l dt)^2)^2
-  // PCISPH region n = l + 1 steps n base steps instead (Section 5).
-  for (int l = 0; l < kMaxLevels; ++l) {
-    double dtl = c.solver == RTS_PCISPH ? dtb * (double)(l + 1) : ldexp(dtb, l);
-    double bet = (l + 1 <= 1) ? INFINITY : c.beta2 * pow(c.beta_ratio, (double)(l + 1 - 2));
-    double vl = isinf(bet) ? INFINITY : c.alpha_rts * bet * rc / dtl;
-    double al = c.lambda_f * c.lambda_f * rc / (dtl * dtl);
-    p.TV[l] = (float)(vl * vl);
-    p.TA[l] = (float)(al * al);
-  }
   p.solver = c.solver;
   p.support = (float)c.support;
   if (c.solver == RTS_PCISPH) {
@@ -263,11 +291,11 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
     p.two_ring_levels = c.two_ring_levels > 0 ? c.two_ring_levels : 1;
     const double rl = c.r_list > 0.0 ? c.r_list : c.block_edge;
     p.r2l = (float)(rl * rl);
-    p.delta = (float)(c.delta > 0.0 ? c.delta : pci_delta(c, mass, dtb));
     p.eta_half = (float)(0.5 * c.eta);
     p.pci_nu = (float)(c.visc_alpha * c.h * c.c0 / c.rho0);
     p.w0m = (float)(mass * sigma);
   }
+  step_params(c, mass, dtb, p);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -401,6 +429,12 @@ rts_status pci_major_begin(rts_ctx *c) {
   const DevPtrs &d = c->d;
   hipStream_t st = c->stream;
   const int cur = c->cur, nx = cur ^ 1;
+  // what a roll-back of this major step restores besides the particles
+  c->snap_time = c->pci_time;
+  c->snap_steps = c->pci_steps;
+  c->snap_major_len = c->pci_major_len;
+  c->snap_clean = c->pci_clean;
+  c->pci_peak = 0;
   launch_key_hist(p, d, cur, st);
   launch_scan(p, d, d.CELL_START, true, st);
   launch_scatter(p, d, st);
@@ -423,9 +457,34 @@ rts_status pci_read(rts_ctx *c, DevPci *h) {
   return RTS_OK;
 }
 
+double pci_dt_lo(const rts_config &c) { return c.pci_dt_min > 0 ? c.pci_dt_min : 0.25 * c.dt_base; }
+
+// Adaptive base step: the next major step's base step from the effort of
+// the one just ended and the fastest particle after it (squared maxima, in
+// float).  Eq. 3 takes beta_2: beta_1 = infinity bounds nothing.
+double pci_next_dt(const rts_config &c, double dt, int peak, int excess, float v2max,
+                   float a2max) {
+  const int grow_at = c.pci_grow_iters > 0 ? c.pci_grow_iters : c.it_min;
+  const int shrink_at = c.pci_shrink_iters > 0 ? c.pci_shrink_iters : c.it_min;
+  const double hi = c.pci_dt_max > 0 ? c.pci_dt_max : 4.0 * c.dt_base;
+  double next = (excess || peak > shrink_at) ? dt * c.pci_shrink
+                                             : (peak <= grow_at ? dt * c.pci_grow : dt);
+  next = fmin(next, hi);
+  const double r = r_crit_of(c);
+  if (v2max > 0.0f) next = fmin(next, c.alpha_rts * c.beta2 * r / sqrt((double)v2max));
+  if (a2max > 0.0f) next = fmin(next, c.lambda_f * sqrt(r / sqrt((double)a2max)));
+  return fmax(next, pci_dt_lo(c));
+}
+
+void pci_set_step(rts_ctx *c, double dt) {
+  c->dt_base = dt;
+  step_params(c->cfg, c->mass, dt, c->prm);
+}
+
 // One minor step of Algorithm 2 with the density correction of Algorithm 3.
 rts_status pci_minor_step(rts_ctx *c) {
   const bool standard = c->cfg.mode != RTS_MODE_RTS;
+  const bool adapt = !standard && c->cfg.pci_adapt_dt;
   if (standard) c->pci_major_len = 1;
   if (!c->pci_ready) {
     rts_status s = pci_major_begin(c);
@@ -489,9 +548,6 @@ rts_status pci_minor_step(rts_ctx *c) {
   }
   launch_pci_integrate(p, d, cur, c->pci_major_len, st);
   if (!standard) launch_pci_demote(p, d, cur, c->pci_major_len, st);
-  // region counts after the step, read by rts_sync
-  launch_pci_errstats(p, d, cur, 0, st);
-  HIP_OK(c, hipGetLastError());
   c->pci_last[0] = iter - 1;
   c->pci_last[1] = global_iters;
   c->pci_last[2] = resets;
@@ -499,7 +555,10 @@ rts_status pci_minor_step(rts_ctx *c) {
   c->pci_errmax = errmax;
   c->pci_avg = avg;
   c->pci_iters_total += iter - 1;
-  c->pci_time += c->dt_base;
+  if (iter - 1 > c->pci_peak) c->pci_peak = iter - 1;
+  const double dt = c->dt_base;
+  c->dt_last = dt;
+  c->pci_time += dt;
   c->pci_steps += 1;
   c->pci_minor_in_major += 1;
   int early = 0;
@@ -508,9 +567,19 @@ rts_status pci_minor_step(rts_ctx *c) {
     if (c->pci_minor_in_major < c->pci_major_len) early = 1;
   }
   c->pci_last[4] = early;
-  if (c->pci_minor_in_major >= c->pci_major_len || early) {
+  const bool ends = c->pci_minor_in_major >= c->pci_major_len || early;
+  // region counts after the step, read by rts_sync; at the end of a major
+  // step of the adaptive base step also the speed and acceleration maxima
+  launch_pci_errstats(p, d, cur, 0, st, adapt && ends);
+  HIP_OK(c, hipGetLastError());
+  if (ends) {
     c->pci_minor_in_major = 0;
     c->pci_ready = false;
+    if (adapt) {
+      rts_status s = pci_read(c, &h);
+      if (s) return s;
+      pci_set_step(c, pci_next_dt(c->cfg, dt, c->pci_peak, c->pci_excess, h.v2max, h.a2max));
+    }
     if (!standard) {
       const int shortened = c->cfg.n_minor < 2 ? c->cfg.n_minor : 2;
       if (c->pci_excess) {
@@ -521,6 +590,21 @@ rts_status pci_minor_step(rts_ctx *c) {
         c->pci_clean = 0;
       }
     }
+  }
+  // a correction that did not converge: back to the state the major step
+  // started from (still in the sort's source buffers), restarted with half
+  // the step
+  const double lo = pci_dt_lo(c->cfg);
+  if (adapt && errmax >= eta && dt > lo) {
+    c->cur = cur ^ 1;
+    c->pci_time = c->snap_time;
+    c->pci_steps = c->snap_steps;
+    c->pci_major_len = c->snap_major_len;
+    c->pci_clean = c->snap_clean;
+    c->pci_minor_in_major = 0;
+    c->pci_ready = false;
+    c->pci_rollbacks += 1;
+    pci_set_step(c, fmax(0.5 * dt, lo));
   }
   return RTS_OK;
 }
@@ -573,6 +657,13 @@ void rts_default_config(rts_config *c) {
   c->eta_T = 0.0025;
   c->delta = 0.0;
   c->r_list = 0.0;
+  c->pci_adapt_dt = 0;
+  c->pci_grow_iters = 0;
+  c->pci_shrink_iters = 0;
+  c->pci_dt_min = 0.0;
+  c->pci_dt_max = 0.0;
+  c->pci_grow = 1.02;
+  c->pci_shrink = 0.95;
 }
 
 const char *rts_status_string(rts_status s) {
@@ -707,6 +798,8 @@ rts_status rts_set_state(rts_ctx *c, const float *d_pos, const float *d_vel, int
   c->pci_steps = 0;
   c->pci_iters_total = 0;
   c->pci_time = 0.0;
+  c->pci_rollbacks = 0;
+  if (c->cfg.solver == RTS_PCISPH) pci_set_step(c, c->cfg.dt_base);
   launch_reset_scalars(c->d.S, c->stream);
   launch_set_state(c->prm, c->d, 0, d_pos, d_vel, c->stream);
   HIP_OK(c, hipGetLastError());
@@ -760,7 +853,9 @@ rts_status rts_advance(rts_ctx *c, int32_t n_steps) {
   if (c->poisoned) return fail(c, RTS_E_STATE, "state failed; set or load a state first");
   if (n_steps == 0) return RTS_OK;
   if (c->cfg.solver == RTS_PCISPH) {
-    for (int32_t k = 0; k < n_steps; ++k) {
+    // accepted minor steps: a rolled-back major step takes pci_steps back
+    const int64_t target = c->pci_steps + n_steps;
+    while (c->pci_steps < target) {
       rts_status s = pci_minor_step(c);
       if (s) return s;
     }
@@ -860,7 +955,9 @@ rts_status rts_sync(rts_ctx *c, rts_stats *out) {
       c->pci_last[5] = h.ncomp_first;
       out->step = c->pci_steps;
       out->time = c->pci_time;
-      out->dt_last = c->dt_base;
+      out->dt_last = c->pci_steps > 0 ? c->dt_last : c->dt_base;
+      out->pci_dt_next = c->dt_base;
+      out->pci_rollbacks = c->pci_rollbacks;
       out->err_max_last = (float)c->pci_errmax;
       for (int l = 0; l < RTS_MAX_LEVELS; ++l) out->level_hist[l] = l < 4 ? c->pci_hist[l] : 0;
       out->pci_iters = c->pci_last[0];

@@ -71,12 +71,14 @@ struct DevPci {
   int32_t hist[4];       // particles per region
   int32_t ncomp;         // particles with the compute flag
   int32_t ncomp_first;   // the same at the first iteration of the minor step (lists built)
+  float v2max, a2max;    // max |v|^2 and |a|^2 after the step (when asked for)
 };
 struct PciPart {
   float errmax;
   int32_t ncomp;
   double sum;
   int32_t hist[4];
+  float v2max, a2max;
 };
 constexpr int kPciStatBlocks = 512;
 
@@ -221,7 +223,7 @@ void launch_pci_mark_se(const DevParams &p, const DevPtrs &d, hipStream_t st);
 void launch_pci_force(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
                       hipStream_t st);
 void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, int first,
-                         hipStream_t st);
+                         hipStream_t st, bool motion = false);
 void launch_pci_pressure_copy(const DevParams &p, const DevPtrs &d, int to_backup,
                               hipStream_t st);
 void launch_pci_integrate(const DevParams &p, const DevPtrs &d, int cur, int major_len,

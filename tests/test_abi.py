@@ -75,9 +75,11 @@ def test_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     checks = {
-        "rts_config": (_rts.RtsConfig, ["n_minor", "nbr_cap", "two_ring_levels", "eta", "r_list",
-                                        "beta_ratio"]),
-        "rts_stats": (_rts.RtsStats, ["bad_index", "pci_iters", "pci_errmax", "pci_iters_total"]),
+        "rts_config": (_rts.RtsConfig, ["n_minor", "nbr_cap", "two_ring_levels", "pci_adapt_dt",
+                                        "eta", "r_list", "beta_ratio", "pci_grow_iters", "pci_shrink_iters",
+                                        "pci_dt_min", "pci_shrink"]),
+        "rts_stats": (_rts.RtsStats, ["bad_index", "pci_iters", "pci_errmax", "pci_iters_total",
+                                      "pci_rollbacks", "pci_dt_next"]),
         "rts_tune": (_rts.RtsTune, ["candidates", "ms_per_step"]),
         "rts_diff_desc": (_rts.RtsDiffDesc, ["list_cap", "dt", "alpha"]),
     }
@@ -108,3 +110,18 @@ def test_invalid_pcisph_configurations_are_rejected(field, value):
     setattr(cfg, field, value)
     with pytest.raises(_rts.RtsError):
         _rts.workspace_size(cfg, sc.n, sc.nw)
+
+
+@pytest.mark.parametrize("over", [dict(pci_grow=0.9), dict(pci_shrink=0.0),
+                                  dict(pci_shrink=1.5), dict(delta=1.0),
+                                  dict(pci_dt_min=2e-3), dict(pci_dt_max=5e-4),
+                                  dict(pci_adapt_dt=2)])
+def test_invalid_adaptive_step_configurations_are_rejected(over):
+    sc = scenes.pcisph_dam_break_small(dt_base=1e-3)
+    kw = dict(pci_adapt_dt=1)
+    kw.update(over)
+    cfg = _rts.config_from_params(sc.params, **kw)
+    with pytest.raises(_rts.RtsError):
+        _rts.workspace_size(cfg, sc.n, sc.nw)
+    ok = _rts.config_from_params(sc.params, pci_adapt_dt=1)
+    assert _rts.workspace_size(ok, sc.n, sc.nw) > 0

@@ -53,27 +53,35 @@ def test_next_step_respects_the_displacement_and_acceleration_bounds(seed):
 
 
 def test_effort_steers_the_step():
-    """An overrun shrinks, an easy major step grows, anything between holds
+    """By default a major step whose minor steps all converged in it_min
+    iterations grows the step, one needing more (or overrunning the global
+    limit) shrinks it; with a band between the two thresholds the step holds
     (with no speed or acceleration to cap it)."""
     c = O.cfg_from_params(scenes.pcisph_dam_break_small().params, pci_adapt_dt=1)
     dt = c.dt_base
-    assert O.pci_next_dt(c, dt, 9, 1, 0.0, 0.0) == pytest.approx(0.7 * dt, rel=1e-15)
-    assert O.pci_next_dt(c, dt, 4, 0, 0.0, 0.0) == pytest.approx(1.1 * dt, rel=1e-15)
-    assert O.pci_next_dt(c, dt, 5, 0, 0.0, 0.0) == dt
+    assert O.pci_next_dt(c, dt, 3, 1, 0.0, 0.0) == pytest.approx(0.95 * dt, rel=1e-15)
+    assert O.pci_next_dt(c, dt, 4, 0, 0.0, 0.0) == pytest.approx(0.95 * dt, rel=1e-15)
+    assert O.pci_next_dt(c, dt, 3, 0, 0.0, 0.0) == pytest.approx(1.02 * dt, rel=1e-15)
+    band = O.cfg_from_params(scenes.pcisph_dam_break_small().params, pci_adapt_dt=1,
+                             pci_shrink_iters=5)
+    assert O.pci_next_dt(band, dt, 4, 0, 0.0, 0.0) == dt
+    assert O.pci_next_dt(band, dt, 5, 0, 0.0, 0.0) == dt
+    assert O.pci_next_dt(band, dt, 6, 0, 0.0, 0.0) == pytest.approx(0.95 * dt, rel=1e-15)
     assert O.pci_next_dt(c, 0.26 * dt, 9, 1, 0.0, 0.0) == 0.25 * dt     # floor
-    assert O.pci_next_dt(c, 3.9 * dt, 3, 0, 0.0, 0.0) == 4.0 * dt       # ceiling
+    assert O.pci_next_dt(c, 3.95 * dt, 3, 0, 0.0, 0.0) == 4.0 * dt      # ceiling
+    assert O.pci_next_dt(c, dt, 3, 0, 0.0, 0.0) == O.pci_next_dt(c, dt, 2, 0, 0.0, 0.0)
 
 
 def test_calm_start_grows_geometrically_at_major_boundaries():
     """The first 40 ms of the small double dam break converge in the minimum
-    three iterations, so major step k runs at dt0 1.1^k, the same for all
+    three iterations, so major step k runs at dt0 1.02^k, the same for all
     its minor steps, and simulated time is the sum of the steps."""
     sc = scenes.pcisph_dam_break_small(dt_base=1e-3)
     sim = run(sc, 24, pci_adapt_dt=1)
     hs = accepted(sim)
     assert len(hs) == 24 and all(h["iters"] == 3 for h in hs)
     for k, h in enumerate(hs):
-        assert h["dt"] == pytest.approx(1e-3 * 1.1 ** (k // 4), rel=1e-12), k
+        assert h["dt"] == pytest.approx(1e-3 * 1.02 ** (k // 4), rel=1e-12), k
     assert sim.t == pytest.approx(sum(h["dt"] for h in hs), rel=1e-12)
     # the maxima the rule read at the last major end, recomputed from the state
     assert hs[-1]["minor_in_major"] == 0
@@ -108,12 +116,13 @@ def test_rule_that_cannot_act_leaves_the_fixed_step_run_unchanged():
 
 def test_rollback_lands_on_the_fixed_run_at_the_shortened_step():
     """A tolerance no correction reaches within four iterations: the first
-    major step is rolled back at dt0 and at dt0/2, then accepted at the floor
+    major step is rolled back at dt0 and at dt0/2 (each roll-back halves the
+    step), then accepted at the floor
     dt0/4; the run is then the fixed-step run at dt0/4 bit for bit, so the
     roll-back restored every particle array and counter it needs."""
     sc = scenes.pcisph_dam_break_small(dt_base=1e-3)
     strict = dict(eta=1e-7, it_max=4)
-    a = run(sc, 8, pci_adapt_dt=1, pci_grow=1.0, pci_shrink=0.5, pci_dt_min=2.5e-4, **strict)
+    a = run(sc, 8, pci_adapt_dt=1, pci_grow=1.0, pci_dt_min=2.5e-4, **strict)
     assert [h["rollback"] for h in a.history[:3]] == [1, 1, 0]
     assert a.state.rollbacks == 2
     b = run(scenes.pcisph_dam_break_small(dt_base=2.5e-4), 8, **strict)

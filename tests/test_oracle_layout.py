@@ -17,7 +17,7 @@ def test_oracle_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     checks = {
         "orc_cfg": (oracle.OrcCfg, ["two_ring_levels", "eta", "r_list", "adapt_dt", "grow_iters",
-                                    "dt_min", "shrink"]),
+                                    "shrink_iters", "dt_min", "shrink"]),
         "orc_pci_state": (oracle.OrcPciState, ["major_len", "minor_steps", "hist", "dt_cur",
                                                "peak_iters", "last_a2max", "snap", "snap_t",
                                                "snap_clean", "last_rollback"]),
