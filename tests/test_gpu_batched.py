@@ -76,3 +76,50 @@ def test_autotune_keeps_results_bitwise():
     tuned.sync()
     a, b = ref.state(), tuned.state()
     assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+
+
+def test_full_size_batch_structure_lists_and_sampled_density():
+    """The 64-scene batch the benchmark times (2.78M particles), after the
+    autotuner, as one particle set: keys, order, block starts, levels and
+    flags bit-exact over every particle; lists of 1,000 sampled active
+    particles bit-exact and inside their scene; their densities within 1e-5."""
+    from parity import expected_structure, gpu_lists, oracle_density, oracle_lists, \
+        snapshot_after_step
+    import oracle
+    sc = scenes.batched_dam_breaks()
+    print(f"batch: {len(sc.parts)} scenes, {sc.n} particles", flush=True)
+    sim = Simulation(sc)
+    sim.autotune(steps=3)
+    sim.advance(20)
+    sim.sync()
+    sim.advance(1)
+    sim.sync()
+    snap = snapshot_after_step(sim)
+    cfg = oracle.cfg_from_params(sc.params)
+    exp = expected_structure(cfg, snap)
+    assert np.array_equal(snap["PERM"], exp["perm"])
+    assert np.array_equal(snap["KEY"], exp["keys"])
+    assert np.array_equal(snap["CELL_START"], exp["cell_start"])
+    assert np.array_equal(snap["BLK_LEVEL"], exp["lvl"])
+    from paper_2009_14514_amd.sim import decode_meta
+    level, comp, _, _ = decode_meta(snap["META"])
+    assert np.array_equal(comp, exp["compute"]) and np.array_equal(level, exp["level"])
+    active = np.nonzero(comp)[0]
+    rng = np.random.default_rng(3)
+    sample = np.sort(rng.choice(active, size=min(1000, active.size), replace=False))
+    want = np.zeros(sc.n, np.uint8)
+    want[sample] = 1
+    nbr, nnb = oracle_lists(cfg, snap, want)
+    got, _ = gpu_lists(sim, snap, sample)
+    owner = np.zeros(sc.n, np.int32)
+    for k, (a, b) in enumerate(sc.parts):
+        owner[a:b] = k
+    ids = snap["ID"]
+    for r, i in enumerate(sample):
+        assert np.array_equal(got[r], nbr[i, :nnb[i]]), f"list of particle {i}"
+        fl = got[r][got[r] < 0x80000000]
+        assert np.all(owner[ids[fl]] == owner[ids[i]])
+    rho_o, _ = oracle_density(cfg, snap, want)
+    rel = np.abs(snap["POS"][sample, 3] - rho_o[sample]) / rho_o[sample]
+    assert rel.max() <= 1e-5
+    sim.close()
