@@ -396,8 +396,13 @@ void enqueue_step(rts_ctx *c, int cur, hipStream_t st) {
   launch_rmin_flags(p, d, nx, 1, c->grid_wave, st);
   launch_search_density(p, d, nx, c->grid_search, st);
   launch_force(p, d, nx, c->grid_force, st);
-  launch_step_stats(p, d, st);
-  launch_correct_predict(p, d, nx, st);
+  if (p.mode == RTS_MODE_GLOBAL_ADAPTIVE) {
+    // the step length comes from this step's statistics
+    launch_step_stats(p, d, st);
+    launch_correct_predict(p, d, nx, st);
+  } else {
+    launch_stats_correct_predict(p, d, nx, st);
+  }
 }
 
 rts_status build_graphs(rts_ctx *c) {

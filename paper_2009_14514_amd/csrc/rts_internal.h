@@ -201,6 +201,8 @@ void launch_step_stats(const DevParams &p, const DevPtrs &d, hipStream_t st);
 void launch_debug_lists(const DevParams &p, const DevPtrs &d, int cur, uint32_t *out, uint32_t *out_n,
                         hipStream_t st);
 void launch_correct_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+void launch_stats_correct_predict(const DevParams &p, const DevPtrs &d, int cur,
+                                  hipStream_t st);
 void launch_set_state(const DevParams &p, const DevPtrs &d, int cur, const float *pos,
                       const float *vel, hipStream_t st);
 void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos, float *vel,

@@ -942,19 +942,20 @@ __device__ inline void part_add(StatPart &t, const StatPart &u) {
   for (int k = 0; k < kMaxLevels; ++k) t.hist[k] += u.hist[k];
 }
 
-__global__ void __launch_bounds__(256) k_step_stats(DevParams p, const uint32_t *__restrict__ occ,
-                                                   const uint4 *__restrict__ blku,
-                                                   const float *__restrict__ blkerr,
-                                                   const float *__restrict__ blkamax,
-                                                   const uint8_t *__restrict__ lvl,
-                                                   StatPart *__restrict__ part, DevCtrl *ctrl,
-                                                   DevScalars *S) {
+// Workgroup `wg` of `nwg` (256 threads each); every one of the nwg must run it.
+__device__ inline void step_stats_body(const DevParams &p, const uint32_t *__restrict__ occ,
+                                       const uint4 *__restrict__ blku,
+                                       const float *__restrict__ blkerr,
+                                       const float *__restrict__ blkamax,
+                                       const uint8_t *__restrict__ lvl,
+                                       StatPart *__restrict__ part, DevCtrl *ctrl, DevScalars *S,
+                                       uint32_t wg, uint32_t nwg) {
   __shared__ StatPart s_w[4];
   __shared__ uint32_t s_last;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t nocc = S->n_occ;
   StatPart t = {};
-  for (uint32_t q = blockIdx.x * blockDim.x + tid; q < nocc; q += gridDim.x * blockDim.x) {
+  for (uint32_t q = wg * 256u + (uint32_t)tid; q < nocc; q += nwg * 256u) {
     const uint32_t b = occ[q];
     const uint4 u = blku[b];
     t.act += u.x;
@@ -983,16 +984,16 @@ __global__ void __launch_bounds__(256) k_step_stats(DevParams p, const uint32_t 
   if (tid == 0) {
     StatPart w = s_w[0];
     for (int k = 1; k < 4; ++k) part_add(w, s_w[k]);
-    part[blockIdx.x] = w;
+    part[wg] = w;
     __threadfence();
-    s_last = atomicAdd(&ctrl->stats_ticket, 1u) == gridDim.x - 1 ? 1u : 0u;
+    s_last = atomicAdd(&ctrl->stats_ticket, 1u) == nwg - 1u ? 1u : 0u;
   }
   __syncthreads();
   if (!s_last || wave != 0) return;
   __threadfence();
   // one wave folds the partials: lane g reads partial g
   StatPart a = {};
-  for (unsigned g = (unsigned)lane; g < gridDim.x; g += 64) part_add(a, part[g]);
+  for (unsigned g = (unsigned)lane; g < nwg; g += 64) part_add(a, part[g]);
   for (int o = 32; o > 0; o >>= 1) {
     a.act += __shfl_xor(a.act, o, 64);
     a.inter += __shfl_xor(a.inter, o, 64);
@@ -1029,26 +1030,33 @@ __global__ void __launch_bounds__(256) k_step_stats(DevParams p, const uint32_t 
   S->step += 1;
 }
 
+__global__ void __launch_bounds__(256) k_step_stats(DevParams p, const uint32_t *__restrict__ occ,
+                                                   const uint4 *__restrict__ blku,
+                                                   const float *__restrict__ blkerr,
+                                                   const float *__restrict__ blkamax,
+                                                   const uint8_t *__restrict__ lvl,
+                                                   StatPart *__restrict__ part, DevCtrl *ctrl,
+                                                   DevScalars *S) {
+  step_stats_body(p, occ, blku, blkerr, blkamax, lvl, part, ctrl, S, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // corrector (active) + predictor (all)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_correct_predict(DevParams p, float4 *__restrict__ P,
-                                                        float4 *__restrict__ V,
-                                                        float4 *__restrict__ A,
-                                                        uint32_t *__restrict__ M,
-                                                        const float4 *__restrict__ anew,
-                                                        const DevScalars *__restrict__ S) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  const float dt = (float)S->dt_next;
+// Particle i with step dt; dt_prev is the last step's length (global
+// adaptive comparator only).
+__device__ inline void correct_predict_one(const DevParams &p, float4 *__restrict__ P,
+                                           float4 *__restrict__ V, float4 *__restrict__ A,
+                                           uint32_t *__restrict__ M,
+                                           const float4 *__restrict__ anew, int i, float dt,
+                                           float dt_prev) {
   float4 x = P[i], v = V[i], a = A[i];
   const uint32_t m = M[i];
   uint32_t age = meta_age(m);
   if (meta_compute(m)) {
     const float4 an = anew[i];
     if (p.serna_correct) {
-      const float dtau =
-          p.mode == RTS_MODE_GLOBAL_ADAPTIVE ? (float)S->dt_prev : (float)age * p.dt_base;
+      const float dtau = p.mode == RTS_MODE_GLOBAL_ADAPTIVE ? dt_prev : (float)age * p.dt_base;
       const float cx = dtau * dtau * (1.0f / 6.0f), cv = dtau * 0.5f;
       const float dax = an.x - a.x, day = an.y - a.y, daz = an.z - a.z;
       x.x += dax * cx; x.y += day * cx; x.z += daz * cx;
@@ -1069,6 +1077,32 @@ __global__ void __launch_bounds__(256) k_correct_predict(DevParams p, float4 *__
   V[i] = v;
   A[i] = a;
   M[i] = meta_pack(meta_level(m), meta_compute(m), age, meta_validity(m));
+}
+
+__global__ void __launch_bounds__(256) k_correct_predict(DevParams p, float4 *__restrict__ P,
+                                                        float4 *__restrict__ V,
+                                                        float4 *__restrict__ A,
+                                                        uint32_t *__restrict__ M,
+                                                        const float4 *__restrict__ anew,
+                                                        const DevScalars *__restrict__ S) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  correct_predict_one(p, P, V, A, M, anew, i, (float)S->dt_next, (float)S->dt_prev);
+}
+
+// Fixed base step (RTS, global fixed): the corrector-predictor does not wait
+// for the statistics, so one launch carries both; workgroups below
+// kStatBlocks also take their share of the statistics.
+__global__ void __launch_bounds__(256) k_stats_correct_predict(
+    DevParams p, const uint32_t *__restrict__ occ, const uint4 *__restrict__ blku,
+    const float *__restrict__ blkerr, const float *__restrict__ blkamax,
+    const uint8_t *__restrict__ lvl, StatPart *__restrict__ part, DevCtrl *ctrl, DevScalars *S,
+    float4 *__restrict__ P, float4 *__restrict__ V, float4 *__restrict__ A,
+    uint32_t *__restrict__ M, const float4 *__restrict__ anew) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < p.n) correct_predict_one(p, P, V, A, M, anew, i, p.dt_base, p.dt_base);
+  if (blockIdx.x < (unsigned)kStatBlocks)
+    step_stats_body(p, occ, blku, blkerr, blkamax, lvl, part, ctrl, S, blockIdx.x, kStatBlocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1236,6 +1270,14 @@ void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipSt
 void launch_step_stats(const DevParams &p, const DevPtrs &d, hipStream_t st) {
   hipLaunchKernelGGL(k_step_stats, dim3(kStatBlocks), dim3(256), 0, st, p, d.OCC, d.BLKU,
                      d.BLKERR, d.BLKAMAX, d.LVL, d.PART, d.CTRL, d.S);
+}
+void launch_stats_correct_predict(const DevParams &p, const DevPtrs &d, int cur,
+                                  hipStream_t st) {
+  const unsigned nb = blocks_for(p.n, 256);
+  const unsigned grid = nb > (unsigned)kStatBlocks ? nb : (unsigned)kStatBlocks;
+  hipLaunchKernelGGL(k_stats_correct_predict, dim3(grid), dim3(256), 0, st, p, d.OCC, d.BLKU,
+                     d.BLKERR, d.BLKAMAX, d.LVL, d.PART, d.CTRL, d.S, d.P[cur], d.V[cur],
+                     d.A[cur], d.M[cur], d.ANEW);
 }
 void launch_correct_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
   if (p.n == 0) return;
