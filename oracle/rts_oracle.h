@@ -203,7 +203,9 @@ void orc_pci_nonpressure(const orc_cfg *c, int32_t n, const double *x, const dou
                          const double *wx, const uint32_t *nbr, const int32_t *nnb,
                          const uint8_t *which, double *fvg);
 /* Schedule of Figure "iterations": regions (bit n-1 for region n) that take
- * row `row` (1..3) of minor-step column `col` (0..3). */
+ * row `row` (1..3) of minor-step column `col` (0..3).  The figure is not in
+ * the text; the table meets every constraint the text states (pinned by a
+ * test), but its equality with the paper's own table is parity unpinned. */
 uint32_t orc_pci_turn(int32_t col, int32_t row);
 /* One minor step of Algorithm 2 (a major step begins when due). */
 int orc_pci_step(const orc_cfg *c, orc_pci_state *s);
@@ -211,6 +213,9 @@ int orc_pci_step(const orc_cfg *c, orc_pci_state *s);
  * it_max iterations rolls its major step back to the state it started from
  * and restarts it with half the step (not below dt_min): the
  * call then leaves minor_steps and t as they were before the major step.
+ * The paper only suggests adapting the base step; this rule is a reading,
+ * pinned against its own stated properties, and its parity with the paper
+ * is unpinned (there is no rule there to compare with).
  * Base step of the next major step (adapt_dt): dt scaled by shrink after a
  * major step that overran global_limit or had a minor step needing more than
  * shrink_iters iterations, else by grow after one whose minor steps all
