@@ -11,13 +11,30 @@
 // collects its share of every pair's partial derivatives, using that the
 // neighbour relation is symmetric and that a pair enters a_i and a_j with
 // opposite signs, so the pair's upstream gradient is abar_j - abar_i.  No
-// thread writes another particle's adjoint, so no atomics are needed and the
-// sums are in list order (deterministic).  Lists are built per block from
-// LDS-staged candidates; the pair sums run one thread per particle.
+// thread writes another particle's adjoint, so no atomics are needed.  Lists
+// are built per block from LDS-staged candidates.  The pair sums give a
+// particle kDiffSub lanes (lane s takes list entries s, s + kDiffSub, ...),
+// whose partial sums are folded in a fixed order: runs are deterministic.
 #include "rts_device.h"
 #include "xcd.h"
 
 namespace rts {
+
+// lanes per particle in the pair sums: one lane per particle leaves too few
+// waves to hide the gathers' latency at 100k particles
+constexpr int kDiffSub = 8;
+
+// the lanes of a particle: its index and this lane's rank among them
+__device__ inline int diff_particle(int &s) {
+  const uint32_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  s = (int)(t % (uint32_t)kDiffSub);
+  return (int)(t / (uint32_t)kDiffSub);
+}
+// fixed-order fold of the kDiffSub lanes' partial sums
+__device__ inline float diff_fold(float v) {
+  for (int o = 1; o < kDiffSub; o <<= 1) v += __shfl_xor(v, o, kDiffSub);
+  return v;
+}
 
 struct DiffArgs {
   float dt, B, alpha, hc0;  // step, Tait stiffness, viscosity alpha, h c0
@@ -147,19 +164,23 @@ __global__ void __launch_bounds__(kDiffListThreads) k_diff_lists_blocks(
 }
 
 // Density by summation (compensated) and the unclamped Tait pressure, both
-// from the deviation d = rho/rho0 - 1 formed before rounding to rho.
+// from the deviation d = rho/rho0 - 1 formed before rounding to rho.  The
+// force pass gathers two float4 per neighbour: (x, P) with P = p / rho^2 and
+// (v, rho), packed here.
 __global__ void __launch_bounds__(256) k_diff_density(
-    DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ L,
-    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float *__restrict__ rho,
-    float *__restrict__ prs, float *__restrict__ pq) {
-  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-  if (i >= a.n) return;
+    DevParams p, DiffArgs a, const float4 *__restrict__ X, const float4 *__restrict__ V,
+    const uint32_t *__restrict__ L, const uint32_t *__restrict__ nn,
+    const float4 *__restrict__ WP, float *__restrict__ rho, float *__restrict__ prs,
+    float4 *__restrict__ XP, float4 *__restrict__ VR) {
+  int s;
+  const int i = diff_particle(s);
+  if (i >= a.n) return;  // the particle's lanes leave together
   const float4 xi = X[i];
   const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
   float sum = 0.0f, comp = 0.0f;
 #pragma unroll 4
-  for (uint32_t k = 0; k < cnt; ++k) {
+  for (uint32_t k = (uint32_t)s; k < cnt; k += kDiffSub) {
     const uint32_t j = row[(size_t)k * (size_t)a.n];
     const float4 q = (j & kWallBit) ? WP[j & ~kWallBit] : X[j];
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
@@ -169,27 +190,34 @@ __global__ void __launch_bounds__(256) k_diff_density(
     comp = (t - sum) - y;
     sum = t;
   }
+  for (int o = 1; o < kDiffSub; o <<= 1) {
+    const float s2 = __shfl_xor(sum, o, kDiffSub), c2 = __shfl_xor(comp, o, kDiffSub);
+    kahan_merge(sum, comp, s2, c2);
+  }
+  if (s != 0) return;
   const float dev = p.kms * ((sum - p.c_hi) - (comp + p.c_lo));
   const float r = p.rho0 + p.rho0 * dev, pr = a.B * pow7m1(dev);
   rho[i] = r;
   prs[i] = pr;
-  pq[i] = pr / (r * r);  // P = p / rho^2, which the force pass gathers
+  const float4 vi = V[i];
+  XP[i] = make_float4(xi.x, xi.y, xi.z, pr / (r * r));
+  VR[i] = make_float4(vi.x, vi.y, vi.z, r);
 }
 
 __global__ void __launch_bounds__(256) k_diff_force_euler(
-    DevParams p, DiffArgs a, const float4 *__restrict__ X, const float4 *__restrict__ V,
-    const float *__restrict__ rho, const float *__restrict__ pq, const uint32_t *__restrict__ L,
-    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float4 *__restrict__ Xn,
-    float4 *__restrict__ Vn) {
-  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-  if (i >= a.n) return;
-  const float4 xi = X[i], vi = V[i];
-  const float ri = rho[i], Pi = pq[i];
+    DevParams p, DiffArgs a, const float4 *__restrict__ XP, const float4 *__restrict__ VR,
+    const uint32_t *__restrict__ L, const uint32_t *__restrict__ nn,
+    const float4 *__restrict__ WP, float4 *__restrict__ Xn, float4 *__restrict__ Vn) {
+  int s;
+  const int i = diff_particle(s);
+  if (i >= a.n) return;  // the particle's lanes leave together
+  const float4 xi = XP[i], vi = VR[i];
+  const float ri = vi.w, Pi = xi.w;
   const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
-  float ax = p.g[0], ay = p.g[1], az = p.g[2];
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
 #pragma unroll 4
-  for (uint32_t k = 0; k < cnt; ++k) {
+  for (uint32_t k = (uint32_t)s; k < cnt; k += kDiffSub) {
     const uint32_t j = row[(size_t)k * (size_t)a.n];
     const bool wall = (j & kWallBit) != 0u;
     float4 q, u = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -199,11 +227,10 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
       coef = 2.0f * Pi;
       nu = a.alpha * a.hc0 / ri;
     } else {
-      q = X[j];
-      u = V[j];
-      const float rj = rho[j];
-      coef = Pi + pq[j];
-      nu = 2.0f * a.alpha * a.hc0 / (ri + rj);
+      q = XP[j];
+      u = VR[j];
+      coef = Pi + q.w;
+      nu = 2.0f * a.alpha * a.hc0 / (ri + u.w);
     }
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
@@ -217,16 +244,28 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
     ay -= t * dy;
     az -= t * dz;
   }
+  ax = p.g[0] + diff_fold(ax);
+  ay = p.g[1] + diff_fold(ay);
+  az = p.g[2] + diff_fold(az);
+  if (s != 0) return;
   const float vx = vi.x + a.dt * ax, vy = vi.y + a.dt * ay, vz = vi.z + a.dt * az;
   Vn[i] = make_float4(vx, vy, vz, 0.0f);
   Xn[i] = make_float4(xi.x + a.dt * vx, xi.y + a.dt * vy, xi.z + a.dt * vz, 0.0f);
 }
 
-// x' = x + dt v', v' = v + dt a: vbar <- vbar' + dt xbar', abar = dt vbar (xbar unchanged)
+// x' = x + dt v', v' = v + dt a: vbar <- vbar' + dt xbar', abar = dt vbar (xbar
+// unchanged).  Also packs the frame as (x, rho) and (v, p) for the adjoint
+// force pass, which then gathers two float4 per neighbour besides abar.
 __global__ void k_diff_adj_euler(DiffArgs a, const float4 *__restrict__ XB, float4 *__restrict__ VB,
-                                 float4 *__restrict__ AB) {
+                                 float4 *__restrict__ AB, const float4 *__restrict__ X,
+                                 const float4 *__restrict__ V, const float *__restrict__ rho,
+                                 const float *__restrict__ prs, float4 *__restrict__ XR,
+                                 float4 *__restrict__ VP) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
+  const float4 x = X[i], v = V[i];
+  XR[i] = make_float4(x.x, x.y, x.z, rho[i]);
+  VP[i] = make_float4(v.x, v.y, v.z, prs[i]);
   const float4 xb = XB[i];
   float4 vb = VB[i];
   vb.x += a.dt * xb.x;
@@ -237,16 +276,19 @@ __global__ void k_diff_adj_euler(DiffArgs a, const float4 *__restrict__ XB, floa
 }
 
 // Adjoint of the forces, the pressure p / rho^2 and the equation of state.
+// The frame comes packed as (x, rho), (v, p); rbar leaves packed with x as
+// (x, rbar) for the density adjoint.
 __global__ void __launch_bounds__(256) k_diff_adj_force(
-    DevParams p, DiffArgs a, const float4 *__restrict__ X, const float4 *__restrict__ V,
-    const float *__restrict__ rho, const float *__restrict__ prs, const uint32_t *__restrict__ L,
-    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, const float4 *__restrict__ AB,
-    float4 *__restrict__ XB, float4 *__restrict__ VB, float *__restrict__ RB,
-    double *__restrict__ BB, double *__restrict__ AA) {
-  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-  if (i >= a.n) return;
-  const float4 xi = X[i], vi = V[i], abi = AB[i];
-  const float ri = rho[i], pi = prs[i], Pi = pi / (ri * ri);
+    DevParams p, DiffArgs a, const float4 *__restrict__ XR, const float4 *__restrict__ VP,
+    const uint32_t *__restrict__ L, const uint32_t *__restrict__ nn,
+    const float4 *__restrict__ WP, const float4 *__restrict__ AB, float4 *__restrict__ XB,
+    float4 *__restrict__ VB, float4 *__restrict__ XRB, double *__restrict__ BB,
+    double *__restrict__ AA) {
+  int sl;
+  const int i = diff_particle(sl);
+  if (i >= a.n) return;  // the particle's lanes leave together
+  const float4 xi = XR[i], vi = VP[i], abi = AB[i];
+  const float ri = xi.w, pi = vi.w, Pi = pi / (ri * ri);
   const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
   const float m = p.mass, e = p.visc_eps_h2;
@@ -254,7 +296,7 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
   float gxx = 0.0f, gxy = 0.0f, gxz = 0.0f, gvx = 0.0f, gvy = 0.0f, gvz = 0.0f;
   float Pb = 0.0f, rb = 0.0f, alb = 0.0f;
 #pragma unroll 4
-  for (uint32_t k = 0; k < cnt; ++k) {
+  for (uint32_t k = (uint32_t)sl; k < cnt; k += kDiffSub) {
     const uint32_t j = row[(size_t)k * (size_t)a.n];
     const bool wall = (j & kWallBit) != 0u;
     float4 q, vj = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -267,10 +309,10 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
       uy = -abi.y;
       uz = -abi.z;
     } else {
-      q = X[j];
-      vj = V[j];
-      rj = rho[j];
-      coef = Pi + prs[j] / (rj * rj);
+      q = XR[j];
+      vj = VP[j];
+      rj = q.w;
+      coef = Pi + vj.w / (rj * rj);
       nu = 2.0f * a.alpha * a.hc0 / (ri + rj);
       const float4 abj = AB[j];
       ux = abj.x - abi.x;
@@ -315,6 +357,16 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
     }
     Pb += (wall ? 2.0f : 1.0f) * m * Gu;
   }
+  gxx = diff_fold(gxx);
+  gxy = diff_fold(gxy);
+  gxz = diff_fold(gxz);
+  gvx = diff_fold(gvx);
+  gvy = diff_fold(gvy);
+  gvz = diff_fold(gvz);
+  Pb = diff_fold(Pb);
+  rb = diff_fold(rb);
+  alb = diff_fold(alb);
+  if (sl != 0) return;
   // P = p / rho^2 ; p = B ((1 + d)^7 - 1), d = rho / rho0 - 1
   const float dev = ri / p.rho0 - 1.0f;
   const float pb = Pb / (ri * ri);
@@ -330,27 +382,27 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
   vb.z += gvz;
   XB[i] = xb;
   VB[i] = vb;
-  RB[i] = rb;
+  XRB[i] = make_float4(xi.x, xi.y, xi.z, rb);
 }
 
 // Adjoint of the density summation: xbar_i += sum_j m gradW_ij (rbar_i + rbar_j).
 __global__ void __launch_bounds__(256) k_diff_adj_density(
-    DevParams p, DiffArgs a, const float4 *__restrict__ X, const uint32_t *__restrict__ L,
-    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, const float *__restrict__ RB,
-    float4 *__restrict__ XB) {
-  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
-  if (i >= a.n) return;
-  const float4 xi = X[i];
-  const float rbi = RB[i];
+    DevParams p, DiffArgs a, const float4 *__restrict__ XRB, const uint32_t *__restrict__ L,
+    const uint32_t *__restrict__ nn, const float4 *__restrict__ WP, float4 *__restrict__ XB) {
+  int s;
+  const int i = diff_particle(s);
+  if (i >= a.n) return;  // the particle's lanes leave together
+  const float4 xi = XRB[i];
+  const float rbi = xi.w;
   const uint32_t *row = L + (size_t)i;
   const uint32_t cnt = nn[i];
   float gx = 0.0f, gy = 0.0f, gz = 0.0f;
 #pragma unroll 4
-  for (uint32_t k = 0; k < cnt; ++k) {
+  for (uint32_t k = (uint32_t)s; k < cnt; k += kDiffSub) {
     const uint32_t j = row[(size_t)k * (size_t)a.n];
     const bool wall = (j & kWallBit) != 0u;
-    const float4 q = wall ? WP[j & ~kWallBit] : X[j];
-    const float rs = wall ? rbi : rbi + RB[j];
+    const float4 q = wall ? WP[j & ~kWallBit] : XRB[j];
+    const float rs = wall ? rbi : rbi + q.w;
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 > 0.0f) || r2 >= p.r2f) continue;
@@ -360,6 +412,10 @@ __global__ void __launch_bounds__(256) k_diff_adj_density(
     gy += t * dy;
     gz += t * dz;
   }
+  gx = diff_fold(gx);
+  gy = diff_fold(gy);
+  gz = diff_fold(gz);
+  if (s != 0) return;
   float4 xb = XB[i];
   xb.x += gx;
   xb.y += gy;
@@ -447,8 +503,8 @@ void launch_diff_zero(int n, float4 *a, double *b, double *c, hipStream_t st) {
 // Lists, density and pressure of the state X (caller order): the sort of
 // the WCSPH path supplies the canonical block order.
 void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, float B,
-                       const float4 *X, uint32_t *L, uint32_t *nn, float *rho, float *prs, float *pq,
-                       int grid_wave, hipStream_t st) {
+                       const float4 *X, const float4 *V, uint32_t *L, uint32_t *nn, float *rho,
+                       float *prs, float4 *XP, float4 *VR, int grid_wave, hipStream_t st) {
   const DiffArgs a = dargs(n, cap, 0.0f, B, 0.0f, 0.0f);
   if (n > 0)
     hipLaunchKernelGGL(k_diff_copy_in, dim3(dgrid(n)), dim3(256), 0, st, a, X, d.P[0], d.V[0],
@@ -460,30 +516,31 @@ void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, flo
   if (n == 0) return;
   hipLaunchKernelGGL(k_diff_lists_blocks, dim3(1024), dim3(kDiffListThreads), 0, st, p, a,
                      d.P[1], d.PERM, d.OCC, d.CELL_START, d.WP, d.WCELL_START, L, nn, d.S);
-  hipLaunchKernelGGL(k_diff_density, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, L, nn, d.WP, rho,
-                     prs, pq);
+  hipLaunchKernelGGL(k_diff_density, dim3(dgrid((int64_t)n * kDiffSub)), dim3(256), 0, st, p, a, X, V, L, nn, d.WP,
+                     rho, prs, XP, VR);
 }
 void launch_diff_force_euler(const DevParams &p, const DevPtrs &d, int n, int cap, float dt,
-                             float alpha, float hc0, const float4 *X, const float4 *V,
-                             const float *rho, const float *pq, const uint32_t *L,
-                             const uint32_t *nn, float4 *Xn, float4 *Vn, hipStream_t st) {
+                             float alpha, float hc0, const float4 *XP, const float4 *VR,
+                             const uint32_t *L, const uint32_t *nn, float4 *Xn, float4 *Vn,
+                             hipStream_t st) {
   if (n == 0) return;
   const DiffArgs a = dargs(n, cap, dt, 0.0f, alpha, hc0);
-  hipLaunchKernelGGL(k_diff_force_euler, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, V, rho, pq, L,
-                     nn, d.WP, Xn, Vn);
+  hipLaunchKernelGGL(k_diff_force_euler, dim3(dgrid((int64_t)n * kDiffSub)), dim3(256), 0, st, p, a, XP, VR, L, nn,
+                     d.WP, Xn, Vn);
 }
 void launch_diff_adjoint(const DevParams &p, const DevPtrs &d, int n, int cap, float dt, float B,
                          float alpha, float hc0, const float4 *X, const float4 *V,
                          const float *rho, const float *prs, const uint32_t *L,
-                         const uint32_t *nn, float4 *XB, float4 *VB, float4 *AB, float *RB,
-                         double *BB, double *AA, hipStream_t st) {
+                         const uint32_t *nn, float4 *XB, float4 *VB, float4 *AB, float4 *XR,
+                         float4 *VP, float4 *XRB, double *BB, double *AA, hipStream_t st) {
   if (n == 0) return;
   const DiffArgs a = dargs(n, cap, dt, B, alpha, hc0);
-  hipLaunchKernelGGL(k_diff_adj_euler, dim3(dgrid(n)), dim3(256), 0, st, a, XB, VB, AB);
-  hipLaunchKernelGGL(k_diff_adj_force, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, V, rho, prs, L,
-                     nn, d.WP, AB, XB, VB, RB, BB, AA);
-  hipLaunchKernelGGL(k_diff_adj_density, dim3(dgrid(n)), dim3(256), 0, st, p, a, X, L, nn, d.WP,
-                     RB, XB);
+  hipLaunchKernelGGL(k_diff_adj_euler, dim3(dgrid(n)), dim3(256), 0, st, a, XB, VB, AB, X, V, rho,
+                     prs, XR, VP);
+  hipLaunchKernelGGL(k_diff_adj_force, dim3(dgrid((int64_t)n * kDiffSub)), dim3(256), 0, st, p, a, XR, VP, L, nn,
+                     d.WP, AB, XB, VB, XRB, BB, AA);
+  hipLaunchKernelGGL(k_diff_adj_density, dim3(dgrid((int64_t)n * kDiffSub)), dim3(256), 0, st, p, a, XRB, L, nn,
+                     d.WP, XB);
 }
 void launch_diff_reduce(int n, const double *BB, const double *AA, double *out, hipStream_t st) {
   hipLaunchKernelGGL(k_diff_reduce, dim3(1), dim3(256), 0, st, n, BB, AA, out);

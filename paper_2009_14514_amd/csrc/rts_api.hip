@@ -1223,11 +1223,12 @@ struct DiffTape {
   float4 *CKX, *CKV;       // checkpoints, n each
   float4 *FX, *FV;         // segment frames: state at the start of each substep
   float *FR, *FP;          // density, pressure of each frame
-  float *PQ;               // p / rho^2 of the substep being advanced
+  float4 *XP, *VR;         // packed (x, p / rho^2), (v, rho) of the substep being advanced;
+                           // in the adjoint, the frame's (x, rho), (v, p)
   uint32_t *FL, *FN;       // lists and counts of each frame
   float4 *TX, *TV;         // state after the segment's last substep
   float4 *XB, *VB, *AB;    // adjoints of x, v, a
-  float *RB;               // adjoint of rho
+  float4 *XRB;             // (x, adjoint of rho) of the frame being differentiated
   double *BB, *AA;         // per-particle parameter adjoints
   double *RED;             // their sums
 };
@@ -1251,13 +1252,14 @@ size_t diff_carve(const rts_diff_desc &D, int64_t n, char *base, DiffTape *t) {
   u.FP = (float *)take(nf * nn * 4);
   u.FL = (uint32_t *)take(nf * nn * (size_t)D.list_cap * 4);
   u.FN = (uint32_t *)take(nf * nn * 4);
-  u.PQ = (float *)take(nn * 4);
+  u.XP = (float4 *)take(nn * 16);
+  u.VR = (float4 *)take(nn * 16);
   u.TX = (float4 *)take(nn * 16);
   u.TV = (float4 *)take(nn * 16);
   u.XB = (float4 *)take(nn * 16);
   u.VB = (float4 *)take(nn * 16);
   u.AB = (float4 *)take(nn * 16);
-  u.RB = (float *)take(nn * 4);
+  u.XRB = (float4 *)take(nn * 16);
   u.BB = (double *)take(nn * 8);
   u.AA = (double *)take(nn * 8);
   u.RED = (double *)take(16);
@@ -1292,15 +1294,15 @@ void diff_run_segment(rts_ctx *c, const rts_diff_desc &D, int n, const DiffTape 
     }
     uint32_t *L = t.FL + f * nn * (size_t)D.list_cap, *NN = t.FN + f * nn;
     float *R = t.FR + f * nn, *P = t.FP + f * nn;
-    launch_diff_setup(c->prm, c->d, n, D.list_cap, (float)D.B, fx, L, NN, R, P, t.PQ,
+    launch_diff_setup(c->prm, c->d, n, D.list_cap, (float)D.B, fx, fv, L, NN, R, P, t.XP, t.VR,
                       c->grid_wave, c->stream);
     // the next state never aliases the frame being read: without kept frames
     // it goes to TX / TV and is copied into frame 0 by the next substep
     const bool last = k + 1 == len;
     float4 *xn = last ? Xend : (keep ? t.FX + (f + 1) * nn : t.TX);
     float4 *vn = last ? Vend : (keep ? t.FV + (f + 1) * nn : t.TV);
-    launch_diff_force_euler(c->prm, c->d, n, D.list_cap, (float)D.dt, (float)D.alpha, hc0, fx,
-                            fv, R, t.PQ, L, NN, xn, vn, c->stream);
+    launch_diff_force_euler(c->prm, c->d, n, D.list_cap, (float)D.dt, (float)D.alpha, hc0, t.XP,
+                            t.VR, L, NN, xn, vn, c->stream);
     X = xn;
     V = vn;
   }
@@ -1386,7 +1388,7 @@ rts_status rts_diff_backward(rts_ctx *c, const rts_diff_desc *D, int64_t n,
       launch_diff_adjoint(c->prm, c->d, (int)n, D->list_cap, (float)D->dt, (float)D->B,
                           (float)D->alpha, hc0, t.FX + f * nn, t.FV + f * nn, t.FR + f * nn,
                           t.FP + f * nn, t.FL + f * nn * (size_t)D->list_cap, t.FN + f * nn,
-                          t.XB, t.VB, t.AB, t.RB, t.BB, t.AA, c->stream);
+                          t.XB, t.VB, t.AB, t.XP, t.VR, t.XRB, t.BB, t.AA, c->stream);
     }
   }
   if (d_x0_bar) launch_diff_planes_out((int)n, t.XB, d_x0_bar, c->stream);

@@ -96,6 +96,15 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
+// Combines two Kahan accumulators (true value = s - c), the rounding of the
+// sum s + s2 being carried into c.
+__device__ inline void kahan_merge(float &s, float &c, float s2, float c2) {
+  const float t = s + s2;
+  const float v = t - s;
+  const float e = (s - (t - v)) + (s2 - v);  // t + e == s + s2 exactly
+  s = t;
+  c = (c + c2) - e;
+}
 
 // ---------------------------------------------------------------------------
 // a block's 27-block candidate set, staged in LDS (search, force, the lists

@@ -239,17 +239,17 @@ void launch_diff_planes_in(int n, const float *src, float4 *dst, hipStream_t st)
 void launch_diff_planes_out(int n, const float4 *src, float *dst, hipStream_t st);
 void launch_diff_zero(int n, float4 *a, double *b, double *c, hipStream_t st);
 void launch_diff_setup(const DevParams &p, const DevPtrs &d, int n, int cap, float B,
-                       const float4 *X, uint32_t *L, uint32_t *nn, float *rho, float *prs,
-                       float *pq, int grid_wave, hipStream_t st);
+                       const float4 *X, const float4 *V, uint32_t *L, uint32_t *nn, float *rho,
+                       float *prs, float4 *XP, float4 *VR, int grid_wave, hipStream_t st);
 void launch_diff_force_euler(const DevParams &p, const DevPtrs &d, int n, int cap, float dt,
-                             float alpha, float hc0, const float4 *X, const float4 *V,
-                             const float *rho, const float *pq, const uint32_t *L,
-                             const uint32_t *nn, float4 *Xn, float4 *Vn, hipStream_t st);
+                             float alpha, float hc0, const float4 *XP, const float4 *VR,
+                             const uint32_t *L, const uint32_t *nn, float4 *Xn, float4 *Vn,
+                             hipStream_t st);
 void launch_diff_adjoint(const DevParams &p, const DevPtrs &d, int n, int cap, float dt, float B,
                          float alpha, float hc0, const float4 *X, const float4 *V,
                          const float *rho, const float *prs, const uint32_t *L,
-                         const uint32_t *nn, float4 *XB, float4 *VB, float4 *AB, float *RB,
-                         double *BB, double *AA, hipStream_t st);
+                         const uint32_t *nn, float4 *XB, float4 *VB, float4 *AB, float4 *XR,
+                         float4 *VP, float4 *XRB, double *BB, double *AA, hipStream_t st);
 void launch_diff_reduce(int n, const double *BB, const double *AA, double *out, hipStream_t st);
 
 }  // namespace rts

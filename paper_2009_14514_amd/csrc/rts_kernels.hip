@@ -450,19 +450,6 @@ __device__ inline uint32_t active_block(const DevParams &p, const uint32_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// neighbour search + density + Tait pressure, one workgroup per block
-// ---------------------------------------------------------------------------
-// Combines two Kahan accumulators (true value = s - c), the rounding of the
-// sum s + s2 being carried into c.
-__device__ inline void kahan_merge(float &s, float &c, float s2, float c2) {
-  const float t = s + s2;
-  const float v = t - s;
-  const float e = (s - (t - v)) + (s2 - v);  // t + e == s + s2 exactly
-  s = t;
-  c = (c + c2) - e;
-}
-
-// ---------------------------------------------------------------------------
 // balanced walk over a particle's neighbour bits
 // ---------------------------------------------------------------------------
 // The kSub lanes of a particle own interleaved candidates, so their hit counts
@@ -566,6 +553,9 @@ __device__ inline void walk_balanced(WordQueue &Q, uint32_t cnt, uint16_t *win, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// neighbour search + density + Tait pressure, one workgroup per block
+// ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6))) k_search_density(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, float4 *__restrict__ P, float4 *__restrict__ V,
