@@ -79,7 +79,9 @@ __global__ void k_diff_copy_in(DiffArgs a, const float4 *__restrict__ X, float4 
 // and test interleaved candidates, and a ballot of the group's hits over each
 // run of kSub consecutive candidates places them in the canonical order.  A
 // block with more candidates than LDS slots is scanned from memory by one
-// lane per particle.
+// lane per particle.  Lists are particle-major (entry k of particle i at
+// i * cap + k): a ballot's hits land in consecutive words, and the pair
+// passes' lanes of a particle read consecutive words.
 constexpr int kDiffListThreads = 512;
 __global__ void __launch_bounds__(kDiffListThreads) k_diff_lists_blocks(
     DevParams p, DiffArgs a, const float4 *__restrict__ Ps, const uint32_t *__restrict__ perm,
@@ -124,7 +126,7 @@ __global__ void __launch_bounds__(kDiffListThreads) k_diff_lists_blocks(
       const uint32_t s = s0 + (live ? slot : 0u);
       const uint32_t i = perm[s];  // caller index
       const float4 xi = Ps[s];
-      uint32_t *out = L + (size_t)i;
+      uint32_t *out = L + (size_t)i * (size_t)a.cap;  // particle-major
       uint32_t cnt = 0;  // the same in the group's lanes
       if (staged) {
         const uint32_t selfk = s + self_off;
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(kDiffListThreads) k_diff_lists_blocks(
           const uint32_t mask = (uint32_t)(__ballot(hit) >> first) & ((1u << kSub) - 1u);
           if (hit) {
             const uint32_t pos = cnt + (uint32_t)__popc(mask & ((1u << sub) - 1u));
-            if (pos < (uint32_t)a.cap) out[(size_t)pos * (size_t)a.n] = s_code[k];
+            if (pos < (uint32_t)a.cap) out[pos] = s_code[k];
           }
           cnt += (uint32_t)__popc(mask);
         }
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(kDiffListThreads) k_diff_lists_blocks(
           if (!wall && g == s) continue;
           const float4 qj = wall ? WP[g] : Ps[g];
           if (!(dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z) < p.r2f)) continue;
-          if (cnt < (uint32_t)a.cap) out[(size_t)cnt * (size_t)a.n] = wall ? (g | kWallBit) : perm[g];
+          if (cnt < (uint32_t)a.cap) out[cnt] = wall ? (g | kWallBit) : perm[g];
           ++cnt;
         }
       }
@@ -176,12 +178,12 @@ __global__ void __launch_bounds__(256) k_diff_density(
   const int i = diff_particle(s);
   if (i >= a.n) return;  // the particle's lanes leave together
   const float4 xi = X[i];
-  const uint32_t *row = L + (size_t)i;
+  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
   const uint32_t cnt = nn[i];
   float sum = 0.0f, comp = 0.0f;
 #pragma unroll 4
   for (uint32_t k = (uint32_t)s; k < cnt; k += kDiffSub) {
-    const uint32_t j = row[(size_t)k * (size_t)a.n];
+    const uint32_t j = row[k];
     const float4 q = (j & kWallBit) ? WP[j & ~kWallBit] : X[j];
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float w = w_shape(__builtin_sqrtf(dx * dx + dy * dy + dz * dz) * p.inv_h);
@@ -213,12 +215,12 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
   if (i >= a.n) return;  // the particle's lanes leave together
   const float4 xi = XP[i], vi = VR[i];
   const float ri = vi.w, Pi = xi.w;
-  const uint32_t *row = L + (size_t)i;
+  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
   const uint32_t cnt = nn[i];
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
 #pragma unroll 4
   for (uint32_t k = (uint32_t)s; k < cnt; k += kDiffSub) {
-    const uint32_t j = row[(size_t)k * (size_t)a.n];
+    const uint32_t j = row[k];
     const bool wall = (j & kWallBit) != 0u;
     float4 q, u = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float coef, nu;
@@ -289,7 +291,7 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
   if (i >= a.n) return;  // the particle's lanes leave together
   const float4 xi = XR[i], vi = VP[i], abi = AB[i];
   const float ri = xi.w, pi = vi.w, Pi = pi / (ri * ri);
-  const uint32_t *row = L + (size_t)i;
+  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
   const uint32_t cnt = nn[i];
   const float m = p.mass, e = p.visc_eps_h2;
   const float inv_h2 = p.inv_h * p.inv_h;
@@ -297,7 +299,7 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
   float Pb = 0.0f, rb = 0.0f, alb = 0.0f;
 #pragma unroll 4
   for (uint32_t k = (uint32_t)sl; k < cnt; k += kDiffSub) {
-    const uint32_t j = row[(size_t)k * (size_t)a.n];
+    const uint32_t j = row[k];
     const bool wall = (j & kWallBit) != 0u;
     float4 q, vj = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float coef, nu, rj = ri, ux, uy, uz;
@@ -394,12 +396,12 @@ __global__ void __launch_bounds__(256) k_diff_adj_density(
   if (i >= a.n) return;  // the particle's lanes leave together
   const float4 xi = XRB[i];
   const float rbi = xi.w;
-  const uint32_t *row = L + (size_t)i;
+  const uint32_t *row = L + (size_t)i * (size_t)a.cap;
   const uint32_t cnt = nn[i];
   float gx = 0.0f, gy = 0.0f, gz = 0.0f;
 #pragma unroll 4
   for (uint32_t k = (uint32_t)s; k < cnt; k += kDiffSub) {
-    const uint32_t j = row[(size_t)k * (size_t)a.n];
+    const uint32_t j = row[k];
     const bool wall = (j & kWallBit) != 0u;
     const float4 q = wall ? WP[j & ~kWallBit] : XRB[j];
     const float rs = wall ? rbi : rbi + q.w;
