@@ -210,16 +210,17 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
     DevParams p, DiffArgs a, const float4 *__restrict__ XP, const float4 *__restrict__ VR,
     const uint32_t *__restrict__ L, const uint32_t *__restrict__ nn,
     const float4 *__restrict__ WP, float4 *__restrict__ Xn, float4 *__restrict__ Vn) {
-  int s;
-  const int i = diff_particle(s);
+  int sl;
+  const int i = diff_particle(sl);
   if (i >= a.n) return;  // the particle's lanes leave together
   const float4 xi = XP[i], vi = VR[i];
   const float ri = vi.w, Pi = xi.w;
+  const float nu_wall = a.alpha * a.hc0 * __builtin_amdgcn_rcpf(ri);
   const uint32_t *row = L + (size_t)i * (size_t)a.cap;
   const uint32_t cnt = nn[i];
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
 #pragma unroll 4
-  for (uint32_t k = (uint32_t)s; k < cnt; k += kDiffSub) {
+  for (uint32_t k = (uint32_t)sl; k < cnt; k += kDiffSub) {
     const uint32_t j = row[k];
     const bool wall = (j & kWallBit) != 0u;
     float4 q, u = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -227,20 +228,20 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
     if (wall) {
       q = WP[j & ~kWallBit];
       coef = 2.0f * Pi;
-      nu = a.alpha * a.hc0 / ri;
+      nu = nu_wall;
     } else {
       q = XP[j];
       u = VR[j];
       coef = Pi + q.w;
-      nu = 2.0f * a.alpha * a.hc0 / (ri + u.w);
+      nu = 2.0f * a.alpha * a.hc0 * __builtin_amdgcn_rcpf(ri + u.w);
     }
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 > 0.0f) || r2 >= p.r2f) continue;
-    const float s = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
-    if (s < 0.0f) coef += -nu * s / (r2 + p.visc_eps_h2);
-    const float r = __builtin_sqrtf(r2);
-    const float F = p.sigma * p.inv_h * dw_shape(r * p.inv_h) / r;
+    const float sv = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
+    if (sv < 0.0f) coef += -nu * sv * __builtin_amdgcn_rcpf(r2 + p.visc_eps_h2);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float F = p.sigma * p.inv_h * dw_shape(r2 * rinv * p.inv_h) * rinv;
     const float t = p.mass * coef * F;
     ax -= t * dx;
     ay -= t * dy;
@@ -249,7 +250,7 @@ __global__ void __launch_bounds__(256) k_diff_force_euler(
   ax = p.g[0] + diff_fold(ax);
   ay = p.g[1] + diff_fold(ay);
   az = p.g[2] + diff_fold(az);
-  if (s != 0) return;
+  if (sl != 0) return;
   const float vx = vi.x + a.dt * ax, vy = vi.y + a.dt * ay, vz = vi.z + a.dt * az;
   Vn[i] = make_float4(vx, vy, vz, 0.0f);
   Xn[i] = make_float4(xi.x + a.dt * vx, xi.y + a.dt * vy, xi.z + a.dt * vz, 0.0f);
@@ -295,6 +296,8 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
   const uint32_t cnt = nn[i];
   const float m = p.mass, e = p.visc_eps_h2;
   const float inv_h2 = p.inv_h * p.inv_h;
+  // reciprocals from the hardware's rcp / rsq (about 1 ulp)
+  const float iri = __builtin_amdgcn_rcpf(ri), inv_alpha = __builtin_amdgcn_rcpf(a.alpha);
   float gxx = 0.0f, gxy = 0.0f, gxz = 0.0f, gvx = 0.0f, gvy = 0.0f, gvz = 0.0f;
   float Pb = 0.0f, rb = 0.0f, alb = 0.0f;
 #pragma unroll 4
@@ -302,20 +305,21 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
     const uint32_t j = row[k];
     const bool wall = (j & kWallBit) != 0u;
     float4 q, vj = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float coef, nu, rj = ri, ux, uy, uz;
+    float coef, nu, isum = iri, ux, uy, uz;  // isum: 1 / (rho_i + rho_j), 1 / rho_i at a wall
     if (wall) {
       q = WP[j & ~kWallBit];
       coef = 2.0f * Pi;
-      nu = a.alpha * a.hc0 / ri;
+      nu = a.alpha * a.hc0 * iri;
       ux = -abi.x;
       uy = -abi.y;
       uz = -abi.z;
     } else {
       q = XR[j];
       vj = VP[j];
-      rj = q.w;
-      coef = Pi + vj.w / (rj * rj);
-      nu = 2.0f * a.alpha * a.hc0 / (ri + rj);
+      const float irj = __builtin_amdgcn_rcpf(q.w);
+      coef = Pi + vj.w * irj * irj;
+      isum = __builtin_amdgcn_rcpf(ri + q.w);
+      nu = 2.0f * a.alpha * a.hc0 * isum;
       const float4 abj = AB[j];
       ux = abj.x - abi.x;
       uy = abj.y - abi.y;
@@ -324,37 +328,36 @@ __global__ void __launch_bounds__(256) k_diff_adj_force(
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 > 0.0f) || r2 >= p.r2f) continue;
-    const float r = __builtin_sqrtf(r2);
+    const float rinv = __builtin_amdgcn_rsqf(r2), r = r2 * rinv;
     const float wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
     const float s = wx * dx + wy * dy + wz * dz;
     const bool visc = s < 0.0f;
-    const float den = r2 + e;
-    if (visc) coef += -nu * s / den;
+    const float iden = __builtin_amdgcn_rcpf(r2 + e);
+    if (visc) coef += -nu * s * iden;
     const float qn = r * p.inv_h;
     const float W1 = p.sigma * p.inv_h * dw_shape(qn), W2 = p.sigma * inv_h2 * d2w_shape(qn);
-    const float F = W1 / r, dF = (W2 * r - W1) / r2;
+    const float F = W1 * rinv, dF = (W2 * r - W1) * rinv * rinv;
     const float Gu = F * (dx * ux + dy * uy + dz * uz);
     const float xu = dx * ux + dy * uy + dz * uz;
-    const float c1 = m * coef * F, c2 = m * coef * dF / r * xu;
+    const float c1 = m * coef * F, c2 = m * coef * dF * rinv * xu;
     gxx += c1 * ux + c2 * dx;
     gxy += c1 * uy + c2 * dy;
     gxz += c1 * uz + c2 * dz;
     if (visc) {
       const float mg = m * Gu;
-      const float k1 = -nu / den, k2 = 2.0f * nu * s / (den * den);
+      const float k1 = -nu * iden, k2 = 2.0f * nu * s * iden * iden;
       gxx += (k1 * wx + k2 * dx) * mg;
       gxy += (k1 * wy + k2 * dy) * mg;
       gxz += (k1 * wz + k2 * dz) * mg;
       gvx += k1 * dx * mg;
       gvy += k1 * dy * mg;
       gvz += k1 * dz * mg;
-      const float nub = -s / den * mg;
+      const float nub = -s * iden * mg;
+      rb += nub * (-nu * isum);
       if (wall) {
-        rb += nub * (-nu / ri);
-        alb += nub * nu / a.alpha;
+        alb += nub * nu * inv_alpha;
       } else {
-        rb += nub * (-nu / (ri + rj));
-        alb += 0.5f * nub * nu / a.alpha;   // the pair is visited from both ends
+        alb += 0.5f * nub * nu * inv_alpha;   // the pair is visited from both ends
       }
     }
     Pb += (wall ? 2.0f : 1.0f) * m * Gu;
@@ -408,8 +411,8 @@ __global__ void __launch_bounds__(256) k_diff_adj_density(
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 > 0.0f) || r2 >= p.r2f) continue;
-    const float r = __builtin_sqrtf(r2);
-    const float t = p.mass * p.sigma * p.inv_h * dw_shape(r * p.inv_h) / r * rs;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float t = p.mass * p.sigma * p.inv_h * dw_shape(r2 * rinv * p.inv_h) * rinv * rs;
     gx += t * dx;
     gy += t * dy;
     gz += t * dz;
