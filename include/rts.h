@@ -286,8 +286,8 @@ rts_status rts_grid_info(rts_ctx *ctx, int32_t *h_nc3, int64_t *h_nblocks, doubl
  * context's stream, and adds each kernel's time in milliseconds to
  * h_ms[0..RTS_PROF_COUNT) in the order of rts_prof_kernel.  Waits for the
  * stream.  The simulation result is identical to rts_advance.  (With a fixed
- * base step rts_advance runs the statistics and the corrector-predictor as
- * one launch; here they are timed apart.) */
+ * base step rts_advance runs the statistics, the corrector-predictor and the
+ * next step's binning as one launch; here they are timed apart.) */
 typedef enum {
   RTS_PROF_KEY_HIST = 0, RTS_PROF_SCAN, RTS_PROF_SCATTER, RTS_PROF_CELL_GATHER,
   RTS_PROF_RMIN_FLAGS, RTS_PROF_SEARCH_DENSITY, RTS_PROF_FORCE, RTS_PROF_STEP_STATS,

@@ -47,6 +47,11 @@ struct rts_ctx {
   double snap_time;
   int64_t snap_steps;
   int snap_major_len, snap_clean;
+  // fixed base step: the last step's closing kernel has binned the current
+  // positions for the next sort (keys, ranks, block counts), so the next
+  // step starts with its scan; anything else that sorts, or that replaces
+  // the particles, first clears those counts (unbin)
+  bool binned;
   int tune_candidates;
   double tune_ms;
   char err[512];
@@ -383,26 +388,39 @@ void destroy_graphs(rts_ctx *c) {
   c->graph_ok = false;
 }
 
+bool fixed_step(const rts_ctx *c) { return c->prm.mode != RTS_MODE_GLOBAL_ADAPTIVE; }
+
 // The kernels of one base step, reading buffer `cur` and leaving the state in
-// buffer cur ^ 1.
+// buffer cur ^ 1.  With a fixed base step the binning of buffer `cur` was
+// done by the previous step's closing kernel (or by rts_advance's prologue)
+// and this step's closing kernel bins buffer cur ^ 1.
 void enqueue_step(rts_ctx *c, int cur, hipStream_t st) {
   const DevParams &p = c->prm;
   const DevPtrs &d = c->d;
   const int nx = cur ^ 1;
-  launch_key_hist(p, d, cur, st);
+  if (!fixed_step(c)) launch_key_hist(p, d, cur, st);
   launch_scan(p, d, d.CELL_START, true, st);
   launch_scatter(p, d, st);
   launch_cell_gather(p, d, cur, c->grid_wave, st);
   launch_rmin_flags(p, d, nx, 1, c->grid_wave, st);
   launch_search_density(p, d, nx, c->grid_search, st);
   launch_force(p, d, nx, c->grid_force, st);
-  if (p.mode == RTS_MODE_GLOBAL_ADAPTIVE) {
+  if (fixed_step(c)) {
+    launch_stats_correct_predict(p, d, nx, st);
+  } else {
     // the step length comes from this step's statistics
     launch_step_stats(p, d, st);
     launch_correct_predict(p, d, nx, st);
-  } else {
-    launch_stats_correct_predict(p, d, nx, st);
   }
+}
+
+// Clears the block counts a closing kernel left for the next sort, before
+// anything else sorts or the particles change.
+rts_status unbin(rts_ctx *c) {
+  if (!c->binned) return RTS_OK;
+  c->binned = false;
+  HIP_OK(c, hipMemsetAsync(c->d.COUNT, 0, (size_t)c->prm.nb * 4, c->stream));
+  return RTS_OK;
 }
 
 rts_status build_graphs(rts_ctx *c) {
@@ -782,6 +800,8 @@ rts_status rts_set_walls(rts_ctx *c, const float *d_pos, int64_t nw) {
   if (!c) return RTS_E_INVALID;
   if (nw < 0 || nw > c->nwcap) return fail(c, RTS_E_CAPACITY, "nw %lld exceeds capacity %lld", (long long)nw, (long long)c->nwcap);
   if (nw > 0 && !d_pos) return fail(c, RTS_E_INVALID, "wall positions are NULL");
+  rts_status u = unbin(c);  // the wall sort counts in the same array
+  if (u) return u;
   c->prm.nw = (int32_t)nw;
   launch_wall_sort(c->prm, c->d, d_pos, c->stream);
   HIP_OK(c, hipGetLastError());
@@ -793,6 +813,8 @@ rts_status rts_set_state(rts_ctx *c, const float *d_pos, const float *d_vel, int
   if (!c) return RTS_E_INVALID;
   if (n < 0 || n > c->ncap) return fail(c, RTS_E_CAPACITY, "n %lld exceeds capacity %lld", (long long)n, (long long)c->ncap);
   if (n > 0 && !d_pos) return fail(c, RTS_E_INVALID, "positions are NULL");
+  rts_status u = unbin(c);
+  if (u) return u;
   c->prm.n = (int32_t)n;
   c->cur = 0;
   c->pci_major_len = c->cfg.mode == RTS_MODE_RTS ? c->cfg.n_minor : 1;
@@ -824,6 +846,8 @@ rts_status rts_assign_levels(rts_ctx *c, int32_t *h_hist) {
     if (s) return s;
     c->pci_minor_in_major = 0;
   } else {
+    rts_status u = unbin(c);
+    if (u) return u;
     const int cur = c->cur;
     launch_key_hist(p, c->d, cur, c->stream);
     launch_scan(p, c->d, c->d.CELL_START, true, c->stream);
@@ -870,6 +894,12 @@ rts_status rts_advance(rts_ctx *c, int32_t n_steps) {
     rts_status s = build_graphs(c);
     if (s) return s;
   }
+  if (fixed_step(c) && !c->binned) {
+    // the first step's binning, which later steps get from their predecessor
+    launch_key_hist(c->prm, c->d, c->cur, c->stream);
+    HIP_OK(c, hipGetLastError());
+  }
+  c->binned = fixed_step(c);
   for (int32_t k = 0; k < n_steps; ++k) {
     if (c->graph_ok) {
       HIP_OK(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
@@ -888,6 +918,9 @@ rts_status rts_profile_advance(rts_ctx *c, int32_t n_steps, double *h_ms) {
     return fail(c, RTS_E_UNSUPPORTED, "per-kernel profiling covers the WCSPH step");
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
   if (c->poisoned) return fail(c, RTS_E_STATE, "state failed; set or load a state first");
+  // the kernels are launched one by one, binning included
+  rts_status u = unbin(c);
+  if (u) return u;
   hipEvent_t ev[RTS_PROF_COUNT + 1];
   for (int k = 0; k <= RTS_PROF_COUNT; ++k) HIP_OK(c, hipEventCreate(&ev[k]));
   rts_status st = RTS_OK;
@@ -1036,6 +1069,8 @@ rts_status rts_load_state(rts_ctx *c, const void *d_buf, size_t len) {
   if (hdr[0] != 0x5254535354415445LL || hdr[1] < 0 || hdr[1] > c->ncap || hdr[2] != c->prm.nb)
     return fail(c, RTS_E_INVALID, "buffer does not hold a state for this context");
   size_t n = (size_t)hdr[1];
+  rts_status u = unbin(c);
+  if (u) return u;
   const bool same_n = c->prm.n == (int32_t)n;
   c->prm.n = (int32_t)n;
   size_t need;
@@ -1326,6 +1361,8 @@ rts_status rts_diff_forward(rts_ctx *c, const rts_diff_desc *D, int64_t n, const
   if (n > 0 && (!d_x0 || !d_v0 || !d_xT || !d_vT)) return fail(c, RTS_E_INVALID, "NULL array");
   if (!d_tape || tape_bytes < diff_carve(*D, n, nullptr, nullptr) || ((uintptr_t)d_tape & 255u))
     return fail(c, RTS_E_CAPACITY, "tape too small or not 256-byte aligned");
+  rts_status u = unbin(c);  // the substeps sort with the context's arrays
+  if (u) return u;
   DiffTape t;
   diff_carve(*D, n, (char *)d_tape, &t);
   c->prm.n = (int32_t)n;
@@ -1362,6 +1399,8 @@ rts_status rts_diff_backward(rts_ctx *c, const rts_diff_desc *D, int64_t n,
   if (n > 0 && !d_xT_bar) return fail(c, RTS_E_INVALID, "NULL dL/dx(T)");
   if (!d_tape || tape_bytes < diff_carve(*D, n, nullptr, nullptr) || ((uintptr_t)d_tape & 255u))
     return fail(c, RTS_E_CAPACITY, "tape too small or not 256-byte aligned");
+  rts_status u = unbin(c);  // the substeps sort with the context's arrays
+  if (u) return u;
   DiffTape t;
   diff_carve(*D, n, (char *)d_tape, &t);
   c->prm.n = (int32_t)n;

@@ -23,6 +23,10 @@
 //   step_stats      per-step counters and the step length
 //   correct_predict all particles: corrector for the active ones, then the
 //                   predictor of the next base step
+// With a fixed base step (RTS, global fixed) the last two are one launch,
+// stats_correct_predict, which also does the next step's key_hist on the
+// predicted positions; key_hist itself then runs only before the first step
+// after the particles change, and for the adaptive comparator.
 //
 // Every float comparison that decides an integer (block key, neighbour
 // predicate, block level) is evaluated with contraction off and a fixed
@@ -41,27 +45,16 @@ constexpr int kForcePerPass = kForceThreads / kSub;
 // ---------------------------------------------------------------------------
 // key + histogram
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_key_hist(DevParams p, const float4 *__restrict__ P,
-                                                 const uint32_t *__restrict__ ids,
-                                                 uint32_t *__restrict__ keyold,
-                                                 uint32_t *__restrict__ rank,
-                                                 uint32_t *__restrict__ count, DevCtrl *ctrl,
-                                                 uint32_t *__restrict__ actn, DevScalars *S) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Key of particle i at position x, the domain check, and its slot in the
+// histogram of the next sort.  Every lane of the wave must call it (live or
+// not).
+__device__ inline void bin_particle(const DevParams &p, int i, bool live, float4 x,
+                                    const uint32_t *__restrict__ ids,
+                                    uint32_t *__restrict__ keyold, uint32_t *__restrict__ rank,
+                                    uint32_t *__restrict__ count, DevScalars *S) {
   const int lane = threadIdx.x & 63;
-  if (i < kActBuckets) actn[i] = 0u;
-  if (i == 0) {
-    ctrl->epoch += 1u;  // a fresh epoch for this step's scan
-    ctrl->scan_ticket = 0u;
-    ctrl->stats_ticket = 0u;
-    ctrl->search_ticket = 0u;
-    ctrl->force_ticket = 0u;
-    S->dt_prev = S->dt_next;
-  }
-  const bool live = i < p.n;
   uint32_t k = 0;
   if (live) {
-    const float4 x = P[i];
     bool bad = !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z));
     bad = bad || x.x < p.o[0] || x.y < p.o[1] || x.z < p.o[2] || x.x > p.dmax[0] ||
           x.y > p.dmax[1] || x.z > p.dmax[2];
@@ -87,6 +80,36 @@ __global__ void __launch_bounds__(256) k_key_hist(DevParams p, const float4 *__r
     }
     todo = __ballot(!done);
   }
+}
+
+// The words a step's kernels count with start from zero (the statistics'
+// ticket apart: the fold that consumes it clears it); a fresh epoch for the
+// step's scan.
+__device__ inline void step_controls_reset(int i, DevCtrl *ctrl, uint32_t *__restrict__ actn) {
+  if (i < kActBuckets) actn[i] = 0u;
+  if (i == 0) {
+    ctrl->epoch += 1u;
+    ctrl->scan_ticket = 0u;
+    ctrl->search_ticket = 0u;
+    ctrl->force_ticket = 0u;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_key_hist(DevParams p, const float4 *__restrict__ P,
+                                                 const uint32_t *__restrict__ ids,
+                                                 uint32_t *__restrict__ keyold,
+                                                 uint32_t *__restrict__ rank,
+                                                 uint32_t *__restrict__ count, DevCtrl *ctrl,
+                                                 uint32_t *__restrict__ actn, DevScalars *S) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  step_controls_reset(i, ctrl, actn);
+  if (i == 0) {
+    ctrl->stats_ticket = 0u;
+    S->dt_prev = S->dt_next;
+  }
+  const bool live = i < p.n;
+  bin_particle(p, i, live, live ? P[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f), ids, keyold, rank,
+               count, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -1018,6 +1041,7 @@ __device__ inline void step_stats_body(const DevParams &p, const uint32_t *__res
   S->dt_next = dtd;
   S->time += dtd;
   S->step += 1;
+  ctrl->stats_ticket = 0u;
 }
 
 __global__ void __launch_bounds__(256) k_step_stats(DevParams p, const uint32_t *__restrict__ occ,
@@ -1035,7 +1059,7 @@ __global__ void __launch_bounds__(256) k_step_stats(DevParams p, const uint32_t 
 // ---------------------------------------------------------------------------
 // Particle i with step dt; dt_prev is the last step's length (global
 // adaptive comparator only).
-__device__ inline void correct_predict_one(const DevParams &p, float4 *__restrict__ P,
+__device__ inline float4 correct_predict_one(const DevParams &p, float4 *__restrict__ P,
                                            float4 *__restrict__ V, float4 *__restrict__ A,
                                            uint32_t *__restrict__ M,
                                            const float4 *__restrict__ anew, int i, float dt,
@@ -1067,6 +1091,7 @@ __device__ inline void correct_predict_one(const DevParams &p, float4 *__restric
   V[i] = v;
   A[i] = a;
   M[i] = meta_pack(meta_level(m), meta_compute(m), age, meta_validity(m));
+  return x;
 }
 
 __global__ void __launch_bounds__(256) k_correct_predict(DevParams p, float4 *__restrict__ P,
@@ -1077,20 +1102,28 @@ __global__ void __launch_bounds__(256) k_correct_predict(DevParams p, float4 *__
                                                         const DevScalars *__restrict__ S) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
-  correct_predict_one(p, P, V, A, M, anew, i, (float)S->dt_next, (float)S->dt_prev);
+  (void)correct_predict_one(p, P, V, A, M, anew, i, (float)S->dt_next, (float)S->dt_prev);
 }
 
 // Fixed base step (RTS, global fixed): the corrector-predictor does not wait
-// for the statistics, so one launch carries both; workgroups below
-// kStatBlocks also take their share of the statistics.
+// for the statistics, so one launch carries both; it also bins the predicted
+// positions for the next step's sort (keys, histogram, domain check) and
+// resets that step's counters, so the next step starts with its scan.
+// Workgroups below kStatBlocks also take their share of the statistics.
 __global__ void __launch_bounds__(256) k_stats_correct_predict(
     DevParams p, const uint32_t *__restrict__ occ, const uint4 *__restrict__ blku,
     const float *__restrict__ blkerr, const float *__restrict__ blkamax,
     const uint8_t *__restrict__ lvl, StatPart *__restrict__ part, DevCtrl *ctrl, DevScalars *S,
     float4 *__restrict__ P, float4 *__restrict__ V, float4 *__restrict__ A,
-    uint32_t *__restrict__ M, const float4 *__restrict__ anew) {
+    uint32_t *__restrict__ M, const float4 *__restrict__ anew, const uint32_t *__restrict__ ids,
+    uint32_t *__restrict__ keyold, uint32_t *__restrict__ rank, uint32_t *__restrict__ count,
+    uint32_t *__restrict__ actn) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < p.n) correct_predict_one(p, P, V, A, M, anew, i, p.dt_base, p.dt_base);
+  const bool live = i < p.n;
+  float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (live) x = correct_predict_one(p, P, V, A, M, anew, i, p.dt_base, p.dt_base);
+  bin_particle(p, i, live, x, ids, keyold, rank, count, S);
+  step_controls_reset(i, ctrl, actn);
   if (blockIdx.x < (unsigned)kStatBlocks)
     step_stats_body(p, occ, blku, blkerr, blkamax, lvl, part, ctrl, S, blockIdx.x, kStatBlocks);
 }
@@ -1267,7 +1300,7 @@ void launch_stats_correct_predict(const DevParams &p, const DevPtrs &d, int cur,
   const unsigned grid = nb > (unsigned)kStatBlocks ? nb : (unsigned)kStatBlocks;
   hipLaunchKernelGGL(k_stats_correct_predict, dim3(grid), dim3(256), 0, st, p, d.OCC, d.BLKU,
                      d.BLKERR, d.BLKAMAX, d.LVL, d.PART, d.CTRL, d.S, d.P[cur], d.V[cur],
-                     d.A[cur], d.M[cur], d.ANEW);
+                     d.A[cur], d.M[cur], d.ANEW, d.ID[cur], d.KEYOLD, d.RANK, d.COUNT, d.ACTN);
 }
 void launch_correct_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
   if (p.n == 0) return;

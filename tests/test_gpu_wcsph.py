@@ -191,6 +191,26 @@ def test_graph_replay_matches_eager_bitwise():
         assert np.array_equal(sa[k], sb[k]), k
 
 
+def test_per_kernel_timer_interleaves_bitwise():
+    """With a fixed base step a step's closing kernel bins the predicted
+    positions for the next sort; the per-kernel timer launches the binning
+    at each step's start instead.  Mixing the two paths, in both orders,
+    must reproduce the plain run bit for bit."""
+    sc = rts_scene()
+    a = Simulation(sc)
+    a.advance(12)
+    a.sync()
+    b = Simulation(sc)
+    b.advance(4)
+    b.profile(4)
+    b.advance(4)
+    b.sync()
+    sa, sb = a.state(), b.state()
+    for k in ("pos", "vel", "acc", "rho", "level"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert a.sync().step == b.sync().step == 12
+
+
 def test_runs_are_deterministic():
     sc = rts_scene()
     outs = []
