@@ -450,45 +450,67 @@ __global__ void k_pci_integrate(DevParams p, float4 *__restrict__ P, float4 *__r
                                 const uint32_t *__restrict__ key, uint32_t *__restrict__ dem,
                                 int major_len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  const float dt = p.dt_base;
-  const float4 a0 = fvg[i], a1 = fp[i];
-  const float ax = a0.x + a1.x, ay = a0.y + a1.y, az = a0.z + a1.z;
-  float4 v = V[i], x = P[i];
-  v.x += dt * ax;
-  v.y += dt * ay;
-  v.z += dt * az;
-  x.x += dt * v.x;
-  x.y += dt * v.y;
-  x.z += dt * v.z;
-  x.w = pv[i].w;
-  v.w = pq[i];
-  P[i] = x;
-  V[i] = v;
-  A[i] = make_float4(ax, ay, az, 0.0f);
-  const uint32_t m = M[i];
-  const uint32_t l = meta_level(m);
-  int32_t val = meta_validity(m) - 1;
-  uint32_t comp = 0u;
-  if (val <= 0) {
-    comp = 1u;
-    val = region_validity((int)l, major_len);
-  }
-  M[i] = meta_pack(l, comp, 0u, val);
-  if (p.mode != RTS_MODE_RTS) return;
-  const float v2 = norm2_exact(v.x, v.y, v.z), a2 = norm2_exact(ax, ay, az);
-  uint32_t need = 0;
-  while ((int)need + 1 <= p.lmax && v2 <= p.TV[need + 1] && a2 <= p.TA[need + 1]) ++need;
-  if (need >= l) return;
-  const int3 c = coords_of(p, key[i]);
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int bx = c.x + dx, by = c.y + dy, bz = c.z + dz;
-        if (bx < 0 || by < 0 || bz < 0 || bx >= p.nc[0] || by >= p.nc[1] || bz >= p.nc[2])
-          continue;
-        atomicMin(&dem[(uint32_t)(bx + p.nc[0] * (by + p.nc[1] * bz))], need);
+  const bool live = i < p.n;  // every lane reaches the wave-wide requests below
+  uint32_t need = kNoLevel, b = 0u;
+  if (live) {
+    const float dt = p.dt_base;
+    const float4 a0 = fvg[i], a1 = fp[i];
+    const float ax = a0.x + a1.x, ay = a0.y + a1.y, az = a0.z + a1.z;
+    float4 v = V[i], x = P[i];
+    v.x += dt * ax;
+    v.y += dt * ay;
+    v.z += dt * az;
+    x.x += dt * v.x;
+    x.y += dt * v.y;
+    x.z += dt * v.z;
+    x.w = pv[i].w;
+    v.w = pq[i];
+    P[i] = x;
+    V[i] = v;
+    A[i] = make_float4(ax, ay, az, 0.0f);
+    const uint32_t m = M[i];
+    const uint32_t l = meta_level(m);
+    int32_t val = meta_validity(m) - 1;
+    uint32_t comp = 0u;
+    if (val <= 0) {
+      comp = 1u;
+      val = region_validity((int)l, major_len);
+    }
+    M[i] = meta_pack(l, comp, 0u, val);
+    if (p.mode == RTS_MODE_RTS) {
+      const float v2 = norm2_exact(v.x, v.y, v.z), a2 = norm2_exact(ax, ay, az);
+      uint32_t lv = 0;
+      while ((int)lv + 1 <= p.lmax && v2 <= p.TV[lv + 1] && a2 <= p.TA[lv + 1]) ++lv;
+      if (lv < l) {
+        need = lv;
+        b = key[i];
       }
+    }
+  }
+  // Requests of the wave, one lane per distinct block with the smallest level
+  // its particles ask for (particles arrive in block order, so a burst of
+  // requests costs few atomics).
+  unsigned long long todo = __ballot(need != kNoLevel);
+  const int lane = threadIdx.x & 63;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const uint32_t lb = (uint32_t)__shfl((int)b, leader, 64);
+    const bool mine = need != kNoLevel && b == lb;
+    const uint32_t lvl = wave_min_u32(mine ? need : kNoLevel);
+    if (lane == leader) {
+      const int3 c = coords_of(p, lb);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int bx = c.x + dx, by = c.y + dy, bz = c.z + dz;
+            if (bx < 0 || by < 0 || bz < 0 || bx >= p.nc[0] || by >= p.nc[1] || bz >= p.nc[2])
+              continue;
+            atomicMin(&dem[(uint32_t)(bx + p.nc[0] * (by + p.nc[1] * bz))], lvl);
+          }
+    }
+    if (mine) need = kNoLevel;
+    todo = __ballot(need != kNoLevel);
+  }
 }
 
 // Occupied blocks take the smallest requested level; every request is
