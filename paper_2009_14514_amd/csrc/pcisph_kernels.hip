@@ -32,6 +32,14 @@ namespace rts {
 
 constexpr uint32_t kNoLevel = 0xFFFFFFFFu;
 
+// Neighbour lists in quads: entries 4q .. 4q+3 of particle i are the four
+// words at (q n + i) 4, so a lane reads four entries with one 16-byte load
+// and the 64 lanes of a wave read consecutive quads (the passes over the
+// lists are bound by issuing loads, not by bytes).
+__device__ inline size_t list_word(uint32_t i, uint32_t k, size_t ncap) {
+  return ((size_t)(k >> 2) * ncap + i) * 4u + (k & 3u);
+}
+
 __device__ inline int region_validity(int level, int major_len) {
   // neighbourhoods: region 1 every minor step, region 2 every second one,
   // regions 3 and 4 at the next major step
@@ -156,10 +164,7 @@ __global__ void __launch_bounds__(256) k_pci_lists(
   const float rs2 = p.support * p.support;
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
   const int3 c = coords_of(p, key[i]);
-  // column-major lists: entry k of particle i at nbr[k * ncap + i], so that
-  // a wave's loads of one entry index are contiguous
-  uint32_t *L = nbr + (size_t)i;
-  const size_t stride = (size_t)p.ncap;
+  const size_t ncap = (size_t)p.ncap;
   uint32_t cnt = 0;  // the same in the particle's lanes
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1 && p.nw == 0) break;
@@ -187,7 +192,7 @@ __global__ void __launch_bounds__(256) k_pci_lists(
           const uint32_t mask = (uint32_t)(__ballot(hit) >> first) & ((1u << kPciSub) - 1u);
           if (hit) {
             const uint32_t pos = cnt + (uint32_t)__popc(mask & ((1u << sub) - 1u));
-            if (pos < (uint32_t)p.nbr_cap) L[(size_t)pos * stride] = j | tag;
+            if (pos < (uint32_t)p.nbr_cap) nbr[list_word(i, pos, ncap)] = j | tag;
             const float4 u = pass == 0 ? V[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
             const float r2 = dx * dx + dy * dy + dz * dz;
@@ -260,14 +265,11 @@ __global__ void __launch_bounds__(256) k_pci_density(
   const bool in_se = se[i] != 0;
   if (!(has_turn(turn, meta_level(M[i])) || in_se || ob[b] || nearse[b])) return;
   const float4 xi = xs[i];
-  const uint32_t *L = nbr + (size_t)i;
+  const uint4 *L4 = reinterpret_cast<const uint4 *>(nbr) + i;
   const size_t stride = (size_t)p.ncap;
   const uint32_t n = nnb[i];
   float sum = 0.0f, comp = 0.0f;
-#pragma unroll 4
-  for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t j = L[(size_t)k * stride];
-    const float4 q = (j & kWallBit) ? WP[j & ~kWallBit] : xs[j];
+  auto add = [&](const float4 q) {
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float w = w_shape(__builtin_sqrtf(r2) * p.inv_h);
@@ -275,6 +277,25 @@ __global__ void __launch_bounds__(256) k_pci_density(
     const float t = sum + y;
     comp = (t - sum) - y;
     sum = t;
+  };
+  // a neighbour's position: a wall's from the wall array (one load either way)
+  auto pos = [&](uint32_t j) {
+    return *((j & kWallBit) ? WP + (j & ~kWallBit) : xs + j);
+  };
+  const uint32_t nfull = n & ~3u;
+  for (uint32_t k0 = 0; k0 < nfull; k0 += 4) {
+    // a full quad: its four gathers are issued before they are used
+    const uint4 e = L4[(size_t)(k0 >> 2) * stride];
+    const float4 q0 = pos(e.x), q1 = pos(e.y), q2 = pos(e.z), q3 = pos(e.w);
+    add(q0);
+    add(q1);
+    add(q2);
+    add(q3);
+  }
+  if (nfull < n) {
+    const uint4 e = L4[(size_t)(nfull >> 2) * stride];
+    const uint32_t js[3] = {e.x, e.y, e.z};
+    for (uint32_t u = 0; nfull + u < n; ++u) add(pos(js[u]));
   }
   const float dev = p.kms * ((sum - p.c_hi) - (comp + p.c_lo));
   const float rho = p.rho0 + p.rho0 * dev;
@@ -315,24 +336,39 @@ __global__ void __launch_bounds__(256) k_pci_force(
   if (!(has_turn(turn, meta_level(M[i])) || se[i])) return;
   const float4 xi = xs[i];
   const float qi = pq[i];
-  const uint32_t *L = nbr + (size_t)i;
+  const uint4 *L4 = reinterpret_cast<const uint4 *>(nbr) + i;
   const size_t stride = (size_t)p.ncap;
   const uint32_t n = nnb[i];
   const float rs2 = p.support * p.support;
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
-#pragma unroll 4
-  for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t j = L[(size_t)k * stride];
-    const bool wall = (j & kWallBit) != 0u;
-    const float4 q = wall ? WP[j & ~kWallBit] : xs[j];
-    const float qj = wall ? qi : pq[j];
+  auto add = [&](uint32_t j, const float4 q, float qj) {
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 > 0.0f) || r2 >= rs2) continue;
-    const float s = -p.mass * (qi + qj) * grad_factor(p, r2);
+    if (!(r2 > 0.0f) || r2 >= rs2) return;
+    const float s = -p.mass * (qi + ((j & kWallBit) ? qi : qj)) * grad_factor(p, r2);
     ax += s * dx;
     ay += s * dy;
     az += s * dz;
+  };
+  // one load each for the position and p / rho*^2 (a wall mirrors p_i, rho_i)
+  auto pos = [&](uint32_t j) {
+    return *((j & kWallBit) ? WP + (j & ~kWallBit) : xs + j);
+  };
+  auto prs = [&](uint32_t j) { return pq[(j & kWallBit) ? 0u : j]; };
+  const uint32_t nfull = n & ~3u;
+  for (uint32_t k0 = 0; k0 < nfull; k0 += 4) {
+    const uint4 e = L4[(size_t)(k0 >> 2) * stride];
+    const float4 q0 = pos(e.x), q1 = pos(e.y), q2 = pos(e.z), q3 = pos(e.w);
+    const float p0 = prs(e.x), p1 = prs(e.y), p2 = prs(e.z), p3 = prs(e.w);
+    add(e.x, q0, p0);
+    add(e.y, q1, p1);
+    add(e.z, q2, p2);
+    add(e.w, q3, p3);
+  }
+  if (nfull < n) {
+    const uint4 e = L4[(size_t)(nfull >> 2) * stride];
+    const uint32_t js[3] = {e.x, e.y, e.z};
+    for (uint32_t u = 0; nfull + u < n; ++u) add(js[u], pos(js[u]), prs(js[u]));
   }
   fp[i] = make_float4(ax, ay, az, 0.0f);
 }
@@ -535,14 +571,15 @@ __global__ void k_pci_demote_particles(DevParams p, const uint32_t *__restrict__
   if (l < meta_level(m)) M[i] = meta_pack(l, 1u, 0u, region_validity((int)l, major_len));
 }
 
-// Row view of the column-major lists (debug): out[i * cap + k] = nbr[k * ncap + i].
+// Row view of the lists (debug): out[i * cap + k] = entry k of particle i.
 __global__ void k_pci_lists_rows(DevParams p, const uint32_t *__restrict__ nbr,
                                  const uint32_t *__restrict__ nnb, uint32_t *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   const uint32_t cnt = min(nnb[i], (uint32_t)p.nbr_cap);
   for (uint32_t k = 0; k < (uint32_t)p.nbr_cap; ++k)
-    out[(size_t)i * (size_t)p.nbr_cap + k] = k < cnt ? nbr[(size_t)k * (size_t)p.ncap + i] : 0u;
+    out[(size_t)i * (size_t)p.nbr_cap + k] =
+        k < cnt ? nbr[list_word((uint32_t)i, k, (size_t)p.ncap)] : 0u;
 }
 
 // ---------------------------------------------------------------------------

@@ -364,7 +364,8 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.FP = (float4 *)take(np * 16);
   t.PQ = (float *)take(np * 4);
   t.SE = (uint8_t *)take(np);
-  t.NBRL = (uint32_t *)take(np * (size_t)(pci ? p.nbr_cap : 1) * 4);
+  // lists in quads of entries: capacity rounded up to a multiple of four
+  t.NBRL = (uint32_t *)take(np * (size_t)(pci ? (p.nbr_cap + 3) / 4 * 4 : 1) * 4);
   t.OB = (uint8_t *)take(nbp);
   t.NEARSE = (uint8_t *)take(nbp);
   t.DIL1 = (uint8_t *)take(nbp);

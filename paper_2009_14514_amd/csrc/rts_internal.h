@@ -175,7 +175,8 @@ struct DevPtrs {
   float4 *FP;        // pressure acceleration
   float *PQ;         // p / rho*^2
   uint8_t *SE;       // member of S_e
-  uint32_t *NBRL;    // nbr_cap x ncap neighbour lists, column-major (entry k of i at k*ncap+i)
+  uint32_t *NBRL;    // nbr_cap x ncap neighbour lists in quads (entry k of i at word
+                     // ((k/4) ncap + i) 4 + k%4)
   uint8_t *OB;       // per block: observed
   uint8_t *NEARSE;   // per block: holds or borders an S_e particle
   uint8_t *DIL1, *DIL2;  // per block: dilation masks
