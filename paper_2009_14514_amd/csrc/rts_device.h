@@ -51,6 +51,18 @@ __device__ inline float dist2_exact(float xi, float yi, float zi, float xj, floa
   return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, xx));
 }
 
+// bits * 2 + (d2 < r2): the compare's lane mask is the carry into an add of
+// the word to itself, so a run of 32 tests leaves test t at bit 31 - t
+// (two instructions per test instead of a compare, a select and a merge).
+__device__ inline uint32_t push_hit(uint32_t bits, float d2, float r2) {
+  uint32_t out;
+  asm("v_cmp_gt_f32_e32 vcc, %2, %3\n\tv_addc_co_u32_e32 %0, vcc, %1, %1, vcc"
+      : "=v"(out)
+      : "v"(bits), "s"(r2), "v"(d2)
+      : "vcc");
+  return out;
+}
+
 // Cubic spline shape w(q) and its derivative (support q < 2), branch-free:
 // both pieces are evaluated and the right one selected.
 __device__ inline float w_shape(float q) {

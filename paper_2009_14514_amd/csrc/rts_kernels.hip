@@ -653,9 +653,9 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
 #pragma unroll
           for (uint32_t t = 0; t < 32; ++t) {
             const float4 qj = s_pos[(uint32_t)sub + kSub * (32u * w + t)];
-            const float d2 = dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z);
-            bits |= d2 < p.r2f ? (1u << t) : 0u;
+            bits = push_hit(bits, dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z), p.r2f);
           }
+          bits = __builtin_bitreverse32(bits);
         } else {
           for (uint32_t t = 0; t < 32; ++t) {
             const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
