@@ -5,7 +5,8 @@ positions and velocities, Tait stiffness, viscosity alpha) are compared
 with the FP64 oracle on the 512-particle scene; checkpoint spacing must
 not change any bit; the autograd wrapper must return the same gradients.
 A dense cluster, whose block neighbourhoods exceed the LDS staging of the
-list build, takes the path that reads candidates from memory.
+list build, takes the path that reads candidates from memory; a lone
+particle follows symplectic Euler's closed form, forward and adjoint.
 """
 import numpy as np
 import pytest
@@ -117,3 +118,32 @@ def test_dense_cluster_lists_from_memory():
     xr, vr = oracle.diff_run(cfg, x0h, vel, sc.walls, model.B0, model.alpha0, model.dt, 1)
     assert np.abs(xT.cpu().numpy() - xr).max() <= 1e-4 * sc.params["spacing"]
     assert np.linalg.norm(vT.cpu().numpy() - vr) <= 1e-4 * np.linalg.norm(vr)
+
+
+def test_lone_particle_follows_symplectic_euler_in_closed_form():
+    """One particle far from the walls: no pair term, so the substeps are
+    symplectic Euler under gravity and the adjoint is the identity in x0
+    and n dt in v0; the stiffness and viscosity get no gradient."""
+    from paper_2009_14514_amd.diff import DiffRollout
+    T = torch()
+    base = scenes.diff_scene()
+    x0n = np.array([[0.15, 0.2, 0.15]])
+    v0n = np.array([[0.3, -0.1, 0.2]])
+    sc = scenes.Scene("lone", x0n, v0n, base.walls, dict(base.params))
+    n = 16
+    model = DiffRollout(sc, n_sub=n, ckpt_every=4)
+    try:
+        x0 = T.tensor(x0n, dtype=T.float32, device="cuda")
+        v0 = T.tensor(v0n, dtype=T.float32, device="cuda")
+        xT, vT = model.forward(x0, v0, model.B0, model.alpha0)
+        dt, g = model.dt, np.asarray(sc.params["gravity"])
+        x_cf = x0n + n * dt * v0n + g * dt * dt * n * (n + 1) / 2
+        assert np.abs(vT.cpu().numpy() - (v0n + n * dt * g)).max() <= 1e-6
+        assert np.abs(xT.cpu().numpy() - x_cf).max() <= 1e-6
+        gout = T.full((1, 3), 0.02, dtype=T.float32, device="cuda")
+        gx, gv, gB, ga = model.backward(gout)
+        assert np.allclose(gx.cpu().numpy(), 0.02, rtol=1e-6, atol=0)
+        assert np.allclose(gv.cpu().numpy(), 0.02 * n * dt, rtol=1e-5, atol=0)
+        assert gB == 0.0 and ga == 0.0
+    finally:
+        model.close()
