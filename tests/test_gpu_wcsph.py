@@ -178,17 +178,21 @@ def test_rts_level_cap_zero_is_global_bitwise():
 
 
 def test_graph_replay_matches_eager_bitwise():
+    """Every replay is checked against the eager run, with eager reads of the
+    state and of the sort between replays."""
     sc = rts_scene()
     a = Simulation(sc, use_graph=1)
     b = Simulation(sc, use_graph=0)
-    for _ in range(3):
-        a.advance(7)
-        b.advance(7)
+    for step in range(12):
+        n = 1 if step < 9 else 4
+        a.advance(n)
+        b.advance(n)
         a.sync()
         b.sync()
-    sa, sb = a.state(), b.state()
-    for k in ("pos", "vel", "acc", "rho", "level"):
-        assert np.array_equal(sa[k], sb[k]), k
+        sa, sb = a.state(), b.state()
+        for k in ("pos", "vel", "acc", "rho", "level"):
+            assert np.array_equal(sa[k], sb[k]), f"replay {step}: {k}"
+        assert np.array_equal(a.debug("KEY"), b.debug("KEY")), f"replay {step}: keys"
 
 
 def test_per_kernel_timer_interleaves_bitwise():
