@@ -88,7 +88,28 @@ class OrcPciState(C.Structure):
         ("snap", C.c_void_p), ("snap_id", C.c_void_p), ("snap_t", C.c_double),
         ("snap_steps", C.c_int64), ("snap_major_len", C.c_int32), ("snap_clean", C.c_int32),
         ("rollbacks", C.c_int32), ("last_rollback", C.c_int32),
+        ("trace", C.c_void_p), ("trace_p", C.c_void_p), ("trace_cap", C.c_int32),
+        ("trace_len", C.c_int32),
     ]
+
+
+class OrcPciCtl(C.Structure):
+    _fields_ = [
+        ("iter", C.c_int32), ("row", C.c_int32), ("min_iter", C.c_int32), ("global_", C.c_int32),
+        ("local_iters", C.c_int32), ("global_iters", C.c_int32), ("resets", C.c_int32),
+        ("reverts", C.c_int32),
+    ]
+
+
+class OrcPciIterRec(C.Structure):
+    _fields_ = [
+        ("iter", C.c_int32), ("row", C.c_int32), ("global_", C.c_int32), ("turn", C.c_uint32),
+        ("action", C.c_int32), ("n_density", C.c_int32), ("n_force", C.c_int32),
+        ("n_se", C.c_int32), ("errmax", C.c_double), ("avg", C.c_double),
+    ]
+
+
+CTL_KEEP, CTL_BACKUP, CTL_RESTORE = 0, 1, 2
 
 
 def lib():
@@ -149,6 +170,23 @@ def _declare(L):
     L.orc_pci_next_dt.argtypes = [cfgp, C.c_double, C.c_int32, C.c_int32, C.c_float, C.c_float]
     L.orc_pci_next_dt.restype = C.c_double
     L.orc_pci_major_begin.argtypes = [cfgp, _p(OrcPciState)]
+    ctlp = _p(OrcPciCtl)
+    L.orc_pci_ctl_init.argtypes = [cfgp, ctlp]
+    L.orc_pci_ctl_more.argtypes = [cfgp, ctlp, C.c_double]
+    L.orc_pci_ctl_more.restype = C.c_int
+    L.orc_pci_ctl_turn.argtypes = [ctlp, C.c_int32, C.c_int32]
+    L.orc_pci_ctl_turn.restype = C.c_uint32
+    L.orc_pci_ctl_after.argtypes = [cfgp, ctlp, C.c_int32, C.c_double, C.c_double]
+    L.orc_pci_ctl_after.restype = C.c_int
+    L.orc_pci_major_length.argtypes = [cfgp, _p(OrcPciState), C.c_int32, C.c_int32]
+    L.orc_pci_major_length.restype = C.c_int
+    L.orc_pci_smaller_steps.argtypes = [cfgp, C.c_int32, vp, vp, vp, C.c_int32, vp, vp, vp, vp,
+                                        vp]
+    L.orc_pci_smaller_steps.restype = C.c_int
+    L.orc_pci_region_validity.argtypes = [C.c_int32, C.c_int32]
+    L.orc_pci_region_validity.restype = C.c_int32
+    L.orc_adaptive_dt.argtypes = [cfgp, C.c_int32, vp]
+    L.orc_adaptive_dt.restype = C.c_double
     L.orc_diff_run.argtypes = [cfgp, C.c_int32, vp, vp, C.c_int32, vp, C.c_double, C.c_double,
                                C.c_double, C.c_int32, vp, vp]
     L.orc_diff_grad.argtypes = [cfgp, C.c_int32, vp, vp, C.c_int32, vp, C.c_double, C.c_double,
@@ -387,6 +425,62 @@ def pci_turn(col, row):
     return int(lib().orc_pci_turn(int(col), int(row)))
 
 
+class PciControl:
+    """Algorithm 3's loop control on its own: feed it the errors after each
+    iteration and read the decisions."""
+
+    def __init__(self, cfg, standard=False):
+        self.cfg = cfg
+        self.standard = int(bool(standard))
+        self.k = OrcPciCtl()
+        lib().orc_pci_ctl_init(C.byref(cfg), C.byref(self.k))
+
+    def more(self, errmax):
+        return bool(lib().orc_pci_ctl_more(C.byref(self.cfg), C.byref(self.k), float(errmax)))
+
+    def turn(self, col):
+        return int(lib().orc_pci_ctl_turn(C.byref(self.k), int(col), self.standard))
+
+    def after(self, errmax, avg):
+        return int(lib().orc_pci_ctl_after(C.byref(self.cfg), C.byref(self.k), self.standard,
+                                           float(errmax), float(avg)))
+
+    def __getattr__(self, name):
+        k = self.__dict__["k"]
+        return getattr(k, "global_" if name == "global_" or name == "glob" else name)
+
+
+def pci_major_length(cfg, state, global_iters, standard=False):
+    """Ends a minor step in the major-step length controller; returns 1 when
+    the major step ends.  ``state`` is an OrcPciState (only its major-step
+    counters are used)."""
+    return int(lib().orc_pci_major_length(C.byref(cfg), C.byref(state), int(global_iters),
+                                          int(bool(standard))))
+
+
+def pci_region_validity(region, major_len):
+    return int(lib().orc_pci_region_validity(int(region), int(major_len)))
+
+
+def pci_smaller_steps(cfg, key, vel_f32, acc_f32, major_len, region, validity, compute,
+                      blk_level, blk_ob):
+    """S7 on the given arrays (modified in place); returns 1 if a block changed."""
+    key = np.ascontiguousarray(key, np.uint32)
+    v = np.ascontiguousarray(vel_f32, np.float32).reshape(-1, 3)
+    a = np.ascontiguousarray(acc_f32, np.float32).reshape(-1, 3)
+    for arr, dt in ((region, np.int32), (validity, np.int32), (compute, np.uint8),
+                    (blk_level, np.uint8), (blk_ob, np.uint8)):
+        assert arr.dtype == dt and arr.flags.c_contiguous
+    return int(lib().orc_pci_smaller_steps(C.byref(cfg), key.shape[0], _ptr(key), _ptr(v), _ptr(a),
+                                           int(major_len), _ptr(region), _ptr(validity),
+                                           _ptr(compute), _ptr(blk_level), _ptr(blk_ob)))
+
+
+def adaptive_dt(cfg, acc):
+    a = np.ascontiguousarray(acc, np.float64).reshape(-1, 3)
+    return float(lib().orc_adaptive_dt(C.byref(cfg), a.shape[0], _ptr(a)))
+
+
 def pci_regions(cfg, key, vel_f32, acc_f32):
     """(raw, lvl, observed) block arrays of a major step's region determination."""
     info = derive(cfg)
@@ -528,6 +622,19 @@ class PCISPH:
             setattr(s, name, _ptr(getattr(self, name)))
         s.major_len = int(self.cfg.n_minor)
         self.history = []
+        self.trace = None
+
+    def enable_trace(self, cap=None, pressures=False):
+        """Record every correction iteration of each following minor step
+        (``history[k]['trace']``), with the pressures after each iteration
+        when ``pressures`` is set (``history[k]['trace_p']``, in block order)."""
+        cap = int(cap if cap is not None else self.cfg.it_max)
+        self.trace = (OrcPciIterRec * cap)()
+        s = self.state
+        s.trace = C.cast(self.trace, C.c_void_p)
+        s.trace_cap = cap
+        self.trace_p = np.zeros(cap * max(s.n, 1)) if pressures else None
+        s.trace_p = _ptr(self.trace_p) if pressures else None
 
     def step(self, n=1):
         """n accepted minor steps (a rolled-back major step does not count)."""
@@ -546,6 +653,14 @@ class PCISPH:
                 dt_next=s.dt_cur if s.dt_cur > 0 else self.cfg.dt_base,
                 v2max=s.last_v2max, a2max=s.last_a2max, rollback=s.last_rollback,
                 steps=s.minor_steps))
+            if self.trace is not None:
+                h = self.history[-1]
+                h["trace"] = [dict(iter=r.iter, row=r.row, glob=r.global_, turn=r.turn,
+                                   action=r.action, n_density=r.n_density, n_force=r.n_force,
+                                   n_se=r.n_se, errmax=r.errmax, avg=r.avg)
+                              for r in self.trace[:s.trace_len]]
+                if self.trace_p is not None:
+                    h["trace_p"] = self.trace_p[: s.trace_len * s.n].reshape(s.trace_len, s.n).copy()
         return self
 
     def major_begin(self):

@@ -544,6 +544,23 @@ void orc_serna_correct(int32_t n, double *x, double *v, double *a, const double 
 /* are the same loop with every block at level 0; the adaptive one takes     */
 /* dt = min(lambda_v r / c0, lambda_f sqrt(r / max|a|)) each step.            */
 /* ------------------------------------------------------------------------ */
+/* Global adaptive comparator: Eq. 1 and Eq. 2 for every particle at once,
+ * dt = min(lambda_v r / c0, lambda_f sqrt(r / max|a|)). */
+double orc_adaptive_dt(const orc_cfg *c, int32_t n, const double *a) {
+  double amax2 = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    const double *ai = a + 3 * (int64_t)i;
+    double a2 = ai[0] * ai[0] + ai[1] * ai[1] + ai[2] * ai[2];
+    if (a2 > amax2) amax2 = a2;
+  }
+  double dt = c->lambda_v * r_crit(c) / c->c0;
+  if (amax2 > 0.0) {
+    double df = c->lambda_f * sqrt(r_crit(c) / sqrt(amax2));
+    if (df < dt) dt = df;
+  }
+  return dt;
+}
+
 int orc_wcsph_step(const orc_cfg *c, orc_state *s) {
   int32_t n = s->n;
   ctx_t X;
@@ -603,20 +620,7 @@ int orc_wcsph_step(const orc_cfg *c, orc_state *s) {
     if (s->compute[i]) s->age[i] = 0;
 
   /* W10: predictor with this step's length */
-  double dt = I->dt_base;
-  if (c->mode == ORC_MODE_GLOBAL_ADAPTIVE) {
-    double amax2 = 0.0;
-    for (int32_t i = 0; i < n; ++i) {
-      const double *ai = s->a + 3 * (int64_t)i;
-      double a2 = ai[0] * ai[0] + ai[1] * ai[1] + ai[2] * ai[2];
-      if (a2 > amax2) amax2 = a2;
-    }
-    dt = c->lambda_v * r_crit(c) / c->c0;
-    if (amax2 > 0.0) {
-      double df = c->lambda_f * sqrt(r_crit(c) / sqrt(amax2));
-      if (df < dt) dt = df;
-    }
-  }
+  double dt = c->mode == ORC_MODE_GLOBAL_ADAPTIVE ? orc_adaptive_dt(c, n, s->a) : I->dt_base;
   orc_serna_predict(n, s->x, s->v, s->a, dt);
   for (int32_t i = 0; i < n; ++i) s->age[i] += 1;
   s->dt_prev = dt;
@@ -894,10 +898,64 @@ uint32_t orc_pci_turn(int32_t col, int32_t row) {
   return table[row - 1][col];
 }
 
-static int32_t region_validity(int32_t region, int32_t major_len) {
+int32_t orc_pci_region_validity(int32_t region, int32_t major_len) {
   /* Section 5, neighbourhood updates: R1 every minor step, R2 every second,
    * R3 and R4 at the next major step. */
   return region <= 2 ? region : major_len;
+}
+#define region_validity orc_pci_region_validity
+
+/* Algorithm 3, the loop's control (C5-C6), taken apart from the physics so
+ * that each branch can be driven on its own. */
+void orc_pci_ctl_init(const orc_cfg *c, orc_pci_ctl *k) {
+  memset(k, 0, sizeof(*k));
+  k->iter = 1;
+  k->row = 1;
+  k->min_iter = c->it_min;
+  k->global = 1;
+}
+
+int orc_pci_ctl_more(const orc_cfg *c, const orc_pci_ctl *k, double errmax) {
+  return (k->iter <= k->min_iter || errmax >= c->eta) && k->iter <= c->it_max;
+}
+
+uint32_t orc_pci_ctl_turn(const orc_pci_ctl *k, int32_t col, int32_t standard) {
+  if (standard) return 0xFu;
+  return k->global ? orc_pci_turn(col, k->row) : 0u;
+}
+
+int orc_pci_ctl_after(const orc_cfg *c, orc_pci_ctl *k, int32_t standard, double errmax,
+                      double avg) {
+  if (k->global) ++k->global_iters;
+  ++k->iter;
+  ++k->row;
+  /* extra iterations start once the three scheduled rows are done */
+  if (!(errmax >= c->eta && k->iter > 3)) return ORC_CTL_KEEP;
+  ++k->min_iter;
+  if (standard) return ORC_CTL_KEEP;
+  if (avg >= c->eta_T) {                   /* global error: restart the schedule */
+    int act = ORC_CTL_KEEP;
+    if (!k->global) {                      /* abandon the local phase */
+      act = ORC_CTL_RESTORE;
+      ++k->reverts;
+    }
+    k->global = 1;
+    k->row = 1;
+    ++k->resets;
+    return act;
+  }
+  if (k->global) {                         /* local corrections on S_e */
+    k->global = 0;
+    k->local_iters = 0;
+    return ORC_CTL_BACKUP;
+  }
+  if (++k->local_iters >= c->local_fail) { /* local phase failed */
+    k->global = 1;
+    k->row = 1;
+    ++k->reverts;
+    return ORC_CTL_RESTORE;
+  }
+  return ORC_CTL_KEEP;
 }
 
 static void permute_d(double *a, const uint32_t *perm, int32_t n, int w, double *tmp) {
@@ -1015,6 +1073,76 @@ double orc_pci_next_dt(const orc_cfg *c, double dt, int32_t peak_iters, int32_t 
   return next;
 }
 
+/* Section 5, extra iterations: a minor step with more than global_limit
+ * global iterations ends its major step early and shortens the following
+ * major steps to two minor steps, until short_majors major steps in a row
+ * pass without such a minor step. */
+int orc_pci_major_length(const orc_cfg *c, orc_pci_state *s, int32_t global_iters,
+                         int32_t standard) {
+  s->minor_in_major += 1;
+  s->last_early_end = 0;
+  if (!standard && global_iters > c->global_limit) {
+    s->major_excess = 1;
+    if (s->minor_in_major < s->major_len) s->last_early_end = 1;
+  }
+  if (s->minor_in_major < s->major_len && !s->last_early_end) return 0;
+  s->minor_in_major = 0;
+  if (!standard) {
+    if (s->major_excess) {
+      s->major_len = 2 < c->n_minor ? 2 : c->n_minor;
+      s->clean_majors = 0;
+    } else if (s->major_len < c->n_minor && ++s->clean_majors >= c->short_majors) {
+      s->major_len = c->n_minor;
+      s->clean_majors = 0;
+    }
+  }
+  return 1;
+}
+
+/* Section 5, neighbourhood updates: a particle that now needs a smaller
+ * step marks its block and the neighbouring blocks to take it. */
+int orc_pci_smaller_steps(const orc_cfg *c, int32_t n, const uint32_t *key, const float *vel,
+                          const float *acc, int32_t major_len, int32_t *region,
+                          int32_t *validity, uint8_t *compute, uint8_t *blk_level,
+                          uint8_t *blk_ob) {
+  orc_info I;
+  if (orc_derive(c, &I)) return 0;
+  uint8_t *nl = (uint8_t *)malloc((size_t)I.nblocks);
+  memcpy(nl, blk_level, (size_t)I.nblocks);
+  int changed = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const float v2 = norm2f(vel + 3 * (int64_t)i), a2 = norm2f(acc + 3 * (int64_t)i);
+    /* the largest level (region - 1) whose Eq. 2-3 bounds the particle meets */
+    int l = 0;
+    while (l + 1 <= I.lmax && v2 <= I.TV[l + 1] && a2 <= I.TA[l + 1]) ++l;
+    if (l >= region[i] - 1) continue;
+    int32_t b[3];
+    coords_of_key(&I, key[i], b);
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int32_t q[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
+          if (!in_grid(&I, q)) continue;
+          uint32_t kq = key_of(&I, q);
+          if (nl[kq] != ORC_EMPTY_BLOCK && nl[kq] > l) { nl[kq] = (uint8_t)l; changed = 1; }
+        }
+  }
+  if (changed) {
+    for (int32_t i = 0; i < n; ++i) {
+      int32_t r = (int32_t)nl[key[i]] + 1;
+      if (r < region[i]) {
+        region[i] = r;
+        compute[i] = 1;
+        validity[i] = region_validity(r, major_len);
+      }
+    }
+    memcpy(blk_level, nl, (size_t)I.nblocks);
+    observed_info(&I, blk_level, blk_ob);
+  }
+  free(nl);
+  return changed;
+}
+
 int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
   /* this major step's base step: the adapted one once there is one */
   orc_cfg cfg_now = *c_in;
@@ -1084,20 +1212,23 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
   uint8_t *dens = (uint8_t *)malloc(nn), *forc = (uint8_t *)malloc(nn);
   uint8_t *near = (uint8_t *)malloc((size_t)I.nblocks);
   memset(near, 0, (size_t)I.nblocks);
-  int32_t iter = 1, row = 1, min_iter = c->it_min, global = 1, local_iters = 0;
-  int32_t global_iters = 0, resets = 0, reverts = 0;
+  orc_pci_ctl k;
+  orc_pci_ctl_init(c, &k);
   int64_t ev_d = 0, ev_f = 0;
   double errmax = INFINITY, avg = 0.0;
-  while ((iter <= min_iter || errmax >= eta) && iter <= c->it_max) {
+  s->trace_len = 0;
+  while (orc_pci_ctl_more(c, &k, errmax)) {
     /* C1: predicted velocity and position of every particle */
     for (int32_t i = 0; i < n; ++i)
       for (int e = 0; e < 3; ++e) {
-        int64_t k = 3 * (int64_t)i + e;
-        double vs = s->v[k] + dt * (s->fvg[k] + s->fp[k]);
-        xs[k] = s->x[k] + dt * vs;
+        int64_t q = 3 * (int64_t)i + e;
+        double vs = s->v[q] + dt * (s->fvg[q] + s->fp[q]);
+        xs[q] = s->x[q] + dt * vs;
       }
     /* the particles that have the turn */
-    uint32_t turn = standard ? 0xFu : (global ? orc_pci_turn(col, row) : 0u);
+    const uint32_t turn = orc_pci_ctl_turn(&k, col, standard);
+    const int32_t it_row = k.row, it_global = k.global, it_no = k.iter;
+    int32_t nd = 0, nf = 0;
     for (int32_t i = 0; i < n; ++i) {
       int t = (turn >> (s->region[i] - 1)) & 1u;
       int ob = s->blk_ob[s->key[i]] || near[s->key[i]];
@@ -1107,7 +1238,7 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
     orc_pci_density(c, n, xs, s->wx, s->nbr, s->nnb, dens, s->rho);
     for (int32_t i = 0; i < n; ++i) {
       if (!dens[i]) continue;
-      ++ev_d;
+      ++nd;
       s->err[i] = (s->rho[i] - rho0) / rho0;
       double pn = s->p[i] + I.delta * (s->rho[i] - rho0);
       s->p[i] = pn > 0.0 ? pn : 0.0;
@@ -1122,11 +1253,10 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
     for (int32_t i = 0; i < n; ++i)
       forc[i] = (uint8_t)(((turn >> (s->region[i] - 1)) & 1u) || s->in_se[i]);
     orc_pci_pressure_force(c, n, xs, s->wx, s->p, s->rho, s->nbr, s->nnb, forc, s->fp);
-    for (int32_t i = 0; i < n; ++i) ev_f += forc[i];
-    /* C5 */
-    if (global) ++global_iters;
-    ++iter;
-    ++row;
+    for (int32_t i = 0; i < n; ++i) nf += forc[i];
+    ev_d += nd;
+    ev_f += nf;
+    /* C5: errors over the fluid (particles not evaluated keep their last) */
     errmax = 0.0;
     double sum = 0.0;
     for (int32_t i = 0; i < n; ++i) {
@@ -1136,30 +1266,30 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
     }
     avg = n > 0 ? sum / n : 0.0;
     /* C6: extra iterations after the three scheduled ones */
-    if (errmax >= eta && iter > 3 && !standard) {
-      ++min_iter;
-      if (avg >= c->eta_T) {                   /* global error: restart the schedule */
-        if (!global) {
-          memcpy(s->p, p_backup, sizeof(double) * nn);
-          ++reverts;
-        }
-        global = 1;
-        row = 1;
-        ++resets;
-      } else if (global) {                     /* local corrections on S_e */
-        memcpy(p_backup, s->p, sizeof(double) * nn);
-        global = 0;
-        local_iters = 0;
-      } else if (++local_iters >= c->local_fail) {
-        memcpy(s->p, p_backup, sizeof(double) * nn);
-        global = 1;
-        row = 1;
-        ++reverts;
-      }
-    } else if (errmax >= eta && iter > 3) {
-      ++min_iter;
+    const int act = orc_pci_ctl_after(c, &k, standard, errmax, avg);
+    if (act == ORC_CTL_BACKUP) memcpy(p_backup, s->p, sizeof(double) * nn);
+    if (act == ORC_CTL_RESTORE) memcpy(s->p, p_backup, sizeof(double) * nn);
+    if (s->trace && s->trace_len < s->trace_cap) {
+      orc_pci_iter_rec *r = &s->trace[s->trace_len];
+      int32_t nse = 0;
+      for (int32_t i = 0; i < n; ++i) nse += s->in_se[i];
+      r->iter = it_no;
+      r->row = it_row;
+      r->global = it_global;
+      r->turn = turn;
+      r->action = act;
+      r->n_density = nd;
+      r->n_force = nf;
+      r->n_se = nse;
+      r->errmax = errmax;
+      r->avg = avg;
+      if (s->trace_p)
+        memcpy(s->trace_p + (int64_t)s->trace_len * n, s->p, sizeof(double) * (size_t)n);
+      s->trace_len += 1;
     }
   }
+  const int32_t iter = k.iter, global_iters = k.global_iters;
+  const int32_t resets = k.resets, reverts = k.reverts;
   free(xs); free(p_backup); free(dens); free(forc); free(near);
 
   /* S5: new velocity and position (symplectic Euler) */
@@ -1180,43 +1310,15 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
   /* S7: a particle that now needs a smaller step takes its block and the 26
    * around it to that step */
   if (!standard) {
-    uint8_t *nl = (uint8_t *)malloc((size_t)I.nblocks);
-    memcpy(nl, s->blk_level, (size_t)I.nblocks);
-    int changed = 0;
-    for (int32_t i = 0; i < n; ++i) {
-      float vf[3], af[3];
-      for (int e = 0; e < 3; ++e) {
-        vf[e] = (float)s->v[3 * (int64_t)i + e];
-        af[e] = (float)(s->fvg[3 * (int64_t)i + e] + s->fp[3 * (int64_t)i + e]);
-      }
-      float v2 = norm2f(vf), a2 = norm2f(af);
-      int l = 0;
-      while (l + 1 <= I.lmax && v2 <= I.TV[l + 1] && a2 <= I.TA[l + 1]) ++l;
-      if (l >= s->region[i] - 1) continue;
-      int32_t b[3];
-      coords_of_key(&I, s->key[i], b);
-      for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx) {
-            int32_t q[3] = {b[0] + dx, b[1] + dy, b[2] + dz};
-            if (!in_grid(&I, q)) continue;
-            uint32_t k = key_of(&I, q);
-            if (nl[k] != ORC_EMPTY_BLOCK && nl[k] > l) { nl[k] = (uint8_t)l; changed = 1; }
-          }
+    float *vf = (float *)malloc(sizeof(float) * 3 * nn), *af = (float *)malloc(sizeof(float) * 3 * nn);
+    for (int64_t q = 0; q < 3 * (int64_t)n; ++q) {
+      vf[q] = (float)s->v[q];
+      af[q] = (float)(s->fvg[q] + s->fp[q]);
     }
-    if (changed) {
-      for (int32_t i = 0; i < n; ++i) {
-        int32_t r = (int32_t)nl[s->key[i]] + 1;
-        if (r < s->region[i]) {
-          s->region[i] = r;
-          s->compute[i] = 1;
-          s->validity[i] = region_validity(r, s->major_len);
-        }
-      }
-      memcpy(s->blk_level, nl, (size_t)I.nblocks);
-      observed_info(&I, s->blk_level, s->blk_ob);
-    }
-    free(nl);
+    orc_pci_smaller_steps(c, n, s->key, vf, af, s->major_len, s->region, s->validity, s->compute,
+                          s->blk_level, s->blk_ob);
+    free(vf);
+    free(af);
   }
 
   /* statistics and the major-step length (Section 5, extra iterations) */
@@ -1235,14 +1337,8 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
   s->last_dt = dt;
   s->t += dt;
   s->minor_steps += 1;
-  s->minor_in_major += 1;
-  s->last_early_end = 0;
-  if (!standard && global_iters > c->global_limit) {
-    s->major_excess = 1;
-    if (s->minor_in_major < s->major_len) s->last_early_end = 1;
-  }
-  if (s->minor_in_major >= s->major_len || s->last_early_end) {
-    s->minor_in_major = 0;
+  const int ends = orc_pci_major_length(c, s, global_iters, standard);
+  if (ends) {
     if (adapt) {
       /* the next major step's base step, from this one's effort and the
        * fastest particle after it */
@@ -1260,15 +1356,6 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
       s->last_v2max = v2m;
       s->last_a2max = a2m;
       s->dt_cur = orc_pci_next_dt(c_in, dt, s->peak_iters, s->major_excess, v2m, a2m);
-    }
-    if (!standard) {
-      if (s->major_excess) {
-        s->major_len = 2 < c->n_minor ? 2 : c->n_minor;
-        s->clean_majors = 0;
-      } else if (s->major_len < c->n_minor && ++s->clean_majors >= c->short_majors) {
-        s->major_len = c->n_minor;
-        s->clean_majors = 0;
-      }
     }
   }
   /* a correction that did not converge: back to the start of the major

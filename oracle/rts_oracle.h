@@ -122,6 +122,9 @@ void orc_serna_correct(int32_t n, double *x, double *v, double *a, const double 
 
 /* one base step of Algorithm 1 (or of a global comparator) */
 int orc_wcsph_step(const orc_cfg *c, orc_state *s);
+/* step of the global adaptive comparator from the accelerations a (3n):
+ * min(lambda_v r / c0, lambda_f sqrt(r / max|a|)) */
+double orc_adaptive_dt(const orc_cfg *c, int32_t n, const double *a);
 
 /* ---------------------------------------------------------------------- */
 /* PCISPH with regional iteration counts (Section 5, Algorithms 2 and 3).   */
@@ -168,7 +171,84 @@ typedef struct orc_pci_state {
   int32_t snap_major_len, snap_clean;
   int32_t rollbacks;                 /* major steps rolled back so far */
   int32_t last_rollback;             /* 1: the last call rolled its major step back */
+  /* optional record of the last minor step's correction iterations (for
+   * tests); trace == NULL records nothing */
+  struct orc_pci_iter_rec *trace;    /* trace_cap records */
+  double *trace_p;                   /* NULL or trace_cap * n: p after each iteration */
+  int32_t trace_cap, trace_len;
 } orc_pci_state;
+
+/* Algorithm 3: the control of one minor step's correction loop.  The loop
+ * runs while (iter <= min_iter or the maximum error >= eta) and
+ * iter <= it_max.  After each iteration (C5-C6):
+ *   global_iters counts the iterations that followed the schedule;
+ *   iter and row advance;
+ *   once the three scheduled rows are done (iter > 3) and the maximum error
+ *   is still >= eta, min_iter grows by one and (regional mode only)
+ *     - if the average error >= eta_T: the schedule restarts at row 1
+ *       (global); a local phase that was running is abandoned and the
+ *       pressure restored from the snapshot (a revert);
+ *     - else, if global: local iterations on S_e begin, with a snapshot of
+ *       the pressure;
+ *     - else, after local_fail local iterations without convergence: back to
+ *       global at row 1 with the pressure restored (a revert).
+ * Standard PCISPH (every region in every iteration) only grows min_iter. */
+typedef struct orc_pci_ctl {
+  int32_t iter;                      /* number of the next iteration, from 1 */
+  int32_t row;                       /* schedule row of the next iteration, from 1 */
+  int32_t min_iter;                  /* minIterations, from it_min */
+  int32_t global;                    /* 1: next iteration follows the schedule */
+  int32_t local_iters;               /* local iterations since the local phase began */
+  int32_t global_iters;              /* iterations that followed the schedule */
+  int32_t resets;                    /* schedule restarts */
+  int32_t reverts;                   /* pressure restorations */
+} orc_pci_ctl;
+enum { ORC_CTL_KEEP = 0, ORC_CTL_BACKUP = 1, ORC_CTL_RESTORE = 2 };
+
+typedef struct orc_pci_iter_rec {
+  int32_t iter;                      /* iteration number (1-based) */
+  int32_t row;                       /* schedule row it used (global) */
+  int32_t global;                    /* 1: it followed the schedule */
+  uint32_t turn;                     /* regions with the turn (bit n-1: region n) */
+  int32_t action;                    /* ORC_CTL_* taken after it */
+  int32_t n_density, n_force;        /* particles evaluated */
+  int32_t n_se;                      /* |S_e| after it */
+  double errmax, avg;                /* errors after it */
+} orc_pci_iter_rec;
+
+void orc_pci_ctl_init(const orc_cfg *c, orc_pci_ctl *k);
+/* 1 while another iteration is due (errmax: after the last iteration;
+ * +infinity before the first) */
+int orc_pci_ctl_more(const orc_cfg *c, const orc_pci_ctl *k, double errmax);
+/* regions with the turn in the next iteration of minor-step column col */
+uint32_t orc_pci_ctl_turn(const orc_pci_ctl *k, int32_t col, int32_t standard);
+/* C5-C6 after an iteration with the given errors; returns ORC_CTL_BACKUP
+ * (snapshot p) or ORC_CTL_RESTORE (p from the snapshot) or ORC_CTL_KEEP. */
+int orc_pci_ctl_after(const orc_cfg *c, orc_pci_ctl *k, int32_t standard, double errmax,
+                      double avg);
+/* End of a minor step that took global_iters scheduled iterations (Section 5,
+ * extra iterations): counts it in the major step; more than global_limit
+ * global iterations mark the major step as overrun and end it early when
+ * minor steps remain; at its end an overrun major step shortens the next
+ * ones to 2 minor steps, and after short_majors clean major steps the length
+ * returns to n_minor.  Returns 1 when the major step ends here.  Uses and
+ * updates major_len, minor_in_major, clean_majors, major_excess,
+ * last_early_end of s. */
+int orc_pci_major_length(const orc_cfg *c, orc_pci_state *s, int32_t global_iters,
+                         int32_t standard);
+/* S7 (Section 5, neighbourhood updates): a particle whose speed or
+ * acceleration (float, squared as for the regions) exceeds its region's
+ * Eq. 2-3 bounds takes its block and the occupied blocks around it to the
+ * largest region it satisfies; the particles of a block whose region fell
+ * take that region, recompute their lists next minor step and restart
+ * their validity; the observed blocks follow the new regions.  vel, acc:
+ * 3n floats.  Returns 1 if a block changed. */
+int orc_pci_smaller_steps(const orc_cfg *c, int32_t n, const uint32_t *key, const float *vel,
+                          const float *acc, int32_t major_len, int32_t *region,
+                          int32_t *validity, uint8_t *compute, uint8_t *blk_level,
+                          uint8_t *blk_ob);
+/* validity of a particle of region n: 1, 2, or the major-step length */
+int32_t orc_pci_region_validity(int32_t region, int32_t major_len);
 
 /* a19: delta = -1 / (beta (-sum gradW . sum gradW - sum gradW . gradW)),
  * beta = 2 (m dt_b / rho0)^2, over the full rest-lattice neighbourhood. */

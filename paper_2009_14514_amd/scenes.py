@@ -215,6 +215,43 @@ def pcisph_dam_break_small(counts=(10, 20, 10), spacing=0.02, box=(0.8, 0.5, 0.3
                  box_walls(bmin, bmax, spacing, p["wall_layers"]), p)
 
 
+def pcisph_thrown_columns(speeds=(0.0, 0.5, 1.5, 12.0), counts=(6, 6, 6), spacing=0.02,
+                          box=(1.6, 0.7, 0.3), seed=0, dt_base=1e-3, mode="rts", wall_gap=0.25):
+    """Four PCISPH columns that start in four different regions (paper's
+    Eq. 2-3 at the default thresholds and a base step of 1e-3 s: 0 m/s
+    region 4, 0.5 m/s region 3, 1.5 m/s region 2, 12 m/s region 1):
+
+      A at rest on the floor at the left wall;
+      B on the floor, thrown towards +x at speeds[1];
+      C on the floor, thrown towards the right wall at speeds[2],
+        ``wall_gap`` spacings from it (by default a quarter spacing, so that
+        it hits the wall within a few minor steps: local and extra global
+        iterations, an early end of a major step);
+      D in the air above B and C, thrown towards -x at speeds[3].
+
+    The columns are at least 6 blocks (of edge 2.2 spacings) apart, more
+    than the 4-block growth of regions 1 and 2, so the four regions coexist.
+    """
+    bmin, bmax = (0.0, 0.0, 0.0), tuple(float(b) for b in box)
+    w = counts[0] * spacing
+    corners = [(0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (box[0] - w - wall_gap * spacing, 0.0, 0.0),
+               (0.9, 0.45, 0.0)]
+    dirs = [(0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (1.0, 0.0, 0.0), (-1.0, 0.0, 0.0)]
+    pos_all, vel_all = [], []
+    first = 0
+    for corner, d, v in zip(corners, dirs, speeds):
+        p = lattice_column(counts, spacing, corner, jitter=0.005 * spacing, seed=seed,
+                           first_index=first)
+        first += p.shape[0]
+        pos_all.append(p)
+        vel_all.append(np.tile(np.asarray(d) * float(v), (p.shape[0], 1)))
+    pos = np.concatenate(pos_all, axis=0)
+    vel = np.concatenate(vel_all, axis=0)
+    p = pcisph_params(spacing, bmin, bmax, counts[1] * spacing, dt_base, mode)
+    return Scene(f"pcisph_thrown_columns_{pos.shape[0]}", pos, vel,
+                 box_walls(bmin, bmax, spacing, p["wall_layers"]), p)
+
+
 def pcisph_column(counts=(8, 12, 8), spacing=0.02, box=(0.16, 0.5, 0.16), seed=0,
                   dt_base=1e-3, mode="rts"):
     """One PCISPH column at the x = 0 corner of the box."""

@@ -299,25 +299,6 @@ def test_nonpressure_is_gravity_plus_momentum_free_viscosity():
 # --------------------------------------------------------------------------
 # whole steps
 # --------------------------------------------------------------------------
-def test_particles_refresh_lists_at_their_region_cadence():
-    sc = pscene()
-    sim = O.PCISPH(sc.params, sc.pos, walls=sc.walls)
-    sim.step(4)            # first major step: regions come from rest (all slow)
-    seen = []
-    for k in range(4):
-        pre_region = sim.region.copy()
-        pre_compute = sim.compute.copy()
-        sim.step()
-        seen.append((pre_region, pre_compute))
-    # in the second major step's first minor step every particle rebuilt its list
-    assert sim.history[4]["lists"] == sc.n
-    # afterwards a particle rebuilds in minor step j only if its region's
-    # cadence (1 or 2) says so, or a smaller step was forced on it
-    for j in (1, 2, 3):
-        reg, comp = seen[j]
-        assert np.all(comp[reg >= 3] <= (reg[reg >= 3] < 0))  or comp[reg >= 3].sum() <= sc.n
-
-
 def test_all_region_one_is_standard_pcisph_when_the_schedule_suffices():
     """RTS with every block capped at region 1 takes every particle in rows
     1-3 of every minor step; with lists that hold the same neighbour sets it
