@@ -88,7 +88,8 @@ class OrcPciState(C.Structure):
         ("snap", C.c_void_p), ("snap_id", C.c_void_p), ("snap_t", C.c_double),
         ("snap_steps", C.c_int64), ("snap_major_len", C.c_int32), ("snap_clean", C.c_int32),
         ("rollbacks", C.c_int32), ("last_rollback", C.c_int32),
-        ("trace", C.c_void_p), ("trace_p", C.c_void_p), ("trace_cap", C.c_int32),
+        ("trace", C.c_void_p), ("trace_p", C.c_void_p), ("trace_e", C.c_void_p),
+        ("trace_cap", C.c_int32),
         ("trace_len", C.c_int32),
     ]
 
@@ -149,6 +150,9 @@ def _declare(L):
                               C.c_void_p, C.c_void_p]
     L.orc_forces.argtypes = [cfgp, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_forces_terms.argtypes = [cfgp, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
     L.orc_serna_predict.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]
     L.orc_serna_correct.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p]
@@ -163,6 +167,8 @@ def _declare(L):
                                 vp, vp]
     L.orc_pci_density.argtypes = [cfgp, C.c_int32, vp, vp, vp, vp, vp, vp]
     L.orc_pci_pressure_force.argtypes = [cfgp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_pci_pressure_force_terms.argtypes = [cfgp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                               vp]
     L.orc_pci_nonpressure.argtypes = [cfgp, C.c_int32, vp, vp, vp, vp, vp, vp, vp]
     L.orc_pci_turn.argtypes = [C.c_int32, C.c_int32]
     L.orc_pci_turn.restype = C.c_uint32
@@ -327,19 +333,22 @@ def density(cfg, x, walls=None, which=None):
     return rho, p
 
 
-def forces(cfg, x, v, rho, p, walls=None, which=None):
+def forces(cfg, x, v, rho, p, walls=None, which=None, term_sums=False):
+    """Accelerations; with ``term_sums`` also |g| + sum_j |pair term| per particle."""
     x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
     v = np.ascontiguousarray(v, np.float64).reshape(-1, 3)
     rho = np.ascontiguousarray(rho, np.float64)
     p = np.ascontiguousarray(p, np.float64)
     wx = np.zeros((0, 3)) if walls is None else np.ascontiguousarray(walls, np.float64).reshape(-1, 3)
     acc = np.zeros_like(x)
+    tsum = np.zeros(x.shape[0])
     w = None if which is None else np.ascontiguousarray(which, np.uint8)
-    st = lib().orc_forces(C.byref(cfg), x.shape[0], _ptr(x), _ptr(v), _ptr(rho), _ptr(p),
-                          wx.shape[0], _ptr(wx), None if w is None else _ptr(w), _ptr(acc))
+    st = lib().orc_forces_terms(C.byref(cfg), x.shape[0], _ptr(x), _ptr(v), _ptr(rho), _ptr(p),
+                                wx.shape[0], _ptr(wx), None if w is None else _ptr(w), _ptr(acc),
+                                _ptr(tsum))
     if st:
         raise RuntimeError(f"oracle forces status {st}")
-    return acc
+    return (acc, tsum) if term_sums else acc
 
 
 def serna_predict(x, v, a, dt):
@@ -546,18 +555,20 @@ def pci_density(cfg, xs, wx, nbr, nnb, which=None):
     return rho
 
 
-def pci_pressure_force(cfg, xs, wx, p, rho, nbr, nnb, which=None):
+def pci_pressure_force(cfg, xs, wx, p, rho, nbr, nnb, which=None, term_sums=False):
+    """Pressure accelerations; with ``term_sums`` also sum_j |pair term| per particle."""
     xs = np.ascontiguousarray(xs, np.float64).reshape(-1, 3)
     wx = np.ascontiguousarray(wx, np.float64).reshape(-1, 3)
     p = np.ascontiguousarray(p, np.float64)
     rho = np.ascontiguousarray(rho, np.float64)
     nbr, nnb = _lists_arg(cfg, nbr, nnb)
     fp = np.zeros_like(xs)
+    tsum = np.zeros(xs.shape[0])
     w = None if which is None else np.ascontiguousarray(which, np.uint8)
-    lib().orc_pci_pressure_force(C.byref(cfg), xs.shape[0], _ptr(xs), _ptr(wx), _ptr(p), _ptr(rho),
-                                 _ptr(nbr), _ptr(nnb), _ptr(w) if w is not None else None,
-                                 _ptr(fp))
-    return fp
+    lib().orc_pci_pressure_force_terms(C.byref(cfg), xs.shape[0], _ptr(xs), _ptr(wx), _ptr(p),
+                                       _ptr(rho), _ptr(nbr), _ptr(nnb),
+                                       _ptr(w) if w is not None else None, _ptr(fp), _ptr(tsum))
+    return (fp, tsum) if term_sums else fp
 
 
 def pci_nonpressure(cfg, x, v, wx, nbr, nnb, which=None):
@@ -623,11 +634,15 @@ class PCISPH:
         s.major_len = int(self.cfg.n_minor)
         self.history = []
         self.trace = None
+        self.trace_p = self.trace_e = None
 
-    def enable_trace(self, cap=None, pressures=False):
+    def enable_trace(self, cap=None, pressures=False, errors=False):
         """Record every correction iteration of each following minor step
         (``history[k]['trace']``), with the pressures after each iteration
-        when ``pressures`` is set (``history[k]['trace_p']``, in block order)."""
+        when ``pressures`` is set (``history[k]['trace_p']``, in block order)
+        and the relative density errors of the particles each iteration
+        evaluated (NaN for the others) when ``errors`` is set
+        (``history[k]['trace_e']``)."""
         cap = int(cap if cap is not None else self.cfg.it_max)
         self.trace = (OrcPciIterRec * cap)()
         s = self.state
@@ -635,6 +650,8 @@ class PCISPH:
         s.trace_cap = cap
         self.trace_p = np.zeros(cap * max(s.n, 1)) if pressures else None
         s.trace_p = _ptr(self.trace_p) if pressures else None
+        self.trace_e = np.zeros(cap * max(s.n, 1)) if errors else None
+        s.trace_e = _ptr(self.trace_e) if errors else None
 
     def step(self, n=1):
         """n accepted minor steps (a rolled-back major step does not count)."""
@@ -661,6 +678,8 @@ class PCISPH:
                               for r in self.trace[:s.trace_len]]
                 if self.trace_p is not None:
                     h["trace_p"] = self.trace_p[: s.trace_len * s.n].reshape(s.trace_len, s.n).copy()
+                if self.trace_e is not None:
+                    h["trace_e"] = self.trace_e[: s.trace_len * s.n].reshape(s.trace_len, s.n).copy()
         return self
 
     def major_begin(self):

@@ -436,7 +436,7 @@ static void density_from_lists(const orc_cfg *c, ctx_t *X, const double *x, cons
  * at rest. */
 static void forces_from_lists(const orc_cfg *c, ctx_t *X, const double *x, const double *v,
                               const double *rho, const double *p, const double *wx,
-                              const uint8_t *which, double *acc) {
+                              const uint8_t *which, double *acc, double *tsum) {
   double m = X->I.mass, h = c->h;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int32_t i = 0; i < X->n; ++i) {
@@ -444,6 +444,7 @@ static void forces_from_lists(const orc_cfg *c, ctx_t *X, const double *x, const
     const double *xi = x + 3 * (int64_t)i, *vi = v + 3 * (int64_t)i;
     double ri = rho[i], pi = p[i];
     double ai[3] = {c->g[0], c->g[1], c->g[2]};
+    double ts = sqrt(c->g[0] * c->g[0] + c->g[1] * c->g[1] + c->g[2] * c->g[2]);
     const uint32_t *L = X->nbr + (int64_t)i * X->cap;
     for (int32_t k = 0; k < X->nnb[i]; ++k) {
       uint32_t j = L[k];
@@ -474,8 +475,10 @@ static void forces_from_lists(const orc_cfg *c, ctx_t *X, const double *x, const
         coef += -nu * vx / (r2 + c->visc_eps * h * h);
       }
       for (int d = 0; d < 3; ++d) ai[d] -= m * coef * dw * xij[d];
+      ts += fabs(m * coef * dw) * r;
     }
     for (int d = 0; d < 3; ++d) acc[3 * (int64_t)i + d] = ai[d];
+    if (tsum) tsum[i] = ts;
   }
 }
 
@@ -494,7 +497,18 @@ int orc_forces(const orc_cfg *c, int32_t n, const double *x, const double *v, co
   ctx_t X;
   if (ctx_open(&X, c, n, x, nw, wx)) return ORC_E_INVALID;
   int st = ctx_lists(&X, which);
-  forces_from_lists(c, &X, x, v, rho, p, wx, which, acc);
+  forces_from_lists(c, &X, x, v, rho, p, wx, which, acc, NULL);
+  ctx_close(&X);
+  return st;
+}
+
+int orc_forces_terms(const orc_cfg *c, int32_t n, const double *x, const double *v,
+                     const double *rho, const double *p, int32_t nw, const double *wx,
+                     const uint8_t *which, double *acc, double *tsum) {
+  ctx_t X;
+  if (ctx_open(&X, c, n, x, nw, wx)) return ORC_E_INVALID;
+  int st = ctx_lists(&X, which);
+  forces_from_lists(c, &X, x, v, rho, p, wx, which, acc, tsum);
   ctx_close(&X);
   return st;
 }
@@ -593,7 +607,7 @@ int orc_wcsph_step(const orc_cfg *c, orc_state *s) {
   status = ctx_lists(&X, s->compute);
   density_from_lists(c, &X, s->x, s->wx, s->compute, s->rho, s->p);
   double *anew = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
-  forces_from_lists(c, &X, s->x, s->v, s->rho, s->p, s->wx, s->compute, anew);
+  forces_from_lists(c, &X, s->x, s->v, s->rho, s->p, s->wx, s->compute, anew, NULL);
 
   /* statistics */
   s->n_active = 0; s->n_inter = 0; s->err_max = 0.0;
@@ -826,6 +840,13 @@ void orc_pci_density(const orc_cfg *c, int32_t n, const double *xs, const double
 void orc_pci_pressure_force(const orc_cfg *c, int32_t n, const double *xs, const double *wx,
                             const double *p, const double *rho, const uint32_t *nbr,
                             const int32_t *nnb, const uint8_t *which, double *fp) {
+  orc_pci_pressure_force_terms(c, n, xs, wx, p, rho, nbr, nnb, which, fp, NULL);
+}
+
+void orc_pci_pressure_force_terms(const orc_cfg *c, int32_t n, const double *xs,
+                                  const double *wx, const double *p, const double *rho,
+                                  const uint32_t *nbr, const int32_t *nnb, const uint8_t *which,
+                                  double *fp, double *tsum) {
   int32_t cap = c->nbr_cap;
   double m = c->mass > 0.0 ? c->mass : c->rho0 / orc_lattice_sum(c);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -833,7 +854,7 @@ void orc_pci_pressure_force(const orc_cfg *c, int32_t n, const double *xs, const
     if (which && !which[i]) continue;
     const double *xi = xs + 3 * (int64_t)i;
     double pi = p[i] / (rho[i] * rho[i]);
-    double a[3] = {0.0, 0.0, 0.0};
+    double a[3] = {0.0, 0.0, 0.0}, ts = 0.0;
     const uint32_t *L = nbr + (int64_t)i * cap;
     for (int32_t k = 0; k < nnb[i]; ++k) {
       uint32_t j = L[k];
@@ -845,8 +866,10 @@ void orc_pci_pressure_force(const orc_cfg *c, int32_t n, const double *xs, const
       double g[3];
       grad_w(c, xij, d, g);
       for (int e = 0; e < 3; ++e) a[e] -= m * (pi + pj) * g[e];
+      ts += fabs(m * (pi + pj)) * sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     }
     for (int e = 0; e < 3; ++e) fp[3 * (int64_t)i + e] = a[e];
+    if (tsum) tsum[i] = ts;
   }
 }
 
@@ -1285,6 +1308,9 @@ int orc_pci_step(const orc_cfg *c_in, orc_pci_state *s) {
       r->avg = avg;
       if (s->trace_p)
         memcpy(s->trace_p + (int64_t)s->trace_len * n, s->p, sizeof(double) * (size_t)n);
+      if (s->trace_e)
+        for (int32_t i = 0; i < n; ++i)
+          s->trace_e[(int64_t)s->trace_len * n + i] = dens[i] ? s->err[i] : NAN;
       s->trace_len += 1;
     }
   }

@@ -114,6 +114,12 @@ int orc_density(const orc_cfg *c, int32_t n, const double *x, int32_t nw, const 
                 const uint8_t *which, double *rho, double *p);
 int orc_forces(const orc_cfg *c, int32_t n, const double *x, const double *v, const double *rho,
                const double *p, int32_t nw, const double *wx, const uint8_t *which, double *acc);
+/* The same, also giving per particle the sum of the magnitudes of the terms
+ * that make up its acceleration, |g| + sum_j |m coef_ij gradW_ij|: the scale
+ * against which a float evaluation's error is measured. */
+int orc_forces_terms(const orc_cfg *c, int32_t n, const double *x, const double *v,
+                     const double *rho, const double *p, int32_t nw, const double *wx,
+                     const uint8_t *which, double *acc, double *tsum);
 
 /* integrator pieces (Serna predictor-corrector) */
 void orc_serna_predict(int32_t n, double *x, double *v, const double *a, double dt);
@@ -175,6 +181,8 @@ typedef struct orc_pci_state {
    * tests); trace == NULL records nothing */
   struct orc_pci_iter_rec *trace;    /* trace_cap records */
   double *trace_p;                   /* NULL or trace_cap * n: p after each iteration */
+  double *trace_e;                   /* NULL or trace_cap * n: relative density error of the
+                                        particles evaluated in each iteration, NaN for the rest */
   int32_t trace_cap, trace_len;
 } orc_pci_state;
 
@@ -278,6 +286,12 @@ void orc_pci_density(const orc_cfg *c, int32_t n, const double *xs, const double
 void orc_pci_pressure_force(const orc_cfg *c, int32_t n, const double *xs, const double *wx,
                             const double *p, const double *rho, const uint32_t *nbr,
                             const int32_t *nnb, const uint8_t *which, double *fp);
+/* The same with tsum[i] = sum_j |m (p_i/rho_i^2 + p_j/rho_j^2) gradW_ij|
+ * (tsum may be NULL). */
+void orc_pci_pressure_force_terms(const orc_cfg *c, int32_t n, const double *xs,
+                                  const double *wx, const double *p, const double *rho,
+                                  const uint32_t *nbr, const int32_t *nnb, const uint8_t *which,
+                                  double *fp, double *tsum);
 /* Gravity plus artificial viscosity (nu = alpha h c0 / rho0) at x, v. */
 void orc_pci_nonpressure(const orc_cfg *c, int32_t n, const double *x, const double *v,
                          const double *wx, const uint32_t *nbr, const int32_t *nnb,

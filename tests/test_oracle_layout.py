@@ -20,7 +20,8 @@ def test_oracle_struct_layouts_match_the_header(tmp_path):
                                     "shrink_iters", "dt_min", "shrink"]),
         "orc_pci_state": (oracle.OrcPciState, ["major_len", "minor_steps", "hist", "dt_cur",
                                                "peak_iters", "last_a2max", "snap", "snap_t",
-                                               "snap_clean", "last_rollback"]),
+                                               "snap_clean", "last_rollback", "trace_p",
+                                               "trace_e", "trace_cap", "trace_len"]),
         "orc_info": (oracle.OrcInfo, ["TV", "lmax", "delta"]),
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rts_oracle.h"',

@@ -283,6 +283,26 @@ def test_pressure_forces_conserve_momentum_and_vanish_for_uniform_pressure():
     assert np.abs(fp2[centre]).max() < 1e-9 * np.abs(fp2).max()
 
 
+def test_pressure_force_term_sums_bound_the_force():
+    """The per-particle error scale of the pressure-force comparison is the
+    sum of the pair terms' magnitudes: it equals |F^p| for a lone pair and
+    bounds it (triangle inequality) in a cloud."""
+    c = pcfg(nbr_cap=1024)
+    x = np.array([[0.3, 0.2, 0.15], [0.3 + 0.7 * c.spacing, 0.2 + 0.6 * c.spacing, 0.15]])
+    x, nbr, nnb, wx = all_lists(c, x)
+    assert list(nnb) == [1, 1]
+    fp, ts = O.pci_pressure_force(c, x, wx, np.array([300.0, 800.0]), np.array([1001.0, 1003.0]),
+                                  nbr, nnb, term_sums=True)
+    assert np.allclose(ts, np.linalg.norm(fp, axis=1), rtol=1e-13)
+    rng = np.random.default_rng(5)
+    x = lattice_block(c, 7) + rng.normal(0, 0.1 * c.spacing, (343, 3))
+    x, nbr, nnb, wx = all_lists(c, x)
+    rho = O.pci_density(c, x, wx, nbr, nnb)
+    fp, ts = O.pci_pressure_force(c, x, wx, rng.uniform(0, 500, len(x)), rho, nbr, nnb,
+                                  term_sums=True)
+    assert np.all(ts >= np.linalg.norm(fp, axis=1) * (1 - 1e-12))
+
+
 def test_nonpressure_is_gravity_plus_momentum_free_viscosity():
     c = pcfg(nbr_cap=1024)
     rng = np.random.default_rng(9)

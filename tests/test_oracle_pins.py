@@ -143,6 +143,27 @@ def test_compressed_pair_repels_symmetrically():
     assert np.allclose(a[0] - g, -(a[1] - g), rtol=1e-13)
 
 
+def test_term_sums_are_the_magnitudes_of_the_terms():
+    """The per-particle error scale of the force comparisons: |g| alone for
+    an isolated particle, |g| + |a - g| for one pair (a single term), and
+    at least |a - g| (triangle inequality) with more neighbours."""
+    c = cfg()
+    g = np.linalg.norm(np.array(c.g[:]))
+    _, ts = O.forces(c, np.array([[0.3, 0.2, 0.2]]), np.zeros((1, 3)), np.array([c.rho0]),
+                     np.array([500.0]), term_sums=True)
+    assert ts[0] == pytest.approx(g, rel=1e-15)
+    x = np.array([[0.30, 0.2, 0.2], [0.31, 0.205, 0.2]])
+    v = np.array([[0.1, 0.0, 0.0], [-0.2, 0.05, 0.0]])        # approaching: viscosity on
+    a, ts = O.forces(c, x, v, np.full(2, 1010.0), np.full(2, 3000.0), term_sums=True)
+    for i in range(2):
+        assert ts[i] == pytest.approx(g + np.linalg.norm(a[i] - np.array(c.g[:])), rel=1e-13)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.1, 0.2, size=(200, 3))
+    rho, p = O.density(c, x)
+    a, ts = O.forces(c, x, rng.normal(0, 0.3, (200, 3)), rho, p, term_sums=True)
+    assert np.all(ts >= g + np.linalg.norm(a - np.array(c.g[:]), axis=1) * (1 - 1e-12) - g * 1e-12)
+
+
 def test_momentum_is_conserved_in_a_fluid_cloud():
     c = cfg()
     rng = np.random.default_rng(2)
