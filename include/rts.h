@@ -197,6 +197,19 @@ rts_status rts_set_walls(rts_ctx *ctx, const float *d_pos, int64_t nw);
  * so the first step evaluates all of them (Algorithm 1 initialisation). */
 rts_status rts_set_state(rts_ctx *ctx, const float *d_pos, const float *d_vel, int64_t n);
 
+/* External impulse: adds d_dv (planes, 3*n floats, caller order) to the
+ * particles' velocities and changes nothing else: levels, validity, ages and
+ * stored accelerations stay.  The next base step's block maxima see the new
+ * speeds, so a block that now needs a smaller step takes it and its
+ * particles that were in the middle of a longer step are pre-empted
+ * (Section 4.2, pre-emption; Algorithm 1: a particle whose parent block has a
+ * different step recomputes).  PCISPH: the next minor step's smaller-step
+ * check sees them; with the adaptive base step a roll-back of the current
+ * major step discards the impulse.  n must equal the particle count given
+ * to rts_set_state (else RTS_E_INVALID); RTS_E_STATE before any state.
+ * Asynchronous; d_dv must stay valid until the stream reaches the call. */
+rts_status rts_add_velocity(rts_ctx *ctx, const float *d_dv, int64_t n);
+
 /* Region determination only (Section 3.1 and R_min of Section 4.2): rebuilds
  * the block grid, takes block maxima and levels and smooths them, without
  * touching particle flags or physics.  h_level_hist[n_levels]: number of

@@ -29,8 +29,8 @@ DBG = {name: i for i, name in enumerate([
 # exported symbols, in the order include/rts.h declares them
 EXPORTS = [
     "rts_default_config", "rts_workspace_size", "rts_create", "rts_destroy", "rts_set_walls",
-    "rts_set_state", "rts_assign_levels", "rts_advance", "rts_sync", "rts_get_state",
-    "rts_state_bytes", "rts_save_state", "rts_load_state", "rts_debug_get", "rts_grid_info",
+    "rts_set_state", "rts_add_velocity", "rts_assign_levels", "rts_advance", "rts_sync",
+    "rts_get_state", "rts_state_bytes", "rts_save_state", "rts_load_state", "rts_debug_get", "rts_grid_info",
     "rts_profile_advance", "rts_autotune", "rts_get_tune", "rts_diff_tape_bytes",
     "rts_diff_forward", "rts_diff_backward", "rts_last_error", "rts_status_string",
 ]
@@ -120,6 +120,7 @@ def lib():
         L.rts_destroy.restype = None
         L.rts_set_walls.argtypes = [vp, vp, i64]
         L.rts_set_state.argtypes = [vp, vp, vp, i64]
+        L.rts_add_velocity.argtypes = [vp, vp, i64]
         L.rts_assign_levels.argtypes = [vp, vp]
         L.rts_advance.argtypes = [vp, i32]
         L.rts_sync.argtypes = [vp, C.POINTER(RtsStats)]
@@ -218,6 +219,10 @@ def set_walls(ctx, d_pos, nw):
 
 def set_state(ctx, d_pos, d_vel, n):
     check(lib().rts_set_state(ctx, C.c_void_p(d_pos), C.c_void_p(d_vel), int(n)), ctx)
+
+
+def add_velocity(ctx, d_dv, n):
+    check(lib().rts_add_velocity(ctx, C.c_void_p(d_dv), int(n)), ctx)
 
 
 def assign_levels(ctx, n_levels):

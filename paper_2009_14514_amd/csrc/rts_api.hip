@@ -837,6 +837,18 @@ rts_status rts_set_state(rts_ctx *c, const float *d_pos, const float *d_vel, int
   return RTS_OK;
 }
 
+rts_status rts_add_velocity(rts_ctx *c, const float *d_dv, int64_t n) {
+  if (!c) return RTS_E_INVALID;
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  if (n != (int64_t)c->prm.n)
+    return fail(c, RTS_E_INVALID, "n %lld differs from the particle count %d", (long long)n,
+                c->prm.n);
+  if (n > 0 && !d_dv) return fail(c, RTS_E_INVALID, "velocity changes are NULL");
+  launch_add_velocity(c->prm, c->d, c->cur, d_dv, c->stream);
+  HIP_OK(c, hipGetLastError());
+  return RTS_OK;
+}
+
 rts_status rts_assign_levels(rts_ctx *c, int32_t *h_hist) {
   if (!c) return RTS_E_INVALID;
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");

@@ -206,6 +206,8 @@ void launch_stats_correct_predict(const DevParams &p, const DevPtrs &d, int cur,
                                   hipStream_t st);
 void launch_set_state(const DevParams &p, const DevPtrs &d, int cur, const float *pos,
                       const float *vel, hipStream_t st);
+void launch_add_velocity(const DevParams &p, const DevPtrs &d, int cur, const float *dv,
+                         hipStream_t st);
 void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos, float *vel,
                       float *acc, float *rho, float *pres, uint8_t *level, hipStream_t st);
 void launch_wall_sort(const DevParams &p, const DevPtrs &d, const float *pos, hipStream_t st);

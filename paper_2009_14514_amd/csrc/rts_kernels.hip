@@ -1146,6 +1146,23 @@ __global__ void k_set_state(DevParams p, const float *__restrict__ pos,
   pres[i] = 0.0f;
 }
 
+// External impulse: the caller's velocity change (planes, caller order) is
+// added to each particle's velocity; levels, validity, ages and stored
+// accelerations stay as they are, so the next step's block maxima see the
+// change and pre-empt the particles whose block needs a smaller step.
+__global__ void k_add_velocity(DevParams p, const float *__restrict__ dv, const uint32_t *ID,
+                               float4 *V) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const size_t n = (size_t)p.n;
+  const uint32_t c = ID[i];
+  float4 v = V[i];
+  v.x += dv[c];
+  v.y += dv[n + c];
+  v.z += dv[2 * n + c];
+  V[i] = v;
+}
+
 __global__ void k_get_state(DevParams p, const float4 *P, const float4 *V, const float4 *A,
                             const uint32_t *M, const uint32_t *ID, float *pos, float *vel,
                             float *acc, float *rho, float *po, uint8_t *level) {
@@ -1318,6 +1335,12 @@ void launch_set_state(const DevParams &p, const DevPtrs &d, int cur, const float
   if (p.n == 0) return;
   hipLaunchKernelGGL(k_set_state, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p, pos, vel,
                      d.P[cur], d.V[cur], d.A[cur], d.M[cur], d.ID[cur], d.PRES);
+}
+void launch_add_velocity(const DevParams &p, const DevPtrs &d, int cur, const float *dv,
+                         hipStream_t st) {
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_add_velocity, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p, dv,
+                     d.ID[cur], d.V[cur]);
 }
 void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos, float *vel,
                       float *acc, float *rho, float *pres, uint8_t *level, hipStream_t st) {

@@ -79,6 +79,12 @@ class Simulation:
                        tv.data_ptr() if tv is not None else 0, self.n)
         self.stream.synchronize()
 
+    def add_velocity(self, dv):
+        """Adds a velocity change (N, 3) in caller order, keeping levels and flags."""
+        t = self._dev(_planes(dv))
+        _rts.add_velocity(self.ctx, t.data_ptr(), self.n)
+        self.stream.synchronize()
+
     def advance(self, n_steps=1):
         _rts.advance(self.ctx, n_steps)
 
