@@ -1,0 +1,136 @@
+"""GPU parity of PCISPH's data-dependent control against the oracle.
+
+Section "Regional Time Stepping with PCISPH" (subsections "Extra Correction
+Iterations", "Local Density Correction", "Neighborhood Computation and
+Updates") and Algorithms 2-3: after the three scheduled rows, extra
+iterations restart the schedule when the mean compression is at least eta_T
+and otherwise correct S_e locally, reverting the pressures after local_fail
+failed local iterations; a minor step with more than global_limit global
+iterations ends its major step early and the next major steps are two
+minor steps long until short_majors clean ones pass; particles that need a
+smaller step take their block and its 26 neighbours to it.
+
+The scene is four columns that start in regions 1-4 (so all four regions
+coexist), one of them thrown at a wall.  Every minor step compares with the
+oracle: iterations, global iterations, resets, reverts, early end, major
+step length and position, list rebuilds, the region histogram, and per
+particle the region, validity, compute flag and S_e membership (both sides
+hold the particles in the same block order).  Final positions agree within
+1e-4 spacings.  The oracle's control on these settings is pinned by
+tests/test_oracle_pcisph_control_pins.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_14514_amd import scenes
+from paper_2009_14514_amd.sim import Simulation, decode_meta
+
+pytestmark = pytest.mark.gpu
+
+COUNTERS = (("pci_iters", "iters"), ("pci_global_iters", "global_iters"),
+            ("pci_resets", "resets"), ("pci_reverts", "reverts"),
+            ("pci_early_end", "early_end"), ("pci_major_len", "major_len"),
+            ("pci_minor_in_major", "minor_in_major"), ("pci_lists", "lists"))
+
+
+def check_se(k, sim, ref, h, eta):
+    """S_e membership (err > eta / 2 in any evaluation of the minor step)
+    bit for bit, except at near-ties: a particle may differ only where the
+    oracle's error came within `band` of eta / 2 during the step, with
+    `band` twice the largest GPU-vs-oracle difference of the particles'
+    last evaluated errors in the same step (FP32 against FP64 drift of the
+    trajectories).  Ties are printed, and at most 2 per minor step pass."""
+    se_gpu = sim.debug("PCI_SE")
+    diff = np.flatnonzero(se_gpu != ref.in_se)
+    if diff.size == 0:
+        return 0
+    err_gpu = sim.debug("PCI_PV")[:, 1].astype(np.float64)
+    band = 2.0 * np.abs(err_gpu - ref.err).max()
+    trace = h["trace_e"]
+    closest = np.nanmin(np.abs(trace[:, diff] - 0.5 * eta), axis=0)
+    for i, c in zip(diff, closest):
+        print(f"minor step {k}: S_e near-tie at particle {i} (id {ref.id[i]}): oracle error "
+              f"within {c:.3e} of eta/2, band {band:.3e}, gpu {se_gpu[i]} oracle {ref.in_se[i]}")
+    assert np.all(closest <= band) and diff.size <= 2, f"minor step {k}: S_e"
+    return int(diff.size)
+
+
+def run_both(steps, **over):
+    sc = scenes.pcisph_thrown_columns()
+    sim = Simulation(sc, **over)
+    ref = oracle.PCISPH(sc.params, sc.pos.astype(np.float32), vel=sc.vel,
+                        walls=sc.walls.astype(np.float32), **over)
+    ref.enable_trace(errors=True)
+    seen = dict(resets=0, reverts=0, early=0, short=0, back_to_long=0, mixed=0, marked=0,
+                ties=0)
+    prev_len = int(sc.params["n_minor"])
+    prev_region = None
+    for k in range(steps):
+        sim.advance(1)
+        st = sim.sync()
+        ref.step()
+        h = ref.history[-1]
+        for g, o in COUNTERS:
+            assert getattr(st, g) == h[o], f"minor step {k}: {g} {getattr(st, g)} vs {h[o]}"
+        assert list(st.level_hist)[:4] == h["hist"], f"minor step {k}: region histogram"
+        # per particle, in the block order of the current major step
+        assert np.array_equal(sim.debug("ID"), ref.id), f"minor step {k}: block order"
+        level, comp, _, val = decode_meta(sim.debug("META"))
+        assert np.array_equal(level + 1, ref.region), f"minor step {k}: regions"
+        assert np.array_equal(val, ref.validity), f"minor step {k}: validity"
+        assert np.array_equal(comp, ref.compute), f"minor step {k}: compute flags"
+        seen["ties"] += check_se(k, sim, ref, h, float(over.get("eta", sc.params["eta"])))
+        seen["resets"] += h["resets"]
+        seen["reverts"] += h["reverts"]
+        seen["early"] += h["early_end"]
+        seen["short"] += h["major_len"] < prev_len
+        seen["back_to_long"] += h["major_len"] > prev_len
+        seen["mixed"] = max(seen["mixed"], sum(1 for c in h["hist"] if c > 0))
+        # a region change within a major step is the smaller-step marking
+        if prev_region is not None and h["minor_in_major"] != 1:
+            seen["marked"] += int(np.count_nonzero(ref.region < prev_region))
+        prev_region = ref.region.copy()
+        prev_len = h["major_len"]
+    x_gpu = sim.state()["pos"]
+    x_ref = ref.in_caller_order(ref.x)
+    dx = np.abs(x_gpu - x_ref).max() / sc.params["spacing"]
+    print(f"{steps} minor steps {over}: max |dx| / s = {dx:.2e}, {seen}")
+    assert dx <= 1e-4
+    return sim, ref, seen
+
+
+def test_mixed_regions_local_phases_and_early_end():
+    """Default settings: the column thrown at the wall drives local phases
+    with reverts and a minor step past global_limit that ends its major step;
+    all four regions are present and regions shrink within major steps."""
+    _, _, seen = run_both(16)
+    assert seen["mixed"] == 4
+    assert seen["reverts"] > 0 and seen["early"] > 0 and seen["short"] > 0
+    assert seen["marked"] > 0
+
+
+def test_return_to_long_major_steps_after_clean_ones():
+    _, _, seen = run_both(12, short_majors=2)
+    assert seen["short"] == 1 and seen["back_to_long"] == 1
+
+
+def test_every_extra_iteration_restarts_the_schedule_when_the_mean_is_high():
+    """eta_T = 1e-9: the mean compression is always at least eta_T, so every
+    extra iteration is a global restart of the schedule and no local phase
+    runs."""
+    _, _, seen = run_both(8, eta_T=1e-9, it_max=12)
+    assert seen["resets"] > 0 and seen["reverts"] == 0
+
+
+def test_local_phases_revert_the_pressure_bit_for_bit():
+    """eta far below reach and eta_T far above: every minor step runs it_max
+    iterations of three scheduled rows and then alternating local phases of
+    local_fail iterations, each ending in a revert; the last iteration
+    (14 = 3 + 3 + 1 + 3 + 1 + 3) ends one, so the pressures after the step
+    equal their snapshot bit for bit."""
+    sim, ref, seen = run_both(6, eta=1e-6, eta_T=1.0, it_max=14)
+    for h in ref.history:
+        assert (h["iters"], h["global_iters"], h["reverts"]) == (14, 5, 3)
+    pv = sim.debug("PCI_PV")
+    assert np.array_equal(pv[:, 0].view(np.uint32), pv[:, 2].view(np.uint32))
