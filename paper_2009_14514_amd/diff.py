@@ -47,6 +47,7 @@ class DiffRollout:
         self.tape_ptr = addr + (-addr) % 256
         self.tape_bytes = nbytes
         self._last = None
+        self.generation = 0       # forward runs so far: the tape holds the last one only
 
     def desc(self, B, alpha):
         return _rts.diff_desc(self.n_sub, self.ckpt_every, self.list_cap, self.dt, B, alpha)
@@ -61,8 +62,9 @@ class DiffRollout:
         d = self.desc(B, alpha)
         _rts.diff_forward(self.sim.ctx, d, n, px.data_ptr(), pv.data_ptr(), xT.data_ptr(),
                           vT.data_ptr(), self.tape_ptr, self.tape_bytes)
-        st = self.sim.sync(raise_on_error=True)
+        self.sim.sync(raise_on_error=True)
         self._last = (float(B), float(alpha))
+        self.generation += 1
         return _unplanes(xT, n), _unplanes(vT, n)
 
     def backward(self, xT_bar, vT_bar=None):
@@ -94,11 +96,18 @@ def rollout_function():
         def forward(ctx, x0, v0, B, alpha, model):
             xT, _ = model.forward(x0, v0, float(B), float(alpha))
             ctx.model = model
+            ctx.generation = model.generation
             ctx.dtypes = (B.dtype, alpha.dtype, B.device)
             return xT
 
         @staticmethod
         def backward(ctx, g):
+            # the rollout keeps one tape: a later forward run on the same
+            # rollout has overwritten the checkpoints this backward needs
+            if ctx.model.generation != ctx.generation:
+                raise RuntimeError("the rollout ran forward again after this call; its tape "
+                                   "no longer holds this call's checkpoints (use one "
+                                   "DiffRollout per pending backward)")
             gx, gv, gB, ga = ctx.model.backward(g)
             bdt, adt, dev = ctx.dtypes
             return (gx, gv, torch.tensor(gB, dtype=bdt, device=dev),

@@ -53,13 +53,14 @@ def oracle_density(cfg, snap, which):
     return oracle.density(cfg, x, w, which=which)
 
 
-def oracle_forces_stage(cfg, snap, which):
+def oracle_forces_stage(cfg, snap, which, term_sums=False):
     """Force stage alone: the oracle consumes the GPU's own float density and
-    pressure of every particle (fresh for active, stale for the others)."""
+    pressure of every particle (fresh for active, stale for the others).
+    With ``term_sums`` also each particle's sum of term magnitudes."""
     perm = snap["PERM"]
     x = snap["PRE_POS"][perm, :3].astype(np.float64)
     v = snap["PRE_VEL"][perm, :3].astype(np.float64)
     rho = snap["POS"][:, 3].astype(np.float64)
     p = snap["VEL"][:, 3].astype(np.float64) * rho * rho   # the GPU keeps p / rho^2
     w = snap["WALL_POS"][:, :3].astype(np.float64)
-    return oracle.forces(cfg, x, v, rho, p, w, which=which)
+    return oracle.forces(cfg, x, v, rho, p, w, which=which, term_sums=term_sums)

@@ -109,9 +109,11 @@ def test_dense_cluster_takes_the_unstaged_path():
     rho_o, _ = oracle_density(cfg, snap, comp)
     rel = np.abs(snap["POS"][:, 3] - rho_o) / rho_o
     assert rel.max() <= 1e-5
-    a_o = oracle_forces_stage(cfg, snap, comp)
+    a_o, tsum = oracle_forces_stage(cfg, snap, comp, term_sums=True)
     a_g = snap["ACC_NEW"][:, :3].astype(np.float64)
     assert np.linalg.norm(a_g - a_o) <= 1e-5 * np.linalg.norm(a_o)
+    per = np.linalg.norm(a_g - a_o, axis=1) / tsum
+    assert per.max() <= 1e-5, (per.max(), np.argmax(per))
 
 
 def test_candidate_capacity_overflow_is_reported():

@@ -129,9 +129,19 @@ def test_iteration_stages_match_the_oracle(v0):
     assert np.abs(pv[:, 0] - p_want).max() <= 1e-5 * max(p_want.max(), 1.0)
     # pressure acceleration from the GPU's x*, p, rho*
     fp = sim.debug("PCI_FP")[:, :3].astype(np.float64)
-    want_fp = oracle.pci_pressure_force(cfg, xs, wx, pv[:, 0], pv[:, 3], nbr, nnb)
+    want_fp, tsum = oracle.pci_pressure_force(cfg, xs, wx, pv[:, 0], pv[:, 3], nbr, nnb,
+                                              term_sums=True)
     mag = np.linalg.norm(want_fp, axis=1)
     assert np.abs(fp - want_fp).max() <= 1e-5 * max(mag.max(), 1.0)
+    # per particle against the magnitudes of the terms of its acceleration
+    # update, |g| + sum_j |pair term|, as for the WCSPH force: a particle
+    # whose only term comes from a neighbour at the support's edge (where
+    # gradW ~ (2 - q)^2 is ill-conditioned in float) is measured against
+    # the gravity it falls with; particles with no pressure around them
+    # have no terms and exactly no force
+    dfp = np.linalg.norm(fp - want_fp, axis=1)
+    assert np.all(dfp[tsum == 0] == 0.0)
+    assert (dfp / (np.linalg.norm(g) + tsum)).max() <= 1e-5
 
 
 @pytest.mark.parametrize("mode", ["rts", "global_fixed"])
