@@ -185,7 +185,31 @@ rts_status rts_workspace_size(const rts_config *cfg, int64_t n_fluid_max, int64_
 rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
                       void *d_workspace, size_t bytes, void *hip_stream, rts_ctx **out);
 
-/* Releases the host context and its graphs.  The workspace stays the caller's. */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): rts_create with
+ * the library's own workspace instead of a caller buffer.  The workspace is
+ * a static device array of RTS_STATIC_WORKSPACE_BYTES per device, reserved
+ * when the library is loaded and held until the process ends; its address
+ * on the current device is looked up on the first call there.  The call
+ * allocates no device memory and launches only kernels on hip_stream (it
+ * clears the counters the run needs at zero; the array keeps whatever the
+ * previous context there left).  The context behaves exactly like one from
+ * rts_create; to keep rts_advance free of allocations too, set use_graph = 0
+ * (graph instantiation allocates).
+ *   RTS_E_CAPACITY: rts_workspace_size(cfg, n_fluid_max, n_wall_max) exceeds
+ *                   RTS_STATIC_WORKSPACE_BYTES;
+ *   RTS_E_STATE:    another live context on this device already uses the
+ *                   array (one at a time per device; rts_destroy frees it);
+ *   RTS_E_DEVICE:   no current device, or its array could not be located;
+ *   RTS_E_INVALID:  as rts_create.
+ * Work on the array from different host threads is serialised only at
+ * create / destroy: calls on one context must not overlap in time. */
+#define RTS_STATIC_WORKSPACE_BYTES (32u << 20)
+rts_status rts_create_static(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
+                             void *hip_stream, rts_ctx **out);
+
+/* Releases the host context and its graphs.  The workspace stays the caller's
+ * (a static-workspace context releases its claim on the device's array). */
 void rts_destroy(rts_ctx *ctx);
 
 /* Static wall particles (boundary; Section 6 uses static boundary particles).

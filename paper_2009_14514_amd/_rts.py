@@ -28,7 +28,8 @@ DBG = {name: i for i, name in enumerate([
 
 # exported symbols, in the order include/rts.h declares them
 EXPORTS = [
-    "rts_default_config", "rts_workspace_size", "rts_create", "rts_destroy", "rts_set_walls",
+    "rts_default_config", "rts_workspace_size", "rts_create", "rts_create_static", "rts_destroy",
+    "rts_set_walls",
     "rts_set_state", "rts_add_velocity", "rts_assign_levels", "rts_advance", "rts_sync",
     "rts_get_state", "rts_state_bytes", "rts_save_state", "rts_load_state", "rts_debug_get", "rts_grid_info",
     "rts_profile_advance", "rts_autotune", "rts_get_tune", "rts_diff_tape_bytes",
@@ -116,6 +117,7 @@ def lib():
         L.rts_default_config.restype = None
         L.rts_workspace_size.argtypes = [cfgp, i64, i64, C.POINTER(C.c_size_t)]
         L.rts_create.argtypes = [cfgp, i64, i64, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.rts_create_static.argtypes = [cfgp, i64, i64, vp, C.POINTER(vp)]
         L.rts_destroy.argtypes = [vp]
         L.rts_destroy.restype = None
         L.rts_set_walls.argtypes = [vp, vp, i64]
@@ -206,6 +208,14 @@ def create(cfg, n_fluid_max, n_wall_max, d_workspace, nbytes, stream):
     ctx = C.c_void_p()
     check(lib().rts_create(C.byref(cfg), int(n_fluid_max), int(n_wall_max), C.c_void_p(d_workspace),
                            int(nbytes), C.c_void_p(stream), C.byref(ctx)))
+    return ctx
+
+
+def create_static(cfg, n_fluid_max, n_wall_max, stream):
+    """A context in the library's static device workspace (no allocation)."""
+    ctx = C.c_void_p()
+    check(lib().rts_create_static(C.byref(cfg), int(n_fluid_max), int(n_wall_max),
+                                  C.c_void_p(stream), C.byref(ctx)))
     return ctx
 
 

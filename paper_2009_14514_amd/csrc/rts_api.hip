@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "rts_internal.h"
@@ -54,8 +55,24 @@ struct rts_ctx {
   bool binned;
   int tune_candidates;
   double tune_ms;
+  int static_dev;    // device whose static workspace holds this context, or -1
   char err[512];
 };
+
+// The library's own workspace for callers that cannot allocate device
+// memory (rts_create_static): one array per device, held until the process
+// ends.  Host code never uses the array's name as an address: each device's
+// address comes from hipGetSymbolAddress with that device current.
+static __device__ __align__(256) uint8_t scratch[RTS_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];   // device address of `scratch` on each device
+bool g_static_busy[kMaxDevices];   // a live context uses that device's array
+
+}  // namespace
 
 namespace {
 
@@ -420,12 +437,15 @@ void enqueue_step(rts_ctx *c, int cur, hipStream_t st) {
 rts_status unbin(rts_ctx *c) {
   if (!c->binned) return RTS_OK;
   c->binned = false;
-  HIP_OK(c, hipMemsetAsync(c->d.COUNT, 0, (size_t)c->prm.nb * 4, c->stream));
+  launch_fill(c->d.COUNT, 0, (size_t)c->prm.nb * 4, c->stream);
+  HIP_OK(c, hipGetLastError());
   return RTS_OK;
 }
 
 rts_status build_graphs(rts_ctx *c) {
   destroy_graphs(c);
+  if (!c->cap_stream)
+    HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   for (int k = 0; k < 2; ++k) {
     HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
     enqueue_step(c, k, c->cap_stream);
@@ -633,6 +653,74 @@ rts_status pci_minor_step(rts_ctx *c) {
   return RTS_OK;
 }
 
+// Context set-up in a given workspace.  Launches kernels only: no device
+// memory is allocated, and the stream for graph capture is created when
+// the first graph is built.  static_dev >= 0 marks a context living in the
+// library's static workspace of that device.
+rts_status create_in(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
+                     void *d_workspace, size_t bytes, void *hip_stream, int static_dev,
+                     rts_ctx **out) {
+  if (!out) return RTS_E_INVALID;
+  *out = nullptr;
+  char msg[256];
+  rts_status s = validate(cfg, msg, sizeof(msg));
+  if (s) return s;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255u) || n_fluid_max < 0 || n_wall_max < 0 ||
+      n_fluid_max > 0x7FFFFFFF || n_wall_max > 0x7FFFFFFF)
+    return RTS_E_INVALID;
+  rts_ctx *c = new (std::nothrow) rts_ctx();
+  if (!c) return RTS_E_DEVICE;
+  c->cfg = *cfg;
+  c->ncap = n_fluid_max;
+  c->nwcap = n_wall_max;
+  c->static_dev = static_dev;
+  derive(*cfg, n_fluid_max, n_wall_max, c->prm, c->mass, c->B, c->dt_base);
+  size_t need = carve(c->prm, n_fluid_max, n_wall_max, nullptr, nullptr);
+  if (bytes < need) {
+    delete c;
+    return RTS_E_CAPACITY;
+  }
+  carve(c->prm, n_fluid_max, n_wall_max, (char *)d_workspace, &c->d);
+  c->stream = (hipStream_t)hip_stream;
+  c->cur = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete c;
+    return RTS_E_DEVICE;
+  }
+  const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  // persistent grids: enough workgroups to fill every CU, each striding over
+  // the occupied blocks or taking active blocks by ticket (search and force:
+  // two 512-thread workgroups per CU are resident, limited by registers)
+  c->grid_wave = cus * 8;
+  c->grid_search = cus * 3;
+  c->grid_force = cus * 2;
+  // counts must start at zero; everything else is written before it is read
+  hipStream_t st = c->stream;
+  const size_t tiles = ((size_t)c->prm.nb + kScanTile - 1) / kScanTile * 8;
+  launch_fill(c->d.COUNT, 0, (size_t)c->prm.nb * 4, st);
+  launch_fill(c->d.TILES, 0, tiles, st);
+  launch_fill(c->d.TILES2, 0, tiles, st);
+  launch_fill(c->d.NNB, 0, (size_t)(n_fluid_max > 0 ? n_fluid_max : 1) * 4, st);
+  launch_fill(c->d.WCELL_START, 0, ((size_t)c->prm.nb + 1) * 4, st);
+  launch_fill(c->d.CTRL, 0, sizeof(DevCtrl), st);
+  if (cfg->solver == RTS_PCISPH) {
+    launch_fill(c->d.DEM, 0xFF, (size_t)c->prm.nb * 4, st);
+    launch_fill(c->d.PCI, 0, sizeof(DevPci), st);
+    launch_fill(c->d.OB, 0, (size_t)c->prm.nb, st);
+  }
+  c->pci_major_len = cfg->mode == RTS_MODE_RTS ? cfg->n_minor : 1;
+  launch_reset_scalars(c->d.S, st);
+  if (hipGetLastError() != hipSuccess) {
+    delete c;
+    return RTS_E_DEVICE;
+  }
+  *out = c;
+  return RTS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -722,71 +810,30 @@ rts_status rts_workspace_size(const rts_config *cfg, int64_t n_fluid_max, int64_
 
 rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
                       void *d_workspace, size_t bytes, void *hip_stream, rts_ctx **out) {
+  return create_in(cfg, n_fluid_max, n_wall_max, d_workspace, bytes, hip_stream, -1, out);
+}
+
+rts_status rts_create_static(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
+                             void *hip_stream, rts_ctx **out) {
   if (!out) return RTS_E_INVALID;
   *out = nullptr;
-  char msg[256];
-  rts_status s = validate(cfg, msg, sizeof(msg));
+  size_t need = 0;
+  rts_status s = rts_workspace_size(cfg, n_fluid_max, n_wall_max, &need);
   if (s) return s;
-  if (!d_workspace || ((uintptr_t)d_workspace & 255u) || n_fluid_max < 0 || n_wall_max < 0 ||
-      n_fluid_max > 0x7FFFFFFF || n_wall_max > 0x7FFFFFFF)
-    return RTS_E_INVALID;
-  rts_ctx *c = new (std::nothrow) rts_ctx();
-  if (!c) return RTS_E_DEVICE;
-  c->cfg = *cfg;
-  c->ncap = n_fluid_max;
-  c->nwcap = n_wall_max;
-  derive(*cfg, n_fluid_max, n_wall_max, c->prm, c->mass, c->B, c->dt_base);
-  size_t need = carve(c->prm, n_fluid_max, n_wall_max, nullptr, nullptr);
-  if (bytes < need) {
-    delete c;
-    return RTS_E_CAPACITY;
-  }
-  carve(c->prm, n_fluid_max, n_wall_max, (char *)d_workspace, &c->d);
-  c->stream = (hipStream_t)hip_stream;
-  c->cur = 0;
+  if (need > (size_t)RTS_STATIC_WORKSPACE_BYTES) return RTS_E_CAPACITY;
   int dev = 0;
-  (void)hipGetDevice(&dev);
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
-    delete c;
-    return RTS_E_DEVICE;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RTS_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RTS_E_DEVICE;
+    g_static_ptr[dev] = p;
   }
-  const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  // persistent grids: enough workgroups to fill every CU, each striding over
-  // the occupied blocks or taking active blocks by ticket (search and force:
-  // two 512-thread workgroups per CU are resident, limited by registers)
-  c->grid_wave = cus * 8;
-  c->grid_search = cus * 3;
-  c->grid_force = cus * 2;
-  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-    delete c;
-    return RTS_E_DEVICE;
-  }
-  // counts must start at zero; everything else is written before it is read
-  hipError_t e = hipMemsetAsync(c->d.COUNT, 0, (size_t)c->prm.nb * 4, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->d.TILES, 0,
-                                          ((size_t)c->prm.nb + kScanTile - 1) / kScanTile * 8,
-                                          c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->d.TILES2, 0,
-                                          ((size_t)c->prm.nb + kScanTile - 1) / kScanTile * 8,
-                                          c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->d.NNB, 0, (size_t)(n_fluid_max > 0 ? n_fluid_max : 1) * 4, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->d.WCELL_START, 0, ((size_t)c->prm.nb + 1) * 4, c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->d.CTRL, 0, sizeof(DevCtrl), c->stream);
-  if (e == hipSuccess && cfg->solver == RTS_PCISPH) {
-    e = hipMemsetAsync(c->d.DEM, 0xFF, (size_t)c->prm.nb * 4, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d.PCI, 0, sizeof(DevPci), c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d.OB, 0, (size_t)c->prm.nb, c->stream);
-  }
-  c->pci_major_len = cfg->mode == RTS_MODE_RTS ? cfg->n_minor : 1;
-  if (e != hipSuccess) {
-    (void)hipStreamDestroy(c->cap_stream);
-    delete c;
-    return RTS_E_DEVICE;
-  }
-  launch_reset_scalars(c->d.S, c->stream);
-  *out = c;
-  return RTS_OK;
+  if (g_static_busy[dev]) return RTS_E_STATE;
+  s = create_in(cfg, n_fluid_max, n_wall_max, g_static_ptr[dev],
+                (size_t)RTS_STATIC_WORKSPACE_BYTES, hip_stream, dev, out);
+  if (s == RTS_OK) g_static_busy[dev] = true;
+  return s;
 }
 
 void rts_destroy(rts_ctx *c) {
@@ -794,6 +841,10 @@ void rts_destroy(rts_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_busy[c->static_dev] = false;
+  }
   delete c;
 }
 

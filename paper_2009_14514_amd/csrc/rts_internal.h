@@ -212,6 +212,8 @@ void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos,
                       float *acc, float *rho, float *pres, uint8_t *level, hipStream_t st);
 void launch_wall_sort(const DevParams &p, const DevPtrs &d, const float *pos, hipStream_t st);
 void launch_reset_scalars(DevScalars *S, hipStream_t st);
+// p must be 4-byte aligned
+void launch_fill(void *p, uint8_t v, size_t bytes, hipStream_t st);
 
 // PCISPH launchers (pcisph_kernels.hip)
 void launch_pci_dilate(const DevParams &p, const DevPtrs &d, const uint8_t *src, uint8_t *dst,

@@ -1255,6 +1255,18 @@ __global__ void __launch_bounds__(64) k_wall_gather(DevParams p, const uint32_t 
   }
 }
 
+// Byte fill of a device range (a kernel rather than hipMemsetAsync, so that
+// set-up and resets stay plain kernel launches on the caller's stream).
+__global__ void k_fill_bytes(uint8_t *p, uint8_t v, size_t bytes) {
+  const uint32_t w = (uint32_t)v * 0x01010101u;
+  const size_t words = bytes >> 2;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+    reinterpret_cast<uint32_t *>(p)[i] = w;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (bytes & 3u)) p[(words << 2) + t] = v;
+}
+
 __global__ void k_reset_scalars(DevScalars *S) {
   DevScalars z = {};
   z.bad_index = -1;
@@ -1360,6 +1372,12 @@ void launch_wall_sort(const DevParams &p, const DevPtrs &d, const float *pos, hi
     hipLaunchKernelGGL(k_wall_gather, dim3((unsigned)p.nb), dim3(64), 0, st, p, d.WCELL_START,
                        d.WTMP, pos, d.WP, d.WID, d.S);
   }
+}
+void launch_fill(void *p, uint8_t v, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return;
+  const size_t words = (bytes + 3) / 4;
+  const unsigned grid = (unsigned)(words < 256 * 1024 ? (words + 255) / 256 : 1024);
+  hipLaunchKernelGGL(k_fill_bytes, dim3(grid), dim3(256), 0, st, (uint8_t *)p, v, bytes);
 }
 void launch_reset_scalars(DevScalars *S, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, st, S);

@@ -33,9 +33,12 @@ class Simulation:
 
     ``scene`` is a :class:`paper_2009_14514_amd.scenes.Scene`; keyword
     arguments override entries of its parameter dictionary.
+    ``static_workspace`` places the context in the library's static device
+    workspace (rts_create_static) instead of a torch allocation.
     """
 
-    def __init__(self, scene, device="cuda", n_fluid_max=None, n_wall_max=None, **over):
+    def __init__(self, scene, device="cuda", n_fluid_max=None, n_wall_max=None,
+                 static_workspace=False, **over):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("the RTS library needs a GPU; none is visible")
@@ -48,11 +51,17 @@ class Simulation:
         self.nw = scene.nw
         self.n_fluid_max = int(n_fluid_max if n_fluid_max is not None else max(self.n, 1))
         self.n_wall_max = int(n_wall_max if n_wall_max is not None else max(self.nw, 1))
-        nbytes = _rts.workspace_size(self.cfg, self.n_fluid_max, self.n_wall_max)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
-        self.ctx = _rts.create(self.cfg, self.n_fluid_max, self.n_wall_max,
-                               _aligned(self.workspace), nbytes, self.stream.cuda_stream)
+        if static_workspace:
+            # the library's own device array: nothing is allocated here
+            self.workspace = None
+            self.ctx = _rts.create_static(self.cfg, self.n_fluid_max, self.n_wall_max,
+                                          self.stream.cuda_stream)
+        else:
+            nbytes = _rts.workspace_size(self.cfg, self.n_fluid_max, self.n_wall_max)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.ctx = _rts.create(self.cfg, self.n_fluid_max, self.n_wall_max,
+                                   _aligned(self.workspace), nbytes, self.stream.cuda_stream)
         self.info = _rts.grid_info(self.ctx)
         self.set_walls(scene.walls)
         self.set_state(scene.pos, scene.vel)
