@@ -39,6 +39,7 @@ class OrcCfg(C.Structure):
         ("adapt_dt", C.c_int32), ("grow_iters", C.c_int32), ("shrink_iters", C.c_int32),
         ("pad_adapt", C.c_int32), ("dt_min", C.c_double),
         ("dt_max", C.c_double), ("grow", C.c_double), ("shrink", C.c_double),
+        ("phase_align", C.c_int32), ("pad_phase", C.c_int32),
     ]
 
 
@@ -143,7 +144,8 @@ def _declare(L):
     L.orc_sort.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_block_levels.argtypes = [cfgp, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_rmin.argtypes = [cfgp, C.c_void_p, C.c_void_p]
-    L.orc_flags.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_flags.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_int64, C.c_int32]
     L.orc_neighbors.argtypes = [cfgp, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                 C.c_int32, C.c_void_p, C.c_void_p]
     L.orc_density.argtypes = [cfgp, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
@@ -232,6 +234,7 @@ def cfg_from_params(p: dict, **over) -> OrcCfg:
     c.shrink_iters = int(q.get("pci_shrink_iters", 0))
     c.dt_min, c.dt_max = q.get("pci_dt_min", 0.0), q.get("pci_dt_max", 0.0)
     c.grow, c.shrink = q.get("pci_grow", 1.02), q.get("pci_shrink", 0.95)
+    c.phase_align = int(q.get("phase_align", 0))
     return c
 
 
@@ -297,13 +300,15 @@ def rmin(cfg, lvl):
     return out
 
 
-def flags(key, blk, level, validity):
+def flags(key, blk, level, validity, step=0, phase_align=0):
+    """W5 at base step ``step``: (level, validity, compute)."""
     key = np.ascontiguousarray(key, np.uint32)
     blk = np.ascontiguousarray(blk, np.uint8)
     level = np.array(level, np.int32, copy=True)
     validity = np.array(validity, np.int32, copy=True)
     compute = np.zeros(key.shape[0], np.uint8)
-    lib().orc_flags(key.shape[0], _ptr(key), _ptr(blk), _ptr(level), _ptr(validity), _ptr(compute))
+    lib().orc_flags(key.shape[0], _ptr(key), _ptr(blk), _ptr(level), _ptr(validity),
+                    _ptr(compute), int(step), int(phase_align))
     return level, validity, compute
 
 

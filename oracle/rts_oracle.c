@@ -252,14 +252,17 @@ void orc_rmin(const orc_cfg *c, const uint8_t *in, uint8_t *out) {
  * pre-emption rule); an active particle takes the block's step and a
  * validity of 2^level base steps. */
 void orc_flags(int32_t n, const uint32_t *key, const uint8_t *blk, int32_t *level,
-               int32_t *validity, uint8_t *compute) {
+               int32_t *validity, uint8_t *compute, int64_t step, int32_t phase_align) {
   for (int32_t i = 0; i < n; ++i) {
     int32_t bl = blk[key[i]];
     validity[i] -= 1;
     if (validity[i] <= 0 || level[i] != bl) {
+      /* due: the step of its block, for 2^l base steps (Algorithm 1), or
+       * up to the next multiple of 2^l (phase-aligned) */
+      const int32_t len = 1 << bl;
       compute[i] = 1;
       level[i] = bl;
-      validity[i] = 1 << bl;
+      validity[i] = phase_align ? len - (int32_t)(step % len) : len;
     } else {
       compute[i] = 0;
     }
@@ -601,7 +604,7 @@ int orc_wcsph_step(const orc_cfg *c, orc_state *s) {
   orc_rmin(c, lraw, lvl);
 
   /* W5 */
-  orc_flags(n, X.gf.key, lvl, s->level, s->validity, s->compute);
+  orc_flags(n, X.gf.key, lvl, s->level, s->validity, s->compute, s->step, c->phase_align);
 
   /* W6-W8 */
   status = ctx_lists(&X, s->compute);

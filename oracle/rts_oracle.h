@@ -61,6 +61,12 @@ typedef struct orc_cfg {
   int32_t pad_adapt;
   double dt_min, dt_max;             /* bounds of the adapted step (<= 0: dt_base/4, 4 dt_base) */
   double grow, shrink;               /* factors after an easy / an overrun major step */
+  /* WCSPH: 1 = a particle that takes level l is next due at the next base
+   * step that is a multiple of 2^l (so every particle of a level updates on
+   * the same steps); 0 = 2^l base steps after the current one (Algorithm 1
+   * as printed) */
+  int32_t phase_align;
+  int32_t pad_phase;
 } orc_cfg;
 
 typedef struct orc_info {
@@ -104,8 +110,9 @@ int  orc_sort(int64_t nb, int32_t n, const uint32_t *key, uint32_t *perm, uint32
 void orc_block_levels(const orc_cfg *c, int32_t n, const uint32_t *key, const float *vel,
                       const float *acc, uint8_t *lvl);
 void orc_rmin(const orc_cfg *c, const uint8_t *lvl_in, uint8_t *lvl_out);
+/* W5 at base step `step` (the number of steps taken before it). */
 void orc_flags(int32_t n, const uint32_t *key, const uint8_t *blk, int32_t *level,
-               int32_t *validity, uint8_t *compute);
+               int32_t *validity, uint8_t *compute, int64_t step, int32_t phase_align);
 int  orc_neighbors(const orc_cfg *c, int32_t n, const float *pos, int32_t nw, const float *wpos,
                    const uint8_t *want, int32_t cap, uint32_t *nbr, int32_t *nnb);
 

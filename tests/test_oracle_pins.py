@@ -394,6 +394,69 @@ def test_preemption_when_the_block_level_changes():
     assert comp[0] == 1 and level[0] == 1 and val[0] == 2
 
 
+@pytest.mark.parametrize("step,level,validity", [
+    (0, 3, 8), (13, 3, 3), (16, 3, 8), (23, 3, 1), (13, 2, 3), (14, 2, 2), (15, 1, 1),
+    (16, 1, 2), (7, 0, 1), (101, 0, 1)])
+def test_phase_aligned_validity_runs_to_the_next_multiple(step, level, validity):
+    """Phase alignment: a particle that takes level l at base step k is next
+    due at the first multiple of 2^l after k (hand-computed table)."""
+    key = np.zeros(1, np.uint32)
+    lv, val, comp = O.flags(key, np.array([level], np.uint8), np.full(1, 0xF, np.int32),
+                            np.zeros(1, np.int32), step=step, phase_align=1)
+    assert comp[0] == 1 and lv[0] == level and val[0] == validity
+    # Algorithm 1 as printed: 2^l steps from now, whatever the step index
+    lv, val, comp = O.flags(key, np.array([level], np.uint8), np.full(1, 0xF, np.int32),
+                            np.zeros(1, np.int32), step=step, phase_align=0)
+    assert val[0] == 2 ** level
+
+
+def test_phase_aligned_particles_of_a_level_update_together():
+    """Particles taking level 3 at different steps (their block's level
+    changes at staggered times) end up due on the same steps, the multiples
+    of 8, and no step is longer than 8 base steps."""
+    key = np.arange(4, dtype=np.uint32)
+    level = np.full(4, 0xF, np.int32)
+    val = np.zeros(4, np.int32)
+    blk = np.zeros(4, np.uint8)
+    due = {i: [] for i in range(4)}
+    last = np.zeros(4, np.int64)
+    for step in range(48):
+        blk = np.array([3 if step >= s else 0 for s in (0, 3, 5, 11)], np.uint8)
+        level, val, comp = O.flags(key, blk, level, val, step=step, phase_align=1)
+        for i in range(4):
+            if comp[i]:
+                assert step == 0 or step - last[i] <= 2 ** 3
+                last[i] = step
+                due[i].append(step)
+    for i in range(4):
+        late = [k for k in due[i] if k >= 16]
+        assert late == [16, 24, 32, 40], (i, due[i])
+
+
+def test_phase_aligned_run_computes_exactly_on_multiples_or_level_changes():
+    """A developed RTS run with phase alignment: at every base step k a
+    particle computes iff its level changed at k or k is a multiple of
+    2^level; with level cap 0 the run is global stepping bit for bit."""
+    sc = scenes.dam_break_column(counts=(10, 14, 8), spacing=0.02, box=(0.6, 0.4, 0.3),
+                                 c0=scenes.sound_speed_for_column(0.28, factor=10.0))
+    a = O.WCSPH(sc.params, sc.pos, walls=sc.walls, mode="rts", phase_align=1)
+    prev = a.level.copy()
+    seen_levels = set()
+    for k in range(60):
+        a.step(1)
+        lv = a.level
+        seen_levels |= set(np.unique(lv).tolist())
+        want = (lv != prev) | (k % (1 << lv) == 0)
+        assert np.array_equal(a.compute.astype(bool), want), f"step {k}"
+        prev = lv.copy()
+    assert len(seen_levels) >= 2
+    b = O.WCSPH(sc.params, sc.pos, walls=sc.walls, mode="rts", level_cap=0, phase_align=1)
+    g = O.WCSPH(sc.params, sc.pos, walls=sc.walls, mode="global_fixed")
+    b.step(12)
+    g.step(12)
+    assert np.array_equal(b.x, g.x) and np.array_equal(b.v, g.v)
+
+
 def test_rts_with_every_block_at_level_zero_is_global_stepping():
     sc = scenes.dam_break_column(counts=(10, 14, 8), spacing=0.02, box=(0.6, 0.4, 0.3))
     a = O.WCSPH(sc.params, sc.pos, walls=sc.walls, mode="rts", level_cap=0)
