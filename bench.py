@@ -1,21 +1,29 @@
 """Benchmark: WCSPH regional time stepping vs global adaptive stepping on one GPU.
 
 Workload: the 250,000-particle dam break (column 0.5 x 1.0 x 0.5 m at spacing
-0.01 m in a 2 x 1 x 1 m box), block levels 0..3, K base steps (default 500).
+0.01 m in a 2 x 1 x 1 m box), block levels 0..3 with phase-aligned updates.
 A step is one base step of the whole path (grid rebuild, block levels, flags,
 neighbour search + density, forces, corrector/predictor).
 
+Equal error: each arm runs at its own sound speed, the smallest (on a grid)
+that keeps its max compression at or below 1 % over the whole collapse,
+0 -> 0.3 s, through the front's impact on the far wall.
+
 Printed: one JSON line.  ``value`` is RTS particle-steps/s (particles x base
-steps / wall seconds, inputs resident in HBM).  The global adaptive
-comparator is timed over the same simulated time.  The dominant kernel's
-roofline comes from an event-bracketed replay of the same K steps; the CPU
-baseline is the FP64 oracle on a bounded window of the same workload.
+steps / wall seconds, inputs resident in HBM) over K base steps from the
+developed state at 0.15 s, the median of the repeats; the global adaptive
+comparator is timed over the same simulated window from its own state at
+0.15 s.  ``collapse_leg`` times both arms over 0 -> 0.3 s
+(``speedup_at_equal_error``).  The dominant kernel's roofline comes from an
+event-bracketed run of the same K steps; the CPU baseline is the FP64
+oracle on a bounded window of the same workload.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -31,6 +39,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repeats of the K-step window (the median is reported)")
+    ap.add_argument("--no-leg", action="store_true",
+                    help="skip the 0 -> 0.3 s collapse leg at equal error")
+    ap.add_argument("--save-state", default="",
+                    help="write the RTS arm's developed state to this file")
+    ap.add_argument("--load-state", default="",
+                    help="start the RTS arm from this saved state instead of running to it "
+                         "(profiler runs: only the timed window is traced)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time spent on the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -45,8 +62,8 @@ def parse():
                     help="run the PCISPH comparison only (for profiler runs); no JSON line")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="base steps of the 64-scene batch and of its sequential runs (0: skip)")
-    ap.add_argument("--more-steps", type=int, default=500,
-                    help="base steps of the double dam break and block drop legs (0: skip)")
+    ap.add_argument("--more-time", type=float, default=0.3,
+                    help="simulated seconds of the double dam break and block drop legs (0: skip)")
     ap.add_argument("--diff-repeats", type=int, default=3,
                     help="timed forward+backward runs of the differentiable 101k scene (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -109,11 +126,92 @@ def kernel_traffic(name, n, nb, K, act, inter, cand):
     return table[name]
 
 
-def run_gpu(args):
-    import numpy as np
+# Sound speeds c0 = F sqrt(2 g H) of the two arms (H = 1 m column): for each
+# arm the smallest F on a grid of step 1-2 whose 0 -> 0.3 s collapse keeps
+# the max compression at or below 1 % (calibration sweep measured on one
+# MI355X; the collapse leg below re-runs F and the grid point under it).
+C0_FACTOR_RTS = 42.0
+C0_FACTOR_GA = 39.0
+C0_FACTOR_BELOW = {C0_FACTOR_RTS: 40.0, C0_FACTOR_GA: 38.0}
+T_DEVELOPED = 0.15     # s: the timed window starts from the state at this time
+T_LEG = 0.3            # s: collapse leg, past the front's impact on the far wall
+ERR_BOUND = 0.01
+
+
+def dam_break(factor):
+    from paper_2009_14514_amd import scenes
+    return scenes.dam_break_column(c0=scenes.sound_speed_for_column(1.0, factor=factor))
+
+
+def advance_to(sim, t_end, chunk=100):
+    """Advances in chunks until the simulated time reaches t_end; returns the
+    last stats and the max compression seen up to 0.2 s (before the front
+    meets the far wall)."""
+    err_pre = 0.0
+    while True:
+        sim.advance(chunk)
+        st = sim.sync()
+        if st.time <= 0.2 + 1e-12:
+            err_pre = float(st.err_max_run)
+        if st.time >= t_end * (1.0 - 1e-12):
+            return st, err_pre
+
+
+def run_leg(mode, factor):
+    """0 -> T_LEG of the 250k dam break; wall time per simulated second."""
     import torch
 
-    from paper_2009_14514_amd import scenes
+    from paper_2009_14514_amd.sim import Simulation
+
+    sc = dam_break(factor)
+    sim = Simulation(sc, mode=mode)
+    init = sim.save()
+    sim.advance(10)                              # graphs built, caches warm
+    sim.sync()
+    sim.load(init)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, err_pre = advance_to(sim, T_LEG)
+    el = time.perf_counter() - t0
+    sim.close()
+    r = dict(mode=mode, c0_factor=factor, c0=sc.params["c0"], sim_time_s=st.time,
+             steps=int(st.step), wall_ms=el * 1e3, ms_per_sim_s=el * 1e3 / st.time,
+             density_err_max=float(st.err_max_run), density_err_max_to_0p2s=err_pre,
+             active_fraction=st.active_total / (st.step * sc.n))
+    print(f"[bench] leg {mode} F={factor:g}: {st.step} steps to {st.time:.4f} s in "
+          f"{el * 1e3:.1f} ms, max compression {st.err_max_run * 100:.3f} %", file=sys.stderr,
+          flush=True)
+    return r
+
+
+def run_collapse_leg():
+    """Both arms over the whole collapse at their calibrated sound speeds, the
+    grid point below each (which must exceed the bound: the calibration is
+    the smallest passing one), and both at the common 20 sqrt(2 g H)."""
+    legs = {}
+    for mode, f in (("rts", C0_FACTOR_RTS), ("global_adaptive", C0_FACTOR_GA)):
+        legs[mode] = run_leg(mode, f)
+        legs[mode + "_below"] = run_leg(mode, C0_FACTOR_BELOW[f])
+    legs["rts_equal_c0"] = run_leg("rts", 20.0)
+    legs["global_adaptive_equal_c0"] = run_leg("global_adaptive", 20.0)
+    r, g = legs["rts"], legs["global_adaptive"]
+    both_ok = r["density_err_max"] <= ERR_BOUND and g["density_err_max"] <= ERR_BOUND
+    return {
+        "workload": "wcsph_dam_break_250k_collapse_0_to_0.3s",
+        "err_bound": ERR_BOUND,
+        "speedup_at_equal_error": g["ms_per_sim_s"] / r["ms_per_sim_s"] if both_ok else None,
+        "calibration_minimal": {
+            "rts": legs["rts_below"]["density_err_max"] > ERR_BOUND,
+            "global_adaptive": legs["global_adaptive_below"]["density_err_max"] > ERR_BOUND},
+        "speedup_at_equal_c0": (legs["global_adaptive_equal_c0"]["ms_per_sim_s"]
+                                / legs["rts_equal_c0"]["ms_per_sim_s"]),
+        "runs": legs,
+    }
+
+
+def run_gpu(args):
+    import torch
+
     from paper_2009_14514_amd.sim import Simulation
 
     torch.cuda.set_device(0)
@@ -125,11 +223,11 @@ def run_gpu(args):
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    sc = scenes.dam_break_column()          # 250,000 particles, levels 0..3
-    K, W = args.steps, args.warmup
+    K, W, R = args.steps, args.warmup, max(args.repeats, 1)
     out = {}
 
     def timed(sim, steps):
+        # HIP events on the library's stream around `steps` queued steps
         st = sim.stream
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -139,59 +237,102 @@ def run_gpu(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
-    # --- RTS ------------------------------------------------------------------
-    rts = Simulation(sc, mode="rts")
-    init = rts.save()
-    if W:
-        rts.advance(W)
-        rts.sync()
-        rts.load(init)
-    ms_rts = timed(rts, K)
-    st_rts = rts.sync()
-    T = st_rts.time
-    print(f"[bench] rts: {K} steps in {ms_rts:.2f} ms, active {st_rts.active_total}, "
-          f"err_max {st_rts.err_max_run:.4f}", file=sys.stderr, flush=True)
+    def window_error(sim, snap, steps):
+        """Max compression over the steps of the window (untimed pass)."""
+        sim.load(snap)
+        e = 0.0
+        for _ in range(steps):
+            sim.advance(1)
+            e = max(e, float(sim.sync().err_max_last))
+        return e
+
+    def developed(mode, factor):
+        """A context holding the state at T_DEVELOPED (run untimed from rest),
+        saved for the repeats; W warm-up steps from it are run and undone."""
+        sc = dam_break(factor)
+        sim = Simulation(sc, mode=mode)
+        if args.load_state and mode == "rts":
+            import numpy as np
+            buf = torch.from_numpy(np.fromfile(args.load_state, dtype=np.uint8)).cuda()
+            sim.load(buf)
+        else:
+            advance_to(sim, T_DEVELOPED)
+        snap = sim.save()
+        if args.save_state and mode == "rts":
+            snap.cpu().numpy().tofile(args.save_state)
+        if W:
+            sim.advance(W)
+            sim.sync()
+            sim.load(snap)
+        return sc, sim, snap
+
+    # --- RTS: K base steps from the developed state, median of R repeats -------
+    sc, rts, snap_r = developed("rts", C0_FACTOR_RTS)
+    snap_stats_r = rts.sync()
+    t_start = snap_stats_r.time
+    ms_r = []
+    for _ in range(R):
+        rts.load(snap_r)
+        ms_r.append(timed(rts, K))
+    st_r = rts.sync()
+    T = st_r.time - t_start
+    ms_rts = statistics.median(ms_r)
+    print(f"[bench] rts: {K} steps from t = {t_start:.4f} s, median {ms_rts:.3f} ms of "
+          f"{R} ({min(ms_r):.3f}-{max(ms_r):.3f}), active {st_r.active_total}, "
+          f"err_max {st_r.err_max_last:.4f}", file=sys.stderr, flush=True)
     if args.only_rts:
+        if not args.no_profile:
+            rts.load(snap_r)
+            rts.profile(K)
         rts.close()
         return None
 
-    # --- global adaptive comparator over the same simulated time ---------------
-    ga = Simulation(sc, mode="global_adaptive")
-    ga_init = ga.save()
-    if W:
-        ga.advance(W)
-        ga.sync()
-        ga.load(ga_init)
-    ms_ga = timed(ga, K)
-    st_ga = ga.sync()
-    while st_ga.time < T * (1.0 - 1e-9):
-        ms_ga += timed(ga, 10)
-        st_ga = ga.sync()
-    print(f"[bench] global adaptive: {st_ga.step} steps in {ms_ga:.2f} ms, "
-          f"err_max {st_ga.err_max_run:.4f}", file=sys.stderr, flush=True)
+    # --- global adaptive over the same simulated window -------------------------
+    _, ga, snap_g = developed("global_adaptive", C0_FACTOR_GA)
+    tg0 = ga.sync().time
+    steps_g = 0
+    while True:                                  # untimed: how many steps cover T
+        ga.advance(1)
+        steps_g += 1
+        if ga.sync().time - tg0 >= T * (1.0 - 1e-12):
+            break
+    ms_g = []
+    for _ in range(R):
+        ga.load(snap_g)
+        ms_g.append(timed(ga, steps_g))
+    st_g = ga.sync()
+    T_g = st_g.time - tg0
+    ms_ga = statistics.median(ms_g)
+    print(f"[bench] global adaptive: {steps_g} steps over {T_g:.3e} s, median {ms_ga:.3f} ms",
+          file=sys.stderr, flush=True)
 
+    err_r = window_error(rts, snap_r, K)
+    err_g = window_error(ga, snap_g, steps_g)
     n = sc.n
+    dtb = st_r.dt_last
     ps_rts = n * K / (ms_rts * 1e-3)
-    ps_ga = n * (st_ga.time / st_rts.dt_last) / (ms_ga * 1e-3)
+    # base-step equivalents of the comparator's simulated time
+    ps_ga = n * (T_g / dtb) / (ms_ga * 1e-3)
     out.update(
-        n=n, nw=sc.nw, K=K, ms_rts=ms_rts, ms_ga=ms_ga, ps_rts=ps_rts, ps_ga=ps_ga,
-        sim_time=T, dt_base=st_rts.dt_last,
-        rts=dict(active_total=st_rts.active_total, inter_total=st_rts.inter_total,
-                 cand_total=st_rts.cand_total, err_max=float(st_rts.err_max_run),
-                 level_hist_last=list(st_rts.level_hist)[:4], nbr_max=st_rts.nbr_max),
-        ga=dict(steps=st_ga.step, active_total=st_ga.active_total,
-                inter_total=st_ga.inter_total, err_max=float(st_ga.err_max_run)),
+        n=n, nw=sc.nw, K=K, R=R, ms_rts=ms_rts, ms_rts_all=ms_r, ms_ga=ms_ga, ms_ga_all=ms_g,
+        ps_rts=ps_rts, ps_ga=ps_ga, sim_time=T, t_start=t_start, dt_base=dtb, c0=sc.params["c0"],
+        rts=dict(active=st_r.active_total - snap_stats_r.active_total,
+                 inter=st_r.inter_total - snap_stats_r.inter_total,
+                 err_window=err_r, level_hist_last=list(st_r.level_hist)[:4]),
+        ga=dict(steps=steps_g, sim_time=T_g, c0=ga.params["c0"], err_window=err_g),
         nblocks=rts.info["nblocks"],
     )
 
     # --- per-kernel times: the same K steps, kernels bracketed by HIP events -----
     if not args.no_profile:
-        rts.load(init)
+        rts.load(snap_r)
+        a0 = rts.sync()
         prof = rts.profile(K)
         st_p = rts.sync()
         out["kernels_ms"] = prof
-        out["prof_counts"] = dict(active=st_p.active_total, inter=st_p.inter_total,
-                                  cand=st_p.cand_total)
+        out["prof_counts"] = dict(active=st_p.active_total - a0.active_total,
+                                  inter=st_p.inter_total - a0.inter_total,
+                                  cand=st_p.cand_total - a0.cand_total)
     rts.close()
     ga.close()
     return out
@@ -370,71 +511,91 @@ def run_diff(repeats):
                            "alpha": ga}}
 
 
-def run_more_wcsph(steps):
+def run_more_wcsph(t_end):
     """The paper's other WCSPH scenes as synthetic stand-ins: a double dam
-    break (256,000 particles) and a dam break with a dropped block (177,000);
-    regional vs global adaptive stepping over the same simulated time."""
+    break (256,000 particles) and a dam break with a dropped block (177,000),
+    from rest to t_end, each arm at the dam break's calibrated sound speed
+    (scaled to the scene's height); wall time per simulated second."""
     import torch
 
     from paper_2009_14514_amd import scenes
     from paper_2009_14514_amd.sim import Simulation
 
-    def run(sim, k):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.advance(k)
-        st = sim.sync()
-        return (time.perf_counter() - t0) * 1e3, st
-
     out = {}
     for name, make in (("wcsph_double_dam_break_256k", scenes.wcsph_double_dam_break),
                        ("wcsph_block_drop_177k", scenes.block_drop)):
-        sc = make()
-        rts = Simulation(sc, mode="rts")
-        init = rts.save()
-        rts.advance(10)
-        rts.sync()
-        rts.load(init)
-        ms_r, st_r = run(rts, steps)
-        ga = Simulation(sc, mode="global_adaptive")
-        ms_g, st_g = run(ga, steps)
-        while st_g.time < st_r.time * (1.0 - 1e-9):
-            m, st_g = run(ga, 10)
-            ms_g += m
-        out[name] = {"n_particles": sc.n, "base_steps": steps,
-                     "value": sc.n * steps / (ms_r * 1e-3), "unit": "particle-steps/s",
-                     "density_err_max": float(st_r.err_max_run),
-                     "global_adaptive_err_max": float(st_g.err_max_run),
-                     "speedup_vs_global_adaptive": ms_g / ms_r}
-        print(f"[bench] {name}: rts {ms_r:.1f} ms, global adaptive {ms_g:.1f} ms",
+        res = {}
+        for mode, f in (("rts", C0_FACTOR_RTS), ("global_adaptive", C0_FACTOR_GA)):
+            sc = make()
+            # the generators take 20 sqrt(2 g H) for their height H
+            sim = Simulation(sc, mode=mode, c0=sc.params["c0"] * f / 20.0)
+            init = sim.save()
+            sim.advance(10)
+            sim.sync()
+            sim.load(init)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, _ = advance_to(sim, t_end)
+            el = (time.perf_counter() - t0) * 1e3
+            res[mode] = dict(ms=el, sim_time_s=st.time, steps=int(st.step),
+                             ms_per_sim_s=el / st.time, density_err_max=float(st.err_max_run),
+                             c0_m_s=sim.params["c0"],
+                             active_fraction=st.active_total / (st.step * sc.n))
+            sim.close()
+        r, g = res["rts"], res["global_adaptive"]
+        out[name] = {"n_particles": sc.n, "sim_time_s": t_end,
+                     "value": sc.n * r["steps"] / (r["ms"] * 1e-3), "unit": "particle-steps/s",
+                     "rts": r, "global_adaptive": g,
+                     "speedup_vs_global_adaptive": g["ms_per_sim_s"] / r["ms_per_sim_s"]}
+        print(f"[bench] {name}: rts {r['ms']:.1f} ms ({r['density_err_max'] * 100:.2f} %), "
+              f"global adaptive {g['ms']:.1f} ms ({g['density_err_max'] * 100:.2f} %)",
               file=sys.stderr, flush=True)
-        rts.close()
-        ga.close()
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def run_cpu_baseline(budget_s):
-    """FP64 oracle, RTS mode, on the first steps of the same workload."""
+    """FP64 oracle on the same workload from rest, each arm at its sound
+    speed: RTS for about 40 % of the budget, then global adaptive stepping
+    over the same simulated time (bounded by the rest of the budget)."""
     import numpy as np
 
     import oracle
-    from paper_2009_14514_amd import scenes
 
-    sc = scenes.dam_break_column()
-    sim = oracle.WCSPH(sc.params, sc.pos.astype(np.float32), walls=sc.walls.astype(np.float32),
-                       mode="rts")
-    t0 = time.time()
-    steps = 0
-    while True:
-        sim.step()
-        steps += 1
-        el = time.time() - t0
-        if el >= budget_s or steps >= 500:
-            break
-    return dict(value=sc.n * steps / el, unit="particle-steps/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"first {steps} RTS base steps of the 250,000-particle dam break "
-                       f"(FP64, {el:.1f} s)")
+    def arm(mode, factor, t_end, budget):
+        sc = dam_break(factor)
+        sim = oracle.WCSPH(sc.params, sc.pos.astype(np.float32),
+                           walls=sc.walls.astype(np.float32), mode=mode)
+        t0 = time.time()
+        steps = 0
+        while True:
+            sim.step()
+            steps += 1
+            el = time.time() - t0
+            if el >= budget or (t_end is not None and sim.t >= t_end * (1.0 - 1e-12)):
+                return sc.n, steps, sim.t, el
+
+    n, steps, t_r, el_r = arm("rts", C0_FACTOR_RTS, None, 0.4 * budget_s)
+    _, steps_g, t_g, el_g = arm("global_adaptive", C0_FACTOR_GA, t_r, 0.6 * budget_s)
+    dtb = t_r / steps
+    return dict(value=n * steps / el_r, unit="particle-steps/s", cores=oracle.num_threads(),
+                cpu_model=cpu_model(), kind="oracle",
+                sample=f"first {steps} RTS base steps ({t_r:.2e} s simulated) of the "
+                       f"250,000-particle dam break from rest, FP64, {el_r:.1f} s",
+                global_adaptive=dict(value=n * (t_g / dtb) / el_g, steps=steps_g,
+                                     sim_time_s=t_g, seconds=el_g,
+                                     complete=t_g >= t_r * (1.0 - 1e-12)),
+                speedup_vs_global_adaptive=(el_g / t_g) / (el_r / t_r))
 
 
 def main():
@@ -468,14 +629,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": "wcsph_rts_dam_break_250k", "n_particles": g["n"],
                    "n_wall_particles": g["nw"], "spacing_m": 0.01, "h_over_s": 2.0,
-                   "levels": 4, "base_steps": K, "dt_base_s": g["dt_base"]},
-        "global_adaptive": {"value": g["ps_ga"], "unit": "particle-steps/s",
+                   "levels": 4, "phase_align": 1, "base_steps": K, "dt_base_s": g["dt_base"],
+                   "c0_m_s": g["c0"], "c0_factor": C0_FACTOR_RTS,
+                   "window_start_s": g["t_start"], "repeats": g["R"], "timing": "median"},
+        "ms_per_step_repeats": [m / K for m in g["ms_rts_all"]],
+        "global_adaptive": {"value": g["ps_ga"], "unit": "particle-steps/s (base-step equivalents)",
                             "ms_total": g["ms_ga"], "steps": g["ga"]["steps"],
-                            "density_err_max": g["ga"]["err_max"]},
-        "speedup_vs_global_adaptive": g["ms_ga"] / g["ms_rts"],
-        "density_err_max": g["rts"]["err_max"],
-        "active_fraction": g["rts"]["active_total"] / (g["n"] * K),
-        "neighbour_interactions_per_s": g["rts"]["inter_total"] / (g["ms_rts"] * 1e-3),
+                            "sim_time_s": g["ga"]["sim_time"], "c0_m_s": g["ga"]["c0"],
+                            "c0_factor": C0_FACTOR_GA,
+                            "density_err_max_window": g["ga"]["err_window"]},
+        # wall time per simulated second, comparator over RTS
+        "speedup_vs_global_adaptive": g["ps_rts"] / g["ps_ga"],
+        "density_err_max_window": g["rts"]["err_window"],
+        "active_fraction": g["rts"]["active"] / (g["n"] * K),
+        "neighbour_interactions_per_s": g["rts"]["inter"] / (g["ms_rts"] * 1e-3),
         "simulated_time_s": g["sim_time"],
     }
     if "kernels_ms" in g:
@@ -487,14 +654,20 @@ def main():
                                   cnt["cand"])
             avg = ms / K * 1e-3
             rows[name] = {"avg_us": avg * 1e6, "GBps": b / avg / 1e9 if avg > 0 else 0.0,
-                          "TFLOPs": f / avg / 1e12 if avg > 0 else 0.0}
+                          "hbm_frac": b / avg / 1e9 / HBM_PEAK_GBS if avg > 0 else 0.0,
+                          "TFLOPs": f / avg / 1e12 if avg > 0 else 0.0,
+                          "valu_frac": f / avg / 1e12 / FP32_VALU_PEAK_TFLOPS if avg > 0 else 0.0,
+                          "algorithmic_bytes_per_launch": b, "algorithmic_flop_per_launch": f}
         dom = max(km, key=lambda k: km[k])
         d = rows[dom]
         if dom in ("search_density", "force"):
             roof = {"kernel": dom, "bound": "alu", "achieved": d["TFLOPs"],
                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": d["TFLOPs"] / FP32_VALU_PEAK_TFLOPS,
-                    "traffic": measured_traffic(dom)}
+                    "traffic": measured_traffic(dom),
+                    "hbm_GBps_algorithmic": d["GBps"], "hbm_frac_algorithmic": d["hbm_frac"],
+                    "flop_source": "9 flop per candidate test + 23 per density term, "
+                                   "counted from the kernel's float operations"}
         else:
             roof = {"kernel": dom, "bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
@@ -506,15 +679,17 @@ def main():
         tr = km["rmin_flags"] + km["step_stats"]
         ti = km["correct_predict"]
         tot = tn + tp + tr + ti
-        line["phase_split"] = {"grid_and_search_share": None,
-                               "T_grid": tn / tot, "T_search_density_force": tp / tot,
+        line["phase_split"] = {"T_grid": tn / tot, "T_search_density_force": tp / tot,
                                "T_rts_flags": tr / tot, "T_integrate": ti / tot}
+    if not args.no_leg:
+        line["collapse_leg"] = run_collapse_leg()
+        line["speedup_at_equal_error"] = line["collapse_leg"]["speedup_at_equal_error"]
     if args.pcisph_steps > 0:
         line["pcisph"] = run_pcisph(args.pcisph_steps)
     if args.batch_steps > 0:
         line["batched"] = run_batched(args.batch_steps)
-    if args.more_steps > 0:
-        line["more_wcsph"] = run_more_wcsph(args.more_steps)
+    if args.more_time > 0:
+        line["more_wcsph"] = run_more_wcsph(args.more_time)
     if args.diff_repeats > 0:
         line["differentiable"] = run_diff(args.diff_repeats)
     if not args.no_cpu_baseline:

@@ -132,6 +132,15 @@ typedef struct rts_config {
   double pci_dt_max;      /* (<= 0: 4 dt_base) */
   double pci_grow;        /* >= 1 (1.02) */
   double pci_shrink;      /* in (0, 1] (0.95) */
+  /* WCSPH block levels (Algorithm 1).  0: a particle that takes level l
+   * (its validity ran out, or its block's level changed) is next due 2^l
+   * base steps later, as Algorithm 1 prints it.  1 (default): it is next
+   * due at the next base step that is a multiple of 2^l, so all particles of
+   * a level update on the same steps and a block's particles stay in phase;
+   * steps only get shorter (at most 2^l base steps, as before), and the
+   * blocks with work in a step are fewer. */
+  int32_t phase_align;
+  int32_t pad_;
 } rts_config;
 
 /* Per-run counters, filled by rts_sync. */

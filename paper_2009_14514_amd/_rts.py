@@ -58,6 +58,7 @@ class RtsConfig(C.Structure):
         ("eta", C.c_double), ("eta_T", C.c_double), ("delta", C.c_double), ("r_list", C.c_double),
         ("pci_grow_iters", C.c_int32), ("pci_shrink_iters", C.c_int32), ("pci_dt_min", C.c_double),
         ("pci_dt_max", C.c_double), ("pci_grow", C.c_double), ("pci_shrink", C.c_double),
+        ("phase_align", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -186,7 +187,7 @@ def config_from_params(p: dict, **over) -> RtsConfig:
               "pci_shrink"):
         if k in q:
             setattr(c, k, float(q[k]))
-    for k in ("pci_adapt_dt", "pci_grow_iters", "pci_shrink_iters"):
+    for k in ("pci_adapt_dt", "pci_grow_iters", "pci_shrink_iters", "phase_align"):
         if k in q:
             setattr(c, k, int(q[k]))
     c.mass = float(q.get("mass", 0.0))

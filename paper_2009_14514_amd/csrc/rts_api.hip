@@ -162,6 +162,10 @@ rts_status validate(const rts_config *c, char *msg, size_t cap) {
     return RTS_E_INVALID;
   }
   if (c->mode < 0 || c->mode > 2) { snprintf(msg, cap, "bad mode %d", c->mode); return RTS_E_INVALID; }
+  if (c->phase_align != 0 && c->phase_align != 1) {
+    snprintf(msg, cap, "phase_align must be 0 or 1");
+    return RTS_E_INVALID;
+  }
   if (c->solver == RTS_PCISPH) {
     if (c->mode == RTS_MODE_GLOBAL_ADAPTIVE) {
       snprintf(msg, cap, "PCISPH runs regional (rts) or standard (global_fixed) stepping");
@@ -306,6 +310,7 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   p.mode = c.mode;
   p.serna_correct = c.serna_correct;
   p.clamp_p = c.clamp_p;
+  p.phase_align = c.phase_align;
   p.solver = c.solver;
   p.support = (float)c.support;
   if (c.solver == RTS_PCISPH) {
@@ -776,6 +781,7 @@ void rts_default_config(rts_config *c) {
   c->pci_dt_max = 0.0;
   c->pci_grow = 1.02;
   c->pci_shrink = 0.95;
+  c->phase_align = 1;
 }
 
 const char *rts_status_string(rts_status s) {

@@ -50,6 +50,7 @@ struct DevParams {
   double dt_cfl;         // lambda_v r / c0 (adaptive comparator)
   double lf2r;           // lambda_f^2 r (adaptive comparator: dt^2 <= lf2r / |a|)
   int32_t lmax, mode, serna_correct, clamp_p;
+  int32_t phase_align;   // validity runs to the next multiple of 2^level
   float TV[kMaxLevels], TA[kMaxLevels];
   // PCISPH
   int32_t solver;

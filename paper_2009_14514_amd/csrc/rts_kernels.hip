@@ -382,6 +382,9 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
                                                    int do_flags) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nocc = S->n_occ;
+  // base steps taken before this one: with phase alignment a particle that
+  // takes level l is due again at the next multiple of 2^l
+  const uint32_t phase = p.phase_align ? (uint32_t)S->step : 0u;
   for (uint32_t q = blockIdx.x * 4 + wave; q < nocc; q += gridDim.x * 4) {
     const uint32_t b = occ[q];
     const uint32_t own = lraw[b];
@@ -406,7 +409,8 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
       if (k < n) {
         // Algorithm 1: decrement validity; active when it ran out or the
         // block's step differs (pre-emption); an active particle adopts the
-        // block's step and a validity of 2^level base steps.
+        // block's step and a validity of 2^level base steps (phase-aligned:
+        // up to the next multiple of 2^level).
         const uint32_t i = s0 + (uint32_t)k;
         const uint32_t m = M[i];
         int32_t val = meta_validity(m) - 1;
@@ -414,7 +418,7 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
         comp = val <= 0 || lev != l;
         if (comp) {
           lev = l;
-          val = 1 << l;
+          val = (int32_t)((1u << l) - (phase & ((1u << l) - 1u)));
         } else {
           // an inactive particle keeps its last density for this step
           err = fmaxf(err, (P[i].w - p.rho0) / p.rho0);

@@ -118,6 +118,8 @@ def base_params(spacing, box_min, box_max, *, c0, layers=4, h_ratio=2.0,
         dt_base=float(dt_base), r_crit=2.0 * spacing, lambda_v=0.4, lambda_f=0.25,
         alpha_rts=0.4 if solver == "wcsph" else 1.0, beta2=0.4, beta_ratio=0.2,
         n_levels=n_levels, level_cap=level_cap, clamp_p=1, serna_correct=1,
+        # WCSPH: a particle taking level l is due at the next multiple of 2^l
+        phase_align=1,
         wall_layers=layers,
         # PCISPH settings (unused by WCSPH)
         eta=0.01, eta_T=0.0025, it_min=3, it_max=50, n_minor=4, expand_layers=4,

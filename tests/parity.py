@@ -10,10 +10,11 @@ from paper_2009_14514_amd.sim import decode_meta, neighbour_lists
 
 def snapshot_after_step(sim):
     """Arrays of the last step: its input (previous order) and its outputs."""
-    v = {k: sim.debug(k) for k in (
+    v = {"STEP": sim.sync().step - 1}       # base steps taken before the last one
+    v.update({k: sim.debug(k) for k in (
         "PRE_POS", "PRE_VEL", "PRE_ACC", "PRE_META", "PRE_ID", "POS", "VEL", "ACC", "ACC_NEW",
         "META", "ID", "KEY", "PERM", "CELL_START", "BLK_LEVEL_RAW", "BLK_LEVEL", "NNB",
-        "PRESSURE", "WALL_POS", "WALL_ID", "WALL_CELL_START")}
+        "PRESSURE", "WALL_POS", "WALL_ID", "WALL_CELL_START")})
     return v
 
 
@@ -26,7 +27,8 @@ def expected_structure(cfg, snap):
     lraw = oracle.block_levels(cfg, keys_old, snap["PRE_VEL"][:, :3], snap["PRE_ACC"][:, :3])
     lvl = oracle.rmin(cfg, lraw)
     level0, _, age0, val0 = decode_meta(snap["PRE_META"])
-    level1, val1, comp1 = oracle.flags(keys_old, lvl, level0, val0)
+    level1, val1, comp1 = oracle.flags(keys_old, lvl, level0, val0, step=snap["STEP"],
+                                       phase_align=cfg.phase_align)
     age1 = np.where(comp1 == 1, 1, age0 + 1)
     return dict(keys=keys_old[perm], perm=perm, cell_start=start, lraw=lraw, lvl=lvl,
                 level=level1[perm], validity=val1[perm], compute=comp1[perm], age=age1[perm],

@@ -70,7 +70,10 @@ def test_impulse_preempts_its_block_and_the_ring_around_it():
     pre_lvl = pre[0][snap["PERM"]]
     preempted = in_ring & (pre_val > 1) & (pre_lvl != level1)
     assert np.count_nonzero(preempted) >= 4
-    assert np.all(comp1[preempted] == 1) and np.all(val1[preempted] == 2 ** level1[preempted])
+    # a pre-empted particle's next update: the next multiple of 2^level
+    step = snap["STEP"]
+    due = 2 ** level1[preempted] - step % 2 ** level1[preempted]
+    assert np.all(comp1[preempted] == 1) and np.array_equal(val1[preempted], due)
     # the oracle's own run agrees on every particle's level and flag (caller order)
     gid = snap["ID"]
     assert np.array_equal(ref.level[gid], level1)

@@ -69,8 +69,10 @@ def test_structure_first_step_small():
     assert exp["compute"].all()          # validity 0 at start: everyone active
 
 
-def test_structure_rts_levels_after_steps():
+@pytest.mark.parametrize("phase_align", [1, 0])
+def test_structure_rts_levels_after_steps(phase_align):
     sc = rts_scene()
+    sc.params["phase_align"] = phase_align
     sim = Simulation(sc)
     sim.advance(250)
     sim.sync()
@@ -159,10 +161,11 @@ def developed(sc, steps=250):
     return scenes.Scene(sc.name, s["pos"], s["vel"], sc.walls, sc.params)
 
 
-@pytest.mark.parametrize("mode", ["rts", "global_fixed", "global_adaptive"])
-def test_trajectory_developed_10_steps(mode):
+@pytest.mark.parametrize("mode,phase_align", [("rts", 1), ("rts", 0), ("global_fixed", 1),
+                                              ("global_adaptive", 1)])
+def test_trajectory_developed_10_steps(mode, phase_align):
     sc = developed(rts_scene())
-    dx, dv, st, ref = trajectory_errors(sc, 10, mode=mode)
+    dx, dv, st, ref = trajectory_errors(sc, 10, mode=mode, phase_align=phase_align)
     assert dx <= TRAJ_TOL and dv <= TRAJ_TOL, (dx, dv)
     assert st.active_total == sum(h["n_active"] for h in ref.history)
     assert abs(st.time - ref.t) <= 1e-6 * ref.t
