@@ -217,6 +217,21 @@ rts_status rts_create(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall
 rts_status rts_create_static(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
                              void *hip_stream, rts_ctx **out);
 
+/* Batched scenes: independent scenes of n_per_scene[s] particles each in
+ * one context (the benchmark spec's batched configuration), stepped together by
+ * every rts_advance; scene s holds caller indices [first_s, first_s + n_s)
+ * with first_s = n_0 + ... + n_{s-1}.  The scenes must be placed apart in
+ * space (their kernel supports disjoint, walls included) and share the
+ * configuration, so one sound speed and one base step (Eq. 1) hold for all.
+ * d_workspace: at least rts_workspace_size(cfg, sum of n_per_scene,
+ * n_wall_max) bytes.  WCSPH only (RTS_E_UNSUPPORTED otherwise); 1 <=
+ * n_scenes <= RTS_MAX_SCENES.  rts_set_state then takes exactly the summed
+ * count; rts_init_dam_break fills scenes on the device. */
+#define RTS_MAX_SCENES 4096
+rts_status rts_create_batch(const rts_config *cfg, int32_t n_scenes, const int64_t *h_n_per_scene,
+                            int64_t n_wall_max, void *d_workspace, size_t bytes,
+                            void *hip_stream, rts_ctx **out);
+
 /* Releases the host context and its graphs.  The workspace stays the caller's
  * (a static-workspace context releases its claim on the device's array). */
 void rts_destroy(rts_ctx *ctx);
@@ -229,6 +244,24 @@ rts_status rts_set_walls(rts_ctx *ctx, const float *d_pos, int64_t nw);
  * Accelerations start at zero and every particle starts with validity 0,
  * so the first step evaluates all of them (Algorithm 1 initialisation). */
 rts_status rts_set_state(rts_ctx *ctx, const float *d_pos, const float *d_vel, int64_t n);
+
+/* Scene initialisation on the device (the problem statement's "init
+ * scene"), for contexts from rts_create_batch: writes a lattice column of
+ * counts[0] x counts[1] x counts[2] particles (x fastest) into scene `scene`
+ * from its particle `first` on, at h_corner + (i + 1/2) spacing per axis
+ * plus a uniform jitter in [-jitter, jitter): u = (SplitMix64(seed) output
+ * number 3 (first_draw + k) + axis, top 24 bits) / 2^24, offset
+ * jitter (2u - 1), all in double precision with each operation rounded on
+ * its own, then rounded to float; particles at rest, due at once, as after
+ * rts_set_state.  A scene may take several columns (e.g. the two of a
+ * double dam break); the context has a state once every particle of every
+ * scene is written.  The first call after a step (or any call that sorted
+ * the particles) starts a new run: every scene must be written again.
+ * RTS_E_INVALID: bad scene, negative counts, a column past the scene's
+ * end; RTS_E_STATE: a context from rts_create.  Asynchronous. */
+rts_status rts_init_dam_break(rts_ctx *ctx, int32_t scene, int64_t first, const int32_t *h_counts,
+                              const double *h_corner, double spacing, double jitter,
+                              uint64_t seed, uint64_t first_draw);
 
 /* External impulse: adds d_dv (planes, 3*n floats, caller order) to the
  * particles' velocities and changes nothing else: levels, validity, ages and
@@ -271,9 +304,40 @@ rts_status rts_sync(rts_ctx *ctx, rts_stats *h_out);
 rts_status rts_get_state(rts_ctx *ctx, float *d_pos, float *d_vel, float *d_acc, float *d_rho,
                          float *d_p, uint8_t *d_level);
 
-/* Saves / restores the complete particle state and counters, so that a
- * restored run continues bit for bit.  d_buf: device memory.
- * PCISPH contexts return RTS_E_UNSUPPORTED. */
+/* Per-scene counters after the last step (any context; one scene unless
+ * batched): caller index of the scene's first particle, its particle
+ * count, particles active in the last step and their neighbour pairs, the
+ * maximum compression max(rho - rho0, 0) / rho0 of the scene's stored
+ * densities, and particles per level.  h_out[n_scenes]; n_scenes must equal
+ * the context's.  Waits for the stream. */
+typedef struct rts_scene_stats {
+  int64_t first;
+  int64_t n;
+  int64_t active_last;
+  int64_t inter_last;
+  float err_max_last;
+  int32_t level_hist[RTS_MAX_LEVELS];
+  int32_t pad;
+} rts_scene_stats;
+rts_status rts_get_scene_stats(rts_ctx *ctx, rts_scene_stats *h_out, int32_t n_scenes);
+
+/* rts_get_state for one scene: its particles in caller order, from slot 0
+ * (3 * n_s floats per vector plane set, n_s per scalar).  Asynchronous. */
+rts_status rts_get_scene_state(rts_ctx *ctx, int32_t scene, float *d_pos, float *d_vel,
+                               float *d_acc, float *d_rho, float *d_p, uint8_t *d_level);
+
+/* Saves / restores the complete state and counters, so that a restored run
+ * continues bit for bit.  d_buf: device memory of at least rts_state_bytes.
+ * WCSPH: the particle state (positions, velocities, accelerations, levels,
+ * validity, ages, densities, pressures, caller ids) and the counters; it
+ * loads into any context of the same grid with room for the particles.
+ * PCISPH: an image of the context's whole workspace (both sort buffers, the
+ * major step's grid, regions, observed blocks, lists, non-pressure
+ * accelerations, errors) and the correction loop's host counters (position
+ * in the major step, major-step length, clean major steps, step count,
+ * simulated time, base step, roll-back point), taken at any minor step; it
+ * loads only into a context created with the same configuration and
+ * capacities (else RTS_E_INVALID). */
 rts_status rts_state_bytes(rts_ctx *ctx, size_t *bytes);
 rts_status rts_save_state(rts_ctx *ctx, void *d_buf, size_t cap);
 rts_status rts_load_state(rts_ctx *ctx, const void *d_buf, size_t len);

@@ -28,8 +28,9 @@ DBG = {name: i for i, name in enumerate([
 
 # exported symbols, in the order include/rts.h declares them
 EXPORTS = [
-    "rts_default_config", "rts_workspace_size", "rts_create", "rts_create_static", "rts_destroy",
-    "rts_set_walls",
+    "rts_default_config", "rts_workspace_size", "rts_create", "rts_create_static",
+    "rts_create_batch", "rts_destroy", "rts_set_walls", "rts_init_dam_break",
+    "rts_get_scene_stats", "rts_get_scene_state",
     "rts_set_state", "rts_add_velocity", "rts_assign_levels", "rts_advance", "rts_sync",
     "rts_get_state", "rts_state_bytes", "rts_save_state", "rts_load_state", "rts_debug_get", "rts_grid_info",
     "rts_profile_advance", "rts_autotune", "rts_get_tune", "rts_diff_tape_bytes",
@@ -83,6 +84,17 @@ class RtsStats(C.Structure):
         return d
 
 
+class RtsSceneStats(C.Structure):
+    _fields_ = [("first", C.c_int64), ("n", C.c_int64), ("active_last", C.c_int64),
+                ("inter_last", C.c_int64), ("err_max_last", C.c_float),
+                ("level_hist", C.c_int32 * MAX_LEVELS), ("pad", C.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d["level_hist"] = list(self.level_hist)
+        return d
+
+
 class RtsTune(C.Structure):
     _fields_ = [("grid_wave", C.c_int32), ("grid_search", C.c_int32), ("grid_force", C.c_int32),
                 ("candidates", C.c_int32), ("ms_per_step", C.c_double)]
@@ -119,6 +131,11 @@ def lib():
         L.rts_workspace_size.argtypes = [cfgp, i64, i64, C.POINTER(C.c_size_t)]
         L.rts_create.argtypes = [cfgp, i64, i64, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.rts_create_static.argtypes = [cfgp, i64, i64, vp, C.POINTER(vp)]
+        L.rts_create_batch.argtypes = [cfgp, i32, vp, i64, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.rts_init_dam_break.argtypes = [vp, i32, i64, vp, vp, C.c_double, C.c_double,
+                                         C.c_uint64, C.c_uint64]
+        L.rts_get_scene_stats.argtypes = [vp, C.POINTER(RtsSceneStats), i32]
+        L.rts_get_scene_state.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.rts_destroy.argtypes = [vp]
         L.rts_destroy.restype = None
         L.rts_set_walls.argtypes = [vp, vp, i64]
@@ -210,6 +227,36 @@ def create(cfg, n_fluid_max, n_wall_max, d_workspace, nbytes, stream):
     check(lib().rts_create(C.byref(cfg), int(n_fluid_max), int(n_wall_max), C.c_void_p(d_workspace),
                            int(nbytes), C.c_void_p(stream), C.byref(ctx)))
     return ctx
+
+
+def create_batch(cfg, n_per_scene, n_wall_max, d_workspace, nbytes, stream):
+    """A context of independent scenes of the given particle counts."""
+    ctx = C.c_void_p()
+    counts = (C.c_int64 * len(n_per_scene))(*[int(v) for v in n_per_scene])
+    check(lib().rts_create_batch(C.byref(cfg), len(n_per_scene), counts, int(n_wall_max),
+                                 C.c_void_p(d_workspace), int(nbytes), C.c_void_p(stream),
+                                 C.byref(ctx)))
+    return ctx
+
+
+def init_dam_break(ctx, scene, first, counts, corner, spacing, jitter, seed, first_draw):
+    c = (C.c_int32 * 3)(*[int(v) for v in counts])
+    o = (C.c_double * 3)(*[float(v) for v in corner])
+    check(lib().rts_init_dam_break(ctx, int(scene), int(first), c, o, float(spacing),
+                                   float(jitter), int(seed), int(first_draw)), ctx)
+
+
+def scene_stats(ctx, n_scenes):
+    out = (RtsSceneStats * n_scenes)()
+    check(lib().rts_get_scene_stats(ctx, out, int(n_scenes)), ctx)
+    return [s.as_dict() for s in out]
+
+
+def get_scene_state(ctx, scene, d_pos=0, d_vel=0, d_acc=0, d_rho=0, d_p=0, d_level=0):
+    check(lib().rts_get_scene_state(ctx, int(scene), C.c_void_p(d_pos or None),
+                                    C.c_void_p(d_vel or None), C.c_void_p(d_acc or None),
+                                    C.c_void_p(d_rho or None), C.c_void_p(d_p or None),
+                                    C.c_void_p(d_level or None)), ctx)
 
 
 def create_static(cfg, n_fluid_max, n_wall_max, stream):

@@ -56,6 +56,15 @@ struct rts_ctx {
   int tune_candidates;
   double tune_ms;
   int static_dev;    // device whose static workspace holds this context, or -1
+  char *ws;          // workspace base and the bytes the buffer table uses
+  size_t ws_used;
+  // scenes: a batched context has fixed scene sizes (rts_create_batch);
+  // otherwise one scene of whatever rts_set_state gives
+  bool batched;
+  int32_t n_scenes;
+  uint32_t *scene_off;   // n_scenes + 1 caller offsets (host copy)
+  int64_t *scene_fill;   // particles written by rts_init_dam_break since the last reset
+  bool fresh;            // the state is in caller order: nothing has sorted it yet
   char err[512];
 };
 
@@ -397,6 +406,8 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.DEM = (uint32_t *)take(nbp * 4);
   t.PPART = (PciPart *)take(sizeof(PciPart) * kPciStatBlocks);
   t.PCI = (DevPci *)take(sizeof(DevPci));
+  t.SCN_OFF = (uint32_t *)take((size_t)(kMaxScenes + 1) * 4);
+  t.SCN_STAT = (SceneStat *)take(sizeof(SceneStat) * (size_t)kMaxScenes);
   if (d) *d = t;
   return off;
 }
@@ -664,7 +675,7 @@ rts_status pci_minor_step(rts_ctx *c) {
 // library's static workspace of that device.
 rts_status create_in(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_max,
                      void *d_workspace, size_t bytes, void *hip_stream, int static_dev,
-                     rts_ctx **out) {
+                     rts_ctx **out, int32_t n_scenes = 1, const int64_t *counts = nullptr) {
   if (!out) return RTS_E_INVALID;
   *out = nullptr;
   char msg[256];
@@ -679,19 +690,41 @@ rts_status create_in(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_
   c->ncap = n_fluid_max;
   c->nwcap = n_wall_max;
   c->static_dev = static_dev;
+  c->batched = counts != nullptr;
+  c->n_scenes = n_scenes;
+  c->scene_off = new (std::nothrow) uint32_t[(size_t)n_scenes + 1];
+  c->scene_fill = new (std::nothrow) int64_t[(size_t)n_scenes];
+  if (!c->scene_off || !c->scene_fill) {
+    delete[] c->scene_off;
+    delete[] c->scene_fill;
+    delete c;
+    return RTS_E_DEVICE;
+  }
+  c->scene_off[0] = 0;
+  for (int32_t s = 0; s < n_scenes; ++s) {
+    c->scene_off[s + 1] = c->scene_off[s] + (uint32_t)(counts ? counts[s] : 0);
+    c->scene_fill[s] = 0;
+  }
   derive(*cfg, n_fluid_max, n_wall_max, c->prm, c->mass, c->B, c->dt_base);
+  c->prm.n_scenes = n_scenes;
   size_t need = carve(c->prm, n_fluid_max, n_wall_max, nullptr, nullptr);
   if (bytes < need) {
+    delete[] c->scene_off;
+    delete[] c->scene_fill;
     delete c;
     return RTS_E_CAPACITY;
   }
   carve(c->prm, n_fluid_max, n_wall_max, (char *)d_workspace, &c->d);
+  c->ws = (char *)d_workspace;
+  c->ws_used = need;
   c->stream = (hipStream_t)hip_stream;
   c->cur = 0;
   int dev = 0;
   (void)hipGetDevice(&dev);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete[] c->scene_off;
+    delete[] c->scene_fill;
     delete c;
     return RTS_E_DEVICE;
   }
@@ -719,11 +752,88 @@ rts_status create_in(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_
   c->pci_major_len = cfg->mode == RTS_MODE_RTS ? cfg->n_minor : 1;
   launch_reset_scalars(c->d.S, st);
   if (hipGetLastError() != hipSuccess) {
+    delete[] c->scene_off;
+    delete[] c->scene_fill;
     delete c;
     return RTS_E_DEVICE;
   }
   *out = c;
   return RTS_OK;
+}
+
+// A new run of n particles: counters, buffer parity and scene offsets reset
+// (the particles themselves are written by the caller of this helper).
+rts_status reset_run(rts_ctx *c, int32_t n) {
+  rts_status u = unbin(c);
+  if (u) return u;
+  c->prm.n = n;
+  c->cur = 0;
+  c->pci_major_len = c->cfg.mode == RTS_MODE_RTS ? c->cfg.n_minor : 1;
+  c->pci_minor_in_major = 0;
+  c->pci_clean = 0;
+  c->pci_excess = 0;
+  c->pci_ready = false;
+  c->pci_steps = 0;
+  c->pci_iters_total = 0;
+  c->pci_time = 0.0;
+  c->pci_rollbacks = 0;
+  if (c->cfg.solver == RTS_PCISPH) pci_set_step(c, c->cfg.dt_base);
+  if (!c->batched) c->scene_off[1] = (uint32_t)n;
+  for (int32_t s = 0; s < c->n_scenes; ++s) c->scene_fill[s] = 0;
+  HIP_OK(c, hipMemcpyAsync(c->d.SCN_OFF, c->scene_off, ((size_t)c->n_scenes + 1) * 4,
+                           hipMemcpyHostToDevice, c->stream));
+  launch_reset_scalars(c->d.S, c->stream);
+  HIP_OK(c, hipGetLastError());
+  destroy_graphs(c);
+  c->fresh = true;
+  return RTS_OK;
+}
+
+bool scenes_complete(const rts_ctx *c) {
+  for (int32_t s = 0; s < c->n_scenes; ++s)
+    if (c->scene_fill[s] < (int64_t)(c->scene_off[s + 1] - c->scene_off[s])) return false;
+  return true;
+}
+
+// Host side of a PCISPH run (the correction loop is driven from here),
+// saved next to the workspace by rts_save_state.
+struct PciHostState {
+  int32_t n, nw, cur, major_len, minor_in_major, clean, excess, ready, peak, rollbacks;
+  int32_t snap_major_len, snap_clean, last[6], hist[4];
+  int64_t steps, iters_total, snap_steps;
+  double time, dt_base, dt_last, snap_time, errmax, avg;
+};
+static_assert(sizeof(PciHostState) <= 192, "PCISPH host state fits its header slot");
+constexpr int64_t kMagicWcsph = 0x5254535354415445LL;   // WCSPH particle state
+constexpr int64_t kMagicPcisph = 0x5254535043495354LL;  // PCISPH workspace image
+constexpr size_t kPciHeader = 256;                      // 64-byte header + host state
+
+void pci_host_save(const rts_ctx *c, PciHostState &h) {
+  memset(&h, 0, sizeof(h));
+  h.n = c->prm.n; h.nw = c->prm.nw; h.cur = c->cur;
+  h.major_len = c->pci_major_len; h.minor_in_major = c->pci_minor_in_major;
+  h.clean = c->pci_clean; h.excess = c->pci_excess; h.ready = c->pci_ready ? 1 : 0;
+  h.peak = c->pci_peak; h.rollbacks = c->pci_rollbacks;
+  h.snap_major_len = c->snap_major_len; h.snap_clean = c->snap_clean;
+  for (int k = 0; k < 6; ++k) h.last[k] = c->pci_last[k];
+  for (int k = 0; k < 4; ++k) h.hist[k] = c->pci_hist[k];
+  h.steps = c->pci_steps; h.iters_total = c->pci_iters_total; h.snap_steps = c->snap_steps;
+  h.time = c->pci_time; h.dt_base = c->dt_base; h.dt_last = c->dt_last;
+  h.snap_time = c->snap_time; h.errmax = c->pci_errmax; h.avg = c->pci_avg;
+}
+
+void pci_host_load(rts_ctx *c, const PciHostState &h) {
+  c->prm.n = h.n; c->prm.nw = h.nw; c->cur = h.cur;
+  c->pci_major_len = h.major_len; c->pci_minor_in_major = h.minor_in_major;
+  c->pci_clean = h.clean; c->pci_excess = h.excess; c->pci_ready = h.ready != 0;
+  c->pci_peak = h.peak; c->pci_rollbacks = h.rollbacks;
+  c->snap_major_len = h.snap_major_len; c->snap_clean = h.snap_clean;
+  for (int k = 0; k < 6; ++k) c->pci_last[k] = h.last[k];
+  for (int k = 0; k < 4; ++k) c->pci_hist[k] = h.hist[k];
+  c->pci_steps = h.steps; c->pci_iters_total = h.iters_total; c->snap_steps = h.snap_steps;
+  c->pci_time = h.time; c->dt_last = h.dt_last; c->snap_time = h.snap_time;
+  c->pci_errmax = h.errmax; c->pci_avg = h.avg;
+  pci_set_step(c, h.dt_base);
 }
 
 }  // namespace
@@ -842,6 +952,23 @@ rts_status rts_create_static(const rts_config *cfg, int64_t n_fluid_max, int64_t
   return s;
 }
 
+rts_status rts_create_batch(const rts_config *cfg, int32_t n_scenes, const int64_t *h_n_per_scene,
+                            int64_t n_wall_max, void *d_workspace, size_t bytes,
+                            void *hip_stream, rts_ctx **out) {
+  if (!out) return RTS_E_INVALID;
+  *out = nullptr;
+  if (!cfg || !h_n_per_scene || n_scenes < 1 || n_scenes > RTS_MAX_SCENES) return RTS_E_INVALID;
+  if (cfg->solver != RTS_WCSPH) return RTS_E_UNSUPPORTED;
+  int64_t total = 0;
+  for (int32_t s = 0; s < n_scenes; ++s) {
+    if (h_n_per_scene[s] < 0) return RTS_E_INVALID;
+    total += h_n_per_scene[s];
+  }
+  if (total > 0x7FFFFFFF) return RTS_E_INVALID;
+  return create_in(cfg, total, n_wall_max, d_workspace, bytes, hip_stream, -1, out, n_scenes,
+                   h_n_per_scene);
+}
+
 void rts_destroy(rts_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
@@ -851,6 +978,8 @@ void rts_destroy(rts_ctx *c) {
     std::lock_guard<std::mutex> lock(g_static_mu);
     g_static_busy[c->static_dev] = false;
   }
+  delete[] c->scene_off;
+  delete[] c->scene_fill;
   delete c;
 }
 
@@ -871,24 +1000,15 @@ rts_status rts_set_state(rts_ctx *c, const float *d_pos, const float *d_vel, int
   if (!c) return RTS_E_INVALID;
   if (n < 0 || n > c->ncap) return fail(c, RTS_E_CAPACITY, "n %lld exceeds capacity %lld", (long long)n, (long long)c->ncap);
   if (n > 0 && !d_pos) return fail(c, RTS_E_INVALID, "positions are NULL");
-  rts_status u = unbin(c);
+  if (c->batched && n != (int64_t)c->scene_off[c->n_scenes])
+    return fail(c, RTS_E_INVALID, "a batch of %d scenes holds %u particles, not %lld",
+                c->n_scenes, c->scene_off[c->n_scenes], (long long)n);
+  rts_status u = reset_run(c, (int32_t)n);
   if (u) return u;
-  c->prm.n = (int32_t)n;
-  c->cur = 0;
-  c->pci_major_len = c->cfg.mode == RTS_MODE_RTS ? c->cfg.n_minor : 1;
-  c->pci_minor_in_major = 0;
-  c->pci_clean = 0;
-  c->pci_excess = 0;
-  c->pci_ready = false;
-  c->pci_steps = 0;
-  c->pci_iters_total = 0;
-  c->pci_time = 0.0;
-  c->pci_rollbacks = 0;
-  if (c->cfg.solver == RTS_PCISPH) pci_set_step(c, c->cfg.dt_base);
-  launch_reset_scalars(c->d.S, c->stream);
+  for (int32_t s = 0; s < c->n_scenes; ++s)
+    c->scene_fill[s] = (int64_t)(c->scene_off[s + 1] - c->scene_off[s]);
   launch_set_state(c->prm, c->d, 0, d_pos, d_vel, c->stream);
   HIP_OK(c, hipGetLastError());
-  destroy_graphs(c);
   c->has_state = true;
   c->poisoned = false;
   return RTS_OK;
@@ -906,9 +1026,101 @@ rts_status rts_add_velocity(rts_ctx *c, const float *d_dv, int64_t n) {
   return RTS_OK;
 }
 
+rts_status rts_init_dam_break(rts_ctx *c, int32_t scene, int64_t first, const int32_t *h_counts,
+                              const double *h_corner, double spacing, double jitter,
+                              uint64_t seed, uint64_t first_draw) {
+  if (!c) return RTS_E_INVALID;
+  if (!c->batched)
+    return fail(c, RTS_E_STATE, "scene sizes are fixed by rts_create_batch; this context "
+                "takes its particles from rts_set_state");
+  if (scene < 0 || scene >= c->n_scenes || !h_counts || !h_corner || first < 0)
+    return fail(c, RTS_E_INVALID, "bad scene %d or column arguments", scene);
+  int64_t cnt = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (h_counts[a] < 0) return fail(c, RTS_E_INVALID, "negative lattice count");
+    cnt *= h_counts[a];
+  }
+  const int64_t n_s = (int64_t)(c->scene_off[scene + 1] - c->scene_off[scene]);
+  if (first + cnt > n_s)
+    return fail(c, RTS_E_INVALID, "column of %lld particles from %lld exceeds scene %d's %lld",
+                (long long)cnt, (long long)first, scene, (long long)n_s);
+  if (!(spacing > 0.0) || !(jitter >= 0.0))
+    return fail(c, RTS_E_INVALID, "spacing must be positive and jitter non-negative");
+  if (!c->fresh) {
+    // the first column after anything that sorted starts a new run of every scene
+    rts_status u = reset_run(c, (int32_t)c->scene_off[c->n_scenes]);
+    if (u) return u;
+    c->has_state = false;
+  }
+  LatticeSpec L;
+  memset(&L, 0, sizeof(L));
+  for (int a = 0; a < 3; ++a) {
+    L.counts[a] = h_counts[a];
+    L.corner[a] = h_corner[a];
+  }
+  L.spacing = spacing;
+  L.jitter = jitter;
+  L.seed = seed;
+  L.first_draw = first_draw;
+  launch_init_lattice(c->prm, c->d, c->scene_off[scene] + (uint32_t)first, (uint32_t)cnt, L,
+                      c->stream);
+  HIP_OK(c, hipGetLastError());
+  c->scene_fill[scene] += cnt;
+  if (scenes_complete(c)) {
+    c->has_state = true;
+    c->poisoned = false;
+  }
+  return RTS_OK;
+}
+
+rts_status rts_get_scene_stats(rts_ctx *c, rts_scene_stats *h_out, int32_t n_scenes) {
+  if (!c || !h_out) return RTS_E_INVALID;
+  if (n_scenes != c->n_scenes)
+    return fail(c, RTS_E_INVALID, "the context holds %d scenes", c->n_scenes);
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  launch_scene_stats(c->prm, c->d, c->cur, c->stream);
+  HIP_OK(c, hipGetLastError());
+  SceneStat *tmp = new (std::nothrow) SceneStat[(size_t)n_scenes];
+  if (!tmp) return fail(c, RTS_E_DEVICE, "host memory");
+  hipError_t e = hipMemcpyAsync(tmp, c->d.SCN_STAT, sizeof(SceneStat) * (size_t)n_scenes,
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete[] tmp;
+    return fail(c, RTS_E_DEVICE, "copy of the scene counters failed: %s", hipGetErrorString(e));
+  }
+  for (int32_t s = 0; s < n_scenes; ++s) {
+    rts_scene_stats &o = h_out[s];
+    memset(&o, 0, sizeof(o));
+    o.first = c->scene_off[s];
+    o.n = (int64_t)(c->scene_off[s + 1] - c->scene_off[s]);
+    o.active_last = tmp[s].act;
+    o.inter_last = (int64_t)tmp[s].inter;
+    float err;
+    memcpy(&err, &tmp[s].err_bits, 4);
+    o.err_max_last = err;
+    for (int l = 0; l < RTS_MAX_LEVELS; ++l) o.level_hist[l] = tmp[s].hist[l];
+  }
+  delete[] tmp;
+  return RTS_OK;
+}
+
+rts_status rts_get_scene_state(rts_ctx *c, int32_t scene, float *d_pos, float *d_vel,
+                               float *d_acc, float *d_rho, float *d_p, uint8_t *d_level) {
+  if (!c) return RTS_E_INVALID;
+  if (scene < 0 || scene >= c->n_scenes) return fail(c, RTS_E_INVALID, "bad scene %d", scene);
+  if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  const uint32_t lo = c->scene_off[scene], cnt = c->scene_off[scene + 1] - lo;
+  launch_get_range(c->prm, c->d, c->cur, lo, cnt, d_pos, d_vel, d_acc, d_rho, d_p, d_level,
+                   c->stream);
+  HIP_OK(c, hipGetLastError());
+  return RTS_OK;
+}
+
 rts_status rts_assign_levels(rts_ctx *c, int32_t *h_hist) {
   if (!c) return RTS_E_INVALID;
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  c->fresh = false;
   const DevParams &p = c->prm;
   if (c->cfg.solver == RTS_PCISPH) {
     if (c->cfg.mode != RTS_MODE_RTS) c->pci_major_len = 1;
@@ -951,6 +1163,7 @@ rts_status rts_advance(rts_ctx *c, int32_t n_steps) {
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
   if (c->poisoned) return fail(c, RTS_E_STATE, "state failed; set or load a state first");
   if (n_steps == 0) return RTS_OK;
+  c->fresh = false;
   if (c->cfg.solver == RTS_PCISPH) {
     // accepted minor steps: a rolled-back major step takes pci_steps back
     const int64_t target = c->pci_steps + n_steps;
@@ -983,6 +1196,7 @@ rts_status rts_advance(rts_ctx *c, int32_t n_steps) {
 }
 
 rts_status rts_profile_advance(rts_ctx *c, int32_t n_steps, double *h_ms) {
+  if (c) c->fresh = false;
   if (!c || n_steps < 0 || !h_ms) return RTS_E_INVALID;
   if (c->cfg.solver == RTS_PCISPH)
     return fail(c, RTS_E_UNSUPPORTED, "per-kernel profiling covers the WCSPH step");
@@ -1100,22 +1314,78 @@ rts_status rts_get_state(rts_ctx *c, float *d_pos, float *d_vel, float *d_acc, f
 
 rts_status rts_state_bytes(rts_ctx *c, size_t *bytes) {
   if (!c || !bytes) return RTS_E_INVALID;
+  if (c->cfg.solver == RTS_PCISPH) {
+    *bytes = kPciHeader + c->ws_used;
+    return RTS_OK;
+  }
   size_t n = (size_t)c->prm.n;
   *bytes = 64 + n * (16 * 3 + 4 * 3) + sizeof(DevScalars);
   return RTS_OK;
 }
 
+namespace {
+
+// PCISPH: an image of the whole workspace (particles in both sort buffers,
+// the major step's grid, regions and observed blocks, lists, non-pressure
+// accelerations, errors, scan and control words) plus the host loop's
+// counters, so that a restored run continues bit for bit at any minor step.
+rts_status pci_save(rts_ctx *c, void *d_buf, size_t cap) {
+  size_t need;
+  rts_state_bytes(c, &need);
+  if (cap < need) return fail(c, RTS_E_CAPACITY, "buffer holds %zu of %zu bytes", cap, need);
+  char hdr[kPciHeader];
+  memset(hdr, 0, sizeof(hdr));
+  int64_t *h64 = (int64_t *)hdr;
+  h64[0] = kMagicPcisph;
+  h64[1] = c->ncap;
+  h64[2] = c->nwcap;
+  h64[3] = c->prm.nb;
+  h64[4] = (int64_t)c->ws_used;
+  h64[5] = c->cfg.mode;
+  PciHostState hs;
+  pci_host_save(c, hs);
+  memcpy(hdr + 64, &hs, sizeof(hs));
+  char *b = (char *)d_buf;
+  HIP_OK(c, hipMemcpyAsync(b, hdr, kPciHeader, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(b + kPciHeader, c->ws, c->ws_used, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));  // the header lives on this host stack
+  return RTS_OK;
+}
+
+rts_status pci_load(rts_ctx *c, const void *d_buf, size_t len) {
+  if (len < kPciHeader) return fail(c, RTS_E_INVALID, "buffer too short");
+  char hdr[kPciHeader];
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  HIP_OK(c, hipMemcpy(hdr, d_buf, kPciHeader, hipMemcpyDeviceToHost));
+  const int64_t *h64 = (const int64_t *)hdr;
+  if (h64[0] != kMagicPcisph || h64[1] != c->ncap || h64[2] != c->nwcap ||
+      h64[3] != c->prm.nb || h64[4] != (int64_t)c->ws_used || h64[5] != c->cfg.mode)
+    return fail(c, RTS_E_INVALID, "buffer does not hold a PCISPH state for this context");
+  if (len < kPciHeader + c->ws_used) return fail(c, RTS_E_INVALID, "buffer too short");
+  PciHostState hs;
+  memcpy(&hs, hdr + 64, sizeof(hs));
+  HIP_OK(c, hipMemcpyAsync(c->ws, (const char *)d_buf + kPciHeader, c->ws_used,
+                           hipMemcpyDeviceToDevice, c->stream));
+  pci_host_load(c, hs);
+  c->fresh = false;
+  c->has_state = true;
+  c->poisoned = false;
+  return RTS_OK;
+}
+
+}  // namespace
+
 rts_status rts_save_state(rts_ctx *c, void *d_buf, size_t cap) {
   if (!c || !d_buf) return RTS_E_INVALID;
-  if (c->cfg.solver == RTS_PCISPH)
-    return fail(c, RTS_E_UNSUPPORTED, "save/load covers the WCSPH state");
   if (!c->has_state) return fail(c, RTS_E_STATE, "no state");
+  if (c->cfg.solver == RTS_PCISPH) return pci_save(c, d_buf, cap);
   size_t need;
   rts_state_bytes(c, &need);
   if (cap < need) return fail(c, RTS_E_CAPACITY, "buffer holds %zu of %zu bytes", cap, need);
   size_t n = (size_t)c->prm.n;
   char *b = (char *)d_buf;
-  int64_t hdr[8] = {0x5254535354415445LL, (int64_t)n, c->prm.nb, 0, 0, 0, 0, 0};
+  int64_t hdr[8] = {kMagicWcsph, (int64_t)n, c->prm.nb, 0, 0, 0, 0, 0};
   HIP_OK(c, hipMemcpyAsync(b, hdr, 64, hipMemcpyHostToDevice, c->stream));
   size_t off = 64;
   const int k = c->cur;
@@ -1132,11 +1402,10 @@ rts_status rts_save_state(rts_ctx *c, void *d_buf, size_t cap) {
 
 rts_status rts_load_state(rts_ctx *c, const void *d_buf, size_t len) {
   if (!c || !d_buf || len < 64) return RTS_E_INVALID;
-  if (c->cfg.solver == RTS_PCISPH)
-    return fail(c, RTS_E_UNSUPPORTED, "save/load covers the WCSPH state");
+  if (c->cfg.solver == RTS_PCISPH) return pci_load(c, d_buf, len);
   int64_t hdr[8];
   HIP_OK(c, hipMemcpy(hdr, d_buf, 64, hipMemcpyDeviceToHost));
-  if (hdr[0] != 0x5254535354415445LL || hdr[1] < 0 || hdr[1] > c->ncap || hdr[2] != c->prm.nb)
+  if (hdr[0] != kMagicWcsph || hdr[1] < 0 || hdr[1] > c->ncap || hdr[2] != c->prm.nb)
     return fail(c, RTS_E_INVALID, "buffer does not hold a state for this context");
   size_t n = (size_t)hdr[1];
   rts_status u = unbin(c);
@@ -1158,6 +1427,7 @@ rts_status rts_load_state(rts_ctx *c, const void *d_buf, size_t len) {
   HIP_OK(c, hipMemcpyAsync(c->d.S, b + off, sizeof(DevScalars), hipMemcpyDeviceToDevice, c->stream));
   // the graphs hold the particle count; buffers and both parities are fixed
   if (!same_n) destroy_graphs(c);
+  c->fresh = false;
   c->has_state = true;
   c->poisoned = false;
   return RTS_OK;
@@ -1251,6 +1521,7 @@ rts_status rts_get_tune(rts_ctx *c, rts_tune *out) {
 
 rts_status rts_autotune(rts_ctx *c, int32_t steps, void *d_scratch, size_t scratch_bytes,
                         rts_tune *out) {
+  if (c) c->fresh = false;
   if (!c || steps < 1 || !d_scratch) return RTS_E_INVALID;
   if (c->cfg.solver != RTS_WCSPH)
     return fail(c, RTS_E_UNSUPPORTED, "the launch shape is tuned for the WCSPH step");
@@ -1438,6 +1709,7 @@ rts_status rts_diff_forward(rts_ctx *c, const rts_diff_desc *D, int64_t n, const
   c->prm.n = (int32_t)n;
   c->cur = 0;
   c->has_state = false;   // the particle buffers serve as scratch
+  c->fresh = false;
   destroy_graphs(c);
   launch_reset_scalars(c->d.S, c->stream);
   const size_t nn = (size_t)(n > 0 ? n : 1);

@@ -51,6 +51,7 @@ struct DevParams {
   double lf2r;           // lambda_f^2 r (adaptive comparator: dt^2 <= lf2r / |a|)
   int32_t lmax, mode, serna_correct, clamp_p;
   int32_t phase_align;   // validity runs to the next multiple of 2^level
+  int32_t n_scenes;      // independent scenes in the particle set (1 unless batched)
   float TV[kMaxLevels], TA[kMaxLevels];
   // PCISPH
   int32_t solver;
@@ -138,6 +139,17 @@ constexpr int kStatBlocks = 64;
 // MASK[i * kSub * wpl + kSub * w + s].
 constexpr int kSub = 8;
 
+// Per-scene counters of a batched context (rts_get_scene_stats): integer
+// atomics and a max over non-negative float bits, so the result does not
+// depend on the order of the updates.
+struct SceneStat {
+  unsigned long long inter;  // neighbour pairs of the scene's active particles
+  uint32_t act;              // active particles
+  uint32_t err_bits;         // max(compression, 0) as float bits
+  int32_t hist[kMaxLevels];  // particles per level
+};
+constexpr int kMaxScenes = RTS_MAX_SCENES;
+
 struct DevPtrs {
   float4 *P[2];      // x, y, z, rho
   float4 *V[2];      // vx, vy, vz, p / rho^2
@@ -185,6 +197,10 @@ struct DevPtrs {
   uint32_t *DEM;     // per block: smallest level requested this minor step
   PciPart *PPART;    // kPciStatBlocks partials
   DevPci *PCI;
+  // scenes: caller index of each scene's first particle (n_scenes + 1
+  // entries, the last = n) and their counters
+  uint32_t *SCN_OFF;
+  SceneStat *SCN_STAT;
 };
 
 // Launchers (rts_kernels.hip).  All enqueue on `st`.
@@ -209,6 +225,22 @@ void launch_set_state(const DevParams &p, const DevPtrs &d, int cur, const float
                       const float *vel, hipStream_t st);
 void launch_add_velocity(const DevParams &p, const DevPtrs &d, int cur, const float *dv,
                          hipStream_t st);
+// Lattice column with SplitMix64 jitter into caller slots [first, first + cnt)
+// of buffer 0, as rts_set_state leaves a particle (at rest, due at once).
+struct LatticeSpec {
+  int32_t counts[3];
+  int32_t pad;
+  double corner[3];
+  double spacing, jitter;
+  unsigned long long seed, first_draw;
+};
+void launch_init_lattice(const DevParams &p, const DevPtrs &d, uint32_t first, uint32_t cnt,
+                         const LatticeSpec &L, hipStream_t st);
+void launch_scene_stats(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st);
+// rts_get_state restricted to caller indices [lo, lo + cnt), written from 0
+void launch_get_range(const DevParams &p, const DevPtrs &d, int cur, uint32_t lo, uint32_t cnt,
+                      float *pos, float *vel, float *acc, float *rho, float *pres,
+                      uint8_t *level, hipStream_t st);
 void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos, float *vel,
                       float *acc, float *rho, float *pres, uint8_t *level, hipStream_t st);
 void launch_wall_sort(const DevParams &p, const DevPtrs &d, const float *pos, hipStream_t st);

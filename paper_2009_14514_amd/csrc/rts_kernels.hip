@@ -1168,12 +1168,15 @@ __global__ void k_add_velocity(DevParams p, const float *__restrict__ dv, const 
 }
 
 __global__ void k_get_state(DevParams p, const float4 *P, const float4 *V, const float4 *A,
-                            const uint32_t *M, const uint32_t *ID, float *pos, float *vel,
-                            float *acc, float *rho, float *po, uint8_t *level) {
+                            const uint32_t *M, const uint32_t *ID, uint32_t lo, uint32_t cnt,
+                            float *pos, float *vel, float *acc, float *rho, float *po,
+                            uint8_t *level) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
-  const size_t n = (size_t)p.n;
-  const uint32_t c = ID[i];
+  // caller indices [lo, lo + cnt) go to slots [0, cnt) of the planes
+  const uint32_t c = ID[i] - lo;
+  if (c >= cnt) return;
+  const size_t n = (size_t)cnt;
   const float4 x = P[i];
   if (pos) { pos[c] = x.x; pos[n + c] = x.y; pos[2 * n + c] = x.z; }
   if (vel) { const float4 v = V[i]; vel[c] = v.x; vel[n + c] = v.y; vel[2 * n + c] = v.z; }
@@ -1181,6 +1184,78 @@ __global__ void k_get_state(DevParams p, const float4 *P, const float4 *V, const
   if (rho) rho[c] = x.w;
   if (po) po[c] = V[i].w * x.w * x.w;  // V.w holds p / rho^2
   if (level) level[c] = (uint8_t)meta_level(M[i]);
+}
+
+// SplitMix64: output number `idx` (0-based) of the stream started at `seed`.
+__device__ inline unsigned long long splitmix64(unsigned long long seed,
+                                                unsigned long long idx) {
+  unsigned long long z = seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Column of counts[0] x counts[1] x counts[2] lattice sites (x fastest) at
+// corner + (i + 1/2) spacing, each axis offset by jitter (2u - 1) with u the
+// top 24 bits of SplitMix64 draw 3 (first_draw + k) + axis, scaled by 2^-24.
+// Double precision, every operation rounded on its own (no fused
+// multiply-add), then rounded once to float.
+__global__ void k_init_lattice(DevParams p, uint32_t first, uint32_t cnt, LatticeSpec L,
+                               float4 *P, float4 *V, float4 *A, uint32_t *M, uint32_t *ID,
+                               float *pres) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cnt) return;
+  const uint32_t ix = k % (uint32_t)L.counts[0];
+  const uint32_t iy = (k / (uint32_t)L.counts[0]) % (uint32_t)L.counts[1];
+  const uint32_t iz = k / ((uint32_t)L.counts[0] * (uint32_t)L.counts[1]);
+  const uint32_t idx[3] = {ix, iy, iz};
+  float x[3];
+  for (int a = 0; a < 3; ++a) {
+    double q = __dadd_rn(L.corner[a], __dmul_rn((double)idx[a] + 0.5, L.spacing));
+    if (L.jitter != 0.0) {
+      const unsigned long long draw = 3ull * (L.first_draw + k) + (unsigned long long)a;
+      const double u = (double)(splitmix64(L.seed, draw) >> 40) * 0x1p-24;
+      q = __dadd_rn(q, __dmul_rn(L.jitter, 2.0 * u - 1.0));
+    }
+    x[a] = (float)q;
+  }
+  const uint32_t i = first + k;
+  P[i] = make_float4(x[0], x[1], x[2], p.rho0);
+  V[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  A[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  M[i] = meta_pack(0xFu, 0u, 0u, 0);
+  ID[i] = i;
+  pres[i] = 0.0f;
+}
+
+// Scene of caller index c: the largest s with off[s] <= c.
+__device__ inline uint32_t scene_of(const uint32_t *__restrict__ off, int ns, uint32_t c) {
+  uint32_t lo = 0, hi = (uint32_t)ns;   // off[lo] <= c < off[hi]
+  while (hi - lo > 1u) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= c) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Per-scene counters of the last step from the particles' flags, levels,
+// neighbour counts and stored densities.
+__global__ void k_scene_stats(DevParams p, const float4 *__restrict__ P,
+                              const uint32_t *__restrict__ M, const uint32_t *__restrict__ ID,
+                              const uint32_t *__restrict__ nnb, const uint32_t *__restrict__ off,
+                              SceneStat *st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const uint32_t s = scene_of(off, p.n_scenes, ID[i]);
+  const uint32_t m = M[i];
+  if (meta_compute(m)) {
+    atomicAdd(&st[s].act, 1u);
+    atomicAdd(&st[s].inter, (unsigned long long)nnb[i]);
+  }
+  const float e = fmaxf((P[i].w - p.rho0) / p.rho0, 0.0f);
+  atomicMax(&st[s].err_bits, __float_as_uint(e));
+  const uint32_t lev = meta_level(m);
+  if (lev < (uint32_t)kMaxLevels) atomicAdd(&st[s].hist[lev], 1);
 }
 
 // Canonical global neighbour lists of the last step's active particles:
@@ -1360,9 +1435,27 @@ void launch_add_velocity(const DevParams &p, const DevPtrs &d, int cur, const fl
 }
 void launch_get_state(const DevParams &p, const DevPtrs &d, int cur, float *pos, float *vel,
                       float *acc, float *rho, float *pres, uint8_t *level, hipStream_t st) {
-  if (p.n == 0) return;
+  launch_get_range(p, d, cur, 0u, (uint32_t)p.n, pos, vel, acc, rho, pres, level, st);
+}
+void launch_get_range(const DevParams &p, const DevPtrs &d, int cur, uint32_t lo, uint32_t cnt,
+                      float *pos, float *vel, float *acc, float *rho, float *pres,
+                      uint8_t *level, hipStream_t st) {
+  if (p.n == 0 || cnt == 0) return;
   hipLaunchKernelGGL(k_get_state, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
-                     d.V[cur], d.A[cur], d.M[cur], d.ID[cur], pos, vel, acc, rho, pres, level);
+                     d.V[cur], d.A[cur], d.M[cur], d.ID[cur], lo, cnt, pos, vel, acc, rho, pres,
+                     level);
+}
+void launch_init_lattice(const DevParams &p, const DevPtrs &d, uint32_t first, uint32_t cnt,
+                         const LatticeSpec &L, hipStream_t st) {
+  if (cnt == 0) return;
+  hipLaunchKernelGGL(k_init_lattice, dim3(blocks_for((int)cnt, 256)), dim3(256), 0, st, p,
+                     first, cnt, L, d.P[0], d.V[0], d.A[0], d.M[0], d.ID[0], d.PRES);
+}
+void launch_scene_stats(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
+  launch_fill(d.SCN_STAT, 0, sizeof(SceneStat) * (size_t)p.n_scenes, st);
+  if (p.n == 0) return;
+  hipLaunchKernelGGL(k_scene_stats, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
+                     d.M[cur], d.ID[cur], d.NNB, d.SCN_OFF, d.SCN_STAT);
 }
 void launch_wall_sort(const DevParams &p, const DevPtrs &d, const float *pos, hipStream_t st) {
   launch_prep_scan(d.CTRL, st);

@@ -86,6 +86,10 @@ class Scene:
     parts: list = field(default_factory=list)
     offsets: list = field(default_factory=list)
     subscenes: list = field(default_factory=list)
+    # the lattice columns the fluid was generated from (scene, first particle
+    # in the scene, counts, corner, spacing, jitter, seed, first draw), so a
+    # batched context can generate them on the device instead
+    columns: list = field(default_factory=list)
 
     @property
     def n(self) -> int:
@@ -312,10 +316,16 @@ def batched_dam_breaks(n_scenes=64, lo=2000, hi=200000, seed=0, spacing=0.01,
     start = 0
     walls0 = box_walls((0.0, 0.0, 0.0), box, spacing, layers)
     c0 = sound_speed_for_column(height)
+    columns = []
     for k, cc in enumerate(counts):
         off = pitch * np.array([k % per_row, (k // per_row) % per_row, k // (per_row * per_row)])
         local = lattice_column(cc, spacing, (0.0, 0.0, 0.0), jitter=0.005 * spacing, seed=seed + k)
-        pos = local + off[None, :]
+        # the column generated in place (the same lattice and draws, rounded
+        # at its own position), as rts_init_dam_break produces it
+        pos = lattice_column(cc, spacing, off, jitter=0.005 * spacing, seed=seed + k)
+        columns.append(dict(scene=k, first=0, counts=cc, corner=tuple(float(o) for o in off),
+                            spacing=spacing, jitter=0.005 * spacing, seed=seed + k,
+                            first_draw=0))
         pos_all.append(pos)
         wall_all.append(walls0 + off[None, :])
         parts.append((start, start + pos.shape[0]))
@@ -332,7 +342,7 @@ def batched_dam_breaks(n_scenes=64, lo=2000, hi=200000, seed=0, spacing=0.01,
     bmax = tuple(float(t + b) for t, b in zip(top, box))
     p = base_params(spacing, (0.0, 0.0, 0.0), bmax, c0=c0, dt_base=0.0, level_cap=3)
     return Scene(f"batched_{n_scenes}_scenes_{pos.shape[0]}", pos, np.zeros_like(pos), walls, p,
-                 parts=parts, offsets=offsets, subscenes=subs)
+                 parts=parts, offsets=offsets, subscenes=subs, columns=columns)
 
 
 def normal01(seed: int, idx: np.ndarray) -> np.ndarray:

@@ -34,11 +34,14 @@ class Simulation:
     ``scene`` is a :class:`paper_2009_14514_amd.scenes.Scene`; keyword
     arguments override entries of its parameter dictionary.
     ``static_workspace`` places the context in the library's static device
-    workspace (rts_create_static) instead of a torch allocation.
+    workspace (rts_create_static) instead of a torch allocation.  A scene
+    with ``parts`` (independent sub-scenes) gets a batched context
+    (rts_create_batch); with ``device_init`` its lattice columns are
+    generated on the device (rts_init_dam_break) instead of uploaded.
     """
 
     def __init__(self, scene, device="cuda", n_fluid_max=None, n_wall_max=None,
-                 static_workspace=False, **over):
+                 static_workspace=False, device_init=False, **over):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("the RTS library needs a GPU; none is visible")
@@ -52,7 +55,14 @@ class Simulation:
         self.n_fluid_max = int(n_fluid_max if n_fluid_max is not None else max(self.n, 1))
         self.n_wall_max = int(n_wall_max if n_wall_max is not None else max(self.nw, 1))
         self.stream = torch.cuda.current_stream(self.device)
-        if static_workspace:
+        self.n_scenes = max(len(scene.parts), 1)
+        if scene.parts and not static_workspace:
+            counts = [int(b - a) for a, b in scene.parts]
+            nbytes = _rts.workspace_size(self.cfg, sum(counts), self.n_wall_max)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.ctx = _rts.create_batch(self.cfg, counts, self.n_wall_max,
+                                         _aligned(self.workspace), nbytes, self.stream.cuda_stream)
+        elif static_workspace:
             # the library's own device array: nothing is allocated here
             self.workspace = None
             self.ctx = _rts.create_static(self.cfg, self.n_fluid_max, self.n_wall_max,
@@ -64,7 +74,12 @@ class Simulation:
                                    _aligned(self.workspace), nbytes, self.stream.cuda_stream)
         self.info = _rts.grid_info(self.ctx)
         self.set_walls(scene.walls)
-        self.set_state(scene.pos, scene.vel)
+        if device_init:
+            if not scene.columns:
+                raise ValueError("the scene records no lattice columns to generate")
+            self.init_columns(scene.columns)
+        else:
+            self.set_state(scene.pos, scene.vel)
 
     # -- state ------------------------------------------------------------
     def _dev(self, host: np.ndarray):
@@ -93,6 +108,36 @@ class Simulation:
         t = self._dev(_planes(dv))
         _rts.add_velocity(self.ctx, t.data_ptr(), self.n)
         self.stream.synchronize()
+
+    def init_columns(self, columns):
+        """Generates lattice columns on the device (rts_init_dam_break); each
+        column is a dict of scene, first, counts, corner, spacing, jitter,
+        seed, first_draw."""
+        for c in columns:
+            _rts.init_dam_break(self.ctx, c["scene"], c["first"], c["counts"], c["corner"],
+                                c["spacing"], c["jitter"], c["seed"], c["first_draw"])
+        self.stream.synchronize()
+
+    def scene_stats(self):
+        """Per-scene counters of the last step (rts_get_scene_stats)."""
+        return _rts.scene_stats(self.ctx, self.n_scenes)
+
+    def scene_state(self, k):
+        """Positions, velocities, density, pressure and level of scene k's
+        particles, in their caller order within the scene."""
+        torch = _torch()
+        st = self.scene_stats()[k]
+        n = int(st["n"])
+        buf = torch.zeros(max(n, 1) * 8, dtype=torch.float32, device=self.device)
+        lev = torch.zeros(max(n, 1), dtype=torch.uint8, device=self.device)
+        base = buf.data_ptr()
+        _rts.get_scene_state(self.ctx, k, base, base + 12 * n, 0, base + 24 * n,
+                             base + 28 * n, lev.data_ptr())
+        self.stream.synchronize()
+        h = buf.cpu().numpy()
+        return dict(pos=_from_planes(h[:3 * n], n), vel=_from_planes(h[3 * n:6 * n], n),
+                    rho=h[6 * n:7 * n].copy(), p=h[7 * n:8 * n].copy(),
+                    level=lev.cpu().numpy()[:n].copy())
 
     def advance(self, n_steps=1):
         _rts.advance(self.ctx, n_steps)
