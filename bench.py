@@ -102,8 +102,9 @@ def kernel_traffic(name, n, nb, K, act, inter, cand):
     """Algorithmic bytes and flops per launch of each kernel (averaged over K steps).
 
     Bytes count the particle state each kernel must read and write plus the
-    neighbour bitmasks (one bit per candidate); re-reads of neighbour state
-    served by LDS or caches are not counted.  Flops count the float operations
+    neighbour lists (two bytes per entry: the neighbours and the particle
+    itself); re-reads of neighbour state served by LDS or caches are not
+    counted.  Flops count the float operations
     of the method: 9 per candidate test (3 sub, 1 mul, 2 fma, 1 compare),
     23 per density term (distance 8, sqrt 1, kernel shape 10, compensated
     add 4) and 45 per force term.  ``act``/``inter``/``cand`` are totals over
@@ -116,10 +117,10 @@ def kernel_traffic(name, n, nb, K, act, inter, cand):
         "scatter": (16.0 * n, 1.0 * n),
         "cell_gather": (124.0 * n + nb, 16.0 * n),
         "rmin_flags": (12.0 * n + 27.0 * nb, 8.0 * n),
-        # own state and flag in; bitmask words, density, p/rho^2, p, count out
-        "search_density": (40.0 * a + c / 8.0, 9.0 * c + 23.0 * i),
-        # own state, count and bitmask words in; acceleration out
-        "force": (52.0 * a + c / 8.0, 45.0 * i),
+        # own state and flag in; list entries, density, p/rho^2, p, count out
+        "search_density": (40.0 * a + 2.0 * (i + a), 9.0 * c + 23.0 * i),
+        # own state, count and list entries in; acceleration out
+        "force": (52.0 * a + 2.0 * (i + a), 45.0 * i),
         "step_stats": (30.0 * nb, 12.0 * nb),
         "correct_predict": (104.0 * n + 16.0 * a, 30.0 * n),
     }

@@ -67,8 +67,8 @@ typedef struct rts_config {
   int32_t level_cap;     /* highest level a block may take */
   int32_t clamp_p;       /* clamp pressure at zero */
   int32_t serna_correct; /* 1: apply the predictor-corrector correction (Section 4.1) */
-  int32_t cand_cap;      /* neighbour candidates per block (27 blocks + walls) the neighbour
-                            bitmasks can describe; multiple of 128, <= 65536 */
+  int32_t cand_cap;      /* neighbour candidates per block (27 blocks + walls) that the 16-bit
+                            entries of the WCSPH lists can index; multiple of 256, <= 65536 */
   int32_t use_graph;     /* 1: replay each base step as a captured HIP graph */
   double spacing;         /* initial particle spacing s */
   double h;               /* smoothing length of the cubic spline (support 2h) */
@@ -102,7 +102,9 @@ typedef struct rts_config {
   int32_t local_fail;     /* local iterations before reverting to global ones (3) */
   int32_t global_limit;   /* global iterations in one minor step that end the major step (6) */
   int32_t short_majors;   /* clean major steps before the long major step returns (10) */
-  int32_t nbr_cap;        /* neighbour-list entries per particle (PCISPH) */
+  int32_t nbr_cap;        /* neighbour-list entries per particle, in [8, 4096] (both solvers;
+                             a particle with more neighbours fails the step with
+                             RTS_E_CAPACITY; default 512) */
   int32_t two_ring_levels;/* regions whose lists search two block layers (paper: 1, region 1;
                              2 adds region 2, the variant of the paper's comparison figure) */
   int32_t pci_adapt_dt;   /* 1: adaptive base step between major steps (RTS mode; see below) */

@@ -198,8 +198,7 @@ def config_from_params(p: dict, **over) -> RtsConfig:
               "short_majors", "two_ring_levels"):
         if k in q:
             setattr(c, k, int(q[k]))
-    if c.solver == RTS_PCISPH:
-        c.nbr_cap = int(q.get("nbr_cap", c.nbr_cap))
+    c.nbr_cap = int(q.get("nbr_cap", c.nbr_cap))
     for k in ("eta", "eta_T", "delta", "r_list", "pci_dt_min", "pci_dt_max", "pci_grow",
               "pci_shrink"):
         if k in q:

@@ -175,6 +175,10 @@ rts_status validate(const rts_config *c, char *msg, size_t cap) {
     snprintf(msg, cap, "phase_align must be 0 or 1");
     return RTS_E_INVALID;
   }
+  if (c->nbr_cap < 8 || c->nbr_cap > 4096) {
+    snprintf(msg, cap, "nbr_cap must be in [8, 4096]");
+    return RTS_E_INVALID;
+  }
   if (c->solver == RTS_PCISPH) {
     if (c->mode == RTS_MODE_GLOBAL_ADAPTIVE) {
       snprintf(msg, cap, "PCISPH runs regional (rts) or standard (global_fixed) stepping");
@@ -189,10 +193,6 @@ rts_status validate(const rts_config *c, char *msg, size_t cap) {
     }
     if (c->two_ring_levels < 0 || c->two_ring_levels > 4) {
       snprintf(msg, cap, "two_ring_levels must be in [0, 4]");
-      return RTS_E_INVALID;
-    }
-    if (c->nbr_cap < 8 || c->nbr_cap > 4096) {
-      snprintf(msg, cap, "nbr_cap must be in [8, 4096]");
       return RTS_E_INVALID;
     }
     if (!(c->eta > 0 && c->eta_T > 0 && c->dt_base > 0)) {
@@ -233,7 +233,7 @@ rts_status validate(const rts_config *c, char *msg, size_t cap) {
     snprintf(msg, cap, "n_levels must be in [1, %d]", RTS_MAX_LEVELS);
     return RTS_E_INVALID;
   }
-  // bitmask words of 32 candidates for each of kSub lanes
+  // a block's candidates are indexed by 16-bit list entries
   if (c->cand_cap < 32 * kSub || c->cand_cap > 65536 || c->cand_cap % (32 * kSub)) {
     snprintf(msg, cap, "cand_cap must be a multiple of %d in [%d, 65536]", 32 * kSub, 32 * kSub);
     return RTS_E_INVALID;
@@ -278,7 +278,8 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   memset(&p, 0, sizeof(p));
   p.ncap = (int32_t)ncap;
   p.cand_cap = c.cand_cap;
-  p.wpl = c.cand_cap / (kSub * 32);
+  p.nbr_cap = c.nbr_cap;
+  p.nbr_stride = (c.nbr_cap + 1 + 63) / 64 * 64 + 64;
   int64_t nb = 1;
   for (int d = 0; d < 3; ++d) {
     int32_t n = (int32_t)ceil((c.domain_max[d] - c.domain_min[d]) / c.block_edge);
@@ -303,6 +304,9 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   const double cc = c.rho0 / (mass * sigma) - 1.0;
   p.c_hi = (float)cc;
   p.c_lo = (float)(cc - (double)p.c_hi);
+  const double cs = c.rho0 / (mass * sigma);
+  p.cs_hi = (float)cs;
+  p.cs_lo = (float)(cs - (double)p.cs_hi);
   p.kms = (float)(mass * sigma / c.rho0);
   B = c.B > 0.0 ? c.B : c.rho0 * c.c0 * c.c0 / c.gamma;
   p.B = (float)B;
@@ -323,7 +327,6 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   p.solver = c.solver;
   p.support = (float)c.support;
   if (c.solver == RTS_PCISPH) {
-    p.nbr_cap = c.nbr_cap;
     p.two_ring_levels = c.two_ring_levels > 0 ? c.two_ring_levels : 1;
     const double rl = c.r_list > 0.0 ? c.r_list : c.block_edge;
     p.r2l = (float)(rl * rl);
@@ -365,7 +368,7 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.TMP = (uint32_t *)take(n * 4);
   t.PERM = (uint32_t *)take(n * 4);
   t.NNB = (uint32_t *)take(n * 4);
-  t.MASK = (uint32_t *)take(p.solver == RTS_PCISPH ? 4 : n * (size_t)(kSub * p.wpl) * 4);
+  t.LIST = (uint16_t *)take(p.solver == RTS_PCISPH ? 4 : n * (size_t)p.nbr_stride * 2);
   t.COUNT = (uint32_t *)take(nb * 4);
   t.CELL_START = (uint32_t *)take((nb + 1) * 4);
   t.OCC = (uint32_t *)take(nb * 4);
@@ -878,7 +881,7 @@ void rts_default_config(rts_config *c) {
   c->local_fail = 3;
   c->global_limit = 6;
   c->short_majors = 10;
-  c->nbr_cap = 128;
+  c->nbr_cap = 512;
   c->two_ring_levels = 1;
   c->eta = 0.01;
   c->eta_T = 0.0025;

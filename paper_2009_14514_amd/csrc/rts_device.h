@@ -51,18 +51,6 @@ __device__ inline float dist2_exact(float xi, float yi, float zi, float xj, floa
   return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, xx));
 }
 
-// bits * 2 + (d2 < r2): the compare's lane mask is the carry into an add of
-// the word to itself, so a run of 32 tests leaves test t at bit 31 - t
-// (two instructions per test instead of a compare, a select and a merge).
-__device__ inline uint32_t push_hit(uint32_t bits, float d2, float r2) {
-  uint32_t out;
-  asm("v_cmp_gt_f32_e32 vcc, %2, %3\n\tv_addc_co_u32_e32 %0, vcc, %1, %1, vcc"
-      : "=v"(out)
-      : "v"(bits), "s"(r2), "v"(d2)
-      : "vcc");
-  return out;
-}
-
 // Cubic spline shape w(q) and its derivative (support q < 2), branch-free:
 // both pieces are evaluated and the right one selected.
 __device__ inline float w_shape(float q) {
@@ -176,50 +164,74 @@ __device__ inline void block_ranges_shared(const DevParams &p, const uint32_t *s
                                            const uint32_t *wstart, uint32_t b, uint32_t *s_rs,
                                            uint32_t *s_ro, uint32_t *s_len) {
   const int tid = threadIdx.x;
-  if (tid < 18) {
-    uint32_t rs, len;
-    row_range(p, start, wstart, coords_of(p, b), tid, rs, len);
-    s_rs[tid] = rs;
-    s_len[tid] = len;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t acc = 0;
-    for (int r = 0; r < 18; ++r) {
-      s_ro[r] = acc;
-      acc += s_len[r];
+  if (tid < 64) {
+    // one wave: the 18 lengths and their exclusive prefix by shuffles
+    uint32_t rs = 0, len = 0;
+    if (tid < 18) row_range(p, start, wstart, coords_of(p, b), tid, rs, len);
+    uint32_t v = len;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const uint32_t u = (uint32_t)__shfl_up((int)v, o, 64);
+      if ((tid & 63) >= o) v += u;
     }
-    s_ro[18] = acc;
+    if (tid < 18) {
+      s_rs[tid] = rs;
+      s_len[tid] = len;
+      s_ro[tid] = v - len;
+    }
+    if (tid == 17) s_ro[18] = v;
   }
   __syncthreads();
 }
 
 // Copies the block's candidates into shared memory in canonical order, one
 // range at a time so that consecutive threads read consecutive particles;
-// slots from C up to cpad are filled with far-away positions.
-template <int kThreads>
+// slots from C up to cpad are filled with far-away positions.  The range of a
+// thread's candidates only grows from one slot to the next, so its search
+// resumes where the last one ended.  With kBoxes, wave w also writes the
+// bounding box of each 64-candidate chunk c = w + (kThreads / 64) it it
+// staged (padding included) to s_box[2 c] (low corner) and s_box[2 c + 1].
+template <int kThreads, bool kBoxes = false>
 __device__ inline void stage_positions(const uint32_t *s_rs, const uint32_t *s_ro,
                                        const float4 *__restrict__ P,
                                        const float4 *__restrict__ WP, float4 *s_pos,
-                                       uint32_t cpad) {
+                                       uint32_t cpad, float4 *s_box = nullptr) {
   constexpr int kPer = (kStageCap + kThreads - 1) / kThreads;
   const uint32_t C = s_ro[18];
   float4 v[kPer];
+  int r = 0;
   // every load is issued before the first shared-memory write
 #pragma unroll
   for (int it = 0; it < kPer; ++it) {
     const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kThreads;
     v[it] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);  // padding: never a neighbour
     if (k < C) {
-      bool wall;
-      const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
-      v[it] = wall ? WP[j] : P[j];
+      while (r < 17 && k >= s_ro[r + 1]) ++r;
+      const uint32_t j = s_rs[r] + (k - s_ro[r]);
+      v[it] = r >= 9 ? WP[j] : P[j];
     }
   }
 #pragma unroll
   for (int it = 0; it < kPer; ++it) {
     const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kThreads;
     if (k < cpad) s_pos[k] = v[it];
+    if (kBoxes && k - (threadIdx.x & 63u) < cpad) {  // wave-uniform: the chunk is staged
+      float lx = v[it].x, ly = v[it].y, lz = v[it].z, hx = lx, hy = ly, hz = lz;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        lx = fminf(lx, __shfl_xor(lx, o, 64));
+        ly = fminf(ly, __shfl_xor(ly, o, 64));
+        lz = fminf(lz, __shfl_xor(lz, o, 64));
+        hx = fmaxf(hx, __shfl_xor(hx, o, 64));
+        hy = fmaxf(hy, __shfl_xor(hy, o, 64));
+        hz = fmaxf(hz, __shfl_xor(hz, o, 64));
+      }
+      if ((threadIdx.x & 63u) == 0) {
+        const uint32_t c = k / 64u;
+        s_box[2 * c] = make_float4(lx, ly, lz, 0.0f);
+        s_box[2 * c + 1] = make_float4(hx, hy, hz, 0.0f);
+      }
+    }
   }
 }
 

@@ -31,8 +31,8 @@ __host__ __device__ inline int32_t meta_validity(uint32_t m) { return (int32_t)(
 // and rounded to float.
 struct DevParams {
   int32_t n, ncap, nw;
-  int32_t cand_cap;      // candidates per block the neighbour bitmasks can describe
-  int32_t wpl;           // bitmask words per lane: cand_cap / (kSub * 32)
+  int32_t cand_cap;      // candidates per block (list entries are 16-bit candidate indices)
+  int32_t nbr_stride;    // WCSPH list row: nbr_cap + 1 rounded up to a multiple of 64, + 64
   int32_t nc[3];
   int32_t nb;
   int32_t act_cap;       // entries per active-block list segment: ceil(nb / kActBuckets)
@@ -42,6 +42,7 @@ struct DevParams {
   float dmax[3];         // domain upper corner (particles beyond it are an error)
   float kms;             // m sigma / rho0
   float c_hi, c_lo;      // rho0 / (m sigma) - 1 split in two floats (density deviation)
+  float cs_hi, cs_lo;    // rho0 / (m sigma), the same with the particle's own W(0) = 1 kept
   float B, rho0;
   float visc_num;        // 2 alpha h c0
   float visc_eps_h2;     // eps h^2
@@ -55,7 +56,7 @@ struct DevParams {
   float TV[kMaxLevels], TA[kMaxLevels];
   // PCISPH
   int32_t solver;
-  int32_t nbr_cap;       // list entries per particle
+  int32_t nbr_cap;       // list entries per particle (both solvers)
   int32_t two_ring_levels;  // regions (levels 0..k-1) whose lists search two block layers
   float support;         // kernel support r
   float r2l;             // list radius squared
@@ -133,10 +134,11 @@ struct StatPart {
 };
 constexpr int kStatBlocks = 64;
 
-// Neighbour lists are bitmasks over a block's canonical candidate order:
-// kSub lanes share one particle, lane s owning candidates k = s + kSub * m,
-// one bit per candidate, 32 per word; word w of lane s of particle i is at
-// MASK[i * kSub * wpl + kSub * w + s].
+// WCSPH neighbour lists: row i of LIST (nbr_stride entries) holds the local
+// candidate indices, within its block's candidate set, of particle i's
+// neighbours and of i itself, ascending (the canonical order); NNB[i] counts
+// the neighbours.  The force pass gives kSub lanes to
+// each particle.
 constexpr int kSub = 8;
 
 // Per-scene counters of a batched context (rts_get_scene_stats): integer
@@ -164,7 +166,7 @@ struct DevPtrs {
   uint32_t *TMP;     // block-grouped previous indices, unordered within a block
   uint32_t *PERM;    // previous index of each sorted particle
   uint32_t *NNB;     // neighbour count per particle (last step's active ones)
-  uint32_t *MASK;    // ncap x (kSub * wpl) neighbour bitmask words
+  uint16_t *LIST;    // ncap x nbr_stride WCSPH neighbour lists (16-bit candidate indices)
   uint32_t *COUNT;   // nb, zero between sorts
   uint32_t *CELL_START;  // nb + 1
   uint32_t *OCC;     // occupied blocks, ascending

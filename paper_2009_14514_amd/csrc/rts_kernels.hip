@@ -13,13 +13,15 @@
 //   rmin_flags      one wave per occupied block: R_min smoothing (Section 4.2),
 //                   particle validity / compute / pre-emption (Algorithm 1)
 //   search_density  one workgroup per active block: the 27 surrounding
-//                   blocks are staged in LDS once; kSub lanes per active
-//                   particle test interleaved eighths of them, write the
-//                   neighbour bitmask and sum density; Tait pressure
+//                   blocks are staged in LDS once; a wave tests a few
+//                   particles at a time against chunks of 64 candidates (a
+//                   candidate per lane) and writes each particle's neighbour
+//                   list in canonical order from the lane masks; then sums
+//                   the density over the lists; Tait pressure
 //   force           one workgroup per active block: candidates' position,
 //                   velocity, density and pressure staged in LDS; pressure +
-//                   viscosity + gravity over the bitmask, the hits shared
-//                   evenly by a particle's kSub lanes
+//                   viscosity + gravity over the lists, a particle's entries
+//                   shared evenly by its kSub lanes
 //   step_stats      per-step counters and the step length
 //   correct_predict all particles: corrector for the active ones, then the
 //                   predictor of the next base step
@@ -37,8 +39,7 @@
 
 namespace rts {
 
-constexpr int kBlockThreads = 512;            // search: 64 particles x kSub lanes
-constexpr int kPartPerPass = kBlockThreads / kSub;
+constexpr int kBlockThreads = 512;            // search: eight waves
 constexpr int kForceThreads = 512;            // force: 64 particles x kSub lanes
 constexpr int kForcePerPass = kForceThreads / kSub;
 
@@ -477,129 +478,96 @@ __device__ inline uint32_t active_block(const DevParams &p, const uint32_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// balanced walk over a particle's neighbour bits
+// neighbour lists
 // ---------------------------------------------------------------------------
-// The kSub lanes of a particle own interleaved candidates, so their hit counts
-// differ by several times the square root of the mean, and a walk in which
-// each lane visits its own hits runs as long as the fullest lane of the wave.
-// Here the lanes instead emit their hits in rounds of at most kRound each into
-// a per-particle LDS window, packed in lane order by a prefix over the kSub
-// counts, and then visit that window's entries e = sub, sub + kSub, ...  The
-// visit order depends on the bits alone, so results stay deterministic.  The
-// force pass walks this way; the density pass, with little work per hit,
-// walks each lane's own hits, where the rounds would cost more than they save.
-constexpr uint32_t kRound = 12;             // keeps the force kernel at two workgroups per CU
-constexpr uint32_t kWin = kRound * kSub;   // window entries per particle
-constexpr int kMaxQueueWords = 8;          // words per lane held in registers
-
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// A particle's list holds the local candidate indices k (u16) of its
+// neighbours in ascending order, which is the canonical neighbour order
+// (sorted index, fluid before walls).  The search writes it, the density
+// pass of the same kernel and the force pass read it.
+__device__ inline uint16_t *list_row(const DevParams &p, uint16_t *list, uint32_t i) {
+  return list + (size_t)i * (size_t)p.nbr_stride;
+}
+__device__ inline const uint16_t *list_row(const DevParams &p, const uint16_t *list, uint32_t i) {
+  return list + (size_t)i * (size_t)p.nbr_stride;
+}
+// Entries e .. e + 3 of a row (e a multiple of four, e < the row's stride).
+__device__ inline uint2 list_quad(const uint16_t *row, uint32_t e) {
+  return *reinterpret_cast<const uint2 *>(row + e);
+}
+__device__ inline uint32_t quad_entry(const uint2 q, int j) {
+  const uint32_t w = j < 2 ? q.x : q.y;
+  return (j & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
-// Word queue of one lane: q[0] is the word being walked (index w); popping an
-// exhausted word shifts the rest down, so every access uses a fixed register.
-struct WordQueue {
-  uint32_t q[kMaxQueueWords];
-  uint32_t w;
-  __device__ inline uint32_t count() const {
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < kMaxQueueWords; ++k) c += (uint32_t)__popc(q[k]);
-    return c;
+// Walks the first n entries of a list row with kLanes lanes: lane `sub`
+// takes the quads starting at e = 4 sub + 4 kLanes r for r < rounds (wave-
+// uniform); use(quad, e) handles one (its entries past n are to be ignored).
+// Two quads are in flight, each loaded straight into the register it is
+// used from; the loads are unconditional, at most at entry `last` (the row's
+// last quad), so that no lane mask stands between a load and its wait.
+template <uint32_t kLanes, typename Use>
+__device__ inline void walk_list(const uint16_t *row, uint32_t last, uint32_t rounds, uint32_t sub,
+                                 Use &&use) {
+  constexpr uint32_t kStep = 4u * kLanes;
+  uint32_t e = 4u * sub;
+  uint2 qa = list_quad(row, min(e, last));
+  uint2 qb = list_quad(row, min(e + kStep, last));
+  for (uint32_t r = 0; r < rounds; r += 2, e += 2u * kStep) {
+    use(qa, e);
+    qa = list_quad(row, min(e + 2u * kStep, last));
+    if (r + 1u >= rounds) break;
+    use(qb, e + kStep);
+    qb = list_quad(row, min(e + 3u * kStep, last));
   }
-  // next set bit as a bit index m (candidate k = sub + kSub * m); a hit must
-  // remain
-  __device__ inline uint32_t pop() {
-    for (int guard = 0; q[0] == 0u && guard < kMaxQueueWords; ++guard) {
-#pragma unroll
-      for (int k = 0; k + 1 < kMaxQueueWords; ++k) q[k] = q[k + 1];
-      q[kMaxQueueWords - 1] = 0u;
-      ++w;
-    }
-    if (q[0] == 0u) return 0u;  // unreachable while the count is exact
-    const uint32_t t = (uint32_t)(__ffs(q[0]) - 1);
-    q[0] &= q[0] - 1u;
-    return 32u * w + t;
-  }
-};
-
-// Sets word `w` of a queue (w < kMaxQueueWords) without dynamic indexing.
-__device__ inline void queue_set(WordQueue &Q, uint32_t w, uint32_t bits) {
-#pragma unroll
-  for (int k = 0; k < kMaxQueueWords; ++k)
-    if ((uint32_t)k == w) Q.q[k] = bits;
 }
 
-// Walks the hits of the lane group: `win` is the particle's kWin-entry LDS
-// window, `cnt` this lane's hit count (0 for a lane without a particle).
-// `fetch(k)` loads what candidate k contributes (any k < kStageCap is a valid
-// slot), `use(f)` accumulates it; the next entry is fetched before the
-// current one is used.  Every lane of the wave must call it (the rounds are
-// wave-uniform).
-template <typename Fetch, typename Use>
-__device__ inline void walk_balanced(WordQueue &Q, uint32_t cnt, uint16_t *win, int sub,
-                                     Fetch &&fetch, Use &&use) {
-  // the group's counts, gathered once: each round's packing offsets and
-  // size then follow without further cross-lane traffic
-  uint32_t c[kSub];
-#pragma unroll
-  for (int j = 0; j < kSub; ++j) c[j] = (uint32_t)__shfl((int)cnt, j, kSub);
-  for (uint32_t base = 0; __any(cnt > base); base += kRound) {
-    uint32_t off = 0, total = 0;
-#pragma unroll
-    for (int j = 0; j < kSub; ++j) {
-      const uint32_t t = c[j] > base ? min(c[j] - base, kRound) : 0u;
-      off += j < sub ? t : 0u;
-      total += t;
-    }
-    const uint32_t take = cnt > base ? min(cnt - base, kRound) : 0u;
-    for (uint32_t j = 0; j < take; ++j)
-      win[off + j] = (uint16_t)((uint32_t)sub + (uint32_t)kSub * Q.pop());
-    wave_lds_sync();
-    uint32_t e = (uint32_t)sub;
-    if (e < total) {
-      // two entries in flight, used alternately (no register copies)
-      auto c0 = fetch((uint32_t)win[e]);
-      for (;;) {
-        const uint32_t e1 = e + kSub;
-        const bool m1 = e1 < total;
-        const auto c1 = fetch(m1 ? (uint32_t)win[e1] : 0u);
-        use(c0);
-        if (!m1) break;
-        const uint32_t e2 = e1 + kSub;
-        const bool m2 = e2 < total;
-        c0 = fetch(m2 ? (uint32_t)win[e2] : 0u);
-        use(c1);
-        if (!m2) break;
-        e = e2;
-      }
-    }
-    wave_lds_sync();  // the window is refilled by the next round
-  }
+// start + the number of set lanes of m below this lane.
+__device__ inline uint32_t lanes_below(uint64_t m, uint32_t start) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, start));
+}
+
+__device__ inline float uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ inline uint32_t uniform_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
 // ---------------------------------------------------------------------------
 // neighbour search + density + Tait pressure, one workgroup per block
 // ---------------------------------------------------------------------------
+// The block's candidates are staged in LDS once.  Each wave takes its share
+// of the block's active particles, kTestPart at a time:
+//   test     the wave sweeps the candidates in chunks of 64, one candidate
+//            per lane, and tests each of its particles against the chunk;
+//            the hits of a particle form a lane mask, whose prefix counts
+//            place them in the particle's list, so lists come out in
+//            canonical order with every lane busy on every test
+//   density  each particle gets kDenLanes lanes, which take its list entries
+//            four at a time in turn (balanced however the hits fall) and sum
+//            the kernel shape (Kahan-compensated), merged across the lanes
+constexpr int kTestPart = 4;                 // particles per wave and pass
+constexpr int kDenLanes = 64 / kTestPart;    // density lanes per particle
+
 __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6))) k_search_density(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, float4 *__restrict__ P, float4 *__restrict__ V,
     const uint32_t *__restrict__ M, float *__restrict__ pres, uint32_t *__restrict__ nnb,
-    uint32_t *__restrict__ mask, const float4 *__restrict__ WP, uint4 *__restrict__ blku,
+    uint16_t *__restrict__ list, const float4 *__restrict__ WP, uint4 *__restrict__ blku,
     float *__restrict__ blkerr, const uint32_t *__restrict__ ids,
     const uint32_t *__restrict__ actn, DevCtrl *ctrl, DevScalars *S) {
-  __shared__ float4 s_pos[kStageCap];
-  static_assert(kStageCap <= kMaxQueueWords * 32 * kSub, "staged words fit the queue");
+  __shared__ float4 s_pos[kStageCap + 1];  // + the far slot named by list padding
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
   __shared__ uint16_t s_act[kCellMax];
   __shared__ uint32_t s_nact;
   __shared__ float s_err[kBlockThreads / 64];
   __shared__ uint32_t s_inter[kBlockThreads / 64], s_nmax[kBlockThreads / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int sub = tid & (kSub - 1);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const uint32_t cap = (uint32_t)p.nbr_cap;  // neighbours; a row holds cap + 1 entries
   __shared__ uint32_t s_pre[kActBuckets + 1], s_ticket;
+  if (tid == 0) s_pos[kStageCap] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
   // blocks with active particles are handed out one at a time (the first
   // round by workgroup index), so the workgroups finish together however
   // unevenly the work is spread
@@ -620,131 +588,182 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
     for (int k = tid; k < n; k += kBlockThreads)
       if (meta_compute(M[s0 + (uint32_t)k])) s_act[atomicAdd(&s_nact, 1u)] = (uint16_t)k;
     __syncthreads();
-    const uint32_t nact = s_nact;
     const uint32_t C = s_ro[18];
-    const uint32_t cpad = (C + 32u * kSub - 1u) / (32u * kSub) * (32u * kSub);
+    const uint32_t cpad = (C + 63u) / 64u * 64u;
     const bool staged = cpad <= (uint32_t)kStageCap;
     if (staged) stage_positions<kBlockThreads>(s_rs, s_ro, P, WP, s_pos, cpad);
     __syncthreads();
+    const uint32_t nact = s_nact;
     const uint32_t self_off = s_ro[4] - s_rs[4];  // local index = sorted index + self_off
-    const uint32_t nslot = (C + kSub - 1) / kSub;     // candidate slots per lane
-    const uint32_t nwords = (nslot + 31) / 32;
-    if (nwords > (uint32_t)p.wpl) {
-      if (tid == 0 && nact > 0) set_status(S, RTS_E_CAPACITY, (int32_t)ids[s0]);
-    }
+    const bool fits = C <= (uint32_t)p.cand_cap;  // list entries are 16-bit candidate indices
+    if (!fits && tid == 0 && nact > 0) set_status(S, RTS_E_CAPACITY, (int32_t)ids[s0]);
+    const uint32_t nch = cpad / 64u;
+    // this wave's particles: slots [q_lo, q_hi) of the active list
+    const uint32_t per_wave = (nact + (uint32_t)(kBlockThreads / 64) - 1u) / (uint32_t)(kBlockThreads / 64);
+    const uint32_t q_lo = min((uint32_t)wave * per_wave, nact);
+    const uint32_t q_hi = fits ? min(q_lo + per_wave, nact) : q_lo;
     float err = 0.0f;
     uint32_t inter = 0, nmax = 0;
-    for (uint32_t c0 = 0; c0 < nact && nwords <= (uint32_t)p.wpl; c0 += kPartPerPass) {
-      if (c0 + (uint32_t)(wave * (64 / kSub)) >= nact) break;  // no particle for this wave
-      const uint32_t slot = c0 + (uint32_t)(tid / kSub);
-      const bool live = slot < nact;
-      const uint32_t i = s0 + (live ? (uint32_t)s_act[slot] : 0u);
-      const float4 xi = P[i];
-      const uint32_t selfk = i + self_off;
-      // this lane's words: word w of lane `sub` at mrow[kSub * w]
-      uint32_t *mrow = mask + (size_t)i * (size_t)(kSub * p.wpl) + (size_t)sub;
-      uint32_t cnt = 0;
-      WordQueue Q;  // the lane's words of a staged block (at most 8)
+    for (uint32_t q0 = q_lo; q0 < q_hi; q0 += kTestPart) {
+      const uint32_t np = min((uint32_t)kTestPart, q_hi - q0);  // wave-uniform
+      uint32_t pid[kTestPart], cnt[kTestPart];
+      float px[kTestPart], py[kTestPart], pz[kTestPart];
 #pragma unroll
-      for (int q2 = 0; q2 < kMaxQueueWords; ++q2) Q.q[q2] = 0u;
-      Q.w = 0u;
-      // pass 1: the neighbour predicate over this lane's candidates
-      // k = sub + kSub * m, one bit per candidate, 32 candidates per word
-      for (uint32_t w = 0; w < nwords; ++w) {
-        uint32_t bits = 0;
-        if (staged) {
-          // candidates past C are padded far away in shared memory
+      for (int t = 0; t < kTestPart; ++t) {
+        // slots past np repeat the last particle and are never tested
+        const uint32_t slot = q0 + min((uint32_t)t, np - 1u);
+        pid[t] = uniform_u(s0 + (uint32_t)s_act[slot]);
+        const float4 xi = P[pid[t]];
+        px[t] = uniform_f(xi.x);
+        py[t] = uniform_f(xi.y);
+        pz[t] = uniform_f(xi.z);
+        cnt[t] = 0u;
+      }
+      // test: lane = candidate 64 c + lane; one lane mask per particle.  The
+      // particle itself is a candidate at distance 0 and enters its own list
+      // (the density takes its W(0) from there; the force skips r = 0).  A
+      // row holds 64 entries beyond cap + 1, so the write offset is clamped
+      // there and a list past the capacity only goes on counting.
+      const auto test_chunk = [&](uint32_t c, const float4 xk) {
+        const uint32_t k = 64u * c + (uint32_t)lane;
 #pragma unroll
-          for (uint32_t t = 0; t < 32; ++t) {
-            const float4 qj = s_pos[(uint32_t)sub + kSub * (32u * w + t)];
-            bits = push_hit(bits, dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z), p.r2f);
-          }
-          bits = __builtin_bitreverse32(bits);
-        } else {
-          for (uint32_t t = 0; t < 32; ++t) {
-            const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
-            if (k >= C) break;
+        for (int t = 0; t < kTestPart; ++t) {
+          if ((uint32_t)t >= np) break;
+          const float d2 = dist2_exact(px[t], py[t], pz[t], xk.x, xk.y, xk.z);
+          const bool near = d2 < p.r2f;
+          const uint64_t m = __builtin_amdgcn_ballot_w64(near);
+          const uint32_t off = 2u * min(cnt[t], cap + 1u);  // bytes, wave-uniform
+          if (near)
+            *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(list_row(p, list, pid[t])) +
+                                          off + 2u * lanes_below(m, 0u)) = (uint16_t)k;
+          cnt[t] += (uint32_t)__popcll(m);
+        }
+      };
+      // two chunks in flight, each loaded into the register it is tested
+      // from; one loop per candidate source, so that the staged loop waits
+      // on shared-memory loads only and never on the list stores
+      const auto sweep = [&](auto &&candidate) {
+        float4 xa = candidate((uint32_t)lane);
+        float4 xb = candidate(64u + (uint32_t)lane);  // not tested when nch == 1
+        for (uint32_t c = 0; c < nch; c += 2u) {
+          test_chunk(c, xa);
+          if (c + 2u < nch) xa = candidate(64u * (c + 2u) + (uint32_t)lane);
+          if (c + 1u >= nch) break;
+          test_chunk(c + 1u, xb);
+          if (c + 3u < nch) xb = candidate(64u * (c + 3u) + (uint32_t)lane);
+        }
+      };
+      if (staged) {
+        sweep([&](uint32_t k) { return s_pos[k]; });  // slots from C to cpad are far away
+      } else {
+        sweep([&](uint32_t k) {
+          float4 xk = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+          if (k < C) {
             bool wall;
             const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
-            const float4 qj = wall ? WP[j] : P[j];
-            const float d2 = dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z);
-            bits |= d2 < p.r2f ? (1u << t) : 0u;
+            xk = wall ? WP[j] : P[j];
           }
-        }
-        if ((selfk & (kSub - 1)) == (uint32_t)sub && (selfk / kSub) / 32u == w)
-          bits &= ~(1u << ((selfk / kSub) & 31u));  // a particle is not its own neighbour
-        if (!live) bits = 0u;
-        if (live) mrow[kSub * w] = bits;
-        if (staged) queue_set(Q, w, bits);
-        cnt += (uint32_t)__popc(bits);
+          return xk;
+        });
       }
-      // pass 2: density over this lane's hits in bit order (Kahan-compensated
-      // sum of the kernel shape)
+      // a particle whose own test failed (a non-finite position) gets itself
+      // as its one entry, so that every entry names a real candidate
+      uint32_t most = 0;  // longest list of the pass, wave-uniform
+#pragma unroll
+      for (int t = 0; t < kTestPart; ++t) {
+        if ((uint32_t)t >= np) break;
+        if (cnt[t] == 0u) {
+          if (lane == 0) list_row(p, list, pid[t])[0] = (uint16_t)(pid[t] + self_off);
+          cnt[t] = 1u;
+        }
+        if (lane == 0 && cnt[t] > cap + 1u) set_status(S, RTS_E_CAPACITY, (int32_t)ids[pid[t]]);
+        cnt[t] = min(cnt[t], cap + 1u);
+        most = max(most, cnt[t]);
+      }
+      const uint32_t span = (most + 4u * kDenLanes - 1u) / (4u * kDenLanes) * (4u * kDenLanes);
+      if (staged) {
+        // entries from a list's end to the pass's span name the far slot,
+        // whose kernel value is exactly zero: the density walk then needs no
+        // per-entry bounds
+#pragma unroll
+        for (int t = 0; t < kTestPart; ++t) {
+          if ((uint32_t)t >= np) break;
+          uint16_t *row = list_row(p, list, pid[t]);
+          for (uint32_t e = cnt[t] + (uint32_t)lane; e < span; e += 64u) row[e] = (uint16_t)kStageCap;
+        }
+      }
+      // the entries become visible to the wave's other lanes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // density: lanes [kDenLanes g, kDenLanes (g + 1)) take particle g
+      const uint32_t g = (uint32_t)lane / kDenLanes, sub = (uint32_t)lane % kDenLanes;
+      uint32_t i = pid[0], ng = cnt[0];
+      float xg = px[0], yg = py[0], zg = pz[0];
+#pragma unroll
+      for (int t = 1; t < kTestPart; ++t) {
+        if ((uint32_t)t == g) {
+          i = pid[t];
+          ng = cnt[t];
+          xg = px[t];
+          yg = py[t];
+          zg = pz[t];
+        }
+      }
+      const bool live = g < np;
+      if (!live) ng = 0u;
+      const uint16_t *row = list_row(p, (const uint16_t *)list, i);
       float sum = 0.0f, comp = 0.0f;
-      auto add = [&](const float4 qj) {
-        const float d2 = dist2_exact(xi.x, xi.y, xi.z, qj.x, qj.y, qj.z);
+      const auto add = [&](const float4 qj) {
+        const float d2 = dist2_exact(xg, yg, zg, qj.x, qj.y, qj.z);
         const float wk = w_shape(__builtin_amdgcn_sqrtf(d2) * p.inv_h);
         const float y2 = wk - comp;
         const float tt = sum + y2;
         comp = (tt - sum) - y2;
         sum = tt;
       };
+      const uint32_t rounds = span / (4u * kDenLanes);
+      const uint32_t last = (uint32_t)p.nbr_stride - 4u;
       if (staged) {
-        // the words are in registers; two hits in flight, used in turn
-        uint32_t left = cnt;
-        if (left) {
-          float4 c0 = s_pos[(uint32_t)sub + kSub * Q.pop()];
-          for (;;) {
-            const bool m1 = --left > 0u;
-            const float4 c1 = s_pos[m1 ? (uint32_t)sub + kSub * Q.pop() : 0u];
-            add(c0);
-            if (!m1) break;
-            const bool m2 = --left > 0u;
-            c0 = s_pos[m2 ? (uint32_t)sub + kSub * Q.pop() : 0u];
-            add(c1);
-            if (!m2) break;
-          }
-        }
+        // lanes of a particle past np walk its (repeated) row and discard it
+        walk_list<kDenLanes>(row, last, rounds, sub, [&](const uint2 qd, uint32_t) {
+          float4 v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = s_pos[quad_entry(qd, j)];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) add(v[j]);
+        });
       } else {
-        // walk the set bits word by word, the next word always in flight
-        uint32_t w = 0;
-        uint32_t bits = (live && nwords) ? mrow[0] : 0u;
-        uint32_t nxt = (live && nwords > 1u) ? mrow[kSub] : 0u;
-        for (uint32_t e = 0; e < cnt; ++e) {
-          while (bits == 0u) {
-            bits = nxt;
-            ++w;
-            nxt = (w + 1u < nwords) ? mrow[kSub * (w + 1u)] : 0u;
+        walk_list<kDenLanes>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (e + (uint32_t)j >= ng) break;
+            bool wall;
+            const uint32_t jj = local_to_global(s_rs, s_ro, quad_entry(qd, j), wall);
+            add(wall ? WP[jj] : P[jj]);
           }
-          const uint32_t t = (uint32_t)(__ffs(bits) - 1);
-          bits &= bits - 1u;
-          const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
-          bool wall;
-          const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
-          add(wall ? WP[j] : P[j]);
-        }
+        });
       }
-      // the kSub lanes of a particle are adjacent: merge sums and counts
-      uint32_t total = cnt;
-      for (int o = 1; o < kSub; o <<= 1) {
+      // merge the particle's lanes (adjacent)
+#pragma unroll
+      for (int o = 1; o < kDenLanes; o <<= 1) {
         const float s2 = __shfl_xor(sum, o, 64), c2 = __shfl_xor(comp, o, 64);
         kahan_merge(sum, comp, s2, c2);
-        total += (uint32_t)__shfl_xor((int)total, o, 64);
       }
       if (live && sub == 0) {
-        // rho/rho0 - 1 = (m sigma / rho0) (sum - C) with C = rho0/(m sigma) - 1,
-        // sum = neighbour sum of the kernel shape (self excluded), carried as
-        // sum - comp; the difference is formed before any rounding to rho.
-        const float dev = p.kms * ((sum - p.c_hi) - (comp + p.c_lo));
+        // rho/rho0 - 1 = (m sigma / rho0) (sum - C) with C = rho0/(m sigma),
+        // sum = sum of the kernel shape over the list (the particle's own
+        // W(0) = 1 included), carried as sum - comp; the difference is
+        // formed before any rounding to rho.
+        const float dev = p.kms * ((sum - p.cs_hi) - (comp + p.cs_lo));
         const float rho = p.rho0 + p.rho0 * dev;
         const float pr = tait_from_dev(p, dev);
         reinterpret_cast<float *>(&P[i])[3] = rho;
         reinterpret_cast<float *>(&V[i])[3] = pr / (rho * rho);
         pres[i] = pr;
-        nnb[i] = total;
+        nnb[i] = ng - 1u;  // neighbours, the particle itself not counted
         err = fmaxf(err, dev);
-        inter += total;
-        nmax = max(nmax, total);
+        inter += ng - 1u;
+        nmax = max(nmax, ng - 1u);
       }
     }
     err = wave_max(err);
@@ -774,10 +793,9 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
 // ---------------------------------------------------------------------------
 // forces, one workgroup per block
 // ---------------------------------------------------------------------------
-struct StagedPair {
-  float4 q, u;
-  bool wall;
-};
+// kSub lanes per active particle take its list entries four at a time in
+// turn; the candidates' position, density, velocity and p / rho^2 are
+// staged in LDS.
 
 // Velocity slot of a wall candidate: at rest, and g . x in place of p / rho^2.
 __device__ inline float4 wall_slot(const DevParams &p, const float4 q) {
@@ -788,19 +806,18 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, const float4 *__restrict__ P,
     const float4 *__restrict__ V, const uint32_t *__restrict__ M,
-    const uint32_t *__restrict__ nnb, const uint32_t *__restrict__ mask,
+    const uint32_t *__restrict__ nnb, const uint16_t *__restrict__ list,
     const float4 *__restrict__ WP, float4 *__restrict__ anew, float *__restrict__ blkamax,
     const uint32_t *__restrict__ actn, DevCtrl *ctrl) {
   __shared__ float4 s_p[kForceCap];
   __shared__ float4 s_v[kForceCap];
-  __shared__ uint16_t s_win[kForceThreads / 64][64 / kSub][kWin];
-  static_assert(kForceCap <= kMaxQueueWords * 32 * kSub, "staged words fit the queue");
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
   __shared__ uint16_t s_act[kCellMax];
   __shared__ uint32_t s_nact;
   __shared__ float s_amax[kForceThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int sub = tid & (kSub - 1);
+  const uint32_t sub = (uint32_t)(tid & (kSub - 1));
+  const uint32_t cap = (uint32_t)p.nbr_cap;
   // -m grad W(x_ij) = f x_ij with f = -m (sigma / h) w'(q) / r, q = r / h:
   // f = fA + fB q for q < 1, f = fC (2 - q)^2 / r for 1 <= q < 2
   const float mcoefg = -p.mass * p.sigma * p.inv_h;
@@ -822,9 +839,7 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
     for (int k = tid; k < n; k += kForceThreads)
       if (meta_compute(M[s0 + (uint32_t)k])) s_act[atomicAdd(&s_nact, 1u)] = (uint16_t)k;
     __syncthreads();
-    const uint32_t nact = s_nact;
     const uint32_t C = s_ro[18], Cf = s_ro[9];
-    const uint32_t nwords = ((C + kSub - 1) / kSub + 31) / 32;
     const bool staged = C <= (uint32_t)kForceCap;
     if (staged) {
       // positions (walls included), then velocities: the four loads of a
@@ -852,8 +867,9 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
       if (k3 < C) s_v[k3] = u3;
     }
     __syncthreads();
+    const uint32_t nact = s_nact;
     float a2max = 0.0f;
-    for (uint32_t c0 = 0; c0 < nact && nwords <= (uint32_t)p.wpl; c0 += kForcePerPass) {
+    for (uint32_t c0 = 0; c0 < nact && C <= (uint32_t)p.cand_cap; c0 += kForcePerPass) {
       if (c0 + (uint32_t)(wave * (64 / kSub)) >= nact) break;
       const uint32_t slot = c0 + (uint32_t)(tid / kSub);
       const bool live = slot < nact;
@@ -866,7 +882,7 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
       // pressure of the fluid particle, plus the hydrostatic difference
       // g . (x_j - x_i), clamped at zero; uj.w of a wall holds g . x_j
       const float gxi = p.g[0] * pi.x + p.g[1] * pi.y + p.g[2] * pi.z;
-      auto pair = [&](const float4 qj, const float4 uj, bool wall) {
+      auto pair = [&](const float4 qj, const float4 uj, bool wall, bool valid) {
         const float rhoj = wall ? rhoi : qj.w;
         const float prj = wall ? fmaxf(pri + (uj.w - gxi) * inv_rhoi, 0.0f) : uj.w;
         const float dx = pi.x - qj.x, dy = pi.y - qj.y, dz = pi.z - qj.z;
@@ -874,51 +890,55 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float q = r2 * rinv * p.inv_h;
         const float t = fmaxf(2.0f - q, 0.0f);
-        const float f = q < 1.0f ? fmaf(fB, q, fA) : fC * t * t * rinv;  // -m gradW = f x_ij
+        const float f1 = fmaf(fB, q, fA), f2 = fC * t * t * rinv;
+        const float f = __builtin_unpredictable(q < 1.0f) ? f1 : f2;  // -m gradW = f x_ij
         const float vx = (vi.x - uj.x) * dx + (vi.y - uj.y) * dy + (vi.z - uj.z) * dz;
         // artificial viscosity -nu vx / (r^2 + eps h^2), nu = 2 alpha h c0 / (rho_i + rho_j)
         const float visc = -p.visc_num * vx *
                            __builtin_amdgcn_rcpf((rhoi + rhoj) * (r2 + p.visc_eps_h2));
         const float coef = pri + prj + (vx < 0.0f ? visc : 0.0f);
-        const float sc = r2 > 0.0f ? coef * f : 0.0f;
+        const float sc = valid && r2 > 0.0f ? coef * f : 0.0f;
         ax += sc * dx;
         ay += sc * dy;
         az += sc * dz;
       };
-      const uint32_t *mrow = mask + (size_t)i * (size_t)(kSub * p.wpl) + (size_t)sub;
-      const uint32_t left = live ? nwords : 0u;
+      // list entries: the neighbours and the particle itself (r = 0, skipped)
+      const uint32_t cnt = live ? min(nnb[i], cap) + 1u : 0u;
+      const uint16_t *row = list_row(p, list, i);
+      // rounds of 4 kSub entries, as many as the wave's longest list needs
+      const uint32_t most = wave_max_u32(cnt);
+      const uint32_t rounds = (most + 4u * kSub - 1u) / (4u * kSub);
+      const uint32_t last = (uint32_t)p.nbr_stride - 4u;
       if (staged) {
-        // at most kForceCap candidates: the lane's words fit the queue
-        WordQueue Q;
+        walk_list<kSub>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
+          uint32_t kk[4];
+          bool ok[4];
 #pragma unroll
-        for (int k = 0; k < kMaxQueueWords; ++k)
-          Q.q[k] = (uint32_t)k < left ? mrow[kSub * k] : 0u;
-        Q.w = 0u;
-        // staged wall slots of s_v: zero velocity and g . x_j
-        walk_balanced(Q, Q.count(), s_win[wave][lane / kSub], sub,
-                      [&](uint32_t k) { return StagedPair{s_p[k], s_v[k], k >= Cf}; },
-                      [&](const StagedPair &c) { pair(c.q, c.u, c.wall); });
-      } else {
-        // walk the set bits word by word, the next word always in flight
-        uint32_t w = 0;
-        uint32_t bits = left ? mrow[0] : 0u;
-        uint32_t nxt = left > 1u ? mrow[kSub] : 0u;
-        while (true) {
-          while (bits == 0u && w + 1u < left) {
-            bits = nxt;
-            ++w;
-            nxt = (w + 1u < left) ? mrow[kSub * (w + 1u)] : 0u;
+          for (int j = 0; j < 4; ++j) {
+            ok[j] = e + (uint32_t)j < cnt;
+            kk[j] = ok[j] ? quad_entry(qd, j) : 0u;
           }
-          if (bits == 0u) break;
-          const uint32_t t = (uint32_t)(__ffs(bits) - 1);
-          bits &= bits - 1u;
-          const uint32_t k = (uint32_t)sub + kSub * (32u * w + t);
-          const bool wall = k >= Cf;
-          bool w2;
-          const uint32_t j = local_to_global(s_rs, s_ro, k, w2);
-          const float4 q = wall ? WP[j] : P[j];
-          pair(q, wall ? wall_slot(p, q) : V[j], wall);
-        }
+          float4 qa[4], ua[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            qa[j] = s_p[kk[j]];
+            ua[j] = s_v[kk[j]];
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) pair(qa[j], ua[j], kk[j] >= Cf, ok[j]);
+        });
+      } else {
+        walk_list<kSub>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (e + (uint32_t)j >= cnt) break;
+            const uint32_t k = quad_entry(qd, j);
+            bool wall;
+            const uint32_t jj = local_to_global(s_rs, s_ro, k, wall);
+            const float4 qj = wall ? WP[jj] : P[jj];
+            pair(qj, wall ? wall_slot(p, qj) : V[jj], wall, true);
+          }
+        });
       }
       for (int o = 1; o < kSub; o <<= 1) {
         ax += __shfl_xor(ax, o, 64);
@@ -944,7 +964,6 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
     __syncthreads();
   }
 }
-
 // ---------------------------------------------------------------------------
 // per-step statistics and the step length (kStatBlocks workgroups; the last
 // one to finish folds the partials)
@@ -1261,8 +1280,8 @@ __global__ void k_scene_stats(DevParams p, const float4 *__restrict__ P,
 // Canonical global neighbour lists of the last step's active particles:
 // out[i * kDebugRow + e] = fluid sorted index, or wall sorted index | bit 31.
 __global__ void k_debug_lists(DevParams p, const uint32_t *key, const uint32_t *start,
-                              const uint32_t *wstart, const uint32_t *M, const uint32_t *mask,
-                              uint32_t *out, uint32_t *out_n) {
+                              const uint32_t *wstart, const uint32_t *M, const uint32_t *nnb,
+                              const uint16_t *list, uint32_t *out, uint32_t *out_n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   if (!meta_compute(M[i])) {
@@ -1279,18 +1298,19 @@ __global__ void k_debug_lists(DevParams p, const uint32_t *key, const uint32_t *
     acc += len;
   }
   ro[18] = acc;
-  const uint32_t C = acc;
-  const uint32_t *row = mask + (size_t)i * (size_t)(kSub * p.wpl);
-  uint32_t e = 0;
-  for (uint32_t k = 0; k < C && ((k / kSub) / 32u) < (uint32_t)p.wpl; ++k) {
-    const uint32_t sub = k % kSub, m = k / kSub;
-    if (!((row[kSub * (m / 32u) + sub] >> (m & 31u)) & 1u)) continue;
+  const uint16_t *row = list + (size_t)i * (size_t)p.nbr_stride;
+  const uint32_t cnt = min(nnb[i], (uint32_t)p.nbr_cap) + 1u;  // the particle itself included
+  const uint32_t self = (uint32_t)i - rs[4] + ro[4];
+  uint32_t o = 0;
+  for (uint32_t e = 0; e < cnt; ++e) {
+    const uint32_t k = row[e];
+    if (k == self) continue;
     bool wall;
     const uint32_t j = local_to_global(rs, ro, k, wall);
-    if (e < (uint32_t)RTS_DEBUG_NBR_ROW) out[(size_t)i * RTS_DEBUG_NBR_ROW + e] = wall ? (j | kWallBit) : j;
-    ++e;
+    if (o < (uint32_t)RTS_DEBUG_NBR_ROW) out[(size_t)i * RTS_DEBUG_NBR_ROW + o] = wall ? (j | kWallBit) : j;
+    ++o;
   }
-  out_n[i] = e;
+  out_n[i] = o;
 }
 
 __global__ void k_wall_keys(DevParams p, const float *__restrict__ pos, uint32_t *wkey,
@@ -1391,11 +1411,11 @@ void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int gr
                            hipStream_t st) {
   hipLaunchKernelGGL(k_search_density, dim3((unsigned)grid), dim3(kBlockThreads), 0, st, p, d.ACT,
                      d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.PRES, d.NNB,
-                     d.MASK, d.WP, d.BLKU, d.BLKERR, d.ID[cur], d.ACTN, d.CTRL, d.S);
+                     d.LIST, d.WP, d.BLKU, d.BLKERR, d.ID[cur], d.ACTN, d.CTRL, d.S);
 }
 void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_force, dim3((unsigned)grid), dim3(kForceThreads), 0, st, p, d.ACT,
-                     d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.NNB, d.MASK,
+                     d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.NNB, d.LIST,
                      d.WP, d.ANEW, d.BLKAMAX, d.ACTN, d.CTRL);
 }
 void launch_step_stats(const DevParams &p, const DevPtrs &d, hipStream_t st) {
@@ -1419,7 +1439,7 @@ void launch_debug_lists(const DevParams &p, const DevPtrs &d, int cur, uint32_t 
                         uint32_t *out_n, hipStream_t st) {
   if (p.n == 0) return;
   hipLaunchKernelGGL(k_debug_lists, dim3(blocks_for(p.n, 256)), dim3(256), 0, st, p, d.KEY,
-                     d.CELL_START, d.WCELL_START, d.M[cur], d.MASK, out, out_n);
+                     d.CELL_START, d.WCELL_START, d.M[cur], d.NNB, d.LIST, out, out_n);
 }
 void launch_set_state(const DevParams &p, const DevPtrs &d, int cur, const float *pos,
                       const float *vel, hipStream_t st) {

@@ -83,7 +83,7 @@ def test_dense_cluster_takes_the_unstaged_path():
     pos = np.stack(np.meshgrid(g, h, h, indexing="ij"), axis=-1).reshape(-1, 3)
     pos += np.random.default_rng(4).uniform(-1e-4, 1e-4, pos.shape)
     sc = small_box_scene(pos)
-    sim = Simulation(sc, cand_cap=8192)
+    sim = Simulation(sc, cand_cap=8192, nbr_cap=1024)
     sim.advance(1)
     sim.sync()
     snap = snapshot_after_step(sim)
@@ -129,6 +129,20 @@ def test_candidate_capacity_overflow_is_reported():
     sim.set_state(sc.pos[:1] + 0.1, None)       # a fresh state clears the failure
     sim.advance(1)
     sim.sync()
+
+
+@pytest.mark.parametrize("cap", [64, 130])
+def test_neighbour_list_overflow_is_reported(cap):
+    # about 270 neighbours at rest within the support of 4 spacings: a row of
+    # `cap` entries overflows, the step fails with the particle named
+    sc = scenes.dam_break_small()
+    sim = Simulation(sc, nbr_cap=cap)
+    sim.advance(1)
+    with pytest.raises(_rts.RtsError) as e:
+        sim.sync()
+    assert e.value.status == _rts.RTS_E_CAPACITY
+    st = sim.sync(raise_on_error=False)
+    assert 0 <= st.bad_index < sc.n
 
 
 def test_nan_and_out_of_domain_are_numerical_failures():

@@ -53,7 +53,7 @@ def test_static_workspace_runs_equal_caller_workspace_runs():
 
 
 def test_static_workspace_limits():
-    big = scenes.dam_break_column()                 # 250,000 particles: 174 MiB of workspace
+    big = scenes.dam_break_column()                 # 250,000 particles: 327 MiB of workspace
     with pytest.raises(_rts.RtsError) as e:
         Simulation(big, static_workspace=True)
     assert e.value.status == _rts.RTS_E_CAPACITY
