@@ -184,54 +184,39 @@ __device__ inline void block_ranges_shared(const DevParams &p, const uint32_t *s
   __syncthreads();
 }
 
+// A staged position without the fourth component (12 bytes in LDS).
+struct Pos3 {
+  float x, y, z;
+};
+__device__ inline void put_pos(float4 *s, uint32_t k, const float4 v) { s[k] = v; }
+__device__ inline void put_pos(Pos3 *s, uint32_t k, const float4 v) { s[k] = Pos3{v.x, v.y, v.z}; }
+
 // Copies the block's candidates into shared memory in canonical order, one
 // range at a time so that consecutive threads read consecutive particles;
-// slots from C up to cpad are filled with far-away positions.  The range of a
-// thread's candidates only grows from one slot to the next, so its search
-// resumes where the last one ended.  With kBoxes, wave w also writes the
-// bounding box of each 64-candidate chunk c = w + (kThreads / 64) it it
-// staged (padding included) to s_box[2 c] (low corner) and s_box[2 c + 1].
-template <int kThreads, bool kBoxes = false>
+// slots from C up to cpad are filled with far-away positions.
+template <int kThreads, typename Slot>
 __device__ inline void stage_positions(const uint32_t *s_rs, const uint32_t *s_ro,
                                        const float4 *__restrict__ P,
-                                       const float4 *__restrict__ WP, float4 *s_pos,
-                                       uint32_t cpad, float4 *s_box = nullptr) {
+                                       const float4 *__restrict__ WP, Slot *s_pos,
+                                       uint32_t cpad) {
   constexpr int kPer = (kStageCap + kThreads - 1) / kThreads;
   const uint32_t C = s_ro[18];
   float4 v[kPer];
-  int r = 0;
   // every load is issued before the first shared-memory write
 #pragma unroll
   for (int it = 0; it < kPer; ++it) {
     const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kThreads;
     v[it] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);  // padding: never a neighbour
     if (k < C) {
-      while (r < 17 && k >= s_ro[r + 1]) ++r;
-      const uint32_t j = s_rs[r] + (k - s_ro[r]);
-      v[it] = r >= 9 ? WP[j] : P[j];
+      bool wall;
+      const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
+      v[it] = wall ? WP[j] : P[j];
     }
   }
 #pragma unroll
   for (int it = 0; it < kPer; ++it) {
     const uint32_t k = (uint32_t)threadIdx.x + (uint32_t)it * kThreads;
-    if (k < cpad) s_pos[k] = v[it];
-    if (kBoxes && k - (threadIdx.x & 63u) < cpad) {  // wave-uniform: the chunk is staged
-      float lx = v[it].x, ly = v[it].y, lz = v[it].z, hx = lx, hy = ly, hz = lz;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        lx = fminf(lx, __shfl_xor(lx, o, 64));
-        ly = fminf(ly, __shfl_xor(ly, o, 64));
-        lz = fminf(lz, __shfl_xor(lz, o, 64));
-        hx = fmaxf(hx, __shfl_xor(hx, o, 64));
-        hy = fmaxf(hy, __shfl_xor(hy, o, 64));
-        hz = fmaxf(hz, __shfl_xor(hz, o, 64));
-      }
-      if ((threadIdx.x & 63u) == 0) {
-        const uint32_t c = k / 64u;
-        s_box[2 * c] = make_float4(lx, ly, lz, 0.0f);
-        s_box[2 * c + 1] = make_float4(hx, hy, hz, 0.0f);
-      }
-    }
+    if (k < cpad) put_pos(s_pos, k, v[it]);
   }
 }
 

@@ -35,6 +35,8 @@
 // operation order, so the structure is reproducible bit for bit on the CPU.
 // No floating-point atomics are used; same-address integer atomics are
 // limited to one per group of equal keys in a wave.
+#include <type_traits>
+
 #include "rts_device.h"
 
 namespace rts {
@@ -547,8 +549,14 @@ __device__ inline uint32_t uniform_u(uint32_t v) {
 //   density  each particle gets kDenLanes lanes, which take its list entries
 //            four at a time in turn (balanced however the hits fall) and sum
 //            the kernel shape (Kahan-compensated), merged across the lanes
+// The lists are built in the wave's own LDS rows and copied to memory by the
+// density walk that reads them, so no pass waits on its own list stores; a
+// pass with a list longer than an LDS row (or a block whose candidates are
+// read from memory) builds its lists in memory instead.
 constexpr int kTestPart = 4;                 // particles per wave and pass
 constexpr int kDenLanes = 64 / kTestPart;    // density lanes per particle
+constexpr int kLdsRow = 384;                 // entries of a wave's LDS list row
+constexpr int kLdsUse = kLdsRow - 64;        // entries it holds (a chunk adds up to 64)
 
 __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6))) k_search_density(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
@@ -557,7 +565,8 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
     uint16_t *__restrict__ list, const float4 *__restrict__ WP, uint4 *__restrict__ blku,
     float *__restrict__ blkerr, const uint32_t *__restrict__ ids,
     const uint32_t *__restrict__ actn, DevCtrl *ctrl, DevScalars *S) {
-  __shared__ float4 s_pos[kStageCap + 1];  // + the far slot named by list padding
+  __shared__ Pos3 s_pos[kStageCap + 1];  // + the far slot named by list padding
+  __shared__ uint2 s_lq[kBlockThreads / 64][kTestPart][kLdsRow / 4];  // LDS list rows, in quads
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
   __shared__ uint16_t s_act[kCellMax];
   __shared__ uint32_t s_nact;
@@ -567,7 +576,7 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const uint32_t cap = (uint32_t)p.nbr_cap;  // neighbours; a row holds cap + 1 entries
   __shared__ uint32_t s_pre[kActBuckets + 1], s_ticket;
-  if (tid == 0) s_pos[kStageCap] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+  if (tid == 0) s_pos[kStageCap] = Pos3{1e30f, 1e30f, 1e30f};
   // blocks with active particles are handed out one at a time (the first
   // round by workgroup index), so the workgroups finish together however
   // unevenly the work is spread
@@ -598,12 +607,15 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
     const bool fits = C <= (uint32_t)p.cand_cap;  // list entries are 16-bit candidate indices
     if (!fits && tid == 0 && nact > 0) set_status(S, RTS_E_CAPACITY, (int32_t)ids[s0]);
     const uint32_t nch = cpad / 64u;
-    // this wave's particles: slots [q_lo, q_hi) of the active list
-    const uint32_t per_wave = (nact + (uint32_t)(kBlockThreads / 64) - 1u) / (uint32_t)(kBlockThreads / 64);
-    const uint32_t q_lo = min((uint32_t)wave * per_wave, nact);
-    const uint32_t q_hi = fits ? min(q_lo + per_wave, nact) : q_lo;
+    // this wave's particles: slots [q_lo, q_hi) of the active list, whole
+    // tiles of kTestPart (only the block's last tile can be partial)
+    const uint32_t ntile = (nact + kTestPart - 1u) / kTestPart;
+    const uint32_t per_wave = (ntile + (uint32_t)(kBlockThreads / 64) - 1u) / (uint32_t)(kBlockThreads / 64);
+    const uint32_t q_lo = min((uint32_t)wave * per_wave * kTestPart, nact);
+    const uint32_t q_hi = fits ? min(q_lo + per_wave * kTestPart, nact) : q_lo;
     float err = 0.0f;
     uint32_t inter = 0, nmax = 0;
+    uint16_t *const lrows = reinterpret_cast<uint16_t *>(&s_lq[wave][0][0]);  // this wave's
     for (uint32_t q0 = q_lo; q0 < q_hi; q0 += kTestPart) {
       const uint32_t np = min((uint32_t)kTestPart, q_hi - q0);  // wave-uniform
       uint32_t pid[kTestPart], cnt[kTestPart];
@@ -613,36 +625,51 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
         // slots past np repeat the last particle and are never tested
         const uint32_t slot = q0 + min((uint32_t)t, np - 1u);
         pid[t] = uniform_u(s0 + (uint32_t)s_act[slot]);
-        const float4 xi = P[pid[t]];
-        px[t] = uniform_f(xi.x);
-        py[t] = uniform_f(xi.y);
-        pz[t] = uniform_f(xi.z);
+        // the same in every lane, held in vector registers; a staged block
+        // holds the particle among its own candidates
+        if (staged) {
+          const Pos3 xi = s_pos[pid[t] + self_off];
+          px[t] = xi.x;
+          py[t] = xi.y;
+          pz[t] = xi.z;
+        } else {
+          const float4 xi = P[pid[t]];
+          px[t] = xi.x;
+          py[t] = xi.y;
+          pz[t] = xi.z;
+        }
         cnt[t] = 0u;
       }
       // test: lane = candidate 64 c + lane; one lane mask per particle.  The
       // particle itself is a candidate at distance 0 and enters its own list
       // (the density takes its W(0) from there; the force skips r = 0).  A
-      // row holds 64 entries beyond cap + 1, so the write offset is clamped
-      // there and a list past the capacity only goes on counting.
-      const auto test_chunk = [&](uint32_t c, const float4 xk) {
-        const uint32_t k = 64u * c + (uint32_t)lane;
+      // row holds 64 entries beyond its clamp, so the write offset is clamped
+      // there and a list past the row only goes on counting.
+      const auto sweep = [&](auto np_c, auto to_lds_c, auto &&candidate) {
+        constexpr int kNp = decltype(np_c)::value;
+        constexpr bool kLds = decltype(to_lds_c)::value;
+        const auto test_chunk = [&](uint32_t c, const float4 xk) {
+          const uint32_t k = 64u * c + (uint32_t)lane;
 #pragma unroll
-        for (int t = 0; t < kTestPart; ++t) {
-          if ((uint32_t)t >= np) break;
-          const float d2 = dist2_exact(px[t], py[t], pz[t], xk.x, xk.y, xk.z);
-          const bool near = d2 < p.r2f;
-          const uint64_t m = __builtin_amdgcn_ballot_w64(near);
-          const uint32_t off = 2u * min(cnt[t], cap + 1u);  // bytes, wave-uniform
-          if (near)
-            *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(list_row(p, list, pid[t])) +
-                                          off + 2u * lanes_below(m, 0u)) = (uint16_t)k;
-          cnt[t] += (uint32_t)__popcll(m);
-        }
-      };
-      // two chunks in flight, each loaded into the register it is tested
-      // from; one loop per candidate source, so that the staged loop waits
-      // on shared-memory loads only and never on the list stores
-      const auto sweep = [&](auto &&candidate) {
+          for (int t = 0; t < kTestPart; ++t) {
+            if (kNp == kTestPart ? false : (uint32_t)t >= np) break;
+            const float d2 = dist2_exact(px[t], py[t], pz[t], xk.x, xk.y, xk.z);
+            const bool near = d2 < p.r2f;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(near);
+            if (kLds) {
+              const uint32_t base = (uint32_t)t * kLdsRow + min(cnt[t], (uint32_t)kLdsUse);
+              if (near) lrows[base + lanes_below(m, 0u)] = (uint16_t)k;
+            } else {
+              const uint32_t off = 2u * min(cnt[t], cap + 1u);  // bytes, wave-uniform
+              if (near)
+                *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(list_row(p, list, pid[t])) +
+                                              off + 2u * lanes_below(m, 0u)) = (uint16_t)k;
+            }
+            cnt[t] += (uint32_t)__popcll(m);
+          }
+        };
+        // two chunks in flight, each loaded into the register it is tested
+        // from
         float4 xa = candidate((uint32_t)lane);
         float4 xb = candidate(64u + (uint32_t)lane);  // not tested when nch == 1
         for (uint32_t c = 0; c < nch; c += 2u) {
@@ -653,18 +680,37 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
           if (c + 3u < nch) xb = candidate(64u * (c + 3u) + (uint32_t)lane);
         }
       };
+      using Full = std::integral_constant<int, kTestPart>;
+      using Part = std::integral_constant<int, 0>;
+      using Lds = std::true_type;
+      using Mem = std::false_type;
+      const auto staged_pos = [&](uint32_t k) {  // slots from C to cpad are far away
+        const Pos3 q = s_pos[k];
+        return make_float4(q.x, q.y, q.z, 0.0f);
+      };
+      const auto memory_pos = [&](uint32_t k) {
+        float4 xk = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+        if (k < C) {
+          bool wall;
+          const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
+          xk = wall ? WP[j] : P[j];
+        }
+        return xk;
+      };
+      bool in_lds = staged;
       if (staged) {
-        sweep([&](uint32_t k) { return s_pos[k]; });  // slots from C to cpad are far away
-      } else {
-        sweep([&](uint32_t k) {
-          float4 xk = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
-          if (k < C) {
-            bool wall;
-            const uint32_t j = local_to_global(s_rs, s_ro, k, wall);
-            xk = wall ? WP[j] : P[j];
-          }
-          return xk;
-        });
+        // one loop per candidate source, so that this loop waits on
+        // shared-memory loads only
+        if (np == kTestPart) sweep(Full{}, Lds{}, staged_pos); else sweep(Part{}, Lds{}, staged_pos);
+#pragma unroll
+        for (int t = 0; t < kTestPart; ++t) in_lds = in_lds && cnt[t] <= (uint32_t)kLdsUse;
+      }
+      if (!in_lds) {
+        // a list longer than an LDS row, or candidates from memory: the
+        // lists are built in memory (rare)
+#pragma unroll
+        for (int t = 0; t < kTestPart; ++t) cnt[t] = 0u;
+        if (staged) sweep(Part{}, Mem{}, staged_pos); else sweep(Part{}, Mem{}, memory_pos);
       }
       // a particle whose own test failed (a non-finite position) gets itself
       // as its one entry, so that every entry names a real candidate
@@ -673,7 +719,10 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
       for (int t = 0; t < kTestPart; ++t) {
         if ((uint32_t)t >= np) break;
         if (cnt[t] == 0u) {
-          if (lane == 0) list_row(p, list, pid[t])[0] = (uint16_t)(pid[t] + self_off);
+          const uint16_t self = (uint16_t)(pid[t] + self_off);
+          if (lane == 0) {
+            if (in_lds) lrows[t * kLdsRow] = self; else list_row(p, list, pid[t])[0] = self;
+          }
           cnt[t] = 1u;
         }
         if (lane == 0 && cnt[t] > cap + 1u) set_status(S, RTS_E_CAPACITY, (int32_t)ids[pid[t]]);
@@ -688,13 +737,25 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
 #pragma unroll
         for (int t = 0; t < kTestPart; ++t) {
           if ((uint32_t)t >= np) break;
-          uint16_t *row = list_row(p, list, pid[t]);
-          for (uint32_t e = cnt[t] + (uint32_t)lane; e < span; e += 64u) row[e] = (uint16_t)kStageCap;
+          if (in_lds) {
+            for (uint32_t e = cnt[t] + (uint32_t)lane; e < span; e += 64u)
+              lrows[t * kLdsRow + e] = (uint16_t)kStageCap;
+          } else {
+            uint16_t *row = list_row(p, list, pid[t]);
+            for (uint32_t e = cnt[t] + (uint32_t)lane; e < span; e += 64u) row[e] = (uint16_t)kStageCap;
+          }
         }
       }
-      // the entries become visible to the wave's other lanes
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // the entries become visible to the wave's other lanes: shared memory
+      // in order within the wave, memory through a fence
+      if (in_lds) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
       // density: lanes [kDenLanes g, kDenLanes (g + 1)) take particle g
       const uint32_t g = (uint32_t)lane / kDenLanes, sub = (uint32_t)lane % kDenLanes;
       uint32_t i = pid[0], ng = cnt[0];
@@ -711,7 +772,7 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
       }
       const bool live = g < np;
       if (!live) ng = 0u;
-      const uint16_t *row = list_row(p, (const uint16_t *)list, i);
+      uint16_t *row = list_row(p, list, i);
       float sum = 0.0f, comp = 0.0f;
       const auto add = [&](const float4 qj) {
         const float d2 = dist2_exact(xg, yg, zg, qj.x, qj.y, qj.z);
@@ -721,17 +782,27 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
         comp = (tt - sum) - y2;
         sum = tt;
       };
+      const auto add_quad = [&](const uint2 qd) {
+        float4 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = staged_pos(quad_entry(qd, j));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) add(v[j]);
+      };
       const uint32_t rounds = span / (4u * kDenLanes);
       const uint32_t last = (uint32_t)p.nbr_stride - 4u;
-      if (staged) {
-        // lanes of a particle past np walk its (repeated) row and discard it
-        walk_list<kDenLanes>(row, last, rounds, sub, [&](const uint2 qd, uint32_t) {
-          float4 v[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) v[j] = s_pos[quad_entry(qd, j)];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) add(v[j]);
-        });
+      if (in_lds) {
+        // quads of the wave's LDS row, copied to the memory row on the way
+        // (a live particle's row; lanes past np walk a repeated row)
+        const uint2 *lq = &s_lq[wave][min(g, np - 1u)][0];
+        for (uint32_t r = 0; r < rounds; ++r) {
+          const uint32_t e = 4u * sub + 4u * kDenLanes * r;
+          const uint2 qd = lq[e / 4u];
+          if (live) *reinterpret_cast<uint2 *>(row + e) = qd;
+          add_quad(qd);
+        }
+      } else if (staged) {
+        walk_list<kDenLanes>(row, last, rounds, sub, [&](const uint2 qd, uint32_t) { add_quad(qd); });
       } else {
         walk_list<kDenLanes>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
 #pragma unroll
@@ -765,6 +836,10 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
         inter += ng - 1u;
         nmax = max(nmax, ng - 1u);
       }
+      // the next pass rewrites the wave's LDS rows
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     err = wave_max(err);
     inter = wave_sum_u32(inter);
