@@ -507,7 +507,9 @@ __device__ inline uint32_t quad_entry(const uint2 q, int j) {
 // Two quads are in flight, each loaded straight into the register it is
 // used from; the loads are unconditional, at most at entry `last` (the row's
 // last quad), so that no lane mask stands between a load and its wait.
-template <uint32_t kLanes, typename Use>
+// With kPinned the loads are kept ahead of the work by scheduling barriers
+// (a kernel under register pressure otherwise sinks them to their use).
+template <uint32_t kLanes, bool kPinned = false, typename Use>
 __device__ inline void walk_list(const uint16_t *row, uint32_t last, uint32_t rounds, uint32_t sub,
                                  Use &&use) {
   constexpr uint32_t kStep = 4u * kLanes;
@@ -517,9 +519,11 @@ __device__ inline void walk_list(const uint16_t *row, uint32_t last, uint32_t ro
   for (uint32_t r = 0; r < rounds; r += 2, e += 2u * kStep) {
     use(qa, e);
     qa = list_quad(row, min(e + 2u * kStep, last));
+    if (kPinned) __builtin_amdgcn_sched_barrier(0);
     if (r + 1u >= rounds) break;
     use(qb, e + kStep);
     qb = list_quad(row, min(e + 3u * kStep, last));
+    if (kPinned) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -985,7 +989,7 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
       const uint32_t rounds = (most + 4u * kSub - 1u) / (4u * kSub);
       const uint32_t last = (uint32_t)p.nbr_stride - 4u;
       if (staged) {
-        walk_list<kSub>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
+        walk_list<kSub, true>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
           uint32_t kk[4];
           bool ok[4];
 #pragma unroll
@@ -1003,7 +1007,7 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
           for (int j = 0; j < 4; ++j) pair(qa[j], ua[j], kk[j] >= Cf, ok[j]);
         });
       } else {
-        walk_list<kSub>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
+        walk_list<kSub, true>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             if (e + (uint32_t)j >= cnt) break;
