@@ -410,22 +410,34 @@ rts_status rts_profile_advance(rts_ctx *ctx, int32_t n_steps, double *h_ms);
 /* Launch shape of the base step: workgroups of the one-wave-per-block
  * kernels, of the search + density kernel and of the force kernel. */
 typedef struct rts_tune {
-  int32_t grid_wave;
-  int32_t grid_search;
-  int32_t grid_force;
+  int32_t grid_wave;      /* workgroups of the one-wave-per-block kernels */
+  int32_t grid_search;    /* workgroups of the search / density kernel */
+  int32_t grid_force;     /* workgroups of the force kernel */
+  int32_t search_threads; /* threads per search workgroup: 256 or 512 */
+  int32_t force_threads;  /* threads per force workgroup: 512 */
+  int32_t force_lanes;    /* lanes sharing one particle in the force kernel: 4 or 8 */
   int32_t candidates;     /* shapes timed by rts_autotune */
+  int32_t pad_;
   double ms_per_step;     /* replay time of the chosen shape */
 } rts_tune;
 
-/* Times `steps` base steps (WCSPH) under each candidate launch shape from
- * the current state and keeps the fastest; the state is saved to d_scratch
- * (at least rts_state_bytes) before and restored after every candidate, so
- * the run continues exactly as if no tuning had happened (results do not
- * depend on the launch shape).  Waits for the stream. */
+/* Times `steps` base steps (WCSPH) under candidate launch shapes from the
+ * current state and keeps the fastest, one kernel group at a time: the grid
+ * of the one-wave-per-block kernels, then the search kernel's workgroup
+ * size and count, then the force kernel's lanes per particle and workgroup
+ * count.  The state is saved to d_scratch (at least rts_state_bytes) before
+ * and restored after every candidate, so the run continues exactly as if no
+ * tuning had happened: no launch shape changes any result (the force sums a
+ * particle's terms in the same fixed order whatever its lanes).  Waits for
+ * the stream. */
 rts_status rts_autotune(rts_ctx *ctx, int32_t steps, void *d_scratch, size_t scratch_bytes,
                         rts_tune *h_out);
 /* Current launch shape (h_out->candidates = 0, ms_per_step = 0 until tuned). */
 rts_status rts_get_tune(rts_ctx *ctx, rts_tune *h_out);
+/* Sets the launch shape (grids >= 1, the sizes above; candidates and
+ * ms_per_step are ignored), e.g. one tuned before on the same scene.
+ * RTS_E_INVALID for a shape out of range. */
+rts_status rts_set_tune(rts_ctx *ctx, const rts_tune *shape);
 
 /* Differentiable WCSPH substeps (every particle active, symplectic Euler)
  * and their adjoint, for gradient-based inverse problems:

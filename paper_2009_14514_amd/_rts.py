@@ -33,7 +33,7 @@ EXPORTS = [
     "rts_get_scene_stats", "rts_get_scene_state",
     "rts_set_state", "rts_add_velocity", "rts_assign_levels", "rts_advance", "rts_sync",
     "rts_get_state", "rts_state_bytes", "rts_save_state", "rts_load_state", "rts_debug_get", "rts_grid_info",
-    "rts_profile_advance", "rts_autotune", "rts_get_tune", "rts_diff_tape_bytes",
+    "rts_profile_advance", "rts_autotune", "rts_get_tune", "rts_set_tune", "rts_diff_tape_bytes",
     "rts_diff_forward", "rts_diff_backward", "rts_last_error", "rts_status_string",
 ]
 PROF_KERNELS = ["key_hist", "scan", "scatter", "cell_gather", "rmin_flags", "search_density",
@@ -97,10 +97,12 @@ class RtsSceneStats(C.Structure):
 
 class RtsTune(C.Structure):
     _fields_ = [("grid_wave", C.c_int32), ("grid_search", C.c_int32), ("grid_force", C.c_int32),
-                ("candidates", C.c_int32), ("ms_per_step", C.c_double)]
+                ("search_threads", C.c_int32), ("force_threads", C.c_int32),
+                ("force_lanes", C.c_int32), ("candidates", C.c_int32), ("pad_", C.c_int32),
+                ("ms_per_step", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
 class RtsDiffDesc(C.Structure):
@@ -153,6 +155,7 @@ def lib():
         L.rts_profile_advance.argtypes = [vp, i32, C.POINTER(C.c_double)]
         L.rts_autotune.argtypes = [vp, i32, vp, C.c_size_t, C.POINTER(RtsTune)]
         L.rts_get_tune.argtypes = [vp, C.POINTER(RtsTune)]
+        L.rts_set_tune.argtypes = [vp, C.POINTER(RtsTune)]
         dp = C.POINTER(RtsDiffDesc)
         L.rts_diff_tape_bytes.argtypes = [vp, dp, i64, C.POINTER(C.c_size_t)]
         L.rts_diff_forward.argtypes = [vp, dp, i64, vp, vp, vp, vp, vp, C.c_size_t]
@@ -360,6 +363,18 @@ def get_tune(ctx):
     t = RtsTune()
     check(lib().rts_get_tune(ctx, C.byref(t)), ctx)
     return t.as_dict()
+
+
+def set_tune(ctx, shape: dict):
+    """Sets the launch shape from a dict like get_tune's (missing keys keep
+    the current values)."""
+    cur = get_tune(ctx)
+    cur.update(shape)
+    t = RtsTune()
+    for k, _ in t._fields_:
+        if k in cur:
+            setattr(t, k, type(getattr(t, k))(cur[k]))
+    check(lib().rts_set_tune(ctx, C.byref(t)), ctx)
 
 
 def diff_desc(n_sub, ckpt_every, list_cap, dt, B, alpha):

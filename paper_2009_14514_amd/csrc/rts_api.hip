@@ -27,6 +27,8 @@ struct rts_ctx {
   int grid_wave;     // workgroups of the one-wave-per-block kernels (4 waves each)
   int grid_search;   // workgroups of the search / density kernel
   int grid_force;    // workgroups of the force kernel
+  int search_threads;  // threads per search / density workgroup (256, 512)
+  int force_lanes;     // force lanes per particle (4, 8)
   bool has_state;
   bool poisoned;
   double mass, B, dt_base;
@@ -440,8 +442,8 @@ void enqueue_step(rts_ctx *c, int cur, hipStream_t st) {
   launch_scatter(p, d, st);
   launch_cell_gather(p, d, cur, c->grid_wave, st);
   launch_rmin_flags(p, d, nx, 1, c->grid_wave, st);
-  launch_search_density(p, d, nx, c->grid_search, st);
-  launch_force(p, d, nx, c->grid_force, st);
+  launch_search_density(p, d, nx, c->grid_search, c->search_threads, st);
+  launch_force(p, d, nx, c->grid_force, c->force_lanes, st);
   if (fixed_step(c)) {
     launch_stats_correct_predict(p, d, nx, st);
   } else {
@@ -738,6 +740,8 @@ rts_status create_in(const rts_config *cfg, int64_t n_fluid_max, int64_t n_wall_
   c->grid_wave = cus * 8;
   c->grid_search = cus * 3;
   c->grid_force = cus * 2;
+  c->search_threads = 512;
+  c->force_lanes = 8;
   // counts must start at zero; everything else is written before it is read
   hipStream_t st = c->stream;
   const size_t tiles = ((size_t)c->prm.nb + kScanTile - 1) / kScanTile * 8;
@@ -1227,9 +1231,9 @@ rts_status rts_profile_advance(rts_ctx *c, int32_t n_steps, double *h_ms) {
     (void)hipEventRecord(ev[4], q);
     launch_rmin_flags(p, d, nx, 1, c->grid_wave, q);
     (void)hipEventRecord(ev[5], q);
-    launch_search_density(p, d, nx, c->grid_search, q);
+    launch_search_density(p, d, nx, c->grid_search, c->search_threads, q);
     (void)hipEventRecord(ev[6], q);
-    launch_force(p, d, nx, c->grid_force, q);
+    launch_force(p, d, nx, c->grid_force, c->force_lanes, q);
     (void)hipEventRecord(ev[7], q);
     launch_step_stats(p, d, q);
     (void)hipEventRecord(ev[8], q);
@@ -1517,8 +1521,27 @@ rts_status rts_get_tune(rts_ctx *c, rts_tune *out) {
   out->grid_wave = c->grid_wave;
   out->grid_search = c->grid_search;
   out->grid_force = c->grid_force;
+  out->search_threads = c->search_threads;
+  out->force_lanes = c->force_lanes;
+  out->force_threads = 512;
   out->candidates = c->tune_candidates;
   out->ms_per_step = c->tune_ms;
+  return RTS_OK;
+}
+
+rts_status rts_set_tune(rts_ctx *c, const rts_tune *t) {
+  if (!c || !t) return RTS_E_INVALID;
+  if (t->grid_wave < 1 || t->grid_search < 1 || t->grid_force < 1 ||
+      (t->search_threads != 256 && t->search_threads != 512) ||
+      (t->force_lanes != 4 && t->force_lanes != 8) ||
+      (t->force_threads != 0 && t->force_threads != 512))
+    return fail(c, RTS_E_INVALID, "launch shape out of range");
+  c->grid_wave = t->grid_wave;
+  c->grid_search = t->grid_search;
+  c->grid_force = t->grid_force;
+  c->search_threads = t->search_threads;
+  c->force_lanes = t->force_lanes;
+  destroy_graphs(c);  // the next advance captures the new shape
   return RTS_OK;
 }
 
@@ -1541,48 +1564,76 @@ rts_status rts_autotune(rts_ctx *c, int32_t steps, void *d_scratch, size_t scrat
   hipDeviceProp_t prop;
   HIP_OK(c, hipGetDeviceProperties(&prop, dev));
   const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  // candidate workgroup counts per CU of the three launch groups
+  // The launch shape is tuned one kernel group at a time: the grid of the
+  // one-wave-per-block kernels, then the search's workgroup size and count,
+  // then the force's lanes per particle and workgroup count, each against
+  // the best of the ones before.  No choice changes any result.
   const int wave_m[] = {4, 8};
+  const int search_t[] = {512, 256};
   const int search_m[] = {2, 3, 4, 6};
+  const int force_l[] = {8, 4};
   const int force_m[] = {1, 2, 3, 4};
-  int best[3] = {c->grid_wave, c->grid_search, c->grid_force};
+  struct Shape {
+    int gw, gs, gf, st, fl;
+  };
+  Shape best{c->grid_wave, c->grid_search, c->grid_force, c->search_threads, c->force_lanes};
   double best_ms = INFINITY;
   int cand = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
-  for (int a = 0; a < 2 && !s && he == hipSuccess; ++a)
-    for (int b = 0; b < 4 && !s && he == hipSuccess; ++b)
-      for (int f = 0; f < 4 && !s && he == hipSuccess; ++f) {
-        c->grid_wave = cus * wave_m[a];
-        c->grid_search = cus * search_m[b];
-        c->grid_force = cus * force_m[f];
-        destroy_graphs(c);
-        if (c->cfg.use_graph) s = build_graphs(c);
-        if (!s) s = rts_advance(c, 1);                 // first replay of the new shape
-        if (!s) s = rts_load_state(c, d_scratch, need);
-        if (s) break;
-        he = hipEventRecord(e0, c->stream);
-        if (he == hipSuccess) s = rts_advance(c, steps);
-        if (!s && he == hipSuccess) he = hipEventRecord(e1, c->stream);
-        if (!s && he == hipSuccess) he = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (!s && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (s || he != hipSuccess) break;
-        ++cand;
-        if (ms < best_ms) {
-          best_ms = ms;
-          best[0] = c->grid_wave;
-          best[1] = c->grid_search;
-          best[2] = c->grid_force;
-        }
-        s = rts_load_state(c, d_scratch, need);
-      }
+  auto time_shape = [&](const Shape &sh) {
+    c->grid_wave = sh.gw;
+    c->grid_search = sh.gs;
+    c->grid_force = sh.gf;
+    c->search_threads = sh.st;
+    c->force_lanes = sh.fl;
+    destroy_graphs(c);
+    if (c->cfg.use_graph) s = build_graphs(c);
+    if (!s) s = rts_advance(c, 1);                 // first replay of the new shape
+    if (!s) s = rts_load_state(c, d_scratch, need);
+    if (s) return;
+    he = hipEventRecord(e0, c->stream);
+    if (he == hipSuccess) s = rts_advance(c, steps);
+    if (!s && he == hipSuccess) he = hipEventRecord(e1, c->stream);
+    if (!s && he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (!s && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (s || he != hipSuccess) return;
+    ++cand;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = sh;
+    }
+    s = rts_load_state(c, d_scratch, need);
+  };
+  const auto ok = [&] { return !s && he == hipSuccess; };
+  for (int a = 0; a < 2 && ok(); ++a) {
+    Shape sh = best;
+    sh.gw = cus * wave_m[a];
+    time_shape(sh);
+  }
+  for (int t = 0; t < 2 && ok(); ++t)
+    for (int m = 0; m < 4 && ok(); ++m) {
+      Shape sh = best;
+      sh.st = search_t[t];
+      sh.gs = cus * search_m[m];
+      time_shape(sh);
+    }
+  for (int l = 0; l < 2 && ok(); ++l)
+    for (int m = 0; m < 4 && ok(); ++m) {
+      Shape sh = best;
+      sh.fl = force_l[l];
+      sh.gf = cus * force_m[m];
+      time_shape(sh);
+    }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  c->grid_wave = best[0];
-  c->grid_search = best[1];
-  c->grid_force = best[2];
+  c->grid_wave = best.gw;
+  c->grid_search = best.gs;
+  c->grid_force = best.gf;
+  c->search_threads = best.st;
+  c->force_lanes = best.fl;
   destroy_graphs(c);
   rts_status r = rts_load_state(c, d_scratch, need);
   if (s) return s;

@@ -214,9 +214,11 @@ void launch_scatter(const DevParams &p, const DevPtrs &d, hipStream_t st);
 void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st);
 void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags, int grid,
                        hipStream_t st, const uint8_t *src = nullptr);
-void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid,
+// threads: 256 or 512 per workgroup; lanes: 4 or 8 per particle
+void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid, int threads,
                            hipStream_t st);
-void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st);
+void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, int lanes,
+                  hipStream_t st);
 void launch_step_stats(const DevParams &p, const DevPtrs &d, hipStream_t st);
 void launch_debug_lists(const DevParams &p, const DevPtrs &d, int cur, uint32_t *out, uint32_t *out_n,
                         hipStream_t st);

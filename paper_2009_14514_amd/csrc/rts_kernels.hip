@@ -21,7 +21,7 @@
 //   force           one workgroup per active block: candidates' position,
 //                   velocity, density and pressure staged in LDS; pressure +
 //                   viscosity + gravity over the lists, a particle's entries
-//                   shared evenly by its kSub lanes
+//                   shared evenly by its lanes
 //   step_stats      per-step counters and the step length
 //   correct_predict all particles: corrector for the active ones, then the
 //                   predictor of the next base step
@@ -36,14 +36,14 @@
 // No floating-point atomics are used; same-address integer atomics are
 // limited to one per group of equal keys in a wave.
 #include <type_traits>
+#include <utility>
 
 #include "rts_device.h"
 
 namespace rts {
 
-constexpr int kBlockThreads = 512;            // search: eight waves
-constexpr int kForceThreads = 512;            // force: 64 particles x kSub lanes
-constexpr int kForcePerPass = kForceThreads / kSub;
+// search: 256 or 512 threads (a launch-shape choice)
+constexpr int kForceThreads = 512;            // force: 512 / lanes-per-particle particles a pass
 
 // ---------------------------------------------------------------------------
 // key + histogram
@@ -562,7 +562,8 @@ constexpr int kDenLanes = 64 / kTestPart;    // density lanes per particle
 constexpr int kLdsRow = 384;                 // entries of a wave's LDS list row
 constexpr int kLdsUse = kLdsRow - 64;        // entries it holds (a chunk adds up to 64)
 
-__global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(6))) k_search_density(
+template <int kThreads>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) k_search_density(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, float4 *__restrict__ P, float4 *__restrict__ V,
     const uint32_t *__restrict__ M, float *__restrict__ pres, uint32_t *__restrict__ nnb,
@@ -570,12 +571,12 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
     float *__restrict__ blkerr, const uint32_t *__restrict__ ids,
     const uint32_t *__restrict__ actn, DevCtrl *ctrl, DevScalars *S) {
   __shared__ Pos3 s_pos[kStageCap + 1];  // + the far slot named by list padding
-  __shared__ uint2 s_lq[kBlockThreads / 64][kTestPart][kLdsRow / 4];  // LDS list rows, in quads
+  __shared__ uint2 s_lq[kThreads / 64][kTestPart][kLdsRow / 4];  // LDS list rows, in quads
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
   __shared__ uint16_t s_act[kCellMax];
   __shared__ uint32_t s_nact;
-  __shared__ float s_err[kBlockThreads / 64];
-  __shared__ uint32_t s_inter[kBlockThreads / 64], s_nmax[kBlockThreads / 64];
+  __shared__ float s_err[kThreads / 64];
+  __shared__ uint32_t s_inter[kThreads / 64], s_nmax[kThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const uint32_t cap = (uint32_t)p.nbr_cap;  // neighbours; a row holds cap + 1 entries
@@ -598,13 +599,13 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
     if (tid == 0) s_nact = 0;
     block_ranges_shared(p, start, wstart, b, s_rs, s_ro, s_len);
     // active particles of the block (their order here does not matter)
-    for (int k = tid; k < n; k += kBlockThreads)
+    for (int k = tid; k < n; k += kThreads)
       if (meta_compute(M[s0 + (uint32_t)k])) s_act[atomicAdd(&s_nact, 1u)] = (uint16_t)k;
     __syncthreads();
     const uint32_t C = s_ro[18];
     const uint32_t cpad = (C + 63u) / 64u * 64u;
     const bool staged = cpad <= (uint32_t)kStageCap;
-    if (staged) stage_positions<kBlockThreads>(s_rs, s_ro, P, WP, s_pos, cpad);
+    if (staged) stage_positions<kThreads>(s_rs, s_ro, P, WP, s_pos, cpad);
     __syncthreads();
     const uint32_t nact = s_nact;
     const uint32_t self_off = s_ro[4] - s_rs[4];  // local index = sorted index + self_off
@@ -614,7 +615,7 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
     // this wave's particles: slots [q_lo, q_hi) of the active list, whole
     // tiles of kTestPart (only the block's last tile can be partial)
     const uint32_t ntile = (nact + kTestPart - 1u) / kTestPart;
-    const uint32_t per_wave = (ntile + (uint32_t)(kBlockThreads / 64) - 1u) / (uint32_t)(kBlockThreads / 64);
+    const uint32_t per_wave = (ntile + (uint32_t)(kThreads / 64) - 1u) / (uint32_t)(kThreads / 64);
     const uint32_t q_lo = min((uint32_t)wave * per_wave * kTestPart, nact);
     const uint32_t q_hi = fits ? min(q_lo + per_wave * kTestPart, nact) : q_lo;
     float err = 0.0f;
@@ -857,7 +858,7 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
     if (tid == 0) {
       float e = blkerr[b];  // inactive particles, from the flags pass
       uint32_t it = 0, nm = 0;
-      for (int w = 0; w < kBlockThreads / 64; ++w) {
+      for (int w = 0; w < kThreads / 64; ++w) {
         e = fmaxf(e, s_err[w]);
         it += s_inter[w];
         nm = max(nm, s_nmax[w]);
@@ -872,15 +873,61 @@ __global__ void __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per
 // ---------------------------------------------------------------------------
 // forces, one workgroup per block
 // ---------------------------------------------------------------------------
-// kSub lanes per active particle take its list entries four at a time in
-// turn; the candidates' position, density, velocity and p / rho^2 are
-// staged in LDS.
+// 4 or 8 lanes per active particle (a launch-shape choice) take its list
+// entries four at a time in turn; the candidates' position, density,
+// velocity and p / rho^2 are staged in LDS.
 
 // Velocity slot of a wall candidate: at rest, and g . x in place of p / rho^2.
 __device__ inline float4 wall_slot(const DevParams &p, const float4 q) {
   return make_float4(0.0f, 0.0f, 0.0f, p.g[0] * q.x + p.g[1] * q.y + p.g[2] * q.z);
 }
 
+// A particle's acceleration is summed in a fixed decomposition that does not
+// depend on how many lanes share the particle: its list's quads go round-robin
+// to kVirt partial sums (quad q to sum q mod kVirt, each in list order), and
+// the partial sums are folded pairwise at distances kVirt/2, ..., 2, 1.  With
+// kLanes lanes a lane holds kVirt / kLanes of them (lane s the sums s,
+// s + kLanes, ...); the folds at distances of at least kLanes are within a
+// lane, the rest across lanes.  A float sum of two terms does not depend on
+// their order, so every lane count gives the same bits.  Eight sums: at
+// eight lanes a lane holds one (a 16-way split costs the eight-lane shape
+// the registers of a second, and spills).
+constexpr int kVirt = 8;
+
+// Walks a list row like walk_list, kDepth quads in flight; use(quad, e, d)
+// gets the quad's round phase d = round mod kDepth as a compile-time constant
+// (std::integral_constant), so per-phase partial sums stay in registers.
+template <uint32_t kLanes, uint32_t kDepth, typename Use, uint32_t... D>
+__device__ inline void walk_list_phased_(const uint16_t *row, uint32_t last, uint32_t rounds,
+                                         uint32_t sub, Use &&use,
+                                         std::integer_sequence<uint32_t, D...>) {
+  constexpr uint32_t kStep = 4u * kLanes;
+  uint32_t e = 4u * sub;
+  uint2 q[kDepth];
+#pragma unroll
+  for (uint32_t d = 0; d < kDepth; ++d) q[d] = list_quad(row, min(e + d * kStep, last));
+  for (uint32_t r = 0; r < rounds; r += kDepth, e += kDepth * kStep) {
+    (
+        [&] {
+          if (r + D < rounds) {
+            use(q[D], e + D * kStep, std::integral_constant<uint32_t, D>{});
+            q[D] = list_quad(row, min(e + (kDepth + D) * kStep, last));
+            // keeps the load ahead of its use (the kernel's register
+            // pressure would otherwise sink it there)
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }(),
+        ...);
+  }
+}
+template <uint32_t kLanes, uint32_t kDepth, typename Use>
+__device__ inline void walk_list_phased(const uint16_t *row, uint32_t last, uint32_t rounds,
+                                        uint32_t sub, Use &&use) {
+  walk_list_phased_<kLanes, kDepth>(row, last, rounds, sub, use,
+                                    std::make_integer_sequence<uint32_t, kDepth>{});
+}
+
+template <int kLanes>
 __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(4))) k_force(
     DevParams p, const uint32_t *__restrict__ act, const uint32_t *__restrict__ start,
     const uint32_t *__restrict__ wstart, const float4 *__restrict__ P,
@@ -888,6 +935,10 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
     const uint32_t *__restrict__ nnb, const uint16_t *__restrict__ list,
     const float4 *__restrict__ WP, float4 *__restrict__ anew, float *__restrict__ blkamax,
     const uint32_t *__restrict__ actn, DevCtrl *ctrl) {
+  static_assert(kLanes == 4 || kLanes == 8, "lanes per particle divide kVirt");
+  constexpr int kAcc = kVirt / kLanes;                  // partial sums per lane
+  constexpr uint32_t kDepth = kAcc > 2 ? (uint32_t)kAcc : 2u;  // quads in flight
+  constexpr int kPerPass = kForceThreads / kLanes;      // particles per workgroup pass
   __shared__ float4 s_p[kForceCap];
   __shared__ float4 s_v[kForceCap];
   __shared__ uint32_t s_rs[18], s_ro[19], s_len[18];
@@ -895,7 +946,7 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
   __shared__ uint32_t s_nact;
   __shared__ float s_amax[kForceThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t sub = (uint32_t)(tid & (kSub - 1));
+  const uint32_t sub = (uint32_t)(tid & (kLanes - 1));
   const uint32_t cap = (uint32_t)p.nbr_cap;
   // -m grad W(x_ij) = f x_ij with f = -m (sigma / h) w'(q) / r, q = r / h:
   // f = fA + fB q for q < 1, f = fC (2 - q)^2 / r for 1 <= q < 2
@@ -948,20 +999,23 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
     __syncthreads();
     const uint32_t nact = s_nact;
     float a2max = 0.0f;
-    for (uint32_t c0 = 0; c0 < nact && C <= (uint32_t)p.cand_cap; c0 += kForcePerPass) {
-      if (c0 + (uint32_t)(wave * (64 / kSub)) >= nact) break;
-      const uint32_t slot = c0 + (uint32_t)(tid / kSub);
+    for (uint32_t c0 = 0; c0 < nact && C <= (uint32_t)p.cand_cap; c0 += kPerPass) {
+      if (c0 + (uint32_t)(wave * (64 / kLanes)) >= nact) break;
+      const uint32_t slot = c0 + (uint32_t)(tid / kLanes);
       const bool live = slot < nact;
       const uint32_t i = s0 + (live ? (uint32_t)s_act[slot] : 0u);
       const float4 pi = P[i], vi = V[i];
       const float rhoi = pi.w, pri = vi.w;
       const float inv_rhoi = __builtin_amdgcn_rcpf(rhoi);
-      float ax = 0.0f, ay = 0.0f, az = 0.0f;
+      float ax[kAcc], ay[kAcc], az[kAcc];
+#pragma unroll
+      for (int k = 0; k < kAcc; ++k) ax[k] = ay[k] = az[k] = 0.0f;
       // a static wall particle is at rest and mirrors the density and the
       // pressure of the fluid particle, plus the hydrostatic difference
       // g . (x_j - x_i), clamped at zero; uj.w of a wall holds g . x_j
       const float gxi = p.g[0] * pi.x + p.g[1] * pi.y + p.g[2] * pi.z;
-      auto pair = [&](const float4 qj, const float4 uj, bool wall, bool valid) {
+      auto pair = [&](const float4 qj, const float4 uj, bool wall, bool valid, auto kc) {
+        constexpr int k = (int)decltype(kc)::value;
         const float rhoj = wall ? rhoi : qj.w;
         const float prj = wall ? fmaxf(pri + (uj.w - gxi) * inv_rhoi, 0.0f) : uj.w;
         const float dx = pi.x - qj.x, dy = pi.y - qj.y, dz = pi.z - qj.z;
@@ -977,19 +1031,22 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
                            __builtin_amdgcn_rcpf((rhoi + rhoj) * (r2 + p.visc_eps_h2));
         const float coef = pri + prj + (vx < 0.0f ? visc : 0.0f);
         const float sc = valid && r2 > 0.0f ? coef * f : 0.0f;
-        ax += sc * dx;
-        ay += sc * dy;
-        az += sc * dz;
+        ax[k] += sc * dx;
+        ay[k] += sc * dy;
+        az[k] += sc * dz;
       };
       // list entries: the neighbours and the particle itself (r = 0, skipped)
       const uint32_t cnt = live ? min(nnb[i], cap) + 1u : 0u;
       const uint16_t *row = list_row(p, list, i);
-      // rounds of 4 kSub entries, as many as the wave's longest list needs
+      // rounds of 4 kLanes entries, as many as the wave's longest list needs
       const uint32_t most = wave_max_u32(cnt);
-      const uint32_t rounds = (most + 4u * kSub - 1u) / (4u * kSub);
+      const uint32_t rounds = (most + 4u * kLanes - 1u) / (4u * kLanes);
       const uint32_t last = (uint32_t)p.nbr_stride - 4u;
       if (staged) {
-        walk_list<kSub, true>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
+        walk_list_phased<kLanes, kDepth>(row, last, rounds, sub,
+                                         [&](const uint2 qd, uint32_t e, auto dc) {
+          // this round's partial sum
+          const std::integral_constant<int, (int)(decltype(dc)::value % kAcc)> k{};
           uint32_t kk[4];
           bool ok[4];
 #pragma unroll
@@ -1004,32 +1061,44 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
             ua[j] = s_v[kk[j]];
           }
 #pragma unroll
-          for (int j = 0; j < 4; ++j) pair(qa[j], ua[j], kk[j] >= Cf, ok[j]);
+          for (int j = 0; j < 4; ++j) pair(qa[j], ua[j], kk[j] >= Cf, ok[j], k);
         });
       } else {
-        walk_list<kSub, true>(row, last, rounds, sub, [&](const uint2 qd, uint32_t e) {
+        walk_list_phased<kLanes, kDepth>(row, last, rounds, sub,
+                                         [&](const uint2 qd, uint32_t e, auto dc) {
+          const std::integral_constant<int, (int)(decltype(dc)::value % kAcc)> k{};
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             if (e + (uint32_t)j >= cnt) break;
-            const uint32_t k = quad_entry(qd, j);
+            const uint32_t kq = quad_entry(qd, j);
             bool wall;
-            const uint32_t jj = local_to_global(s_rs, s_ro, k, wall);
+            const uint32_t jj = local_to_global(s_rs, s_ro, kq, wall);
             const float4 qj = wall ? WP[jj] : P[jj];
-            pair(qj, wall ? wall_slot(p, qj) : V[jj], wall, true);
+            pair(qj, wall ? wall_slot(p, qj) : V[jj], wall, true, k);
           }
         });
       }
-      for (int o = 1; o < kSub; o <<= 1) {
-        ax += __shfl_xor(ax, o, 64);
-        ay += __shfl_xor(ay, o, 64);
-        az += __shfl_xor(az, o, 64);
+      // fold the kVirt partial sums at distances kVirt/2, ..., 1: within the
+      // lane while the distance is at least kLanes, then across lanes
+#pragma unroll
+      for (int o = kVirt / 2; o >= 1; o >>= 1) {
+        if (o >= kLanes) {
+#pragma unroll
+          for (int k = 0; k < o / kLanes; ++k) {
+            ax[k] = ax[k] + ax[k + o / kLanes];
+            ay[k] = ay[k] + ay[k + o / kLanes];
+            az[k] = az[k] + az[k + o / kLanes];
+          }
+        } else {
+          ax[0] += __shfl_xor(ax[0], o, 64);
+          ay[0] += __shfl_xor(ay[0], o, 64);
+          az[0] += __shfl_xor(az[0], o, 64);
+        }
       }
       if (live && sub == 0) {
-        ax += p.g[0];
-        ay += p.g[1];
-        az += p.g[2];
-        anew[i] = make_float4(ax, ay, az, 0.0f);
-        a2max = fmaxf(a2max, ax * ax + ay * ay + az * az);
+        const float gx = ax[0] + p.g[0], gy = ay[0] + p.g[1], gz = az[0] + p.g[2];
+        anew[i] = make_float4(gx, gy, gz, 0.0f);
+        a2max = fmaxf(a2max, gx * gx + gy * gy + gz * gz);
       }
     }
     a2max = wave_max(a2max);
@@ -1043,6 +1112,7 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
     __syncthreads();
   }
 }
+
 // ---------------------------------------------------------------------------
 // per-step statistics and the step length (kStatBlocks workgroups; the last
 // one to finish folds the partials)
@@ -1486,16 +1556,25 @@ void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_fla
                      src ? src : d.LRAW, d.LVL, d.M[cur], d.P[cur], d.BLKU, d.BLKERR, d.BLKAMAX, d.ACT,
                      d.ACTN, d.S, do_flags);
 }
-void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid,
+void launch_search_density(const DevParams &p, const DevPtrs &d, int cur, int grid, int threads,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_search_density, dim3((unsigned)grid), dim3(kBlockThreads), 0, st, p, d.ACT,
-                     d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.PRES, d.NNB,
-                     d.LIST, d.WP, d.BLKU, d.BLKERR, d.ID[cur], d.ACTN, d.CTRL, d.S);
+  auto go = [&](auto kernel, int nt) {
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3((unsigned)nt), 0, st, p, d.ACT,
+                       d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.PRES, d.NNB,
+                       d.LIST, d.WP, d.BLKU, d.BLKERR, d.ID[cur], d.ACTN, d.CTRL, d.S);
+  };
+  if (threads == 256) go(k_search_density<256>, 256);
+  else go(k_search_density<512>, 512);
 }
-void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_force, dim3((unsigned)grid), dim3(kForceThreads), 0, st, p, d.ACT,
-                     d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.NNB, d.LIST,
-                     d.WP, d.ANEW, d.BLKAMAX, d.ACTN, d.CTRL);
+void launch_force(const DevParams &p, const DevPtrs &d, int cur, int grid, int lanes,
+                  hipStream_t st) {
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kForceThreads), 0, st, p, d.ACT,
+                       d.CELL_START, d.WCELL_START, d.P[cur], d.V[cur], d.M[cur], d.NNB, d.LIST,
+                       d.WP, d.ANEW, d.BLKAMAX, d.ACTN, d.CTRL);
+  };
+  if (lanes == 4) go(k_force<4>);
+  else go(k_force<8>);
 }
 void launch_step_stats(const DevParams &p, const DevPtrs &d, hipStream_t st) {
   hipLaunchKernelGGL(k_step_stats, dim3(kStatBlocks), dim3(256), 0, st, p, d.OCC, d.BLKU,

@@ -178,6 +178,11 @@ class Simulation:
     def tune(self):
         return _rts.get_tune(self.ctx)
 
+    def set_tune(self, **shape):
+        """Sets launch-shape fields (grid_wave, grid_search, grid_force,
+        search_threads, force_lanes); no shape changes any result."""
+        _rts.set_tune(self.ctx, shape)
+
     def save(self):
         torch = _torch()
         nb = _rts.state_bytes(self.ctx)

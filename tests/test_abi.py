@@ -80,7 +80,8 @@ def test_struct_layouts_match_the_header(tmp_path):
                                         "pci_dt_min", "pci_shrink"]),
         "rts_stats": (_rts.RtsStats, ["bad_index", "pci_iters", "pci_errmax", "pci_iters_total",
                                       "pci_rollbacks", "pci_dt_next"]),
-        "rts_tune": (_rts.RtsTune, ["candidates", "ms_per_step"]),
+        "rts_tune": (_rts.RtsTune, ["search_threads", "force_threads", "force_lanes", "candidates",
+                                    "ms_per_step"]),
         "rts_diff_desc": (_rts.RtsDiffDesc, ["list_cap", "dt", "alpha"]),
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rts.h"', "int main(void) {"]

@@ -8,7 +8,7 @@ result.
 import numpy as np
 import pytest
 
-from paper_2009_14514_amd import scenes
+from paper_2009_14514_amd import _rts, scenes
 from paper_2009_14514_amd.sim import Simulation, neighbour_lists
 
 pytestmark = pytest.mark.gpu
@@ -70,12 +70,53 @@ def test_autotune_keeps_results_bitwise():
     ref.sync()
     tuned = Simulation(sc)
     t = tuned.autotune(steps=3)
-    assert t["candidates"] == 32 and t["ms_per_step"] > 0
+    # 2 wave grids, 2 x 4 search shapes, 2 x 4 force shapes
+    assert t["candidates"] == 18 and t["ms_per_step"] > 0
     assert tuned.tune()["grid_force"] == t["grid_force"]
+    assert t["search_threads"] in (256, 512) and t["force_lanes"] in (4, 8)
     tuned.advance(30)
     tuned.sync()
     a, b = ref.state(), tuned.state()
     assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+
+
+SHAPES = [
+    dict(search_threads=512, force_lanes=8, grid_search=768, grid_force=512),
+    dict(search_threads=256, force_lanes=4, grid_search=1024, grid_force=768),
+    dict(search_threads=512, force_lanes=4, grid_search=512, grid_force=256),
+    dict(search_threads=256, force_lanes=8, grid_search=1536, grid_force=1024),
+]
+
+
+def test_launch_shapes_give_identical_bits():
+    # workgroup size and count of the search, lanes per particle and
+    # workgroup count of the force: the same 40 regional steps of a
+    # 19,200-particle dam break bit for bit under each shape
+    sc = scenes.dam_break_column(counts=(24, 40, 20), spacing=0.01, box=(0.6, 0.5, 0.3))
+    runs = []
+    for shape in SHAPES:
+        sim = Simulation(sc)
+        sim.set_tune(**shape)
+        got = sim.tune()
+        assert all(got[k] == v for k, v in shape.items()), (shape, got)
+        sim.advance(40)
+        st = sim.sync()
+        runs.append((st, sim.state()))
+        sim.close()
+    st0, s0 = runs[0]
+    assert st0.active_total > 0
+    for (st, s), shape in zip(runs[1:], SHAPES[1:]):
+        assert (st.active_total, st.inter_total) == (st0.active_total, st0.inter_total), shape
+        for k in ("pos", "vel", "acc", "rho", "p", "level"):
+            assert np.array_equal(s[k], s0[k]), (shape, k)
+
+
+def test_launch_shape_out_of_range_is_refused():
+    sim = Simulation(scenes.dam_break_small())
+    for bad in (dict(search_threads=384), dict(force_lanes=16), dict(grid_force=0)):
+        with pytest.raises(_rts.RtsError) as e:
+            sim.set_tune(**bad)
+        assert e.value.status == _rts.RTS_E_INVALID
 
 
 def test_full_size_batch_structure_lists_and_sampled_density():
