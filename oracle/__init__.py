@@ -99,7 +99,7 @@ class OrcPciCtl(C.Structure):
     _fields_ = [
         ("iter", C.c_int32), ("row", C.c_int32), ("min_iter", C.c_int32), ("global_", C.c_int32),
         ("local_iters", C.c_int32), ("global_iters", C.c_int32), ("resets", C.c_int32),
-        ("reverts", C.c_int32),
+        ("reverts", C.c_int32), ("local_off", C.c_int32),
     ]
 
 

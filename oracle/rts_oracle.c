@@ -964,11 +964,17 @@ int orc_pci_ctl_after(const orc_cfg *c, orc_pci_ctl *k, int32_t standard, double
     if (!k->global) {                      /* abandon the local phase */
       act = ORC_CTL_RESTORE;
       ++k->reverts;
+      k->local_off = 1;
     }
     k->global = 1;
     k->row = 1;
     ++k->resets;
     return act;
+  }
+  if (k->local_off) {                      /* the step's one local phase has */
+    k->row = 1;                            /* failed: global restarts from here */
+    ++k->resets;
+    return ORC_CTL_KEEP;
   }
   if (k->global) {                         /* local corrections on S_e */
     k->global = 0;
@@ -977,6 +983,7 @@ int orc_pci_ctl_after(const orc_cfg *c, orc_pci_ctl *k, int32_t standard, double
   }
   if (++k->local_iters >= c->local_fail) { /* local phase failed */
     k->global = 1;
+    k->local_off = 1;
     k->row = 1;
     ++k->reverts;
     return ORC_CTL_RESTORE;

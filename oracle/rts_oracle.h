@@ -203,10 +203,15 @@ typedef struct orc_pci_state {
  *     - if the average error >= eta_T: the schedule restarts at row 1
  *       (global); a local phase that was running is abandoned and the
  *       pressure restored from the snapshot (a revert);
+ *     - else, once the minor step's local phase has ended unconverged
+ *       (local_off): the schedule restarts at row 1 (global);
  *     - else, if global: local iterations on S_e begin, with a snapshot of
  *       the pressure;
  *     - else, after local_fail local iterations without convergence: back to
  *       global at row 1 with the pressure restored (a revert).
+ *   A minor step thus runs at most one local phase: local correction is
+ *   chosen once, and the switch back to global corrections after it fails
+ *   holds for the rest of the minor step.
  * Standard PCISPH (every region in every iteration) only grows min_iter. */
 typedef struct orc_pci_ctl {
   int32_t iter;                      /* number of the next iteration, from 1 */
@@ -217,6 +222,7 @@ typedef struct orc_pci_ctl {
   int32_t global_iters;              /* iterations that followed the schedule */
   int32_t resets;                    /* schedule restarts */
   int32_t reverts;                   /* pressure restorations */
+  int32_t local_off;                 /* 1 once the minor step's local phase ended */
 } orc_pci_ctl;
 enum { ORC_CTL_KEEP = 0, ORC_CTL_BACKUP = 1, ORC_CTL_RESTORE = 2 };
 

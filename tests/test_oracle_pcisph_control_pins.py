@@ -9,7 +9,9 @@ Updates", and Algorithms 2-3:
   average compression of at least eta_T restarts the schedule (global
   iterations), otherwise local iterations correct S_e; local iterations that
   do not converge within a few (3) iterations switch back to global ones and
-  the pressures return to their values from before the local phase;
+  the pressures return to their values from before the local phase; the
+  switch back holds for the rest of the minor step (local correction is
+  chosen once per minor step);
 * a minor step with more than 6 global iterations ends its major step early;
   the following major steps are 2 minor steps long until 10 major steps in a
   row pass without such a minor step;
@@ -100,15 +102,40 @@ def test_global_error_restarts_the_schedule_after_every_extra_iteration():
 def test_local_phase_reverts_after_local_fail_iterations():
     """Average < eta_T: local iterations on S_e (no region has the turn),
     a pressure snapshot when they begin, and after local_fail = 3 failed
-    ones the pressures come back and the schedule restarts."""
+    ones the pressures come back and the schedule restarts; no second local
+    phase follows in the same minor step: every later extra iteration
+    restarts the schedule (row 1, every region)."""
     c = pcfg(eta=0.01, eta_T=0.0025, it_max=12, local_fail=3)
     k, rec, stopped = drive(c, [(0.02, 0.001)] * 20)
     assert stopped and len(rec) == 12
-    assert [r["glob"] for r in rec] == [1, 1, 1, 0, 0, 0, 1, 0, 0, 0, 1, 0]
-    assert [r["turn"] for r in rec] == [ALL, ALL, R1, 0, 0, 0, ALL, 0, 0, 0, ALL, 0]
+    assert [r["glob"] for r in rec] == [1, 1, 1, 0, 0, 0, 1, 1, 1, 1, 1, 1]
+    assert [r["row"] for r in rec] == [1, 2, 3, 4, 5, 6, 1, 1, 1, 1, 1, 1]
+    assert [r["turn"] for r in rec] == [ALL, ALL, R1, 0, 0, 0, ALL, ALL, ALL, ALL, ALL, ALL]
     assert [r["action"] for r in rec] == [KEEP, KEEP, BACKUP, KEEP, KEEP, RESTORE,
-                                          BACKUP, KEEP, KEEP, RESTORE, BACKUP, KEEP]
-    assert (k.global_iters, k.resets, k.reverts) == (5, 0, 2)
+                                          KEEP, KEEP, KEEP, KEEP, KEEP, KEEP]
+    assert (k.global_iters, k.resets, k.reverts) == (9, 6, 1)
+
+
+def test_a_new_minor_step_may_go_local_again():
+    """The one-local-phase rule is per minor step: a fresh control (the next
+    minor step) chooses local correction again."""
+    c = pcfg(eta=0.01, eta_T=0.0025, it_max=8, local_fail=3)
+    for _ in range(2):
+        k, rec, _ = drive(c, [(0.02, 0.001)] * 20)
+        assert [r["action"] for r in rec] == [KEEP, KEEP, BACKUP, KEEP, KEEP, RESTORE, KEEP, KEEP]
+
+
+def test_a_local_phase_abandoned_for_the_mean_is_not_resumed():
+    """The mean rising to eta_T ends the local phase too (revert and
+    restart); when it falls back below eta_T the step stays global."""
+    c = pcfg(eta=0.01, eta_T=0.0025, it_max=9)
+    errs = [(0.02, 0.001)] * 4 + [(0.02, 0.003)] + [(0.02, 0.001)] * 10
+    k, rec, stopped = drive(c, errs)
+    assert stopped and len(rec) == 9
+    assert [r["glob"] for r in rec] == [1, 1, 1, 0, 0, 1, 1, 1, 1]
+    assert [r["action"] for r in rec] == [KEEP, KEEP, BACKUP, KEEP, RESTORE,
+                                          KEEP, KEEP, KEEP, KEEP]
+    assert (k.global_iters, k.resets, k.reverts) == (7, 5, 1)
 
 
 @pytest.mark.parametrize("fail", [1, 2, 4])
@@ -385,19 +412,22 @@ def traced(steps, **over):
 def test_forced_local_phases_restore_the_pressures_bit_for_bit():
     """eta tiny (never converged) with eta_T above any average: every minor
     step runs it_max = 12 iterations as 3 scheduled rows, 3 local, a revert,
-    1 global, 3 local, a revert, 1 global, 1 local."""
+    then 6 global restarts (row 1, every particle)."""
     sim = traced(2, eta=1e-9, eta_T=1.0, it_max=12)
     for h in sim.history:
         tr = h["trace"]
-        assert [t["glob"] for t in tr] == [1, 1, 1, 0, 0, 0, 1, 0, 0, 0, 1, 0]
+        assert [t["glob"] for t in tr] == [1, 1, 1, 0, 0, 0, 1, 1, 1, 1, 1, 1]
         assert [t["action"] for t in tr] == [KEEP, KEEP, BACKUP, KEEP, KEEP, RESTORE,
-                                             BACKUP, KEEP, KEEP, RESTORE, BACKUP, KEEP]
-        assert (h["iters"], h["global_iters"], h["resets"], h["reverts"]) == (12, 5, 0, 2)
+                                             KEEP, KEEP, KEEP, KEEP, KEEP, KEEP]
+        assert [t["row"] for t in tr][6:] == [1] * 6
+        assert all(t["n_density"] == sim.state.n for t in tr[6:])
+        assert (h["iters"], h["global_iters"], h["resets"], h["reverts"]) == (12, 9, 6, 1)
         P = h["trace_p"]
-        # the snapshot is the pressure after iteration 3 (7); the revert after
-        # iteration 6 (10) brings it back exactly, though iterations 4-6 moved it
-        assert np.array_equal(P[5], P[2]) and np.array_equal(P[9], P[6])
+        # the snapshot is the pressure after iteration 3; the revert after
+        # iteration 6 brings it back exactly, though iterations 4-6 moved it
+        assert np.array_equal(P[5], P[2])
         assert not np.array_equal(P[3], P[2])
+        assert not np.array_equal(P[6], P[5])
         # local iterations: no region has the turn; the pressure force is
         # evaluated on S_e alone, the density on S_e and the observed blocks
         for t in tr:
