@@ -99,7 +99,8 @@ typedef struct rts_config {
   int32_t it_min;         /* correction iterations per minor step, at least (3) */
   int32_t it_max;         /* ... and at most (50) */
   int32_t expand_layers;  /* regions 1 and 2 grow by this many block layers (4) */
-  int32_t local_fail;     /* local iterations before reverting to global ones (3) */
+  int32_t local_fail;     /* local iterations before reverting to global ones (3); a
+                             minor step runs at most one local phase */
   int32_t global_limit;   /* global iterations in one minor step that end the major step (6) */
   int32_t short_majors;   /* clean major steps before the long major step returns (10) */
   int32_t nbr_cap;        /* neighbour-list entries per particle, in [8, 4096] (both solvers;
@@ -164,7 +165,8 @@ typedef struct rts_stats {
   /* PCISPH, last minor step */
   int32_t pci_iters;                 /* correction iterations */
   int32_t pci_global_iters;          /* of which with the schedule (global) */
-  int32_t pci_resets;                /* restarts of the schedule (average error too high) */
+  int32_t pci_resets;                /* restarts of the schedule (average error too high,
+                                        or any extra iteration after a failed local phase) */
   int32_t pci_reverts;               /* local phases abandoned, pressure restored */
   int32_t pci_early_end;             /* 1: the major step ended early after this step */
   int32_t pci_lists;                 /* neighbour lists rebuilt */

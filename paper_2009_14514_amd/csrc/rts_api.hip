@@ -563,6 +563,7 @@ rts_status pci_minor_step(rts_ctx *c) {
   launch_pci_reset(p, d, st);
   HIP_OK(c, hipGetLastError());
   int iter = 1, row = 1, min_iter = c->cfg.it_min, global = 1, local_iters = 0;
+  bool local_off = false;   // the minor step's one local phase has ended
   int global_iters = 0, resets = 0, reverts = 0;
   double errmax = INFINITY, avg = 0.0;
   const double eta = c->cfg.eta;
@@ -595,8 +596,12 @@ rts_status pci_minor_step(rts_ctx *c) {
         if (!global) {
           launch_pci_pressure_copy(p, d, 0, st);
           ++reverts;
+          local_off = true;
         }
         global = 1;
+        row = 1;
+        ++resets;
+      } else if (local_off) {               // back to global for the rest of the step
         row = 1;
         ++resets;
       } else if (global) {                  // local corrections on S_e
@@ -606,6 +611,7 @@ rts_status pci_minor_step(rts_ctx *c) {
       } else if (++local_iters >= c->cfg.local_fail) {
         launch_pci_pressure_copy(p, d, 0, st);
         global = 1;
+        local_off = true;
         row = 1;
         ++reverts;
       }

@@ -5,7 +5,7 @@ Iterations", "Local Density Correction", "Neighborhood Computation and
 Updates") and Algorithms 2-3: after the three scheduled rows, extra
 iterations restart the schedule when the mean compression is at least eta_T
 and otherwise correct S_e locally, reverting the pressures after local_fail
-failed local iterations; a minor step with more than global_limit global
+failed local iterations (after which the minor step stays global); a minor step with more than global_limit global
 iterations ends its major step early and the next major steps are two
 minor steps long until short_majors clean ones pass; particles that need a
 smaller step take their block and its 26 neighbours to it.
@@ -123,14 +123,22 @@ def test_every_extra_iteration_restarts_the_schedule_when_the_mean_is_high():
     assert seen["resets"] > 0 and seen["reverts"] == 0
 
 
-def test_local_phases_revert_the_pressure_bit_for_bit():
+def test_local_phase_reverts_the_pressure_bit_for_bit():
     """eta far below reach and eta_T far above: every minor step runs it_max
-    iterations of three scheduled rows and then alternating local phases of
-    local_fail iterations, each ending in a revert; the last iteration
-    (14 = 3 + 3 + 1 + 3 + 1 + 3) ends one, so the pressures after the step
-    equal their snapshot bit for bit."""
-    sim, ref, seen = run_both(6, eta=1e-6, eta_T=1.0, it_max=14)
+    = 6 iterations, three scheduled rows and one local phase of local_fail
+    iterations that ends in a revert, so the pressures after the step equal
+    their snapshot bit for bit."""
+    sim, ref, seen = run_both(6, eta=1e-6, eta_T=1.0, it_max=6)
     for h in ref.history:
-        assert (h["iters"], h["global_iters"], h["reverts"]) == (14, 5, 3)
+        assert (h["iters"], h["global_iters"], h["resets"], h["reverts"]) == (6, 3, 0, 1)
     pv = sim.debug("PCI_PV")
     assert np.array_equal(pv[:, 0].view(np.uint32), pv[:, 2].view(np.uint32))
+
+
+def test_failed_local_phase_leaves_the_step_global():
+    """The same settings with it_max = 14: after the one local phase and its
+    revert, the remaining 8 iterations are global restarts of the schedule."""
+    _, ref, _ = run_both(6, eta=1e-6, eta_T=1.0, it_max=14)
+    # run_both compares every minor step's counters with the oracle's
+    assert {(h["iters"], h["global_iters"], h["resets"], h["reverts"])
+            for h in ref.history} == {(14, 11, 8, 1)}
