@@ -339,21 +339,22 @@ def run_gpu(args):
     return out
 
 
-def run_pcisph(steps):
-    """RTS PCISPH vs standard PCISPH on the 1,000,188-particle double dam break.
+def pcisph_arms(make_scene, steps, label):
+    """Regional and standard PCISPH over the same minor steps from rest.
 
-    Both arms run the same minor steps from rest (so equal simulated time);
-    the correction loop reads its error reductions between iterations, so
-    each minor step is timed by wall clock around a completed call.
+    The correction loop reads its error reductions between iterations, so
+    each minor step is timed by wall clock around a completed call.  An arm
+    that stops with a device status (a particle leaves the domain when the
+    step is too long for the spacing) records the status instead of a time.
     """
     import torch
 
-    from paper_2009_14514_amd import scenes
+    from paper_2009_14514_amd._rts import RtsError
     from paper_2009_14514_amd.sim import Simulation
 
     out = {}
     for mode in ("rts", "global_fixed"):
-        sc = scenes.double_dam_break()
+        sc = make_scene()
         sc.params["mode"] = mode
         sim = Simulation(sc)
         sim.advance(1)                       # first major step set-up and lists: warm-up
@@ -361,17 +362,55 @@ def run_pcisph(steps):
         sim.set_state(sc.pos, sc.vel)        # back to rest
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim.advance(steps)
-        st = sim.sync()
+        try:
+            sim.advance(steps)
+            st = sim.sync()
+        except RtsError as e:
+            st = sim.sync(raise_on_error=False)
+            out[mode] = dict(n=sc.n, failed=str(e), time=st.time)
+            print(f"[bench] {label} {mode}: stopped at t = {st.time:.4f} s ({e})",
+                  file=sys.stderr, flush=True)
+            sim.close()
+            continue
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         out[mode] = dict(n=sc.n, ms=el * 1e3, iters=int(st.pci_iters_total), time=st.time,
                          errmax=float(st.pci_errmax), hist=list(st.level_hist)[:4])
-        print(f"[bench] pcisph {mode}: {steps} minor steps in {el * 1e3:.1f} ms, "
+        print(f"[bench] {label} {mode}: {steps} minor steps in {el * 1e3:.1f} ms, "
               f"{st.pci_iters_total} iterations", file=sys.stderr, flush=True)
         sim.close()
+    return out
+
+
+def arm_summary(a, steps):
+    if "failed" in a:
+        return {"stopped": a["failed"], "stopped_at_s": a["time"]}
+    return {"value": a["n"] * steps / (a["ms"] * 1e-3), "ms_per_step": a["ms"] / steps,
+            "iterations": a["iters"], "density_err_last": a["errmax"]}
+
+
+def run_pcisph(steps):
+    """RTS PCISPH vs standard PCISPH on the 1,000,188-particle double dam break,
+    and on the same scene at the literal 0.008 m spacing (500,000 particles)
+    with base steps of 1e-3 s and 5e-4 s."""
+    from paper_2009_14514_amd import scenes
+
+    out = pcisph_arms(scenes.double_dam_break, steps, "pcisph 1M")
     r, g = out["rts"], out["global_fixed"]
+    if "failed" in r or "failed" in g:
+        raise RuntimeError(f"PCISPH 1M double dam break stopped: {r.get('failed')} {g.get('failed')}")
     n = r["n"]
+    literal = {}
+    for dt in (1e-3, 5e-4):
+        lo = pcisph_arms(lambda: scenes.double_dam_break(spacing=0.008, dt_base=dt), steps,
+                         f"pcisph 500k dt={dt:g}")
+        e = {"n_particles": lo["rts"]["n"], "spacing_m": 0.008, "dt_base_s": dt,
+             "minor_steps": steps, "unit": "particle-steps/s",
+             "rts": arm_summary(lo["rts"], steps),
+             "standard_pcisph": arm_summary(lo["global_fixed"], steps)}
+        if "ms" in lo["rts"] and "ms" in lo["global_fixed"]:
+            e["speedup_vs_standard"] = lo["global_fixed"]["ms"] / lo["rts"]["ms"]
+        literal[f"dt_{dt:g}"] = e
     return {
         "workload": "pcisph_rts_double_dam_break_1m", "n_particles": n, "minor_steps": steps,
         "dt_base_s": 5e-4, "unit": "particle-steps/s",
@@ -380,6 +419,7 @@ def run_pcisph(steps):
         "standard_pcisph": {"value": n * steps / (g["ms"] * 1e-3), "ms_per_step": g["ms"] / steps,
                             "iterations": g["iters"], "density_err_last": g["errmax"]},
         "speedup_vs_standard": g["ms"] / r["ms"],
+        "literal_spacing_500k": literal,
         "adaptive_base_step": run_pcisph_adaptive(steps * 5e-4, r["ms"] / (steps * 5e-4)),
     }
 
