@@ -293,7 +293,7 @@ void derive(const rts_config &c, int64_t ncap, int64_t nwcap, DevParams &p, doub
   }
   (void)nwcap;
   p.nb = (int32_t)nb;
-  p.act_cap = (int32_t)((nb + kActBuckets - 1) / kActBuckets);
+  p.act_cap = (int32_t)((nb + kActParts - 1) / kActParts);
   p.inv_e = (float)(1.0 / c.block_edge);
   p.r2f = (float)(c.support * c.support);
   p.h = (float)c.h;

@@ -35,7 +35,7 @@ struct DevParams {
   int32_t nbr_stride;    // WCSPH list row: nbr_cap + 1 rounded up to a multiple of 64, + 64
   int32_t nc[3];
   int32_t nb;
-  int32_t act_cap;       // entries per active-block list segment: ceil(nb / kActBuckets)
+  int32_t act_cap;       // entries per active-block list segment: ceil(nb / kActParts)
   float o[3];
   float inv_e, r2f;
   float h, inv_h, sigma, mass;
@@ -98,10 +98,19 @@ struct DevCtrl {
   uint32_t pad[3];
 };
 
-// The active-block list is kActBuckets segments of act_cap entries; blocks
-// at occupied positions [r nocc / kActBuckets, (r+1) nocc / kActBuckets)
-// append to segment r, so appends spread over kActBuckets counters.
-constexpr int kActBuckets = 64;
+// The active-block list is kActBuckets segments of act_cap entries, read in
+// segment order.  A block appends to segment kActParts c + s: its size class
+// c runs from 0 (more than 16 (kActClasses - 1) active particles) to
+// kActClasses - 1 (at most 16), its part s is its position among the nocc
+// occupied blocks in kActParts equal ranges.  The list thus hands out the
+// blocks with the most work first and the smallest last, so that persistent
+// workgroups taking blocks in list order finish close together, and the
+// appends spread over kActBuckets counters.  A part holds at most
+// ceil(nocc / kActParts) blocks, so act_cap = ceil(nb / kActParts) entries
+// always suffice.
+constexpr int kActBuckets = 256;
+constexpr int kActClasses = 8;
+constexpr int kActParts = kActBuckets / kActClasses;
 
 // Counters kept on the device (part of the saved state).
 struct DevScalars {

@@ -434,10 +434,14 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
     if (lane == 0) {
       blku[b] = make_uint4(nact, 0u, 0u, (uint32_t)n << 16);
       blkerr[b] = err;
-      // blocks with work join this step's active-block list (their order
-      // there does not change any result); the others report no force
+      // blocks with work join this step's active-block list, largest size
+      // class first (their order there does not change any result); the
+      // others report no force
       if (nact > 0u) {
-        const uint32_t r = (uint32_t)(((unsigned long long)q * kActBuckets) / nocc);
+        const uint32_t cls = (uint32_t)(kActClasses - 1) - min((nact - 1u) / 16u,
+                                                                (uint32_t)(kActClasses - 1));
+        const uint32_t part = (uint32_t)(((unsigned long long)q * kActParts) / nocc);
+        const uint32_t r = cls * (uint32_t)kActParts + part;
         act[r * (uint32_t)p.act_cap + atomicAdd(&actn[r], 1u)] = b;
       } else {
         blkamax[b] = 0.0f;
@@ -455,14 +459,25 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
 __device__ inline void active_prefix(const uint32_t *__restrict__ actn, uint32_t *pre) {
   const int tid = threadIdx.x;
   if (tid < 64) {
-    static_assert(kActBuckets == 64, "one wave scans the segment lengths");
-    uint32_t v = actn[tid];
+    // one wave: each lane sums kPer consecutive segments, the lane totals
+    // are scanned across the wave
+    constexpr int kPer = kActBuckets / 64;
+    static_assert(kActBuckets % 64 == 0, "segments come in whole waves");
+    uint32_t v[kPer], s = 0u;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      s += actn[tid * kPer + j];
+      v[j] = s;
+    }
+    uint32_t x = s;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t u = (uint32_t)__shfl_up((int)v, o, 64);
-      if (tid >= o) v += u;
+      const uint32_t u = (uint32_t)__shfl_up((int)x, o, 64);
+      if (tid >= o) x += u;
     }
-    pre[tid + 1] = v;
+    const uint32_t before = x - s;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) pre[tid * kPer + j + 1] = before + v[j];
     if (tid == 0) pre[0] = 0u;
   }
   __syncthreads();
