@@ -179,6 +179,7 @@ struct DevPtrs {
   uint32_t *COUNT;   // nb, zero between sorts
   uint32_t *CELL_START;  // nb + 1
   uint32_t *OCC;     // occupied blocks, ascending
+  uint4 *OCCR;       // the same blocks with their sorted range: key, first slot, end slot, 0
   uint32_t *ACT;     // blocks holding an active particle this step, kActBuckets segments
   uint32_t *ACTN;    // kActBuckets segment lengths, zero at every step's start
   uint8_t *LRAW, *LVL;   // block level before / after R_min

@@ -66,23 +66,29 @@ __device__ inline void bin_particle(const DevParams &p, int i, bool live, float4
     keyold[i] = k;
   }
   // Particles arrive in the previous sorted order, so a wave holds few
-  // distinct keys: one atomic per distinct key, ranks handed out in-wave.
+  // distinct keys: one atomic per distinct key, by the key's first lane, all
+  // issued at once; ranks handed out in-wave.
   bool done = !live;
+  int leader_of = 0;          // first lane holding this lane's key
+  uint32_t below = 0, group = 0;
   unsigned long long todo = __ballot(!done);
   while (todo) {
     const int leader = __ffsll((long long)todo) - 1;
     const uint32_t lk = (uint32_t)__shfl((int)k, leader, 64);
     const bool mine = !done && k == lk;
     const unsigned long long same = __ballot(mine);
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&count[lk], (uint32_t)__popcll(same));
-    base = (uint32_t)__shfl((int)base, leader, 64);
     if (mine) {
-      rank[i] = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+      leader_of = leader;
+      below = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
       done = true;
     }
+    if (lane == leader) group = (uint32_t)__popcll(same);
     todo = __ballot(!done);
   }
+  uint32_t base = 0;
+  if (live && lane == leader_of) base = atomicAdd(&count[k], group);
+  base = (uint32_t)__shfl((int)base, leader_of, 64);
+  if (live) rank[i] = base + below;
 }
 
 // The words a step's kernels count with start from zero (the statistics'
@@ -209,6 +215,7 @@ __global__ void __launch_bounds__(256) k_scan(uint32_t *__restrict__ count,
                                              unsigned long long *__restrict__ tiles,
                                              unsigned long long *__restrict__ tiles2,
                                              uint32_t *__restrict__ occ,
+                                             uint4 *__restrict__ occr,
                                              uint8_t *__restrict__ lraw,
                                              uint8_t *__restrict__ lvl, DevCtrl *ctrl,
                                              DevScalars *S) {
@@ -255,6 +262,7 @@ __global__ void __launch_bounds__(256) k_scan(uint32_t *__restrict__ count,
       if (occ) {
         if (v[k]) {
           occ[off2] = (uint32_t)idx;
+          occr[off2] = make_uint4((uint32_t)idx, off, off + v[k], 0u);
         } else {
           lraw[idx] = kEmpty;
           lvl[idx] = kEmpty;
@@ -299,24 +307,41 @@ __device__ inline uint32_t rank_in(const uint32_t *s, int n, uint32_t val) {
   return r;
 }
 
+// The same over a shared-memory row padded with 0xFFFFFFFF up to a multiple
+// of 16 entries (no value ranks above the padding): four 16-byte reads in
+// flight per step instead of one dependent read per entry.
+__device__ inline uint32_t rank_in16(const uint4 *s4, int n, uint32_t val) {
+  uint32_t r = 0;
+  for (int m = 0; m < n; m += 16) {
+    uint4 q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = s4[m / 4 + j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      r += (q[j].x < val ? 1u : 0u) + (q[j].y < val ? 1u : 0u) + (q[j].z < val ? 1u : 0u) +
+           (q[j].w < val ? 1u : 0u);
+  }
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // one wave per occupied block: canonical order, gather, block maxima, level
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_cell_gather(
-    DevParams p, const uint32_t *__restrict__ occ, const uint32_t *__restrict__ start,
-    const uint32_t *__restrict__ tmp, uint32_t *__restrict__ perm, uint32_t *__restrict__ key,
+    DevParams p, const uint4 *__restrict__ occr, const uint32_t *__restrict__ tmp, uint32_t *__restrict__ perm, uint32_t *__restrict__ key,
     const float4 *__restrict__ Pi, const float4 *__restrict__ Vi, const float4 *__restrict__ Ai,
     const uint32_t *__restrict__ Mi, const uint32_t *__restrict__ Ii, float4 *__restrict__ Po,
     float4 *__restrict__ Vo, float4 *__restrict__ Ao, uint32_t *__restrict__ Mo,
     uint32_t *__restrict__ Io, uint8_t *__restrict__ lraw, DevScalars *S) {
-  __shared__ uint32_t s_idx_all[4][kCellMax];
+  static_assert(kCellMax % 16 == 0, "rows pad to whole 16-entry groups");
+  __shared__ uint4 s_idx_all[4][kCellMax / 4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t *s_idx = s_idx_all[wave];
+  uint32_t *s_idx = reinterpret_cast<uint32_t *>(s_idx_all[wave]);
   const uint32_t nocc = S->n_occ;
   for (uint32_t q = blockIdx.x * 4 + wave; q < nocc; q += gridDim.x * 4) {
-    const uint32_t b = occ[q];
-    const uint32_t s0 = start[b];
-    const uint32_t s1 = start[b + 1];
+    // the block and its range, as the scan left them (one wave-uniform load)
+    const uint4 br = occr[__builtin_amdgcn_readfirstlane(q)];
+    const uint32_t b = br.x, s0 = br.y, s1 = br.z;
     if (s1 <= s0 || s1 > (uint32_t)p.n) {
       if (lane == 0) {
         lraw[b] = kEmpty;
@@ -327,19 +352,18 @@ __global__ void __launch_bounds__(256) k_cell_gather(
     const int n = (int)(s1 - s0);
     const bool canon = n <= kCellMax;
     if (!canon && lane == 0) set_status(S, RTS_E_CAPACITY, -1);
+    const int npad = (n + 15) & ~15;
     if (canon)
-      for (int k = lane; k < n; k += 64) s_idx[k] = tmp[s0 + k];
+      for (int k = lane; k < npad; k += 64) s_idx[k] = k < n ? tmp[s0 + k] : 0xFFFFFFFFu;
     // the wave's LDS writes must be visible to the whole wave
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float v2m = 0.0f, a2m = 0.0f;
-    for (int k = lane; k < n; k += 64) {
-      const uint32_t src = canon ? s_idx[k] : tmp[s0 + k];
-      const uint32_t dst = s0 + (canon ? rank_in(s_idx, n, src) : (uint32_t)k);
+    const auto move = [&](uint32_t src, uint32_t dst) {
       if (src >= (uint32_t)p.n) {
         set_status(S, RTS_E_DEVICE, -1);
-        continue;
+        return;
       }
       perm[dst] = src;
       key[dst] = b;
@@ -351,6 +375,14 @@ __global__ void __launch_bounds__(256) k_cell_gather(
       Io[dst] = Ii[src];
       v2m = fmaxf(v2m, norm2_exact(v.x, v.y, v.z));
       a2m = fmaxf(a2m, norm2_exact(a.x, a.y, a.z));
+    };
+    if (canon) {
+      for (int k = lane; k < n; k += 64) {
+        const uint32_t src = s_idx[k];
+        move(src, s0 + rank_in16(s_idx_all[wave], npad, src));
+      }
+    } else {
+      for (int k = lane; k < n; k += 64) move(tmp[s0 + k], s0 + (uint32_t)k);
     }
     v2m = wave_max(v2m);
     a2m = wave_max(a2m);
@@ -371,8 +403,7 @@ __global__ void __launch_bounds__(256) k_cell_gather(
 // ---------------------------------------------------------------------------
 // one wave per occupied block: R_min, particle flags, block active count
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t *__restrict__ occ,
-                                                   const uint32_t *__restrict__ start,
+__global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint4 *__restrict__ occr,
                                                    const uint8_t *__restrict__ lraw,
                                                    uint8_t *__restrict__ lvl,
                                                    uint32_t *__restrict__ M,
@@ -389,7 +420,9 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
   // takes level l is due again at the next multiple of 2^l
   const uint32_t phase = p.phase_align ? (uint32_t)S->step : 0u;
   for (uint32_t q = blockIdx.x * 4 + wave; q < nocc; q += gridDim.x * 4) {
-    const uint32_t b = occ[q];
+    // the block and its range, as the scan left them (one wave-uniform load)
+    const uint4 br = occr[__builtin_amdgcn_readfirstlane(q)];
+    const uint32_t b = br.x;
     const uint32_t own = lraw[b];
     // R_min (Section 4.2): the smaller step of any occupied neighbour wins.
     uint32_t l = 0xFFu;
@@ -402,8 +435,8 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint32_t 
     l = min(wave_min_u32(l), own);
     if (lane == 0) lvl[b] = (uint8_t)l;
     if (!do_flags) continue;
-    const uint32_t s0 = start[b];
-    const int n = (int)(start[b + 1] - s0);
+    const uint32_t s0 = br.y;
+    const int n = (int)(br.z - s0);
     uint32_t nact = 0;
     float err = 0.0f;
     for (int k0 = 0; k0 < n; k0 += 64) {
@@ -1551,8 +1584,8 @@ void launch_prep_scan(DevCtrl *ctrl, hipStream_t st) {
 void launch_scan(const DevParams &p, const DevPtrs &d, uint32_t *start, bool fluid,
                  hipStream_t st) {
   hipLaunchKernelGGL(k_scan, dim3(blocks_for(p.nb, kScanTile)), dim3(256), 0, st, d.COUNT, start,
-                     p.nb, d.TILES, d.TILES2, fluid ? d.OCC : nullptr, d.LRAW, d.LVL, d.CTRL,
-                     d.S);
+                     p.nb, d.TILES, d.TILES2, fluid ? d.OCC : nullptr, d.OCCR, d.LRAW, d.LVL,
+                     d.CTRL, d.S);
 }
 void launch_scatter(const DevParams &p, const DevPtrs &d, hipStream_t st) {
   if (p.n == 0) return;
@@ -1561,13 +1594,12 @@ void launch_scatter(const DevParams &p, const DevPtrs &d, hipStream_t st) {
 }
 void launch_cell_gather(const DevParams &p, const DevPtrs &d, int cur, int grid, hipStream_t st) {
   const int nx = cur ^ 1;
-  hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)grid), dim3(256), 0, st, p, d.OCC,
-                     d.CELL_START, d.TMP, d.PERM, d.KEY, d.P[cur], d.V[cur], d.A[cur], d.M[cur],
+  hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)grid), dim3(256), 0, st, p, d.OCCR, d.TMP, d.PERM, d.KEY, d.P[cur], d.V[cur], d.A[cur], d.M[cur],
                      d.ID[cur], d.P[nx], d.V[nx], d.A[nx], d.M[nx], d.ID[nx], d.LRAW, d.S);
 }
 void launch_rmin_flags(const DevParams &p, const DevPtrs &d, int cur, int do_flags, int grid,
                        hipStream_t st, const uint8_t *src) {
-  hipLaunchKernelGGL(k_rmin_flags, dim3((unsigned)grid), dim3(256), 0, st, p, d.OCC, d.CELL_START,
+  hipLaunchKernelGGL(k_rmin_flags, dim3((unsigned)grid), dim3(256), 0, st, p, d.OCCR,
                      src ? src : d.LRAW, d.LVL, d.M[cur], d.P[cur], d.BLKU, d.BLKERR, d.BLKAMAX, d.ACT,
                      d.ACTN, d.S, do_flags);
 }
