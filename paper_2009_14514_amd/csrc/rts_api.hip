@@ -376,7 +376,7 @@ size_t carve(const DevParams &p, int64_t ncap, int64_t nwcap, char *base, DevPtr
   t.OCC = (uint32_t *)take(nb * 4);
   t.OCCR = (uint4 *)take(nb * 16);
   t.ACT = (uint32_t *)take((size_t)p.act_cap * kActBuckets * 4);
-  t.ACTN = (uint32_t *)take(kActBuckets * 4);
+  t.ACTN = (uint32_t *)take((size_t)kActBuckets * kActnStride * 4);
   t.LRAW = (uint8_t *)take(nb);
   t.LVL = (uint8_t *)take(nb);
   t.BLKU = (uint4 *)take(nb * 16);

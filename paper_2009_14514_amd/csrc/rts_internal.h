@@ -111,6 +111,9 @@ struct DevCtrl {
 constexpr int kActBuckets = 256;
 constexpr int kActClasses = 8;
 constexpr int kActParts = kActBuckets / kActClasses;
+// Segment r's length lives at ACTN[r kActnStride]: one counter per 256 bytes,
+// so that appends to different segments do not queue on one cache line.
+constexpr int kActnStride = 64;
 
 // Counters kept on the device (part of the saved state).
 struct DevScalars {
@@ -181,7 +184,7 @@ struct DevPtrs {
   uint32_t *OCC;     // occupied blocks, ascending
   uint4 *OCCR;       // the same blocks with their sorted range: key, first slot, end slot, 0
   uint32_t *ACT;     // blocks holding an active particle this step, kActBuckets segments
-  uint32_t *ACTN;    // kActBuckets segment lengths, zero at every step's start
+  uint32_t *ACTN;    // kActBuckets segment lengths (kActnStride apart), zero at every step's start
   uint8_t *LRAW, *LVL;   // block level before / after R_min
   uint4 *BLKU;       // per block: active, pairs, candidate tests, max count | n << 16
   float *BLKERR;     // per block: max compression error

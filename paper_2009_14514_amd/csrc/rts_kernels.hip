@@ -95,7 +95,7 @@ __device__ inline void bin_particle(const DevParams &p, int i, bool live, float4
 // ticket apart: the fold that consumes it clears it); a fresh epoch for the
 // step's scan.
 __device__ inline void step_controls_reset(int i, DevCtrl *ctrl, uint32_t *__restrict__ actn) {
-  if (i < kActBuckets) actn[i] = 0u;
+  if (i < kActBuckets) actn[i * kActnStride] = 0u;
   if (i == 0) {
     ctrl->epoch += 1u;
     ctrl->scan_ticket = 0u;
@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(256) k_rmin_flags(DevParams p, const uint4 *__
                                                                 (uint32_t)(kActClasses - 1));
         const uint32_t part = (uint32_t)(((unsigned long long)q * kActParts) / nocc);
         const uint32_t r = cls * (uint32_t)kActParts + part;
-        act[r * (uint32_t)p.act_cap + atomicAdd(&actn[r], 1u)] = b;
+        act[r * (uint32_t)p.act_cap + atomicAdd(&actn[r * kActnStride], 1u)] = b;
       } else {
         blkamax[b] = 0.0f;
       }
@@ -499,7 +499,7 @@ __device__ inline void active_prefix(const uint32_t *__restrict__ actn, uint32_t
     uint32_t v[kPer], s = 0u;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-      s += actn[tid * kPer + j];
+      s += actn[(tid * kPer + j) * kActnStride];
       v[j] = s;
     }
     uint32_t x = s;
