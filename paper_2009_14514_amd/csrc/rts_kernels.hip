@@ -328,7 +328,8 @@ __device__ inline uint32_t rank_in16(const uint4 *s4, int n, uint32_t val) {
 // one wave per occupied block: canonical order, gather, block maxima, level
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_cell_gather(
-    DevParams p, const uint4 *__restrict__ occr, const uint32_t *__restrict__ tmp, uint32_t *__restrict__ perm, uint32_t *__restrict__ key,
+    DevParams p, const uint4 *__restrict__ occr, const uint32_t *__restrict__ tmp,
+    uint32_t *__restrict__ perm, uint32_t *__restrict__ key,
     const float4 *__restrict__ Pi, const float4 *__restrict__ Vi, const float4 *__restrict__ Ai,
     const uint32_t *__restrict__ Mi, const uint32_t *__restrict__ Ii, float4 *__restrict__ Po,
     float4 *__restrict__ Vo, float4 *__restrict__ Ao, uint32_t *__restrict__ Mo,
