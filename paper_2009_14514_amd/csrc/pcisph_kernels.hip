@@ -7,8 +7,8 @@
 // R_min and marks the observed blocks.  Each minor step then
 //   lists        rebuilds the neighbour lists of particles whose validity ran
 //                out, against the grid of the major step (two block layers
-//                for region 1, or regions 1 and 2), and sums their gravity +
-//                viscosity over the hits
+//                for region 1, or regions 1 and 2)
+//   nonpressure  sums their gravity + viscosity over the new lists
 //   reset        p = 0, F^p = 0, S_e empty
 //   per iteration (the host reads the error reductions between iterations):
 //     predict    v* = v + dt (a_vg + a_p), x* = x + dt v*   (all)
@@ -22,9 +22,10 @@
 // Density and pressure force run one thread per particle: the lists hold
 // about 45 entries within 1.1 r and neighbouring threads share most of them,
 // so gathers hit the caches (each XCD takes one contiguous range of
-// particles, so neighbours share its L2).  The list pass gives a particle
-// eight lanes.  Sums run in list order and the reductions are folded in a
-// fixed order: runs are deterministic.
+// particles, so neighbours share its L2).  The list pass sweeps a wave's
+// eight particles' rows together, a candidate per lane.  Sums run in list
+// order and the reductions are folded in a fixed order: runs are
+// deterministic.
 #include "rts_device.h"
 #include "xcd.h"
 
@@ -137,32 +138,33 @@ __device__ inline float grad_factor(const DevParams &p, float r2) {
 // Neighbour lists against the grid of the major step (Section 5,
 // neighbourhood computation): blocks up to `rings` layers around the
 // particle's block, float predicate with the list radius, canonical order
-// (fluid by sorted index, then walls by wall sorted index | bit 31).  The
-// same pass sums the non-pressure acceleration of Algorithm 2 (gravity plus
-// artificial viscosity of approaching pairs within the support; walls at
-// rest) over the hits, while each neighbour's position is at hand.
+// (fluid by sorted index, then walls by wall sorted index | bit 31).
 //
-// kPciSub lanes share a particle: they load kPciSub consecutive candidates
-// of a row at once, and a ballot of their hits gives each hit its place in
-// the list, so the list keeps the canonical order.
+// A wave takes kPciWave consecutive particles of the sorted order.  When the
+// ones that rebuild their lists search one block layer and share a block row
+// (y, z) within two neighbouring blocks in x (most waves: a block holds about
+// 11 particles), the wave sweeps the union of their rows once, a candidate per
+// lane, and tests every particle against each chunk of 64: each candidate is
+// loaded once per wave instead of once per particle.  A candidate counts for
+// a particle only inside the particle's own 27 blocks (its block in x from
+// the row's block starts), so each list holds exactly its own rows' hits, in
+// candidate order.  Other waves give each particle kPciSub lanes, which load
+// kPciSub consecutive candidates of a row at once; a ballot of their hits
+// places each hit, so the list keeps the canonical order either way.
 constexpr int kPciSub = 8;
-__global__ void __launch_bounds__(256) k_pci_lists(
-    DevParams p, const float4 *__restrict__ P, const float4 *__restrict__ V,
-    const uint32_t *__restrict__ M, const uint32_t *__restrict__ key,
-    const uint32_t *__restrict__ start, const float4 *__restrict__ WP,
-    const uint32_t *__restrict__ wstart, uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb,
-    float4 *__restrict__ fvg, const uint32_t *__restrict__ ids, DevScalars *S) {
-  const uint32_t i = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / kPciSub;
-  const uint32_t sub = threadIdx.x & (kPciSub - 1);
-  const uint32_t first = (threadIdx.x & 63u) & ~(uint32_t)(kPciSub - 1);  // group's first lane
-  // the lanes of a particle leave together
-  if (i >= (uint32_t)p.n) return;
-  const uint32_t m = M[i];
-  if (!meta_compute(m)) return;
-  const int rings = (p.mode == RTS_MODE_RTS && (int)meta_level(m) < p.two_ring_levels) ? 2 : 1;
-  const float4 xi = P[i], vi = V[i];
-  const float rs2 = p.support * p.support;
-  float ax = 0.0f, ay = 0.0f, az = 0.0f;
+constexpr int kPciWave = 64 / kPciSub;   // particles per wave, both ways
+
+// One particle's list with kPciSub lanes (lane sub of the group starting at
+// lane `first`).
+__device__ inline void pci_list_lanes(const DevParams &p, const float4 *__restrict__ P,
+                                      const uint32_t *__restrict__ key,
+                                      const uint32_t *__restrict__ start,
+                                      const float4 *__restrict__ WP,
+                                      const uint32_t *__restrict__ wstart,
+                                      uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb,
+                                      const uint32_t *__restrict__ ids, DevScalars *S, uint32_t i,
+                                      int rings, uint32_t sub, uint32_t first) {
+  const float4 xi = P[i];
   const int3 c = coords_of(p, key[i]);
   const size_t ncap = (size_t)p.ncap;
   uint32_t cnt = 0;  // the same in the particle's lanes
@@ -183,9 +185,8 @@ __global__ void __launch_bounds__(256) k_pci_lists(
         for (uint32_t base = s0; base < s1; base += kPciSub) {
           const uint32_t j = base + sub;
           bool hit = false;
-          float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
           if (j < s1 && !(pass == 0 && j == i)) {
-            q = X[j];
+            const float4 q = X[j];
             hit = dist2_exact(xi.x, xi.y, xi.z, q.x, q.y, q.z) < p.r2l;
           }
           // the group's hits among these candidates, in candidate order
@@ -193,28 +194,11 @@ __global__ void __launch_bounds__(256) k_pci_lists(
           if (hit) {
             const uint32_t pos = cnt + (uint32_t)__popc(mask & ((1u << sub) - 1u));
             if (pos < (uint32_t)p.nbr_cap) nbr[list_word(i, pos, ncap)] = j | tag;
-            const float4 u = pass == 0 ? V[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float vx = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
-            if (r2 > 0.0f && r2 < rs2 && vx < 0.0f) {
-              const float pij = -p.pci_nu * vx / (r2 + p.visc_eps_h2);
-              const float sc = -p.mass * pij * grad_factor(p, r2);
-              ax += sc * dx;
-              ay += sc * dy;
-              az += sc * dz;
-            }
           }
           cnt += (uint32_t)__popc(mask);
         }
       }
     }
-  }
-  // the group's partial sums, folded in a fixed order
-  for (int o = 1; o < kPciSub; o <<= 1) {
-    ax += __shfl_xor(ax, o, kPciSub);
-    ay += __shfl_xor(ay, o, kPciSub);
-    az += __shfl_xor(az, o, kPciSub);
   }
   if (sub != 0) return;
   if (cnt > (uint32_t)p.nbr_cap) {
@@ -222,6 +206,273 @@ __global__ void __launch_bounds__(256) k_pci_lists(
     cnt = (uint32_t)p.nbr_cap;
   }
   nnb[i] = cnt;
+}
+
+// The union rows of a wave's particles, one pass (fluid or walls): row r
+// (dz = r / 3 - 1, dy = r % 3 - 1) holds the candidates from rs[r] on, at
+// positions off[r] .. off[r + 1] of the sweep; b[r] are the first sorted
+// indices of its second, third and fourth block in x (or its end).
+struct PciRows {
+  uint4 rb[9];        // rs, b1, b2, b3
+  uint32_t off[10];
+};
+// List entries a wave's particle gathers in LDS before they are stored in
+// quads: the shared sweep runs when the list capacity fits.
+constexpr int kPciLdsCap = 128;
+
+__global__ void __launch_bounds__(256) k_pci_lists(
+    DevParams p, const float4 *__restrict__ P, const uint32_t *__restrict__ M,
+    const uint32_t *__restrict__ key, const uint32_t *__restrict__ start,
+    const float4 *__restrict__ WP, const uint32_t *__restrict__ wstart,
+    uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb, const uint32_t *__restrict__ ids,
+    DevScalars *S) {
+  __shared__ PciRows s_rows[4];
+  __shared__ uint32_t s_list[4][kPciWave][kPciLdsCap];
+  __shared__ float4 s_mem[4][kPciWave];   // the wave's particles: x, y, z, block x
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t i0 = (xcd_block(blockIdx.x, gridDim.x) * 4u + wave) * (uint32_t)kPciWave;
+  if (i0 >= (uint32_t)p.n) return;
+  // the wave's particles, one per lane below kPciWave
+  const uint32_t im = i0 + (lane & (uint32_t)(kPciWave - 1));
+  bool mem = false;
+  int rings = 1;
+  int3 c = make_int3(0, 0, 0);
+  float4 xm = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (lane < (uint32_t)kPciWave && im < (uint32_t)p.n) {
+    const uint32_t m = M[im];
+    if (meta_compute(m)) {
+      mem = true;
+      rings = (p.mode == RTS_MODE_RTS && (int)meta_level(m) < p.two_ring_levels) ? 2 : 1;
+      c = coords_of(p, key[im]);
+      xm = P[im];
+    }
+  }
+  const uint32_t memmask = (uint32_t)__ballot(mem);
+  if (memmask == 0u) return;
+  const int lead = __ffs((int)memmask) - 1;
+  const int cy = __shfl(c.y, lead, 64), cz = __shfl(c.z, lead, 64);
+  int xmn = mem ? c.x : 0x7FFFFFFF, xmx = mem ? c.x : -1;
+#pragma unroll
+  for (int o = 1; o < kPciWave; o <<= 1) {
+    xmn = min(xmn, __shfl_xor(xmn, o, 64));
+    xmx = max(xmx, __shfl_xor(xmx, o, 64));
+  }
+  xmn = __builtin_amdgcn_readfirstlane(xmn);
+  xmx = __builtin_amdgcn_readfirstlane(xmx);
+  const bool odd = mem && (rings != 1 || c.y != cy || c.z != cz);
+  if (__ballot(odd) != 0ull || xmx - xmn > 1 || p.nbr_cap > kPciLdsCap) {
+    // the particle's own kPciSub lanes; a particle's lanes leave together
+    const uint32_t i = i0 + lane / (uint32_t)kPciSub;
+    if (i >= (uint32_t)p.n) return;
+    const uint32_t m = M[i];
+    if (!meta_compute(m)) return;
+    const int ri = (p.mode == RTS_MODE_RTS && (int)meta_level(m) < p.two_ring_levels) ? 2 : 1;
+    pci_list_lanes(p, P, key, start, WP, wstart, nbr, nnb, ids, S, i, ri,
+                   lane & (uint32_t)(kPciSub - 1), lane & ~(uint32_t)(kPciSub - 1));
+    return;
+  }
+  // one sweep of the union rows for every particle of the wave
+  const size_t ncap = (size_t)p.ncap;
+  const int xlo = max(xmn - 1, 0), xhi = min(xmx + 1, p.nc[0] - 1);
+  if (lane < (uint32_t)kPciWave)
+    s_mem[wave][lane] = make_float4(xm.x, xm.y, xm.z, __builtin_bit_cast(float, c.x));
+  uint32_t cnt[kPciWave];
+#pragma unroll
+  for (int t = 0; t < kPciWave; ++t) cnt[t] = 0u;
+  PciRows &rows = s_rows[wave];
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 && p.nw == 0) break;
+    const uint32_t *cs = pass == 0 ? start : wstart;
+    const float4 *X = pass == 0 ? P : WP;
+    const uint32_t tag = pass == 0 ? 0u : kWallBit;
+    // row r in lane r: its range and the block starts inside it
+    uint32_t len = 0;
+    uint4 rb = make_uint4(0u, 0u, 0u, 0u);
+    if (lane < 9u) {
+      const int y = cy + (int)(lane % 3u) - 1, z = cz + (int)(lane / 3u) - 1;
+      if (y >= 0 && y < p.nc[1] && z >= 0 && z < p.nc[2]) {
+        const uint32_t row = (uint32_t)p.nc[0] * ((uint32_t)y + (uint32_t)p.nc[1] * (uint32_t)z);
+        const uint32_t s0 = cs[row + (uint32_t)xlo], s1 = cs[row + (uint32_t)xhi + 1u];
+        const uint32_t e1 = xlo + 1 <= xhi ? cs[row + (uint32_t)xlo + 1u] : s1;
+        const uint32_t e2 = xlo + 2 <= xhi ? cs[row + (uint32_t)xlo + 2u] : s1;
+        const uint32_t e3 = xlo + 3 <= xhi ? cs[row + (uint32_t)xlo + 3u] : s1;
+        rb = make_uint4(s0, e1, e2, e3);
+        len = s1 - s0;
+      }
+    }
+    uint32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= (uint32_t)o) incl += u;
+    }
+    if (lane < 9u) {
+      rows.rb[lane] = rb;
+      rows.off[lane] = incl - len;
+    }
+    if (lane == 8u) rows.off[9] = incl;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t off[10];
+#pragma unroll
+    for (int r = 0; r < 10; ++r) off[r] = __builtin_amdgcn_readfirstlane(rows.off[r]);
+    const uint32_t total = off[9];
+    // candidate at sweep position pos: its sorted index and its block in x
+    // (far away and in no particle's blocks past the end)
+    const auto candidate = [&](uint32_t pos, uint32_t &j, int &cbx) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int k = 1; k < 9; ++k) r += pos >= off[k] ? 1u : 0u;
+      const uint4 rr = rows.rb[r];
+      j = rr.x + (pos - rows.off[r]);
+      cbx = xlo + (j >= rr.y ? 1 : 0) + (j >= rr.z ? 1 : 0) + (j >= rr.w ? 1 : 0);
+      float4 q = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+      if (pos < total) q = X[j];
+      else cbx = -4;
+      return q;
+    };
+    // the wave's particles in block xmn (bit t set), the others in xmx
+    uint32_t in_mn = 0;
+#pragma unroll
+    for (int t = 0; t < kPciWave; ++t)
+      in_mn |= (__builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, s_mem[wave][t].w)) == xmn
+                    ? 1u
+                    : 0u)
+               << t;
+    // two chunks in flight, each loaded into the registers it is tested from
+    const auto test_chunk = [&](const float4 q, const uint32_t j, const int cbx) {
+      // inside the 27 blocks of a particle in block xmn, or of one in xmx
+      const bool okn = (uint32_t)(cbx - xmn + 1) <= 2u;
+      const bool okx = (uint32_t)(cbx - xmx + 1) <= 2u;
+#pragma unroll
+      for (int t = 0; t < kPciWave; ++t) {
+        // every slot is tested (no branch); a slot that is not one of the
+        // wave's particles never hits
+        const uint32_t it = i0 + (uint32_t)t;
+        const float4 mt = s_mem[wave][t];
+        const bool ok = ((in_mn >> t) & 1u) ? okn : okx;
+        const bool hit = (((memmask >> t) & 1u) != 0u) & ok & !(pass == 0 && j == it) &
+                         (dist2_exact(mt.x, mt.y, mt.z, q.x, q.y, q.z) < p.r2l);
+        const unsigned long long hm = __ballot(hit);
+        if (hit) {
+          const uint32_t at = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(hm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hm, cnt[t]));
+          if (at < (uint32_t)p.nbr_cap) s_list[wave][t][at] = j | tag;
+        }
+        cnt[t] += (uint32_t)__popcll(hm);
+      }
+    };
+    uint32_t ja, jb;
+    int ba, bb;
+    float4 qa = candidate(lane, ja, ba);
+    float4 qb = candidate(64u + lane, jb, bb);  // not tested when total <= 64
+    for (uint32_t pos0 = 0; pos0 < total; pos0 += 128u) {
+      test_chunk(qa, ja, ba);
+      if (pos0 + 128u < total) qa = candidate(pos0 + 128u + lane, ja, ba);
+      if (pos0 + 64u >= total) break;
+      test_chunk(qb, jb, bb);
+      if (pos0 + 192u < total) qb = candidate(pos0 + 192u + lane, jb, bb);
+    }
+    // the next pass rewrites the rows
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // the gathered entries, a quad per lane (entries past the list's end are
+  // stored as 0)
+  uint32_t nq[kPciWave], qoff[kPciWave + 1];
+  qoff[0] = 0u;
+#pragma unroll
+  for (int t = 0; t < kPciWave; ++t) {
+    const uint32_t n = min(cnt[t], (uint32_t)p.nbr_cap);
+    nq[t] = ((memmask >> t) & 1u) ? (n + 3u) / 4u : 0u;
+    qoff[t + 1] = qoff[t] + nq[t];
+  }
+  for (uint32_t k0 = 0; k0 < qoff[kPciWave]; k0 += 64u) {
+    const uint32_t k = k0 + lane;
+    if (k >= qoff[kPciWave]) break;
+    uint32_t t = 0;
+#pragma unroll
+    for (int u = 1; u < kPciWave; ++u) t += k >= qoff[u] ? 1u : 0u;
+    uint32_t q = k, n = 0;
+#pragma unroll
+    for (int u = 0; u < kPciWave; ++u)
+      if (t == (uint32_t)u) {
+        q = k - qoff[u];
+        n = min(cnt[u], (uint32_t)p.nbr_cap);
+      }
+    const uint32_t e = 4u * q;
+    const uint32_t *row = s_list[wave][t];
+    const uint4 v = make_uint4(row[e], e + 1u < n ? row[e + 1u] : 0u, e + 2u < n ? row[e + 2u] : 0u,
+                               e + 3u < n ? row[e + 3u] : 0u);
+    *reinterpret_cast<uint4 *>(nbr + list_word(i0 + t, e, ncap)) = v;
+  }
+  // lane t writes particle t's count
+  uint32_t mine = 0;
+#pragma unroll
+  for (int t = 0; t < kPciWave; ++t)
+    if (lane == (uint32_t)t) mine = cnt[t];
+  if (!mem) return;
+  if (mine > (uint32_t)p.nbr_cap) {
+    set_status(S, RTS_E_CAPACITY, (int32_t)ids[im]);
+    mine = (uint32_t)p.nbr_cap;
+  }
+  nnb[im] = mine;
+}
+
+// Non-pressure acceleration of Algorithm 2 for the particles that rebuilt
+// their lists: gravity plus the artificial viscosity of approaching pairs
+// within the support, summed over the list in list order (walls at rest).
+__global__ void __launch_bounds__(256) k_pci_nonpressure(
+    DevParams p, const float4 *__restrict__ P, const float4 *__restrict__ V,
+    const uint32_t *__restrict__ M, const uint32_t *__restrict__ nbr,
+    const uint32_t *__restrict__ nnb, const float4 *__restrict__ WP, float4 *__restrict__ fvg) {
+  const int i = (int)(xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
+  if (i >= p.n) return;
+  if (!meta_compute(M[i])) return;
+  const float4 xi = P[i], vi = V[i];
+  const float rs2 = p.support * p.support;
+  const uint4 *L4 = reinterpret_cast<const uint4 *>(nbr) + i;
+  const size_t stride = (size_t)p.ncap;
+  const uint32_t n = nnb[i];
+  float ax = 0.0f, ay = 0.0f, az = 0.0f;
+  auto add = [&](const float4 q, const float4 u) {
+    const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float vx = (vi.x - u.x) * dx + (vi.y - u.y) * dy + (vi.z - u.z) * dz;
+    if (r2 > 0.0f && r2 < rs2 && vx < 0.0f) {
+      const float pij = -p.pci_nu * vx * __builtin_amdgcn_rcpf(r2 + p.visc_eps_h2);
+      const float sc = -p.mass * pij * grad_factor(p, r2);
+      ax += sc * dx;
+      ay += sc * dy;
+      az += sc * dz;
+    }
+  };
+  const uint32_t nfull = n & ~3u;
+  for (uint32_t k0 = 0; k0 < nfull; k0 += 4) {
+    // a full quad: its gathers are issued before they are used
+    const uint4 e = L4[(size_t)(k0 >> 2) * stride];
+    const uint32_t js[4] = {e.x, e.y, e.z, e.w};
+    float4 q[4], u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool wall = (js[k] & kWallBit) != 0u;
+      q[k] = wall ? WP[js[k] & ~kWallBit] : P[js[k]];
+      u[k] = wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[js[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) add(q[k], u[k]);
+  }
+  if (nfull < n) {
+    const uint4 e = L4[(size_t)(nfull >> 2) * stride];
+    const uint32_t js[3] = {e.x, e.y, e.z};
+    for (uint32_t k = 0; nfull + k < n; ++k) {
+      const bool wall = (js[k] & kWallBit) != 0u;
+      add(wall ? WP[js[k] & ~kWallBit] : P[js[k]],
+          wall ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : V[js[k]]);
+    }
+  }
   fvg[i] = make_float4(p.g[0] + ax, p.g[1] + ay, p.g[2] + az, 0.0f);
 }
 
@@ -609,9 +860,10 @@ void launch_pci_observed(const DevParams &p, const DevPtrs &d, hipStream_t st) {
 void launch_pci_lists(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
   if (p.n == 0) return;
   hipLaunchKernelGGL(k_pci_lists, dim3(grid_of((int64_t)p.n * kPciSub, 256)), dim3(256), 0, st,
-                     p, d.P[cur],
-                     d.V[cur], d.M[cur], d.KEY, d.CELL_START, d.WP, d.WCELL_START, d.NBRL, d.NNB,
-                     d.FVG, d.ID[cur], d.S);
+                     p, d.P[cur], d.M[cur], d.KEY, d.CELL_START, d.WP, d.WCELL_START, d.NBRL,
+                     d.NNB, d.ID[cur], d.S);
+  hipLaunchKernelGGL(k_pci_nonpressure, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
+                     d.V[cur], d.M[cur], d.NBRL, d.NNB, d.WP, d.FVG);
 }
 void launch_pci_reset(const DevParams &p, const DevPtrs &d, hipStream_t st) {
   const int64_t m = p.n > p.nb ? p.n : p.nb;
