@@ -672,19 +672,36 @@ __global__ void __launch_bounds__(256) k_pci_errstats(DevParams p, const float4 
   __shared__ uint32_t s_last;
   const int tid = threadIdx.x;
   PciPart t = {};
-  for (int i = blockIdx.x * blockDim.x + tid; i < p.n; i += gridDim.x * blockDim.x) {
+  const auto take = [&](float e, uint32_t m) {
+    e = fmaxf(e, 0.0f);
+    t.errmax = fmaxf(t.errmax, e);
+    t.sum += (double)e;
+    const uint32_t l = meta_level(m);
+    t.ncomp += (int32_t)meta_compute(m);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t.hist[k] += l == (uint32_t)k ? 1 : 0;
+  };
+  const int stride = (int)(gridDim.x * blockDim.x);
+  int i = (int)(blockIdx.x * blockDim.x) + tid;
+  if (!V) {
+    // four particles' loads issued before any is used
+    for (; i + 3 * stride < p.n; i += 4 * stride) {
+      const float e0 = pv[i].y, e1 = pv[i + stride].y, e2 = pv[i + 2 * stride].y,
+                  e3 = pv[i + 3 * stride].y;
+      const uint32_t m0 = M[i], m1 = M[i + stride], m2 = M[i + 2 * stride], m3 = M[i + 3 * stride];
+      take(e0, m0);
+      take(e1, m1);
+      take(e2, m2);
+      take(e3, m3);
+    }
+  }
+  for (; i < p.n; i += stride) {
     if (V) {
       const float4 v = V[i], a = A[i];
       t.v2max = fmaxf(t.v2max, norm2_exact(v.x, v.y, v.z));
       t.a2max = fmaxf(t.a2max, norm2_exact(a.x, a.y, a.z));
     }
-    const float e = fmaxf(pv[i].y, 0.0f);
-    t.errmax = fmaxf(t.errmax, e);
-    t.sum += (double)e;
-    const uint32_t m = M[i], l = meta_level(m);
-    t.ncomp += (int32_t)meta_compute(m);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) t.hist[k] += l == (uint32_t)k ? 1 : 0;
+    take(pv[i].y, M[i]);
   }
   const PciPart a = pci_block_reduce(t, s_w);
   if (tid == 0) {

@@ -83,7 +83,7 @@ struct PciPart {
   int32_t hist[4];
   float v2max, a2max;
 };
-constexpr int kPciStatBlocks = 512;
+constexpr int kPciStatBlocks = 128;
 
 // Control words.  Zeroed once when the context is created and never reset
 // or restored afterwards: the scan epoch only grows, so look-back words left
