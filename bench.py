@@ -366,9 +366,20 @@ def pcisph_arms(make_scene, steps, label):
             sim.advance(steps)
             st = sim.sync()
         except RtsError as e:
-            st = sim.sync(raise_on_error=False)
-            out[mode] = dict(n=sc.n, failed=str(e), time=st.time)
-            print(f"[bench] {label} {mode}: stopped at t = {st.time:.4f} s ({e})",
+            sim.close()
+            # untimed rerun one minor step at a time: the step that raised it
+            sim = Simulation(sc)
+            t_fail = None
+            for _ in range(steps):
+                t_before = sim.sync(raise_on_error=False).time
+                try:
+                    sim.advance(1)
+                    sim.sync()
+                except RtsError:
+                    t_fail = t_before
+                    break
+            out[mode] = dict(n=sc.n, failed=str(e), time=t_fail)
+            print(f"[bench] {label} {mode}: stopped in the minor step from t = {t_fail} s ({e})",
                   file=sys.stderr, flush=True)
             sim.close()
             continue
@@ -384,7 +395,7 @@ def pcisph_arms(make_scene, steps, label):
 
 def arm_summary(a, steps):
     if "failed" in a:
-        return {"stopped": a["failed"], "stopped_at_s": a["time"]}
+        return {"stopped": a["failed"], "stopped_in_step_from_s": a["time"]}
     return {"value": a["n"] * steps / (a["ms"] * 1e-3), "ms_per_step": a["ms"] / steps,
             "iterations": a["iters"], "density_err_last": a["errmax"]}
 
