@@ -66,13 +66,13 @@ def test_major_step_setup_is_bit_exact(steps):
     assert np.array_equal(val, region_validity(want_level, major_len))
 
 
-def first_iteration(v0):
+def first_iteration(v0, **extra):
     """One minor step with exactly one correction iteration from a major-step
     set-up, so that every particle is evaluated once from the stored
     snapshot.  Columns thrown at v0 = 10 m/s put every block in region 1
     (two-layer search); at 1.5 m/s the blocks take regions 2-3."""
     sc = scene(v0=v0)
-    over = dict(it_min=1, it_max=1)
+    over = dict(it_min=1, it_max=1, **extra)
     sim = Simulation(sc, **over)
     sim.assign_levels()
     before = {k: sim.debug(k) for k in ("POS", "VEL", "META", "KEY", "CELL_START")}
@@ -82,9 +82,13 @@ def first_iteration(v0):
     return sc, sim, cfg, before
 
 
-@pytest.mark.parametrize("v0", [1.5, 10.0])
-def test_lists_match_the_oracle_on_the_stored_grid(v0):
-    sc, sim, cfg, before = first_iteration(v0)
+# (1.5, default capacity): one-layer lists, built by the shared sweep of a
+# wave's particles; (1.5, 256): a capacity above the sweep's LDS rows, so
+# every wave gives each particle its own lanes; (10, default): two layers
+# for region 1, own lanes as well
+@pytest.mark.parametrize("v0,extra", [(1.5, {}), (1.5, {"nbr_cap": 256}), (10.0, {})])
+def test_lists_match_the_oracle_on_the_stored_grid(v0, extra):
+    sc, sim, cfg, before = first_iteration(v0, **extra)
     rows, counts = pcisph_lists(sim)
     level, comp, _, _ = decode_meta(before["META"])
     rings = np.where(level == 0, 2, 1).astype(np.uint8)
