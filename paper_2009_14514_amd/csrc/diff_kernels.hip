@@ -458,7 +458,21 @@ __global__ void __launch_bounds__(256) k_diff_reduce(int n, const double *__rest
   __shared__ double s_b[256], s_a[256];
   const int t = threadIdx.x;
   double sb = 0.0, sa = 0.0;
-  for (int i = t; i < n; i += 256) {
+  int i = t;
+  // four entries' loads issued before they are added (in the same order)
+  for (; i + 3 * 256 < n; i += 4 * 256) {
+    const double b0 = BB[i], b1 = BB[i + 256], b2 = BB[i + 512], b3 = BB[i + 768];
+    const double a0 = AA[i], a1 = AA[i + 256], a2 = AA[i + 512], a3 = AA[i + 768];
+    sb += b0;
+    sb += b1;
+    sb += b2;
+    sb += b3;
+    sa += a0;
+    sa += a1;
+    sa += a2;
+    sa += a3;
+  }
+  for (; i < n; i += 256) {
     sb += BB[i];
     sa += AA[i];
   }
