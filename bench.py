@@ -210,6 +210,20 @@ def run_collapse_leg():
     }
 
 
+def copy_calibration():
+    """Three launches of one elementwise kernel that reads 256 MiB and writes
+    256 MiB: the reference for scaling HBM byte counters."""
+    import torch
+
+    torch.cuda.set_device(0)
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def run_gpu(args):
     import torch
 
@@ -217,13 +231,7 @@ def run_gpu(args):
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        # 256 MiB read and 256 MiB written per launch by one elementwise kernel
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
     K, W, R = args.steps, args.warmup, max(args.repeats, 1)
     out = {}
 
@@ -657,6 +665,8 @@ def main():
               f"(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
         sys.exit(2)
     if args.only_pcisph:
+        if args.copy_calibration:
+            copy_calibration()
         run_pcisph(args.pcisph_steps)
         return
     if args.only_diff:
