@@ -378,7 +378,7 @@ typedef enum {
   RTS_DBG_PRE_ACC, RTS_DBG_PRE_META, RTS_DBG_PRE_ID, RTS_DBG_WALL_POS, RTS_DBG_WALL_ID,
   RTS_DBG_WALL_CELL_START, RTS_DBG_OCCUPIED, RTS_DBG_BLK_STATS,
   /* PCISPH (block order of the current major step) */
-  RTS_DBG_PCI_XS,        /* float4: predicted position x*, 0 */
+  RTS_DBG_PCI_XS,        /* float4: predicted position x*, p / rho*^2 */
   RTS_DBG_PCI_PV,        /* float4: pressure, relative density error, pressure backup, rho* */
   RTS_DBG_PCI_FVG,       /* float4: non-pressure acceleration (gravity + viscosity), 0 */
   RTS_DBG_PCI_FP,        /* float4: pressure acceleration, 0 */

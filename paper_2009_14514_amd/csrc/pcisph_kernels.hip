@@ -491,13 +491,16 @@ __global__ void k_pci_reset(DevParams p, float4 *__restrict__ pv, float4 *__rest
 
 __global__ void k_pci_predict(DevParams p, const float4 *__restrict__ P,
                               const float4 *__restrict__ V, const float4 *__restrict__ fvg,
-                              const float4 *__restrict__ fp, float4 *__restrict__ xs) {
+                              const float4 *__restrict__ fp, const float *__restrict__ pq,
+                              float4 *__restrict__ xs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   const float4 x = P[i], v = V[i], a = fvg[i], b = fp[i];
   const float dt = p.dt_base;
   const float vx = v.x + dt * (a.x + b.x), vy = v.y + dt * (a.y + b.y), vz = v.z + dt * (a.z + b.z);
-  xs[i] = make_float4(x.x + dt * vx, x.y + dt * vy, x.z + dt * vz, 0.0f);
+  // w carries p / rho*^2, so the pressure-force pass gathers one float4 per
+  // neighbour; the density pass updates it for the particles it evaluates
+  xs[i] = make_float4(x.x + dt * vx, x.y + dt * vy, x.z + dt * vz, pq[i]);
 }
 
 // Algorithm 3, density prediction: particles with the turn, S_e and the
@@ -505,7 +508,7 @@ __global__ void k_pci_predict(DevParams p, const float4 *__restrict__ P,
 // excess is formed as (m sigma / rho0) ((sum - c_hi) - (comp + c_lo)) with
 // c = rho0 / (m sigma) - 1, before any rounding to rho*.
 __global__ void __launch_bounds__(256) k_pci_density(
-    DevParams p, const float4 *__restrict__ xs, float4 *__restrict__ pv, float *__restrict__ pq,
+    DevParams p, float4 *__restrict__ xs, float4 *__restrict__ pv, float *__restrict__ pq,
     const uint32_t *__restrict__ M, const uint32_t *__restrict__ key,
     const uint8_t *__restrict__ ob, const uint8_t *__restrict__ nearse,
     uint8_t *__restrict__ se, const uint32_t *__restrict__ nbr, const uint32_t *__restrict__ nnb,
@@ -556,7 +559,10 @@ __global__ void __launch_bounds__(256) k_pci_density(
   s.y = dev;
   s.w = rho;
   pv[i] = s;
-  pq[i] = s.x / (rho * rho);
+  const float q = s.x / (rho * rho);
+  pq[i] = q;
+  // only the w word: other threads read this particle's x* meanwhile
+  reinterpret_cast<float *>(xs + i)[3] = q;
   if (dev > p.eta_half) se[i] = 1;
 }
 
@@ -578,7 +584,7 @@ __global__ void k_pci_mark_se(DevParams p, const uint8_t *__restrict__ se,
 // Pressure acceleration -m sum_j (p_i/rho_i^2 + p_j/rho_j^2) grad W(x*_ij);
 // a wall particle mirrors p_i and rho_i.
 __global__ void __launch_bounds__(256) k_pci_force(
-    DevParams p, const float4 *__restrict__ xs, const float *__restrict__ pq,
+    DevParams p, const float4 *__restrict__ xs,
     const uint32_t *__restrict__ M, const uint8_t *__restrict__ se,
     const uint32_t *__restrict__ nbr, const uint32_t *__restrict__ nnb,
     const float4 *__restrict__ WP, float4 *__restrict__ fp, uint32_t turn) {
@@ -586,40 +592,38 @@ __global__ void __launch_bounds__(256) k_pci_force(
   if (i >= p.n) return;
   if (!(has_turn(turn, meta_level(M[i])) || se[i])) return;
   const float4 xi = xs[i];
-  const float qi = pq[i];
+  const float qi = xi.w;
   const uint4 *L4 = reinterpret_cast<const uint4 *>(nbr) + i;
   const size_t stride = (size_t)p.ncap;
   const uint32_t n = nnb[i];
   const float rs2 = p.support * p.support;
   float ax = 0.0f, ay = 0.0f, az = 0.0f;
-  auto add = [&](uint32_t j, const float4 q, float qj) {
+  auto add = [&](uint32_t j, const float4 q) {
     const float dx = xi.x - q.x, dy = xi.y - q.y, dz = xi.z - q.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 > 0.0f) || r2 >= rs2) return;
-    const float s = -p.mass * (qi + ((j & kWallBit) ? qi : qj)) * grad_factor(p, r2);
+    const float s = -p.mass * (qi + ((j & kWallBit) ? qi : q.w)) * grad_factor(p, r2);
     ax += s * dx;
     ay += s * dy;
     az += s * dz;
   };
-  // one load each for the position and p / rho*^2 (a wall mirrors p_i, rho_i)
+  // one load per neighbour: x* with p / rho*^2 in w (a wall mirrors p_i, rho_i)
   auto pos = [&](uint32_t j) {
     return *((j & kWallBit) ? WP + (j & ~kWallBit) : xs + j);
   };
-  auto prs = [&](uint32_t j) { return pq[(j & kWallBit) ? 0u : j]; };
   const uint32_t nfull = n & ~3u;
   for (uint32_t k0 = 0; k0 < nfull; k0 += 4) {
     const uint4 e = L4[(size_t)(k0 >> 2) * stride];
     const float4 q0 = pos(e.x), q1 = pos(e.y), q2 = pos(e.z), q3 = pos(e.w);
-    const float p0 = prs(e.x), p1 = prs(e.y), p2 = prs(e.z), p3 = prs(e.w);
-    add(e.x, q0, p0);
-    add(e.y, q1, p1);
-    add(e.z, q2, p2);
-    add(e.w, q3, p3);
+    add(e.x, q0);
+    add(e.y, q1);
+    add(e.z, q2);
+    add(e.w, q3);
   }
   if (nfull < n) {
     const uint4 e = L4[(size_t)(nfull >> 2) * stride];
     const uint32_t js[3] = {e.x, e.y, e.z};
-    for (uint32_t u = 0; nfull + u < n; ++u) add(js[u], pos(js[u]), prs(js[u]));
+    for (uint32_t u = 0; nfull + u < n; ++u) add(js[u], pos(js[u]));
   }
   fp[i] = make_float4(ax, ay, az, 0.0f);
 }
@@ -890,7 +894,7 @@ void launch_pci_reset(const DevParams &p, const DevPtrs &d, hipStream_t st) {
 void launch_pci_predict(const DevParams &p, const DevPtrs &d, int cur, hipStream_t st) {
   if (p.n == 0) return;
   hipLaunchKernelGGL(k_pci_predict, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.P[cur],
-                     d.V[cur], d.FVG, d.FP, d.XS);
+                     d.V[cur], d.FVG, d.FP, d.PQ, d.XS);
 }
 void launch_pci_density(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
                         hipStream_t st) {
@@ -906,7 +910,7 @@ void launch_pci_mark_se(const DevParams &p, const DevPtrs &d, hipStream_t st) {
 void launch_pci_force(const DevParams &p, const DevPtrs &d, int cur, uint32_t turn,
                       hipStream_t st) {
   if (p.n == 0) return;
-  hipLaunchKernelGGL(k_pci_force, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.XS, d.PQ,
+  hipLaunchKernelGGL(k_pci_force, dim3(grid_of(p.n, 256)), dim3(256), 0, st, p, d.XS,
                      d.M[cur], d.SE, d.NBRL, d.NNB, d.WP, d.FP, turn);
 }
 void launch_pci_errstats(const DevParams &p, const DevPtrs &d, int cur, int first,
